@@ -1,0 +1,476 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix.
+
+None of these re-types the oracle's own formulas: each checks a closed form, an
+invariant, a brute-force computation or an exact special case (see each docstring
+for the passage it follows).
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import lrh_workloads as W
+from oracle import exact as E
+from oracle import lrh_oracle as O
+
+from conftest import golden, read_reference_energies
+
+
+# ------------------------------------------------------------------------------------------
+# brute-force lift / partial trace from the index definition (not the oracle's einsum)
+# ------------------------------------------------------------------------------------------
+
+def bf_index(digits, dims):
+    i = 0
+    for dgt, d in zip(digits, dims):
+        i = i * d + dgt
+    return i
+
+
+def bf_lift(X, dims_e, pos):
+    """(1_{e\\f} (x) X)[i, j] = X[a(i), a(j)] * delta(rest(i), rest(j)) with site order of e."""
+    De = int(np.prod(dims_e))
+    out = np.zeros((De, De), dtype=np.complex128)
+    fd = [dims_e[p] for p in pos]
+    for di in itertools.product(*[range(d) for d in dims_e]):
+        for dj in itertools.product(*[range(d) for d in dims_e]):
+            if any(di[k] != dj[k] for k in range(len(dims_e)) if k not in pos):
+                continue
+            a = bf_index([di[p] for p in pos], fd)
+            b = bf_index([dj[p] for p in pos], fd)
+            out[bf_index(di, dims_e), bf_index(dj, dims_e)] = X[a, b]
+    return out
+
+
+def bf_ptrace(A, dims_e, pos):
+    fd = [dims_e[p] for p in pos]
+    rest = [k for k in range(len(dims_e)) if k not in pos]
+    Df = int(np.prod(fd))
+    out = np.zeros((Df, Df), dtype=np.complex128)
+    for da in itertools.product(*[range(d) for d in fd]):
+        for db in itertools.product(*[range(d) for d in fd]):
+            s = 0
+            for dr in itertools.product(*[range(dims_e[k]) for k in rest]):
+                di = [0] * len(dims_e)
+                dj = [0] * len(dims_e)
+                for p, x, y in zip(pos, da, db):
+                    di[p], dj[p] = x, y
+                for k, x in zip(rest, dr):
+                    di[k] = dj[k] = x
+                s += A[bf_index(di, dims_e), bf_index(dj, dims_e)]
+            out[bf_index(da, fd), bf_index(db, fd)] = s
+    return out
+
+
+@pytest.mark.parametrize("dims_e,pos", [((2, 2), (0,)), ((2, 2), (1,)), ((2, 2, 2), (0, 2)),
+                                        ((2, 3, 2), (1,)), ((3, 2, 2), (0, 2)),
+                                        ((2, 2, 2, 2), (1, 2))])
+def test_lift_and_partial_trace_brute_force(dims_e, pos):
+    rng = np.random.default_rng(7)
+    De = int(np.prod(dims_e))
+    Df = int(np.prod([dims_e[p] for p in pos]))
+    X = rng.normal(size=(Df, Df)) + 1j * rng.normal(size=(Df, Df))
+    A = rng.normal(size=(De, De)) + 1j * rng.normal(size=(De, De))
+    np.testing.assert_allclose(O.lift(X, dims_e, pos), bf_lift(X, dims_e, pos), atol=1e-14)
+    np.testing.assert_allclose(O.ptrace(A, dims_e, pos), bf_ptrace(A, dims_e, pos), atol=1e-13)
+    # adjointness <Tr_{e\f} A, X> = <A, 1 (x) X>, the identity behind the Lagrangian rewrite
+    lhs = np.vdot(O.ptrace(A, dims_e, pos), X)
+    rhs = np.vdot(A, O.lift(X, dims_e, pos))
+    assert abs(lhs - rhs) < 1e-12
+
+
+def test_basis_convention_is_kron():
+    """A on the first (lower-numbered) site, B on the second == np.kron(A, B)."""
+    rng = np.random.default_rng(1)
+    A = rng.normal(size=(2, 2))
+    B = rng.normal(size=(3, 3))
+    full = O.lift(A, (2, 3), (0,)) @ O.lift(B, (2, 3), (1,))
+    np.testing.assert_allclose(full, np.kron(A, B), atol=1e-15)
+
+
+# ------------------------------------------------------------------------------------------
+# poset
+# ------------------------------------------------------------------------------------------
+
+def test_poset_matches_figure_1():
+    """Fig. 1: chain of 5 sites with Y_3 -> exactly the drawn covering arrows."""
+    arrows = set()
+    with open(golden("fig1_poset.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            p, c = [x.strip() for x in line.split("->")]
+            arrows.add((tuple(int(ch) - 1 for ch in p), tuple(int(ch) - 1 for ch in c)))
+    d = W.random_chain(5, seed=0, top_len=3, subintervals=True)
+    R = O.Relaxation(d)
+    got = {(R.clusters[e], R.clusters[f]) for (e, f) in R.msgs}
+    assert got == arrows
+    assert len(R.clusters) == 12
+
+
+def test_poset_plaquette_children_are_its_four_bonds():
+    """Covering relation, not 'one site fewer': a plaquette's children are its 4 edges."""
+    d = W.tfim_plaquette_batch([3], [1.0])
+    R = O.Relaxation(d)
+    for e, c in enumerate(R.clusters):
+        if len(c) == 4:
+            ch = [R.clusters[f] for f in R.children[e]]
+            assert len(ch) == 4 and all(len(x) == 2 for x in ch)
+        if len(c) == 2:
+            assert len(R.parents[e]) == 2 and len(R.children[e]) == 2
+        if len(c) == 1:
+            assert len(R.parents[e]) == 4
+
+
+# ------------------------------------------------------------------------------------------
+# dual value: closed forms, weak duality, gauge, exact special cases
+# ------------------------------------------------------------------------------------------
+
+def test_anderson_bound_tfim_chain():
+    """Q(0) is the Anderson bound (Sec. 3.1): 15 * (-1) + 16 * (-0.5) = -23."""
+    ref = read_reference_energies()
+    R = O.Relaxation(W.workload_c1())
+    assert R.Q(R.zeros())[0] == pytest.approx(ref["tfim_chain_n16_anderson"], abs=1e-12)
+
+
+def test_anderson_bound_equals_sum_of_term_minima():
+    d = W.random_chain(6, seed=11)
+    R = O.Relaxation(d)
+    want = math.fsum(np.linalg.eigvalsh(m)[0] for _, m in d.terms())
+    assert R.Q(R.zeros())[0] == pytest.approx(want, abs=1e-12)
+
+
+def test_heisenberg_square_level1_closed_form():
+    """Singlets on every bond are locally consistent: f_1* = -3 J per bond, and the Gibbs
+    gradient vanishes at nu = 0 by SU(2) symmetry, so zero messages are optimal."""
+    d = W.workload_c2(32)
+    R = O.Relaxation(d)
+    assert R.Q(R.zeros())[0] == pytest.approx(-6144.0, abs=1e-9)
+    small = O.Relaxation(W.heisenberg_square(4))
+    for beta in (1.0, 64.0, 1024.0):
+        _, g = small.grad_beta(small.zeros(), beta)
+        assert max(np.abs(v).max() for v in g.values()) < 1e-12
+
+
+def test_frustration_free_ferromagnet_is_exact():
+    """Frustration-free H: every level equals E0 = Anderson (Sec. 3.1.1)."""
+    d = W.heisenberg_chain(6, J=-1.0)
+    R = O.Relaxation(d)
+    E0 = E.ground_energy(d)
+    assert E0 == pytest.approx(-5.0, abs=1e-10)
+    assert R.Q(R.zeros())[0] == pytest.approx(E0, abs=1e-12)
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: W.tfim_chain(8, 1.0, 1.0),
+    lambda: W.random_chain(7, seed=3),
+    lambda: W.random_chain(7, seed=4, top_len=3, subintervals=True),
+    lambda: W.heisenberg_graph(8, W.square_edges(2, periodic=False, offset=0)
+                               + [(4, 5), (5, 6), (6, 7), (3, 4)], name="h8"),
+    lambda: W.xxz_triangular(3, 0.5, seed=2),
+])
+def test_weak_duality_random_messages(maker):
+    """Any nu gives a lower bound: Q(nu) <= E0 (partial Lagrangian, Sec. 4.1)."""
+    d = maker()
+    R = O.Relaxation(d)
+    E0 = E.ground_energy(d)
+    for seed in range(4):
+        nu = R.draw(seed, scale=0.7)
+        assert R.Q(nu)[0] <= E0 + 1e-10
+
+
+def test_gauge_invariance():
+    """nu_{e->f} += c 1 lowers theta_e by c 1 and raises theta_f by c 1 (both are traces of
+    identities), so Q is unchanged: the trace of a message is a gauge."""
+    d = W.random_chain(6, seed=5, top_len=3, subintervals=True)
+    R = O.Relaxation(d)
+    nu = R.draw(1, 0.5)
+    q0 = R.Q(nu)[0]
+    for m in [0, 3, R.n_msgs - 1]:
+        nu2 = R.copy(nu)
+        Df = int(R.mDf[m])
+        R.set(nu2, m, R.get(nu2, m) + 0.37 * np.eye(Df))
+        assert R.Q(nu2)[0] == pytest.approx(q0, abs=1e-12)
+
+
+def _exact_messages_whole_cluster(R, desc):
+    """Messages that move every term onto the single top cluster (whole system).
+
+    Site term h_v is sent to one edge containing v (nu_{e->v} = -h_v), every edge term
+    plus what it received is sent to the top (nu_{top->e} = -(h_e + sum lift h_v)).  Then
+    theta_v = theta_e = 0 and theta_top = H, so Q(nu) must equal E0 exactly."""
+    nu = R.zeros()
+    top = max(range(R.n_clusters), key=lambda e: len(R.clusters[e]))
+    ctop = R.clusters[top]
+    sd = R.site_dim
+    received = {}
+    for v in range(desc.n_sites):
+        ev = R.index[(v,)]
+        if ev not in R.h:
+            continue
+        e = R.parents[ev][0]
+        ce = R.clusters[e]
+        R.set(nu, R.msg_index[(e, ev)], -R.h[ev])
+        pos = (ce.index(v),)
+        received[e] = received.get(e, 0) + bf_lift(R.h[ev], [sd[s] for s in ce], pos)
+    for e in R.children[top]:
+        ce = R.clusters[e]
+        tot = R.h.get(e, 0) + received.get(e, 0)
+        R.set(nu, R.msg_index[(top, e)], -np.asarray(tot) if not np.isscalar(tot) else
+              np.zeros((R.D[e], R.D[e])))
+    return nu
+
+
+@pytest.mark.parametrize("maker", [lambda: W.tfim_chain(6, 1.0, 0.7),
+                                   lambda: W.random_chain(5, seed=9)])
+def test_whole_system_cluster_attains_E0(maker):
+    """One cluster holding every site: the relaxation is exact (Sec. 3.2: E0 = f*_{C+m}),
+    and an explicit message assignment reaches Q = lambda_min(H) = E0."""
+    d = W.whole_system(maker())
+    R = O.Relaxation(d)
+    nu = _exact_messages_whole_cluster(R, d)
+    assert R.Q(nu)[0] == pytest.approx(E.ground_energy(d), abs=1e-11)
+
+
+# ------------------------------------------------------------------------------------------
+# smoothing, gradients, subgradients
+# ------------------------------------------------------------------------------------------
+
+def test_smoothing_sandwich():
+    """Q_beta <= Q <= Q_beta + Gamma_G / beta (smoothing-error lemma)."""
+    d = W.random_chain(6, seed=2, top_len=3, subintervals=True)
+    R = O.Relaxation(d)
+    for beta in (0.5, 3.0, 40.0):
+        nu = R.draw(3, 0.5)
+        q, qb = R.Q(nu)[0], R.Q_beta(nu, beta)[0]
+        assert qb <= q + 1e-12
+        assert q <= qb + R.Gamma / beta + 1e-12
+
+
+def _inner(R, a, b):
+    return math.fsum(float(np.real(np.vdot(a[k], b[k]))) for k in a)
+
+
+@pytest.mark.parametrize("maker", [lambda: W.random_chain(5, seed=1),
+                                   lambda: W.random_chain(5, seed=8, top_len=3, subintervals=True),
+                                   lambda: W.xxz_triangular(3, 0.5, seed=1)])
+def test_smoothed_gradient_matches_finite_differences(maker):
+    """grad_{nu_{e->f}} Q_beta = rho_f - Tr_{e\\f} rho_e (Sec. 4.1.2 / 4.2.2)."""
+    d = maker()
+    R = O.Relaxation(d)
+    beta = 2.5
+    nu = R.draw(4, 0.4)
+    X = R.draw(5, 1.0)
+    _, g = R.grad_beta(nu, beta)
+    t = 1e-5
+    qp = R.Q_beta(R.axpby(1, nu, t, X), beta)[0]
+    qm = R.Q_beta(R.axpby(1, nu, -t, X), beta)[0]
+    fd = (qp - qm) / (2 * t)
+    assert fd == pytest.approx(_inner(R, g, X), rel=1e-6, abs=1e-7)
+
+
+def test_subgradient_is_a_supergradient():
+    """Q is concave and mu_f - Tr mu_e lies in its superdifferential (Sec. 4.1.1):
+    Q(nu') <= Q(nu) + <g(nu), nu' - nu> for all nu'."""
+    d = W.random_chain(6, seed=6, top_len=3, subintervals=True)
+    R = O.Relaxation(d)
+    nu = R.draw(10, 0.5)
+    q, g = R.subgrad(nu)
+    for s in range(6):
+        nu2 = R.draw(20 + s, 0.5)
+        diff = R.axpby(1, nu2, -1, nu)
+        assert R.Q(nu2)[0] <= q[0] + _inner(R, g, diff) + 1e-10
+
+
+def test_gibbs_lipschitz():
+    """||rho(K) - rho(K')||_F <= (beta/2) ||K - K'||_F (Lipschitz lemma, m_F = 2)."""
+    rng = np.random.default_rng(3)
+    for D in (2, 4, 8):
+        for beta in (0.3, 2.0, 10.0):
+            K = W.gue(rng, D)
+            K2 = K + 0.3 * W.gue(rng, D)
+            r1 = _gibbs(K, beta)
+            r2 = _gibbs(K2, beta)
+            assert np.linalg.norm(r1 - r2) <= beta / 2 * np.linalg.norm(K - K2) + 1e-12
+
+
+def _gibbs(K, beta):
+    """Gibbs state via the exponential series on a shifted spectrum (independent of eigh use
+    in the oracle): rho = e^{-beta K}/Tr e^{-beta K}."""
+    from scipy.linalg import expm
+    M = expm(-beta * (K - np.eye(len(K)) * np.linalg.eigvalsh(K)[0]))
+    return M / np.trace(M)
+
+
+def test_gibbs_state_matches_matrix_exponential():
+    d = W.random_chain(4, seed=12)
+    R = O.Relaxation(d)
+    nu = R.draw(2, 0.3)
+    F, rho = R.gibbs(nu, 3.0)
+    th = R.thetas(nu)
+    for D in th:
+        for j in range(len(th[D])):
+            np.testing.assert_allclose(rho[D][j], _gibbs(th[D][j], 3.0), atol=1e-12)
+            lam = np.linalg.eigvalsh(th[D][j])
+            from scipy.special import logsumexp
+            assert F[D][j] == pytest.approx(-logsumexp(-3.0 * lam) / 3.0, abs=1e-12)
+
+
+def test_smoothed_dual_gradient_lipschitz_two_local():
+    """||grad Q_b(nu) - grad Q_b(nu')|| <= beta (Delta_G + d)/2 ||nu - nu'|| on traceless nu."""
+    d = W.random_chain(6, seed=13)
+    R = O.Relaxation(d)
+    beta = 1.5
+    L = R.lipschitz(beta)
+    assert R.Lambda == R.Delta_G() + 2
+
+    def traceless(nu):
+        return {k: v - np.trace(v, axis1=1, axis2=2)[:, None, None] / k * np.eye(k) for k, v in nu.items()}
+    for s in range(4):
+        a = traceless(R.draw(30 + s, 0.8))
+        b = traceless(R.draw(40 + s, 0.8))
+        _, ga = R.grad_beta(a, beta)
+        _, gb = R.grad_beta(b, beta)
+        lhs = math.sqrt(_inner(R, R.axpby(1, ga, -1, gb), R.axpby(1, ga, -1, gb)))
+        rhs = L * math.sqrt(_inner(R, R.axpby(1, a, -1, b), R.axpby(1, a, -1, b)))
+        assert lhs <= rhs + 1e-12
+
+
+def test_gibbs_vjp_matches_finite_differences():
+    """Daleckii-Krein VJP of rho_beta (textbook matrix calculus) vs central differences,
+    including an exactly degenerate spectrum."""
+    rng = np.random.default_rng(5)
+    cases = [W.gue(rng, 4), W.gue(rng, 8), np.kron(W.X, W.X) + np.kron(W.Y, W.Y) + np.kron(W.Z, W.Z)]
+    for K in cases:
+        D = len(K)
+        rb = W.gue(rng, D)
+        Edir = W.gue(rng, D)
+        beta = 1.7
+        tb = O.gibbs_vjp(K, beta, rb)
+        h = 1e-6
+        fp = np.real(np.vdot(rb, _gibbs(K + h * Edir, beta)))
+        fm = np.real(np.vdot(rb, _gibbs(K - h * Edir, beta)))
+        assert (fp - fm) / (2 * h) == pytest.approx(np.real(np.vdot(tb, Edir)), rel=1e-6, abs=1e-8)
+
+
+# ------------------------------------------------------------------------------------------
+# the two algorithms
+# ------------------------------------------------------------------------------------------
+
+def test_theta_sequence_identity():
+    """theta_{k+1} = (sqrt(th^4 + 4 th^2) - th^2)/2 solves (1 - t')/t'^2 = 1/t^2 (Tseng)."""
+    th = 1.0
+    for _ in range(200):
+        tn = O.theta_next(th)
+        assert (1 - tn) / tn ** 2 == pytest.approx(1 / th ** 2, rel=1e-12)
+        assert 0 < tn < th
+        th = tn
+
+
+def test_messages_stay_traceless():
+    """Every gradient/subgradient has trace 1 - 1 = 0, so nu stays traceless."""
+    d = W.random_chain(6, seed=14, top_len=3, subintervals=True)
+    R = O.Relaxation(d)
+    nu = O.nesterov(R, [(2.0, 40), (4.0, 40)])
+    for v in nu.values():
+        assert np.abs(np.trace(v, axis1=1, axis2=2)).max() < 1e-12
+    nb, _, nT, _ = O.subgradient(R, 60)
+    for v in nT.values():
+        assert np.abs(np.trace(v, axis1=1, axis2=2)).max() < 1e-12
+
+
+def test_time_reversal_keeps_site_messages_zero():
+    """Zero-field XXZ is time-reversal invariant; spin-1/2 site marginals of TR-invariant
+    states are 1/2, so every message into a single site stays zero."""
+    d = W.xxz_triangular(3, 0.5, seed=3)
+    R = O.Relaxation(d)
+    nu = O.nesterov(R, [(4.0, 30)])
+    assert np.abs(nu[2]).max() < 1e-12
+    assert np.abs(nu[4]).max() > 1e-3
+
+
+def test_subgradient_c1_bracket():
+    """C1: Anderson <= q_best <= E0 (weak duality), q_best nondecreasing along the run."""
+    ref = read_reference_energies()
+    d = W.workload_c1()
+    R = O.Relaxation(d)
+    nb, qb, _, hist = O.subgradient(R, 400)
+    assert ref["tfim_chain_n16_anderson"] <= qb[0] <= ref["tfim_chain_n16_E0"]
+    assert qb[0] == pytest.approx(hist.max(), abs=0)
+    assert R.Q(nb)[0] == pytest.approx(qb[0], abs=1e-12)
+    assert qb[0] > -17.3   # substantial progress from -23 within 400 steps
+
+
+def test_free_fermion_energy_matches_lanczos_and_fixture():
+    ref = read_reference_energies()
+    assert E.tfim_open_chain_E0(16, 1.0, 0.5) == pytest.approx(ref["tfim_chain_n16_E0"], abs=1e-12)
+    for n, J, h in [(6, 1.0, 0.5), (8, 0.7, 1.3)]:
+        assert E.tfim_open_chain_E0(n, J, h) == pytest.approx(
+            E.ground_energy(W.tfim_chain(n, J, h)), abs=1e-10)
+
+
+@pytest.mark.parametrize("seed,rotate", [(1, False), (2, False), (3, True), (4, True)])
+def test_level1_exact_on_commuting_trees(seed, rotate):
+    """Diagonal Hamiltonians on trees (Sec. 3.1.1) and commuting ones (Thm. 2): level 1 is
+    exact; the smoothed solver's certified value reaches the brute-force minimum."""
+    d = W.classical_ising_tree(8, seed, rotate=rotate)
+    R = O.Relaxation(d)
+    E0 = E.classical_min(W.classical_ising_tree(8, seed, rotate=False))
+    nu = O.nesterov(R, O.doubling_schedule(1.0, 4096.0, 1300))
+    q, margin = R.certify(nu)
+    assert q[0] - margin[0] <= E0 + 1e-12
+    assert q[0] == pytest.approx(E0, abs=1e-6)
+
+
+def test_monogamy_three_site_heisenberg():
+    """Sec. 2 monogamy example: level 1 gives -6 (singlets on both edges), E0 = -4."""
+    ref = read_reference_energies()
+    d = W.heisenberg_chain(3)
+    R = O.Relaxation(d)
+    assert E.ground_energy(d) == pytest.approx(ref["heisenberg_chain3_E0"], abs=1e-12)
+    nu = O.nesterov(R, [(8.0, 50)])
+    assert R.Q(nu)[0] == pytest.approx(ref["heisenberg_chain3_level1"], abs=1e-10)
+
+
+def test_tseng_rate_bound():
+    """Alg. 2 at fixed beta: Q_b* - Q_b(nu_T) <= 2 L R^2 / (T+1)^2 (Tseng, Cor. 1)."""
+    d = W.random_chain(5, seed=21)
+    R = O.Relaxation(d)
+    beta = 4.0
+    L = R.lipschitz(beta)
+    ref = O.nesterov(R, [(beta, 3000)])
+    qstar = R.Q_beta(ref, beta)[0]
+    Rn = math.sqrt(_inner(R, ref, ref))
+    for T in (5, 20, 80):
+        nu = O.nesterov(R, [(beta, T)])
+        gap = qstar - R.Q_beta(nu, beta)[0]
+        assert gap <= 2 * L * Rn ** 2 / (T + 1) ** 2 + 1e-9
+
+
+def test_interval_hierarchy_monotone_and_exact_at_full_length():
+    """E0 = f*_n >= ... >= f*_t (Sec. 3.2) and (E0 - f*_t)/n <= 1/t when 2||h|| <= 1."""
+    n = 5
+    base = W.random_chain(n, seed=31, scale=1.0)
+    # rescale every term to 2||h|| <= 1
+    terms = [(s, m / (2 * np.max(np.abs(np.linalg.eigvalsh(m))))) for s, m in base.terms()]
+    b = W._Builder("scaled", n)
+    for s, m in terms:
+        b.add_term(s, m)
+    E0 = None
+    vals = []
+    for t in range(2, n + 1):
+        b.tops = [tuple(range(i, i + t)) for i in range(n - t + 1)]
+        d = b.build(real=False, subintervals=True)
+        if E0 is None:
+            E0 = E.ground_energy(d)
+        R = O.Relaxation(d)
+        nu = O.nesterov(R, O.doubling_schedule(1.0, 2048.0, 1200))
+        q, mg = R.certify(nu)
+        vals.append(q[0] - mg[0])
+        assert (E0 - vals[-1]) / n <= 1.0 / t + 1e-9
+        assert vals[-1] <= E0 + 1e-12
+    for a, c in zip(vals, vals[1:]):
+        assert c >= a - 2e-3
+    assert vals[-1] == pytest.approx(E0, abs=5e-3)
