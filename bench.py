@@ -1,0 +1,244 @@
+"""Benchmark: cluster updates/s and time-to-1e-4 gap/site on one MI355X.
+
+Workload: level-1 relaxation of the Heisenberg antiferromagnet on the 32x32 periodic
+square lattice (2048 edge clusters 4x4 + 1024 site clusters 2x2, real symmetric),
+entropy-smoothed Algorithm 2 with beta doubling 1 -> 1024 (11 stages over 5000
+iterations), FP32 iterations in the fused single-launch form replayed from a captured
+HIP graph, FP64 certification (lambda_min of every cluster + rounding margin) every 50
+iterations.  A "step" is 50 iterations followed by one certification; the default 100
+steps are the whole 5000-iteration solve.  Inputs are synthetic and built on the host,
+then resident in HBM before timing starts.
+
+Also reported: the same solve in the plain FP64 form (two launches per iteration, no
+graph), and the FP64 CPU oracle on a bounded sample of iterations (cpu_baseline).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+ITERS_PER_STEP = 50
+TOTAL_ITERS = 5000
+BETA0, BETA_MAX = 1.0, 1024.0
+Q_REF = -6144.0            # closed form: -3 J per bond, 2048 bonds (singlet on every bond)
+HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK_TFLOPS = 157.3
+
+
+def schedule_iter(schedule):
+    """Yield (stage index, beta) for every global iteration."""
+    for s, (beta, K) in enumerate(schedule):
+        for _ in range(K):
+            yield s, beta
+
+
+class Solver:
+    """Drives Algorithm 2 stage by stage through the library, in steps of 50 iterations."""
+
+    def __init__(self, P, f32, fused, schedule):
+        self.P, self.f32, self.fused, self.schedule = P, f32, fused, schedule
+        self.nu = P.zeros(f32)
+        self.ze = P.zeros(f32)
+        self.stage = 0
+        self.state = P.new_nesterov_state(schedule[0][0])
+        self.left = schedule[0][1]
+
+    def run(self, n):
+        while n > 0:
+            if self.left == 0:
+                self.stage += 1
+                beta, K = self.schedule[self.stage]
+                self.state = self.P.new_nesterov_state(beta)
+                self.left = K
+            m = min(n, self.left)
+            self.P.step_nesterov(self.nu, self.ze, self.state, m, fused=self.fused)
+            self.left -= m
+            n -= m
+
+
+def timed_solve(P, f32, fused, steps, warmup, schedule, torch):
+    """Warm up on a throwaway state, then time `steps` steps from nu = 0."""
+    if warmup > 0:
+        w = Solver(P, f32, fused, schedule)
+        for _ in range(warmup):
+            w.run(ITERS_PER_STEP)
+            P.certify(w.nu)
+        torch.cuda.synchronize()
+    S = Solver(P, f32, fused, schedule)
+    q = torch.zeros((steps, P.n_inst), dtype=torch.float64, device="cuda")
+    mg = torch.zeros_like(q)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    from paper_2609_40336_amd import lrh
+    for k in range(steps):
+        S.run(ITERS_PER_STEP)
+        lrh.lrh_certify(P.h, S.nu, lrh.LRH_F32 if f32 else 0, q[k], mg[k])
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    t_total = ev[0].elapsed_time(ev[-1]) / 1e3
+    t_at = [ev[0].elapsed_time(ev[k + 1]) / 1e3 for k in range(steps)]
+    bound = (q - mg)[:, 0].cpu().numpy()
+    n_sites = P.desc.n_sites
+    gaps = (Q_REF - bound) / n_sites
+    tte = None
+    for k in range(steps):
+        if gaps[k] <= 1e-4:
+            tte = t_at[k]
+            break
+    return dict(seconds=t_total, iters=steps * ITERS_PER_STEP, bound=float(bound[-1]),
+                gap_per_site=float(gaps[-1]), time_to_1e4=tte, nu=S.nu)
+
+
+def kernel_timing(P, torch, f32=True, reps=20):
+    """Average duration of one fused iteration (one k_cluster_pair launch plus 1/64 of the
+    chunk's parameter upload and closing message update), timed with HIP events on the
+    stream the graph is launched on."""
+    S = Solver(P, f32, True, [(BETA0, 10 ** 9)])
+    S.run(64)  # capture
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        S.run(64)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / (reps * 64)
+
+
+def algorithmic_work(P):
+    """Per iteration (Sec. 8(d) of the design notes): bytes B = w (6 sum_msg s_f + 2 sum_{f
+    with parents} s_f) with s the packed size, w = 4 (FP32); flops F = 11 D^3 per real
+    cluster (symmetric eigen-decomposition with vectors plus the U diag U^T rebuild)."""
+    w = 4
+    s_msg = 0
+    for b in P.buckets:
+        s_msg += b["M"] * b["comps"]
+    with_parents = set(int(c) for c in P.msg_child)
+    s_par = 0
+    for c in with_parents:
+        D = 2 ** len(P.clusters[c])
+        s_par += D * (D + 1) // 2 if P.is_real else D * D
+    B = w * (6 * s_msg + 2 * s_par)
+    F = 0
+    for c in P.clusters:
+        D = 2 ** len(c)
+        F += (11 if P.is_real else 44) * D ** 3
+    return B, F
+
+
+def cpu_baseline(desc, budget_s=15.0):
+    """The FP64 oracle, untuned, on one core: Algorithm 2 iterations of the same workload
+    until the time budget is spent (at least 2)."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    from oracle import lrh_oracle as O
+    ctx = threadpool_limits(1) if threadpool_limits else None
+    try:
+        R = O.Relaxation(desc)
+        nu = R.zeros()
+        ze = R.copy(nu)
+        beta = BETA0
+        L = R.lipschitz(beta)
+        th = 1.0
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            eta = R.axpby(1.0 - th, nu, th, ze)
+            _, g = R.grad_beta(eta, beta)
+            ze = R.symmetrise({k: ze[k] + g[k] / (th * L) for k in ze})
+            nu = R.symmetrise(R.axpby(1.0 - th, nu, th, ze))
+            th = O.theta_next(th)
+            n += 1
+            if n >= 2 and time.perf_counter() - t0 > budget_s:
+                break
+        dt = time.perf_counter() - t0
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+    return dict(value=R.n_clusters * n / dt, unit="cluster updates/s", cores=1, kind="oracle",
+                sample=f"{n} Algorithm 2 iterations of the 32x32 Heisenberg workload (FP64 NumPy, "
+                       f"one thread), {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=TOTAL_ITERS // ITERS_PER_STEP)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--plain-steps", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (the path is single-GPU; --gpus {args.gpus} "
+              f"is not supported)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import lrh_workloads as W
+    from paper_2609_40336_amd import lrh
+
+    desc = W.workload_c2(32)
+    P = lrh.Problem(desc, 0)
+    schedule = lrh.nesterov_schedule(BETA0, BETA_MAX, TOTAL_ITERS)
+    print(f"[bench] workload {desc.name}: {P.n_clusters} clusters, {P.n_msgs} messages", file=sys.stderr,
+          flush=True)
+    fused = timed_solve(P, True, True, args.steps, args.warmup, schedule, torch)
+    print(f"[bench] fused fp32: {fused['seconds']:.4f} s for {fused['iters']} iterations", file=sys.stderr,
+          flush=True)
+    plain = timed_solve(P, False, False, args.plain_steps, 1, schedule, torch)
+    print(f"[bench] plain fp64: {plain['seconds']:.4f} s for {plain['iters']} iterations", file=sys.stderr,
+          flush=True)
+    t_it = kernel_timing(P, torch)
+    nchk, nnf = P.check()
+    B, F = algorithmic_work(P)
+    t_B, t_F = B / (HBM_PEAK_GBS * 1e9), F / (FP32_VALU_PEAK_TFLOPS * 1e12)
+    if t_B >= t_F:
+        roof = dict(bound="hbm", achieved=B / t_it / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
+    else:
+        roof = dict(bound="alu", achieved=F / t_it / 1e12, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = "k_cluster_pair<float,false,MODE_GIBBS> (one fused iteration)"
+    roof["per_launch"] = dict(bytes=B, flops=F, seconds=t_it)
+    updates = P.n_clusters * fused["iters"]
+    out = {
+        "metric": "cluster updates/s and time-to-1e-4 gap/site: fused vs plain FP64, 1 MI355X",
+        "value": updates / fused["seconds"],
+        "unit": "cluster updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": fused["seconds"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 iterations, f64 certify",
+        "data": "synthetic",
+        "config": {"workload": "heisenberg_af_32x32_periodic_level1_nesterov_beta1to1024_5000it",
+                   "clusters": P.n_clusters, "messages": P.n_msgs,
+                   "iters_per_step": ITERS_PER_STEP, "parallelism": "single_gpu"},
+        "time_to_1e-4_gap_per_site_s": fused["time_to_1e4"],
+        "certified_bound": fused["bound"],
+        "gap_per_site": fused["gap_per_site"],
+        "plain_fp64": {"value": P.n_clusters * plain["iters"] / plain["seconds"], "unit": "cluster updates/s",
+                       "steps": args.plain_steps, "time_to_1e-4_gap_per_site_s": plain["time_to_1e4"],
+                       "gap_per_site": plain["gap_per_site"]},
+        "jacobi_noconv": nchk, "nonfinite": nnf,
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(desc, args.cpu_budget)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,207 @@
+/*
+ * lrh.h -- C ABI of the local-relaxation message-passing library for MI355X (gfx950).
+ *
+ * The library solves the partial-Lagrangian dual of the cluster-consistent
+ * relaxation f*_C of a local Hamiltonian H = sum_e h_e (paper: Sec. 3.2, definition
+ * of the cluster-consistent set and eq. cluster_relaxation_energy; Sec. 4, dual
+ * Q_C(nu) = sum_e lambda_min(theta_e(nu)) and its smoothed form Q_{C,beta}).
+ *
+ * Conventions shared by every call
+ *   - Every call returns an lrh_status; nothing throws across the ABI.  On failure
+ *     lrh_last_error() returns a thread-local message.
+ *   - "host" pointers are read during the call only; the caller keeps ownership.
+ *     "device" pointers are HIP device memory owned by the caller; the call
+ *     enqueues work on `stream` and returns without waiting: results are valid once
+ *     the stream is synchronised.
+ *   - Sites are spin-1/2 (d = 2) in this release; clusters hold at most 6 sites
+ *     (D_e <= 64).  A cluster's basis is the big-endian product basis of its sites in
+ *     ascending order (first site most significant), so A_{s0} (x) B_{s1} = kron(A, B).
+ *   - Message layout (structure of arrays).  Messages nu_{e->f} (e a cluster, f one of
+ *     its covering children) are grouped into buckets by D_f.  Bucket b holds M_b
+ *     messages of C_b components each; component c of message m lives at element
+ *     offset_b + c * M_b + m.  For a real problem (all terms real, LRH_REAL) the
+ *     components are the upper triangle A[i][j], i <= j, in row-major order
+ *     (C_b = D(D+1)/2).  For a complex problem they are the real parts of the upper
+ *     triangle in the same order, followed by the imaginary parts of the strict upper
+ *     triangle (C_b = D^2).  Element type is double, or float when the call's flags
+ *     carry LRH_F32.  lrh_query() reports every bucket; lrh_export_messages() reports
+ *     which cluster pair each message belongs to.
+ *   - Instances: sites carry an instance id; clusters never span instances and every
+ *     per-instance output is indexed by that id.
+ */
+#ifndef LRH_H
+#define LRH_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LRH_OK = 0,
+  LRH_E_INVALID = 1,      /* bad argument: non-Hermitian term, cluster spanning instances,
+                             beta <= 0, Lipschitz <= 0, null required pointer, ...          */
+  LRH_E_UNSUPPORTED = 2,  /* D_e > 64, site dimension != 2, mixed child dimensions        */
+  LRH_E_NOMEM = 3,        /* device or host allocation failed                             */
+  LRH_E_DEVICE = 4,       /* a HIP runtime call failed                                    */
+  LRH_E_NOCONV = 5,       /* a Jacobi eigen-solve hit its sweep cap (see lrh_check)       */
+  LRH_E_NONFINITE = 6     /* NaN / Inf found in a state or a bound (see lrh_check)        */
+} lrh_status;
+
+/* flags for lrh_problem_desc.flags */
+#define LRH_SUBINTERVALS 0x1u  /* add every contiguous run of each top cluster (Y_t, eq.
+                                  interval_set_defn: intervals "with their subsets")      */
+
+/* flags for the compute calls */
+#define LRH_F32    0x1u   /* state buffers (nu, zeta, grad, marginals) are float, and the
+                             iterations compute in FP32; certification stays FP64          */
+#define LRH_FUSED  0x2u   /* fused iteration: one launch per iteration (message update of
+                             the previous step folded into the cluster kernel), replayed
+                             from a captured HIP graph                                     */
+
+typedef struct lrh_problem_s* lrh_problem;   /* opaque; owned by the library */
+
+/* Problem description (all HOST memory, copied during lrh_build_clusters).
+ * H = sum_t h_t, term t acting on sites term_sites[term_ptr[t] .. term_ptr[t+1]) given
+ * in ascending order; its dense row-major block starts at term_off[t] in term_re /
+ * term_im (term_im == NULL: every term is real, the problem is solved in real
+ * arithmetic).  The cluster family (Sec. 3.2) is the list of top clusters
+ * top_sites[top_ptr[c] .. top_ptr[c+1]) (ascending); the library adds every term
+ * support and every singleton, plus contiguous runs when LRH_SUBINTERVALS is set,
+ * and keeps the covering relations of the inclusion poset (Sec. 4.2: constraints
+ * between consecutive poset levels suffice).  site_instance may be NULL (one
+ * instance). */
+typedef struct {
+  int32_t n_sites;
+  const int32_t* site_dim;        /* [n_sites], must be 2                                */
+  int32_t n_terms;
+  const int64_t* term_ptr;        /* [n_terms+1]                                         */
+  const int32_t* term_sites;
+  const int64_t* term_off;        /* [n_terms+1], offsets into term_re / term_im         */
+  const double* term_re;
+  const double* term_im;          /* NULL => real problem                                */
+  int32_t n_top;
+  const int64_t* top_ptr;         /* [n_top+1]                                           */
+  const int32_t* top_sites;
+  const int32_t* site_instance;   /* [n_sites] or NULL                                   */
+  uint32_t flags;                 /* LRH_SUBINTERVALS                                    */
+} lrh_problem_desc;
+
+#define LRH_MAX_BUCKETS 8
+typedef struct {
+  int64_t n_clusters, n_msgs, n_instances;
+  int32_t is_real;
+  int32_t max_D;
+  int32_t n_buckets;                       /* message buckets, by D_f ascending        */
+  int32_t bucket_D[LRH_MAX_BUCKETS];
+  int64_t bucket_count[LRH_MAX_BUCKETS];   /* M_b                                       */
+  int64_t bucket_comps[LRH_MAX_BUCKETS];   /* C_b                                       */
+  int64_t bucket_offset[LRH_MAX_BUCKETS];  /* element offset of bucket b               */
+  int64_t nu_len;                          /* elements of one message vector           */
+  int64_t marg_len;                        /* elements of the per-cluster marginal
+                                              buffer of lrh_dual_eval (packed like a
+                                              message of size D_e, clusters in the
+                                              order of lrh_export_clusters)            */
+  double Lambda_G;                         /* Lipschitz factor: L = beta * Lambda_G / 2 */
+  double Gamma_G;                          /* sum_e log D_e (smoothing-error lemma)     */
+  int32_t max_sweeps;                      /* Jacobi sweep cap in use                   */
+} lrh_layout;
+
+/* Build the cluster poset, message layout and device-resident problem data on HIP
+ * device `hip_device` (a0: poset + layouts; Sec. 3.2, Sec. 4.2).  hip_device < 0 builds
+ * the poset and layout on the host only (lrh_query / lrh_export_* work, every compute
+ * call returns LRH_E_INVALID).
+ * Errors: LRH_E_INVALID (non-Hermitian term beyond 1e-12 * max|h|, site out of range,
+ * unsorted or repeated sites, cluster spanning instances), LRH_E_UNSUPPORTED (site
+ * dimension != 2, a cluster with more than 6 sites, a cluster whose children have
+ * different dimensions), LRH_E_NOMEM, LRH_E_DEVICE.  On success *out owns device
+ * memory until lrh_destroy. */
+lrh_status lrh_build_clusters(const lrh_problem_desc* desc, int hip_device, lrh_problem* out);
+
+/* Sizes and layout of a built problem (host struct filled in). */
+lrh_status lrh_query(lrh_problem p, lrh_layout* out);
+
+/* Host copies of the poset.  Clusters are numbered in the library's order (grouped by
+ * instance); cluster c has sites sites[ptr[c] .. ptr[c+1]).  ptr: [n_clusters+1],
+ * sites: [ptr[n_clusters]], instance: [n_clusters] (any of them may be NULL). */
+lrh_status lrh_export_clusters(lrh_problem p, int64_t* ptr, int32_t* sites, int32_t* instance);
+
+/* For every message, in bucket order (bucket 0 first, then by index within the bucket):
+ * parent and child cluster ids, bucket and index within the bucket.  Arrays of length
+ * n_msgs; any may be NULL. */
+lrh_status lrh_export_messages(lrh_problem p, int32_t* parent, int32_t* child,
+                               int32_t* bucket, int64_t* index);
+
+/* Dual value and (sub)gradient at nu (Sec. 4.1 / 4.2).
+ *   beta > 0 : q_dev[i] = Q_{C,beta}(nu) of instance i = sum_e F_beta(theta_e), and
+ *              grad = rho_f - Tr_{e\f} rho_e (Gibbs states; Sec. 4.2.2);
+ *   beta == 0: q_dev[i] = Q_C(nu) = sum_e lambda_min(theta_e) and grad = mu_f - Tr mu_e
+ *              with mu the normalised ground-space projector (Sec. 4.2.1).
+ * nu: device, nu_len elements (LRH_F32: float).  q_dev: device double[n_instances].
+ * grad_dev: device, nu_len elements of nu's type, or NULL.  marg_dev: device, marg_len
+ * elements of nu's type receiving every cluster's rho_e / mu_e, or NULL.
+ * Errors: LRH_E_INVALID (null nu or q_dev, beta < 0), LRH_E_DEVICE. */
+lrh_status lrh_dual_eval(lrh_problem p, const void* nu, uint32_t flags, double beta,
+                         double* q_dev, void* grad_dev, void* marg_dev, hipStream_t stream);
+
+/* Algorithm 1 (subgradient ascent), n_iter iterations k = k0 .. k0+n_iter-1 with step
+ * alpha_k = step_scale / sqrt(k + 1) when step_kind == 0, or the constant step_scale
+ * when step_kind == 1.  At each k: q^k = Q(nu^k) per instance; where q^k > q_best the
+ * instance's messages are copied to nu_best and q_best updated; then
+ * nu <- nu + alpha_k (mu_f - Tr_{e\f} mu_e).  nu, nu_best: device, nu_len elements
+ * (LRH_F32: float); q_best_dev: device double[n_instances], initialise to -inf before
+ * the first call.  q_hist_dev: device double[n_iter * n_instances] (row k - k0) or NULL.
+ * Errors: LRH_E_INVALID (null pointers, n_iter < 0, k0 < 0, step_scale <= 0). */
+lrh_status lrh_step_subgrad(lrh_problem p, void* nu, void* nu_best, double* q_best_dev,
+                            int64_t k0, int32_t n_iter, int32_t step_kind, double step_scale,
+                            double* q_hist_dev, uint32_t flags, hipStream_t stream);
+
+/* State of Algorithm 2 within one smoothing stage. */
+typedef struct {
+  int64_t k;        /* iterations done in this stage; k == 0 starts a stage: zeta <- nu,
+                       theta <- 1 (for nu = 0 this is Algorithm 2's initialisation)      */
+  double theta;     /* theta_k (updated by the call)                                     */
+  double beta;      /* inverse temperature of the stage (> 0)                            */
+  double L;         /* Lipschitz bound L_beta (> 0); beta * Lambda_G / 2 is the paper's  */
+} lrh_nesterov_state;
+
+/* Algorithm 2 (accelerated ascent on the smoothed dual): n_iter iterations of
+ *   eta = (1 - theta_k) nu + theta_k zeta;  g = grad Q_beta(eta);
+ *   zeta += g / (theta_k L);  nu = (1 - theta_k) nu + theta_k zeta;
+ *   theta_{k+1} = (sqrt(theta_k^4 + 4 theta_k^2) - theta_k^2) / 2.
+ * nu, zeta: device, nu_len elements (LRH_F32: float).  st: host, updated on return.
+ * With LRH_FUSED the iterations run as one launch each from a captured graph; the
+ * result is the same arithmetic in a different launch structure.
+ * Errors: LRH_E_INVALID (null pointers, beta <= 0, L <= 0, n_iter < 0). */
+lrh_status lrh_step_nesterov(lrh_problem p, void* nu, void* zeta, lrh_nesterov_state* st,
+                             int32_t n_iter, uint32_t flags, hipStream_t stream);
+
+/* Certified lower bound (weak duality, Sec. 4.1): FP64 lambda_min of every cluster at
+ * nu, summed per instance in a fixed order.  q_dev[i] = Q_C(nu), margin_dev[i] =
+ * sum_e 8 D_e eps_64 ||theta_e||_F (backward-error margin of the FP64 eigen-solve);
+ * the certified bound is q - margin <= f*_C <= E0.  nu may be float (LRH_F32); it is
+ * widened to double before theta_e is formed.  lmin_dev: device double[n_clusters]
+ * (library cluster order) or NULL.
+ * Errors: LRH_E_INVALID (null nu/q/margin). */
+lrh_status lrh_certify(lrh_problem p, const void* nu, uint32_t flags, double* q_dev,
+                       double* margin_dev, double* lmin_dev, hipStream_t stream);
+
+/* Synchronise `stream` and report the eigen-solver health flags accumulated since the
+ * last lrh_check: *noconv = clusters that hit the sweep cap, *nonfinite = clusters with
+ * a NaN/Inf eigenvalue.  Returns LRH_E_NONFINITE or LRH_E_NOCONV when either is
+ * non-zero (NONFINITE first), LRH_OK otherwise.  Either pointer may be NULL. */
+lrh_status lrh_check(lrh_problem p, hipStream_t stream, int64_t* noconv, int64_t* nonfinite);
+
+/* Jacobi sweep cap (default 30) and relative off-diagonal tolerance (0 = default:
+ * 4 eps of the iteration precision). */
+lrh_status lrh_set_jacobi(lrh_problem p, int32_t max_sweeps, double rel_tol);
+
+void lrh_destroy(lrh_problem p);
+const char* lrh_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LRH_H */

@@ -1,0 +1,1067 @@
+// Host side of the library: problem validation, the cluster poset, device layouts, and
+// the drivers of Algorithm 1 (subgradient) and Algorithm 2 (accelerated smoothed ascent).
+//
+// Poset (paper Sec. 3.2 and Sec. 4.2): C_full holds the top clusters, every term support,
+// every singleton and, for the interval hierarchy, every contiguous run of a top
+// cluster; only covering relations (maximal proper subsets present in C_full) carry
+// messages.  Terms are added to the cluster equal to their support.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "lrh.h"
+#include "lrh_internal.h"
+
+using namespace lrh;
+
+namespace {
+
+thread_local std::string g_err;
+
+lrh_status fail(lrh_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e__ = (expr);                                                                \
+    if (e__ != hipSuccess)                                                                  \
+      return fail(LRH_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e__));        \
+  } while (0)
+
+constexpr int kMaxSites = 6;  // D_e <= 64 for spin-1/2 sites
+
+struct Key {
+  int k = 0;
+  int32_t s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  bool operator==(const Key& o) const {
+    if (k != o.k) return false;
+    for (int i = 0; i < k; ++i)
+      if (s[i] != o.s[i]) return false;
+    return true;
+  }
+};
+struct KeyHash {
+  size_t operator()(const Key& key) const {
+    uint64_t h = 1469598103934665603ull ^ (uint64_t)key.k;
+    for (int i = 0; i < key.k; ++i) {
+      h ^= (uint64_t)(uint32_t)key.s[i] + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+      h *= 1099511628211ull;
+    }
+    return (size_t)h;
+  }
+};
+
+struct CBucket {
+  int De = 0, Dc = 0, maxch = 0, maxpar = 0;
+  int64_t n = 0;
+  int mb_child = -1;  // message bucket of the children (dimension Dc)
+  int mb_self = -1;   // message bucket of dimension De (messages received from parents)
+  std::vector<int32_t> h_gid;
+  int32_t* gid = nullptr;
+  int64_t* hoff = nullptr;
+  int32_t* ch = nullptr;
+  int32_t* chmask = nullptr;
+  int32_t* par = nullptr;
+  int32_t* rslot = nullptr;
+};
+
+struct MBucket {
+  int D = 0;
+  int64_t M = 0, comps = 0, offset = 0;  // message layout
+  int64_t S = 0, comps_r = 0, roff = 0;  // marginal slots (clusters of dim D with parents)
+  int32_t* rslot = nullptr;              // [M] child's marginal slot
+  int32_t* inst = nullptr;               // [M] instance of the message
+};
+
+template <typename T>
+struct Work {
+  T* Tb[2] = {nullptr, nullptr};  // partial traces, message layout
+  T* Rb[2] = {nullptr, nullptr};  // marginals of clusters with parents
+  T* W[4] = {nullptr, nullptr, nullptr, nullptr};  // fused ping-pong state: nu1, ze1, nu2, ze2
+  bool fused_ready = false;
+};
+
+struct GraphKey {
+  int prec;
+  const void* nu;
+  const void* ze;
+  bool operator<(const GraphKey& o) const {
+    if (prec != o.prec) return prec < o.prec;
+    if (nu != o.nu) return nu < o.nu;
+    return ze < o.ze;
+  }
+};
+
+}  // namespace
+
+struct lrh_problem_s {
+  int device = 0;
+  bool host_only = false;  // built with hip_device < 0: poset and layout only
+  bool cplx = false;
+  int64_t n_clusters = 0, n_msgs = 0, n_inst = 0;
+  int max_D = 0;
+  // host poset
+  std::vector<int64_t> c_ptr;
+  std::vector<int32_t> c_sites, c_inst, c_D;
+  std::vector<int32_t> m_parent, m_child, m_bucket;
+  std::vector<int64_t> m_index;
+  std::vector<CBucket> cb;
+  std::vector<MBucket> mb;
+  double Lambda = 0, Gamma = 0;
+  int max_sweeps = 30;
+  double tol_override = 0.0;
+  int64_t nu_len = 0, R_len = 0, marg_len = 0;
+  // device globals
+  double* h = nullptr;
+  int64_t* inst_ptr = nullptr;
+  double* scal = nullptr;
+  double* scal2 = nullptr;
+  int64_t* marg_off = nullptr;
+  unsigned long long* health = nullptr;  // [0] noconv, [1] nonfinite
+  int32_t* improved = nullptr;
+  double* nu64_tmp = nullptr;            // widened copy of a float nu for certify
+  FusedParams* fp = nullptr;             // [kFusedTableMax]
+  Work<float> w32;
+  Work<double> w64;
+  hipStream_t cap_stream = nullptr;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  std::vector<void*> allocs;
+
+  ~lrh_problem_s() {
+    if (host_only) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(device);
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (void* p : allocs) (void)hipFree(p);
+    (void)hipSetDevice(cur);
+  }
+
+  template <typename T>
+  lrh_status dalloc(T** out, int64_t n) {
+    *out = nullptr;
+    if (n <= 0) return LRH_OK;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, (size_t)n * sizeof(T));
+    if (e != hipSuccess) return fail(LRH_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    allocs.push_back(p);
+    *out = (T*)p;
+    return LRH_OK;
+  }
+  template <typename T>
+  lrh_status upload(T** out, const std::vector<T>& v) {
+    lrh_status st = dalloc(out, (int64_t)v.size());
+    if (st != LRH_OK) return st;
+    if (!v.empty()) HIP_TRY(hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return LRH_OK;
+  }
+  template <typename T>
+  Work<T>& work();
+};
+template <> Work<float>& lrh_problem_s::work<float>() { return w32; }
+template <> Work<double>& lrh_problem_s::work<double>() { return w64; }
+
+namespace {
+
+struct DeviceGuard {
+  int prev = 0;
+  explicit DeviceGuard(int dev) {
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() { (void)hipSetDevice(prev); }
+};
+
+inline int comps_of(int D, bool cplx) { return cplx ? D * D : D * (D + 1) / 2; }
+
+// ------------------------------------------------------------------------------------------
+// problem construction
+// ------------------------------------------------------------------------------------------
+
+lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
+  if (!d) return fail(LRH_E_INVALID, "null problem description");
+  const int n = d->n_sites;
+  if (n <= 0) return fail(LRH_E_INVALID, "n_sites must be positive");
+  if (!d->site_dim) return fail(LRH_E_INVALID, "null site_dim");
+  for (int i = 0; i < n; ++i)
+    if (d->site_dim[i] != 2) return fail(LRH_E_UNSUPPORTED, "only spin-1/2 sites (d = 2) are supported");
+  if (d->n_terms < 0 || d->n_top < 0) return fail(LRH_E_INVALID, "negative counts");
+  if (d->n_terms > 0 && (!d->term_ptr || !d->term_sites || !d->term_off || !d->term_re))
+    return fail(LRH_E_INVALID, "null term arrays");
+  if (d->n_top > 0 && (!d->top_ptr || !d->top_sites)) return fail(LRH_E_INVALID, "null top arrays");
+  P->cplx = (d->term_im != nullptr);
+  std::vector<int32_t> inst(n, 0);
+  if (d->site_instance)
+    for (int i = 0; i < n; ++i) {
+      if (d->site_instance[i] < 0) return fail(LRH_E_INVALID, "negative instance id");
+      inst[i] = d->site_instance[i];
+    }
+  int64_t n_inst = 0;
+  for (int i = 0; i < n; ++i) n_inst = std::max<int64_t>(n_inst, inst[i] + 1);
+  P->n_inst = n_inst;
+
+  // ---- C_full ----
+  std::unordered_map<Key, int32_t, KeyHash> index;
+  std::vector<Key> keys;
+  auto make_key = [&](const int32_t* s, int k, Key& key) -> lrh_status {
+    if (k <= 0) return fail(LRH_E_INVALID, "empty cluster or term support");
+    if (k > kMaxSites) return fail(LRH_E_UNSUPPORTED, "cluster with more than 6 sites (D_e > 64)");
+    key.k = k;
+    for (int i = 0; i < k; ++i) {
+      if (s[i] < 0 || s[i] >= n) return fail(LRH_E_INVALID, "site index out of range");
+      if (i > 0 && s[i] <= s[i - 1]) return fail(LRH_E_INVALID, "sites must be ascending and distinct");
+      key.s[i] = s[i];
+    }
+    return LRH_OK;
+  };
+  auto add = [&](const Key& key) {
+    auto it = index.find(key);
+    if (it != index.end()) return it->second;
+    const int32_t id = (int32_t)keys.size();
+    index.emplace(key, id);
+    keys.push_back(key);
+    return id;
+  };
+  for (int c = 0; c < d->n_top; ++c) {
+    Key key;
+    const int64_t a = d->top_ptr[c], b = d->top_ptr[c + 1];
+    lrh_status st = make_key(d->top_sites + a, (int)(b - a), key);
+    if (st != LRH_OK) return st;
+    add(key);
+    if (d->flags & LRH_SUBINTERVALS) {
+      for (int x = 0; x < key.k; ++x)
+        for (int y = x + 1; y <= key.k; ++y) {
+          Key sub;
+          sub.k = y - x;
+          for (int i = x; i < y; ++i) sub.s[i - x] = key.s[i];
+          add(sub);
+        }
+    }
+  }
+  std::vector<int32_t> term_cluster(d->n_terms);
+  for (int t = 0; t < d->n_terms; ++t) {
+    Key key;
+    const int64_t a = d->term_ptr[t], b = d->term_ptr[t + 1];
+    lrh_status st = make_key(d->term_sites + a, (int)(b - a), key);
+    if (st != LRH_OK) return st;
+    const int64_t D = (int64_t)1 << key.k;
+    if (d->term_off[t + 1] - d->term_off[t] != D * D) return fail(LRH_E_INVALID, "term block size mismatch");
+    term_cluster[t] = add(key);
+  }
+  for (int v = 0; v < n; ++v) {
+    Key key;
+    key.k = 1;
+    key.s[0] = v;
+    add(key);
+  }
+  const int64_t nc = (int64_t)keys.size();
+  if (nc > (int64_t)INT32_MAX / 2) return fail(LRH_E_UNSUPPORTED, "too many clusters");
+  // instance of every cluster
+  std::vector<int32_t> cinst(nc);
+  for (int64_t c = 0; c < nc; ++c) {
+    const Key& k = keys[c];
+    cinst[c] = inst[k.s[0]];
+    for (int i = 1; i < k.k; ++i)
+      if (inst[k.s[i]] != cinst[c]) return fail(LRH_E_INVALID, "cluster spans instances");
+  }
+  // library order: (instance, size, sites)
+  std::vector<int32_t> order(nc);
+  for (int64_t c = 0; c < nc; ++c) order[c] = (int32_t)c;
+  std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    if (cinst[a] != cinst[b]) return cinst[a] < cinst[b];
+    const Key &ka = keys[a], &kb = keys[b];
+    if (ka.k != kb.k) return ka.k < kb.k;
+    for (int i = 0; i < ka.k; ++i)
+      if (ka.s[i] != kb.s[i]) return ka.s[i] < kb.s[i];
+    return false;
+  });
+  std::vector<int32_t> gid_of(nc);
+  for (int64_t g = 0; g < nc; ++g) gid_of[order[g]] = (int32_t)g;
+  P->n_clusters = nc;
+  P->c_ptr.assign(nc + 1, 0);
+  P->c_inst.resize(nc);
+  P->c_D.resize(nc);
+  for (int64_t g = 0; g < nc; ++g) {
+    const Key& k = keys[order[g]];
+    P->c_ptr[g + 1] = P->c_ptr[g] + k.k;
+    P->c_inst[g] = cinst[order[g]];
+    P->c_D[g] = 1 << k.k;
+    P->max_D = std::max(P->max_D, P->c_D[g]);
+  }
+  P->c_sites.resize(P->c_ptr[nc]);
+  for (int64_t g = 0; g < nc; ++g) {
+    const Key& k = keys[order[g]];
+    for (int i = 0; i < k.k; ++i) P->c_sites[P->c_ptr[g] + i] = k.s[i];
+  }
+
+  // ---- Hasse diagram: maximal proper subsets present in C_full ----
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> children(nc);  // (child gid, kernel mask)
+  std::vector<std::vector<int32_t>> parents(nc);
+  for (int64_t g = 0; g < nc; ++g) {
+    const Key& k = keys[order[g]];
+    std::vector<std::pair<int32_t, uint32_t>> found;  // (gid, position mask)
+    const uint32_t full = (1u << k.k) - 1;
+    for (uint32_t pm = 1; pm < full; ++pm) {
+      Key sub;
+      for (int i = 0; i < k.k; ++i)
+        if (pm >> i & 1) sub.s[sub.k++] = k.s[i];
+      auto it = index.find(sub);
+      if (it != index.end()) found.push_back({gid_of[it->second], pm});
+    }
+    for (auto& f : found) {
+      bool maximal = true;
+      for (auto& o : found)
+        if (o.second != f.second && (o.second & f.second) == f.second) { maximal = false; break; }
+      if (!maximal) continue;
+      // position j (0 = first site, most significant) -> kernel bit (k-1-j)
+      int32_t kmask = 0;
+      for (int j = 0; j < k.k; ++j)
+        if (f.second >> j & 1) kmask |= 1 << (k.k - 1 - j);
+      children[g].push_back({f.first, kmask});
+    }
+    std::sort(children[g].begin(), children[g].end());
+    for (auto& ch : children[g]) parents[ch.first].push_back((int32_t)g);
+  }
+  for (auto& p : parents) std::sort(p.begin(), p.end());
+
+  // child dimension per cluster (must be uniform)
+  std::vector<int32_t> Dc(nc, 0);
+  for (int64_t g = 0; g < nc; ++g) {
+    for (auto& ch : children[g]) {
+      const int D = P->c_D[ch.first];
+      if (Dc[g] == 0) Dc[g] = D;
+      else if (Dc[g] != D) return fail(LRH_E_UNSUPPORTED, "cluster whose children have different dimensions");
+    }
+  }
+
+  // ---- buckets ----
+  std::map<std::pair<int, int>, int> cb_index;
+  for (int64_t g = 0; g < nc; ++g) cb_index[{P->c_D[g], Dc[g]}] = 0;
+  int nb = 0;
+  for (auto& kv : cb_index) kv.second = nb++;
+  P->cb.resize(nb);
+  for (auto& kv : cb_index) {
+    P->cb[kv.second].De = kv.first.first;
+    P->cb[kv.second].Dc = kv.first.second;
+  }
+  std::vector<int32_t> cb_of(nc), pos_in_cb(nc);
+  for (int64_t g = 0; g < nc; ++g) {
+    const int b = cb_index[{P->c_D[g], Dc[g]}];
+    cb_of[g] = b;
+    pos_in_cb[g] = (int32_t)P->cb[b].h_gid.size();
+    P->cb[b].h_gid.push_back((int32_t)g);
+  }
+  for (auto& B : P->cb) {
+    B.n = (int64_t)B.h_gid.size();
+    for (int32_t g : B.h_gid) {
+      B.maxch = std::max<int>(B.maxch, (int)children[g].size());
+      B.maxpar = std::max<int>(B.maxpar, (int)parents[g].size());
+    }
+  }
+  // message buckets by child dimension
+  std::map<int, int> mb_index;
+  for (int64_t g = 0; g < nc; ++g)
+    for (auto& ch : children[g]) mb_index[P->c_D[ch.first]] = 0;
+  int nmb = 0;
+  for (auto& kv : mb_index) kv.second = nmb++;
+  if (nmb > LRH_MAX_BUCKETS) return fail(LRH_E_UNSUPPORTED, "too many message buckets");
+  P->mb.resize(nmb);
+  for (auto& kv : mb_index) {
+    P->mb[kv.second].D = kv.first;
+    P->mb[kv.second].comps = comps_of(kv.first, P->cplx);
+  }
+  for (auto& B : P->cb) {
+    if (B.Dc > 0) B.mb_child = mb_index[B.Dc];
+    auto it = mb_index.find(B.De);
+    if (it != mb_index.end()) B.mb_self = it->second;
+  }
+  // message numbering: per child bucket, slot-major over each parent cluster bucket so
+  // lanes of consecutive parents read consecutive messages
+  std::vector<std::vector<int32_t>> h_ch(nb), h_chmask(nb), h_par(nb);
+  for (int b = 0; b < nb; ++b) {
+    h_ch[b].assign((size_t)P->cb[b].maxch * P->cb[b].n, -1);
+    h_chmask[b].assign((size_t)P->cb[b].maxch * P->cb[b].n, 0);
+    h_par[b].assign((size_t)P->cb[b].maxpar * P->cb[b].n, -1);
+  }
+  std::map<std::pair<int32_t, int32_t>, int64_t> msg_of;  // (parent gid, child gid) -> index in bucket
+  for (int mbi = 0; mbi < nmb; ++mbi) {
+    MBucket& M = P->mb[mbi];
+    int64_t cnt = 0;
+    for (int b = 0; b < nb; ++b) {
+      CBucket& B = P->cb[b];
+      if (B.mb_child != mbi) continue;
+      for (int s = 0; s < B.maxch; ++s)
+        for (int64_t c = 0; c < B.n; ++c) {
+          const int32_t g = B.h_gid[c];
+          if ((int)children[g].size() <= s) continue;
+          const int64_t idx = cnt++;
+          if (idx > INT32_MAX) return fail(LRH_E_UNSUPPORTED, "too many messages in a bucket");
+          h_ch[b][(size_t)s * B.n + c] = (int32_t)idx;
+          h_chmask[b][(size_t)s * B.n + c] = children[g][s].second;
+          msg_of[{g, children[g][s].first}] = idx;
+          P->m_parent.push_back(g);
+          P->m_child.push_back(children[g][s].first);
+          P->m_bucket.push_back(mbi);
+          P->m_index.push_back(idx);
+        }
+    }
+    M.M = cnt;
+  }
+  // reorder the exported message list into (bucket, index) order
+  {
+    std::vector<size_t> perm(P->m_parent.size());
+    for (size_t i = 0; i < perm.size(); ++i) perm[i] = i;
+    std::sort(perm.begin(), perm.end(), [&](size_t a, size_t b) {
+      if (P->m_bucket[a] != P->m_bucket[b]) return P->m_bucket[a] < P->m_bucket[b];
+      return P->m_index[a] < P->m_index[b];
+    });
+    auto apply = [&](auto& v) {
+      auto w = v;
+      for (size_t i = 0; i < perm.size(); ++i) w[i] = v[perm[i]];
+      v.swap(w);
+    };
+    apply(P->m_parent);
+    apply(P->m_child);
+    apply(P->m_bucket);
+    apply(P->m_index);
+  }
+  P->n_msgs = (int64_t)P->m_parent.size();
+  int64_t off = 0;
+  for (auto& M : P->mb) {
+    M.offset = off;
+    off += M.M * M.comps;
+  }
+  P->nu_len = off;
+  // parent messages per cluster
+  for (int b = 0; b < nb; ++b) {
+    CBucket& B = P->cb[b];
+    for (int64_t c = 0; c < B.n; ++c) {
+      const int32_t g = B.h_gid[c];
+      for (size_t s = 0; s < parents[g].size(); ++s)
+        h_par[b][s * B.n + c] = (int32_t)msg_of[{parents[g][s], g}];
+    }
+  }
+  // marginal slots: clusters with parents, per dimension
+  std::vector<int32_t> rslot(nc, -1);
+  for (int mbi = 0; mbi < nmb; ++mbi) {
+    MBucket& M = P->mb[mbi];
+    int64_t S = 0;
+    for (int64_t g = 0; g < nc; ++g)
+      if (P->c_D[g] == M.D && !parents[g].empty()) rslot[g] = (int32_t)S++;
+    M.S = S;
+    M.comps_r = comps_of(M.D, P->cplx);
+  }
+  int64_t roff = 0;
+  for (auto& M : P->mb) {
+    M.roff = roff;
+    roff += M.S * M.comps_r;
+  }
+  P->R_len = roff;
+
+  // ---- h_e: sum of the terms whose support is the cluster, packed ----
+  std::vector<std::vector<std::complex<double>>> hdense(nc);
+  for (int t = 0; t < d->n_terms; ++t) {
+    const int32_t g = gid_of[term_cluster[t]];
+    const int D = P->c_D[g];
+    const double* re = d->term_re + d->term_off[t];
+    const double* im = d->term_im ? d->term_im + d->term_off[t] : nullptr;
+    double mx = 0;
+    for (int i = 0; i < D * D; ++i) mx = std::max(mx, std::abs(std::complex<double>(re[i], im ? im[i] : 0)));
+    for (int i = 0; i < D; ++i)
+      for (int j = 0; j < D; ++j) {
+        std::complex<double> a(re[i * D + j], im ? im[i * D + j] : 0.0);
+        std::complex<double> b(re[j * D + i], im ? -im[j * D + i] : 0.0);
+        if (std::abs(a - b) > 1e-12 * std::max(1.0, mx)) return fail(LRH_E_INVALID, "term is not Hermitian");
+      }
+    auto& H = hdense[g];
+    if (H.empty()) H.assign((size_t)D * D, 0.0);
+    for (int i = 0; i < D * D; ++i) H[i] += std::complex<double>(re[i], im ? im[i] : 0.0);
+  }
+  std::vector<double> hpack;
+  std::vector<std::vector<int64_t>> h_hoff(nb);
+  for (int b = 0; b < nb; ++b) h_hoff[b].assign(P->cb[b].n, -1);
+  for (int64_t g = 0; g < nc; ++g) {
+    if (hdense[g].empty()) continue;
+    const int D = P->c_D[g];
+    h_hoff[cb_of[g]][pos_in_cb[g]] = (int64_t)hpack.size();
+    const auto& H = hdense[g];
+    for (int i = 0; i < D; ++i)
+      for (int j = i; j < D; ++j) hpack.push_back(0.5 * (H[i * D + j].real() + H[j * D + i].real()));
+    if (P->cplx)
+      for (int i = 0; i < D; ++i)
+        for (int j = i + 1; j < D; ++j) hpack.push_back(0.5 * (H[i * D + j].imag() - H[j * D + i].imag()));
+  }
+
+  // ---- per-instance cluster ranges, marginal offsets ----
+  std::vector<int64_t> inst_ptr(n_inst + 1, 0);
+  for (int64_t g = 0; g < nc; ++g) inst_ptr[P->c_inst[g] + 1]++;
+  for (int64_t i = 0; i < n_inst; ++i) inst_ptr[i + 1] += inst_ptr[i];
+  std::vector<int64_t> marg_off(nc);
+  int64_t moff = 0;
+  for (int64_t g = 0; g < nc; ++g) {
+    marg_off[g] = moff;
+    moff += comps_of(P->c_D[g], P->cplx);
+  }
+  P->marg_len = moff;
+
+  // ---- Lipschitz factor Lambda_G and Gamma_G ----
+  bool two_local = true;
+  for (int64_t g = 0; g < nc; ++g)
+    if (P->c_ptr[g + 1] - P->c_ptr[g] > 2) two_local = false;
+  if (two_local) {
+    size_t deg = 0;
+    for (int64_t g = 0; g < nc; ++g)
+      if (P->c_ptr[g + 1] - P->c_ptr[g] == 1) deg = std::max(deg, parents[g].size());
+    P->Lambda = (double)deg + 2.0;  // Delta_G + d
+  } else {
+    double lam = 0;
+    for (size_t m = 0; m < P->m_parent.size(); ++m) {
+      const int32_t e = P->m_parent[m], f = P->m_child[m];
+      const double me = (double)(parents[e].size() + children[e].size());
+      const double mf = (double)(parents[f].size() + children[f].size());
+      lam = std::max(lam, mf + me * P->c_D[e] / (double)P->c_D[f]);
+    }
+    P->Lambda = lam;
+  }
+  double gam = 0;
+  for (int64_t g = 0; g < nc; ++g) gam += std::log((double)P->c_D[g]);
+  P->Gamma = gam;
+
+  if (P->host_only) return LRH_OK;
+  // ---- device upload ----
+  lrh_status st;
+#define UP(dst, vec)                      \
+  do {                                    \
+    st = P->upload(&(dst), vec);          \
+    if (st != LRH_OK) return st;          \
+  } while (0)
+  for (int b = 0; b < nb; ++b) {
+    CBucket& B = P->cb[b];
+    std::vector<int32_t> rs(B.n);
+    for (int64_t c = 0; c < B.n; ++c) rs[c] = rslot[B.h_gid[c]];
+    UP(B.gid, B.h_gid);
+    UP(B.hoff, h_hoff[b]);
+    UP(B.ch, h_ch[b]);
+    UP(B.chmask, h_chmask[b]);
+    UP(B.par, h_par[b]);
+    UP(B.rslot, rs);
+  }
+  {
+    size_t pos = 0;
+    for (int mbi = 0; mbi < nmb; ++mbi) {
+      MBucket& M = P->mb[mbi];
+      std::vector<int32_t> rs(M.M), mi(M.M);
+      for (int64_t m = 0; m < M.M; ++m, ++pos) {
+        rs[m] = rslot[P->m_child[pos]];
+        mi[m] = P->c_inst[P->m_parent[pos]];
+      }
+      UP(M.rslot, rs);
+      UP(M.inst, mi);
+    }
+  }
+  if (hpack.empty()) hpack.push_back(0.0);
+  UP(P->h, hpack);
+  UP(P->inst_ptr, inst_ptr);
+  UP(P->marg_off, marg_off);
+  st = P->dalloc(&P->scal, nc);
+  if (st != LRH_OK) return st;
+  st = P->dalloc(&P->scal2, nc);
+  if (st != LRH_OK) return st;
+  st = P->dalloc(&P->health, 2);
+  if (st != LRH_OK) return st;
+  HIP_TRY(hipMemset(P->health, 0, 2 * sizeof(unsigned long long)));
+  st = P->dalloc(&P->improved, std::max<int64_t>(n_inst, 1));
+  if (st != LRH_OK) return st;
+  st = P->dalloc(&P->fp, kFusedTableMax);
+  if (st != LRH_OK) return st;
+#undef UP
+  return LRH_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// drivers
+// ------------------------------------------------------------------------------------------
+
+template <typename T>
+lrh_status ensure_work(lrh_problem_s* P, bool fused) {
+  Work<T>& w = P->work<T>();
+  lrh_status st;
+  if (!w.Tb[0]) {
+    if ((st = P->dalloc(&w.Tb[0], std::max<int64_t>(P->nu_len, 1))) != LRH_OK) return st;
+    if ((st = P->dalloc(&w.Rb[0], std::max<int64_t>(P->R_len, 1))) != LRH_OK) return st;
+  }
+  if (fused && !w.fused_ready) {
+    if ((st = P->dalloc(&w.Tb[1], std::max<int64_t>(P->nu_len, 1))) != LRH_OK) return st;
+    if ((st = P->dalloc(&w.Rb[1], std::max<int64_t>(P->R_len, 1))) != LRH_OK) return st;
+    for (int i = 0; i < 4; ++i)
+      if ((st = P->dalloc(&w.W[i], std::max<int64_t>(P->nu_len, 1))) != LRH_OK) return st;
+    w.fused_ready = true;
+  }
+  return LRH_OK;
+}
+
+template <typename T>
+double default_tol();
+template <> double default_tol<float>() { return 4.0 * 1.1920928955078125e-07; }
+template <> double default_tol<double>() { return 4.0 * 2.220446049250313e-16; }
+
+template <typename T>
+ClusterArgs<T> base_args(lrh_problem_s* P, const CBucket& B) {
+  ClusterArgs<T> a{};
+  a.n = B.n;
+  a.De = B.De;
+  a.Dc = B.Dc;
+  a.maxch = B.maxch;
+  a.maxpar = B.maxpar;
+  a.gid = B.gid;
+  a.hoff = B.hoff;
+  a.ch = B.ch;
+  a.chmask = B.chmask;
+  a.par = B.par;
+  a.rslot = B.rslot;
+  a.h = P->h;
+  a.scal = P->scal;
+  a.scal2 = P->scal2;
+  a.tau_rel = 1e-9;
+  a.max_sweeps = P->max_sweeps;
+  a.tol = P->tol_override > 0 ? P->tol_override : default_tol<T>();
+  a.noconv = P->health;
+  a.nonfinite = P->health + 1;
+  if (B.mb_child >= 0) a.Mc = P->mb[B.mb_child].M;
+  if (B.mb_self >= 0) {
+    a.Mp = P->mb[B.mb_self].M;
+    a.S = P->mb[B.mb_self].S;
+  }
+  return a;
+}
+
+// One plain pass of the cluster kernels over every bucket at (nu, zeta, theta).
+template <typename T>
+lrh_status cluster_pass(lrh_problem_s* P, const T* nu, const T* ze, double theta, int mode, double beta,
+                        T* marg, hipStream_t s) {
+  Work<T>& w = P->work<T>();
+  for (const CBucket& B : P->cb) {
+    ClusterArgs<T> a = base_args<T>(P, B);
+    if (B.mb_child >= 0) {
+      const MBucket& M = P->mb[B.mb_child];
+      a.nu_c = nu + M.offset;
+      a.ze_c = ze ? ze + M.offset : nullptr;
+      a.Tout = w.Tb[0] + M.offset;
+    }
+    if (B.mb_self >= 0) {
+      const MBucket& M = P->mb[B.mb_self];
+      a.nu_p = nu + M.offset;
+      a.ze_p = ze ? ze + M.offset : nullptr;
+      a.R = w.Rb[0] + M.roff;
+    }
+    a.marg = marg;
+    a.marg_off = P->marg_off;
+    a.beta = beta;
+    a.theta = theta;
+    HIP_TRY(launch_cluster<T>(a, P->cplx, mode, 64, s));
+  }
+  return LRH_OK;
+}
+
+template <typename T>
+MsgArgs<T> msg_args(lrh_problem_s* P, const MBucket& M) {
+  Work<T>& w = P->work<T>();
+  MsgArgs<T> a{};
+  a.M = M.M;
+  a.comps = M.comps;
+  a.S = M.S;
+  a.rslot = M.rslot;
+  a.inst = M.inst;
+  a.R = w.Rb[0] + M.roff;
+  a.Tm = w.Tb[0] + M.offset;
+  return a;
+}
+
+template <typename T>
+lrh_status dual_eval_t(lrh_problem_s* P, const T* nu, double beta, double* q, T* grad, T* marg,
+                       hipStream_t s) {
+  lrh_status st = ensure_work<T>(P, false);
+  if (st != LRH_OK) return st;
+  const int mode = beta > 0 ? MODE_GIBBS : MODE_GROUND;
+  if ((st = cluster_pass<T>(P, nu, nullptr, 0.0, mode, beta, marg, s)) != LRH_OK) return st;
+  HIP_TRY(launch_reduce(P->scal, P->inst_ptr, P->n_inst, q, nullptr, nullptr, nullptr, nullptr, nullptr, s));
+  if (grad) {
+    for (const MBucket& M : P->mb) {
+      MsgArgs<T> a = msg_args<T>(P, M);
+      a.grad = grad + M.offset;
+      HIP_TRY(launch_msg<T>(a, MSG_GRAD, 256, s));
+    }
+  }
+  return LRH_OK;
+}
+
+template <typename T>
+lrh_status subgrad_t(lrh_problem_s* P, T* nu, T* nu_best, double* q_best, int64_t k0, int n_iter, int kind,
+                     double scale, double* q_hist, hipStream_t s) {
+  lrh_status st = ensure_work<T>(P, false);
+  if (st != LRH_OK) return st;
+  for (int j = 0; j < n_iter; ++j) {
+    const int64_t k = k0 + j;
+    const double alpha = kind == 0 ? scale / std::sqrt((double)k + 1.0) : scale;
+    if ((st = cluster_pass<T>(P, nu, nullptr, 0.0, MODE_GROUND, 0.0, nullptr, s)) != LRH_OK) return st;
+    HIP_TRY(launch_reduce(P->scal, P->inst_ptr, P->n_inst, nullptr, nullptr, nullptr, q_best, P->improved,
+                          q_hist ? q_hist + (int64_t)j * P->n_inst : nullptr, s));
+    for (const MBucket& M : P->mb) {
+      MsgArgs<T> a = msg_args<T>(P, M);
+      a.nu = nu + M.offset;
+      a.nu_best = nu_best + M.offset;
+      a.improved = P->improved;
+      a.alpha = alpha;
+      HIP_TRY(launch_msg<T>(a, MSG_SUBGRAD, 256, s));
+    }
+  }
+  return LRH_OK;
+}
+
+double theta_next(double th) { return (std::sqrt(th * th * th * th + 4.0 * th * th) - th * th) / 2.0; }
+
+template <typename T>
+lrh_status nesterov_plain(lrh_problem_s* P, T* nu, T* ze, lrh_nesterov_state* stt, int n_iter,
+                          hipStream_t s) {
+  lrh_status st = ensure_work<T>(P, false);
+  if (st != LRH_OK) return st;
+  for (int j = 0; j < n_iter; ++j) {
+    const double th = stt->theta;
+    if ((st = cluster_pass<T>(P, nu, ze, th, MODE_GIBBS, stt->beta, nullptr, s)) != LRH_OK) return st;
+    for (const MBucket& M : P->mb) {
+      MsgArgs<T> a = msg_args<T>(P, M);
+      a.nu = nu + M.offset;
+      a.ze = ze + M.offset;
+      a.theta = th;
+      a.inv_thL = 1.0 / (th * stt->L);
+      HIP_TRY(launch_msg<T>(a, MSG_NESTEROV, 256, s));
+    }
+    stt->theta = theta_next(th);
+    stt->k += 1;
+  }
+  return LRH_OK;
+}
+
+bool fusable(const lrh_problem_s* P) {
+  if (P->mb.size() != 1 || P->mb[0].D != 2) return false;
+  for (const CBucket& B : P->cb)
+    if (!((B.De == 4 && B.Dc == 2) || (B.De == 2 && B.Dc == 0))) return false;
+  return true;
+}
+
+// Enqueue one fused segment of n iterations (kernels read their scalars from P->fp[j]).
+// Kernel j: state S_j-1 -> S_j (S_0 = user buffers, S_j = W[(j-1)%2] for j >= 1), writes
+// T/R of iteration j into buffer j%2; a final message kernel moves S_{n-1} + g into the
+// user buffers.
+template <typename T>
+lrh_status fused_enqueue(lrh_problem_s* P, T* nu, T* ze, int n, hipStream_t s) {
+  Work<T>& w = P->work<T>();
+  const CBucket* E = nullptr;
+  const CBucket* Sb = nullptr;
+  for (const CBucket& B : P->cb) {
+    if (B.De == 4) E = &B;
+    else Sb = &B;
+  }
+  const MBucket& M = P->mb[0];
+  auto state = [&](int j, int which) -> T* {  // which: 0 nu, 1 ze
+    if (j == 0) return which == 0 ? nu : ze;
+    return w.W[((j - 1) % 2) * 2 + which];
+  };
+  for (int j = 0; j < n; ++j) {
+    const int cur = j % 2, prv = (j + 1) % 2;
+    ClusterArgs<T> ea{}, sa{};
+    if (E) ea = base_args<T>(P, *E);
+    if (Sb) sa = base_args<T>(P, *Sb);
+    for (ClusterArgs<T>* a : {&ea, &sa}) {
+      a->fp = P->fp + j;
+      a->fused_first = (j == 0) ? 1 : 0;
+      a->nu_c_prev = state(j == 0 ? 0 : j - 1, 0);
+      a->ze_c_prev = state(j == 0 ? 0 : j - 1, 1);
+      a->nu_p_prev = a->nu_c_prev;
+      a->ze_p_prev = a->ze_c_prev;
+      a->Tprev_c = w.Tb[prv];
+      a->Rprev_c = w.Rb[prv];
+      a->Tprev_p = w.Tb[prv];
+      a->Rprev_p = w.Rb[prv];
+      a->rslot_of_msg_c = M.rslot;
+      a->Sc = M.S;
+      a->nu_c_new = (j == 0) ? nullptr : state(j, 0);
+      a->ze_c_new = (j == 0) ? nullptr : state(j, 1);
+    }
+    ea.Tout = w.Tb[cur] + M.offset;
+    sa.R = w.Rb[cur] + M.roff;
+    sa.S = M.S;
+    // non-null plain pointers keep the (unused) plain path well-defined
+    ea.nu_c = ea.nu_c_prev; sa.nu_p = sa.nu_p_prev;
+    HIP_TRY(launch_cluster_pair<T>(ea, sa, P->cplx, MODE_GIBBS, 64, s));
+  }
+  MsgArgs<T> a{};
+  a.M = M.M;
+  a.comps = M.comps;
+  a.S = M.S;
+  a.rslot = M.rslot;
+  a.inst = M.inst;
+  a.R = w.Rb[(n - 1) % 2] + M.roff;
+  a.Tm = w.Tb[(n - 1) % 2] + M.offset;
+  a.nu = nu;
+  a.ze = ze;
+  a.nu_src = state(n - 1, 0);
+  a.ze_src = state(n - 1, 1);
+  a.fp = P->fp + n;
+  HIP_TRY(launch_msg<T>(a, MSG_NESTEROV, 256, s));
+  return LRH_OK;
+}
+
+template <typename T>
+lrh_status nesterov_fused(lrh_problem_s* P, T* nu, T* ze, lrh_nesterov_state* stt, int n_iter,
+                          hipStream_t s) {
+  lrh_status st = ensure_work<T>(P, true);
+  if (st != LRH_OK) return st;
+  constexpr int CH = kFusedTableMax - 1;  // iterations per captured graph
+  const int prec = sizeof(T) == 4 ? 32 : 64;
+  int done = 0;
+  while (done < n_iter) {
+    const int n = std::min(CH, n_iter - done);
+    FusedTable tab{};
+    double th = stt->theta, thp = 0.0;
+    for (int j = 0; j <= n; ++j) {
+      FusedParams& f = tab.p[j];
+      f.theta_prev = thp;
+      f.inv_thL_prev = j > 0 ? 1.0 / (thp * stt->L) : 0.0;
+      f.theta_cur = th;
+      f.beta = stt->beta;
+      thp = th;
+      th = theta_next(th);
+    }
+    HIP_TRY(launch_set_fused(P->fp, tab, n + 1, s));
+    if (n == CH) {
+      GraphKey key{prec, nu, ze};
+      auto it = P->graphs.find(key);
+      if (it == P->graphs.end()) {
+        if (!P->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeRelaxed));
+        lrh_status est = fused_enqueue<T>(P, nu, ze, n, P->cap_stream);
+        hipGraph_t graph = nullptr;
+        hipError_t ee = hipStreamEndCapture(P->cap_stream, &graph);
+        if (est != LRH_OK) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return est;
+        }
+        if (ee != hipSuccess) return fail(LRH_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+        hipGraphExec_t exec = nullptr;
+        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) return fail(LRH_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+        it = P->graphs.emplace(key, exec).first;
+      }
+      HIP_TRY(hipGraphLaunch(it->second, s));
+    } else {
+      if ((st = fused_enqueue<T>(P, nu, ze, n, s)) != LRH_OK) return st;
+    }
+    for (int j = 0; j < n; ++j) stt->theta = theta_next(stt->theta);
+    stt->k += n;
+    done += n;
+  }
+  return LRH_OK;
+}
+
+template <typename T>
+lrh_status nesterov_t(lrh_problem_s* P, T* nu, T* ze, lrh_nesterov_state* stt, int n_iter, bool fused,
+                      hipStream_t s) {
+  if (stt->k == 0) {
+    HIP_TRY(launch_copy<T>(ze, nu, P->nu_len, s));
+    stt->theta = 1.0;
+  }
+  if (n_iter == 0) return LRH_OK;
+  if (fused) {
+    if (!fusable(P)) return fail(LRH_E_UNSUPPORTED, "fused iteration needs a 2-local problem (edges and sites)");
+    return nesterov_fused<T>(P, nu, ze, stt, n_iter, s);
+  }
+  return nesterov_plain<T>(P, nu, ze, stt, n_iter, s);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// C ABI
+// ------------------------------------------------------------------------------------------
+
+extern "C" {
+
+const char* lrh_last_error(void) { return g_err.c_str(); }
+
+lrh_status lrh_build_clusters(const lrh_problem_desc* desc, int hip_device, lrh_problem* out) {
+  if (!out) return fail(LRH_E_INVALID, "null output handle");
+  *out = nullptr;
+  std::unique_ptr<lrh_problem_s> P(new lrh_problem_s());
+  lrh_status st;
+  if (hip_device < 0) {
+    P->host_only = true;
+    try {
+      st = build(desc, P.get());
+    } catch (const std::bad_alloc&) {
+      return fail(LRH_E_NOMEM, "host allocation failed");
+    }
+  } else {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device >= ndev) return fail(LRH_E_DEVICE, "invalid HIP device");
+    DeviceGuard guard(hip_device);
+    P->device = hip_device;
+    try {
+      st = build(desc, P.get());
+    } catch (const std::bad_alloc&) {
+      return fail(LRH_E_NOMEM, "host allocation failed");
+    }
+  }
+  if (st != LRH_OK) return st;
+  *out = P.release();
+  return LRH_OK;
+}
+
+lrh_status lrh_query(lrh_problem p, lrh_layout* out) {
+  if (!p || !out) return fail(LRH_E_INVALID, "null argument");
+  std::memset(out, 0, sizeof(*out));
+  out->n_clusters = p->n_clusters;
+  out->n_msgs = p->n_msgs;
+  out->n_instances = p->n_inst;
+  out->is_real = p->cplx ? 0 : 1;
+  out->max_D = p->max_D;
+  out->n_buckets = (int32_t)p->mb.size();
+  for (size_t b = 0; b < p->mb.size(); ++b) {
+    out->bucket_D[b] = p->mb[b].D;
+    out->bucket_count[b] = p->mb[b].M;
+    out->bucket_comps[b] = p->mb[b].comps;
+    out->bucket_offset[b] = p->mb[b].offset;
+  }
+  out->nu_len = p->nu_len;
+  out->marg_len = p->marg_len;
+  out->Lambda_G = p->Lambda;
+  out->Gamma_G = p->Gamma;
+  out->max_sweeps = p->max_sweeps;
+  return LRH_OK;
+}
+
+lrh_status lrh_export_clusters(lrh_problem p, int64_t* ptr, int32_t* sites, int32_t* instance) {
+  if (!p) return fail(LRH_E_INVALID, "null problem");
+  if (ptr) std::memcpy(ptr, p->c_ptr.data(), p->c_ptr.size() * sizeof(int64_t));
+  if (sites) std::memcpy(sites, p->c_sites.data(), p->c_sites.size() * sizeof(int32_t));
+  if (instance) std::memcpy(instance, p->c_inst.data(), p->c_inst.size() * sizeof(int32_t));
+  return LRH_OK;
+}
+
+lrh_status lrh_export_messages(lrh_problem p, int32_t* parent, int32_t* child, int32_t* bucket,
+                               int64_t* index) {
+  if (!p) return fail(LRH_E_INVALID, "null problem");
+  const size_t n = p->m_parent.size();
+  if (parent) std::memcpy(parent, p->m_parent.data(), n * sizeof(int32_t));
+  if (child) std::memcpy(child, p->m_child.data(), n * sizeof(int32_t));
+  if (bucket) std::memcpy(bucket, p->m_bucket.data(), n * sizeof(int32_t));
+  if (index) std::memcpy(index, p->m_index.data(), n * sizeof(int64_t));
+  return LRH_OK;
+}
+
+lrh_status lrh_dual_eval(lrh_problem p, const void* nu, uint32_t flags, double beta, double* q_dev,
+                         void* grad_dev, void* marg_dev, hipStream_t stream) {
+  if (!p || !nu || !q_dev) return fail(LRH_E_INVALID, "null argument");
+  if (p->host_only) return fail(LRH_E_INVALID, "problem was built without a device");
+  if (!(beta >= 0.0)) return fail(LRH_E_INVALID, "beta must be >= 0");
+  DeviceGuard guard(p->device);
+  if (flags & LRH_F32)
+    return dual_eval_t<float>(p, (const float*)nu, beta, q_dev, (float*)grad_dev, (float*)marg_dev, stream);
+  return dual_eval_t<double>(p, (const double*)nu, beta, q_dev, (double*)grad_dev, (double*)marg_dev, stream);
+}
+
+lrh_status lrh_step_subgrad(lrh_problem p, void* nu, void* nu_best, double* q_best_dev, int64_t k0,
+                            int32_t n_iter, int32_t step_kind, double step_scale, double* q_hist_dev,
+                            uint32_t flags, hipStream_t stream) {
+  if (!p || !nu || !nu_best || !q_best_dev) return fail(LRH_E_INVALID, "null argument");
+  if (p->host_only) return fail(LRH_E_INVALID, "problem was built without a device");
+  if (n_iter < 0 || k0 < 0) return fail(LRH_E_INVALID, "negative iteration counts");
+  if (!(step_scale > 0.0) || (step_kind != 0 && step_kind != 1)) return fail(LRH_E_INVALID, "bad step rule");
+  DeviceGuard guard(p->device);
+  if (flags & LRH_F32)
+    return subgrad_t<float>(p, (float*)nu, (float*)nu_best, q_best_dev, k0, n_iter, step_kind, step_scale,
+                            q_hist_dev, stream);
+  return subgrad_t<double>(p, (double*)nu, (double*)nu_best, q_best_dev, k0, n_iter, step_kind, step_scale,
+                           q_hist_dev, stream);
+}
+
+lrh_status lrh_step_nesterov(lrh_problem p, void* nu, void* zeta, lrh_nesterov_state* st, int32_t n_iter,
+                             uint32_t flags, hipStream_t stream) {
+  if (!p || !nu || !zeta || !st) return fail(LRH_E_INVALID, "null argument");
+  if (p->host_only) return fail(LRH_E_INVALID, "problem was built without a device");
+  if (!(st->beta > 0.0) || !(st->L > 0.0)) return fail(LRH_E_INVALID, "beta and L must be positive");
+  if (n_iter < 0 || st->k < 0) return fail(LRH_E_INVALID, "negative iteration counts");
+  if (st->k > 0 && !(st->theta > 0.0 && st->theta <= 1.0)) return fail(LRH_E_INVALID, "theta out of (0, 1]");
+  DeviceGuard guard(p->device);
+  const bool fused = (flags & LRH_FUSED) != 0;
+  if (flags & LRH_F32) return nesterov_t<float>(p, (float*)nu, (float*)zeta, st, n_iter, fused, stream);
+  return nesterov_t<double>(p, (double*)nu, (double*)zeta, st, n_iter, fused, stream);
+}
+
+lrh_status lrh_certify(lrh_problem p, const void* nu, uint32_t flags, double* q_dev, double* margin_dev,
+                       double* lmin_dev, hipStream_t stream) {
+  if (!p || !nu || !q_dev || !margin_dev) return fail(LRH_E_INVALID, "null argument");
+  if (p->host_only) return fail(LRH_E_INVALID, "problem was built without a device");
+  DeviceGuard guard(p->device);
+  const double* nu64 = (const double*)nu;
+  if (flags & LRH_F32) {
+    if (!p->nu64_tmp) {
+      lrh_status st = p->dalloc(&p->nu64_tmp, std::max<int64_t>(p->nu_len, 1));
+      if (st != LRH_OK) return st;
+    }
+    HIP_TRY(launch_widen(p->nu64_tmp, (const float*)nu, p->nu_len, stream));
+    nu64 = p->nu64_tmp;
+  }
+  for (const CBucket& B : p->cb) {
+    ClusterArgs<double> a = base_args<double>(p, B);
+    a.tol = p->tol_override > 0 ? p->tol_override : default_tol<double>();
+    if (B.mb_child >= 0) a.nu_c = nu64 + p->mb[B.mb_child].offset;
+    if (B.mb_self >= 0) a.nu_p = nu64 + p->mb[B.mb_self].offset;
+    a.R = nullptr;
+    HIP_TRY(launch_cluster<double>(a, p->cplx, MODE_CERTIFY, 64, stream));
+  }
+  HIP_TRY(launch_reduce(p->scal, p->inst_ptr, p->n_inst, q_dev, p->scal2, margin_dev, nullptr, nullptr, nullptr,
+                        stream));
+  if (lmin_dev) HIP_TRY(launch_copy<double>(lmin_dev, p->scal, p->n_clusters, stream));
+  return LRH_OK;
+}
+
+lrh_status lrh_check(lrh_problem p, hipStream_t stream, int64_t* noconv, int64_t* nonfinite) {
+  if (!p) return fail(LRH_E_INVALID, "null problem");
+  if (p->host_only) return fail(LRH_E_INVALID, "problem was built without a device");
+  DeviceGuard guard(p->device);
+  HIP_TRY(hipStreamSynchronize(stream));
+  unsigned long long h[2] = {0, 0};
+  HIP_TRY(hipMemcpy(h, p->health, sizeof(h), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemset(p->health, 0, sizeof(h)));
+  if (noconv) *noconv = (int64_t)h[0];
+  if (nonfinite) *nonfinite = (int64_t)h[1];
+  if (h[1]) return fail(LRH_E_NONFINITE, "non-finite eigenvalue in " + std::to_string(h[1]) + " cluster solves");
+  if (h[0]) return fail(LRH_E_NOCONV, "Jacobi sweep cap reached in " + std::to_string(h[0]) + " cluster solves");
+  return LRH_OK;
+}
+
+lrh_status lrh_set_jacobi(lrh_problem p, int32_t max_sweeps, double rel_tol) {
+  if (!p) return fail(LRH_E_INVALID, "null problem");
+  if (max_sweeps < 0 || !(rel_tol >= 0.0)) return fail(LRH_E_INVALID, "bad Jacobi settings");
+  p->max_sweeps = max_sweeps;
+  p->tol_override = rel_tol;
+  return LRH_OK;
+}
+
+void lrh_destroy(lrh_problem p) { delete p; }
+
+}  // extern "C"

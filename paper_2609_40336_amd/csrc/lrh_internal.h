@@ -1,0 +1,113 @@
+// Internal interface between the host driver (lrh_host.cpp) and the kernels
+// (lrh_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lrh {
+
+enum ClusterMode : int {
+  MODE_GIBBS = 0,    // F_beta and Gibbs state rho_beta (smoothed dual, Sec. 4.2.2)
+  MODE_GROUND = 1,   // lambda_min and normalised ground projector (Sec. 4.2.1)
+  MODE_CERTIFY = 2,  // FP64 lambda_min and rounding margin only (no eigenvectors)
+};
+
+enum MsgMode : int {
+  MSG_GRAD = 0,      // grad[m] = R[child] - T[m]
+  MSG_SUBGRAD = 1,   // nu_best copy where improved, then nu += alpha g
+  MSG_NESTEROV = 2,  // zeta += g / (theta L); nu = (1 - theta) nu + theta zeta
+};
+
+// Packed Hermitian layout: upper-triangle real parts (row-major), then the imaginary
+// parts of the strict upper triangle.
+__host__ __device__ constexpr int tri_index(int i, int j, int D) {
+  return i * D - (i * (i - 1)) / 2 + (j - i);
+}
+__host__ __device__ constexpr int stri_index(int i, int j, int D) {
+  return i * (D - 1) - (i * (i - 1)) / 2 + (j - i - 1);
+}
+__host__ __device__ constexpr int n_comps(int D, bool cplx) {
+  return cplx ? D * D : D * (D + 1) / 2;
+}
+
+// Per-iteration scalars of the fused Nesterov loop, read from device memory so that a
+// captured graph can be replayed for any stage.
+struct FusedParams {
+  double theta_prev;   // theta_{k-1}
+  double inv_thL_prev; // 1 / (theta_{k-1} L)
+  double theta_cur;    // theta_k
+  double beta;
+};
+
+template <typename T>
+struct ClusterArgs {
+  int64_t n;            // clusters in the bucket
+  int De, Dc;           // cluster and child dimensions (Dc = 0: no children)
+  int maxch, maxpar;
+  const int32_t* gid;   // [n] library cluster id
+  const int64_t* hoff;  // [n] offset into h (packed comps), -1: h_e = 0
+  const int32_t* ch;    // [maxch][n] child-message index in the Dc bucket, -1 unused
+  const int32_t* chmask;// [maxch][n] bit mask of the child's sites inside the cluster
+  const int32_t* par;   // [maxpar][n] parent-message index in the De bucket, -1 unused
+  const int32_t* rslot; // [n] marginal slot in the De marginal buffer, -1: no parents
+  const double* h;      // packed term blocks (double)
+  // child messages (dimension Dc)
+  const T* nu_c; const T* ze_c; int64_t Mc;
+  T* Tout;              // partial traces, message layout of the Dc bucket (nullable)
+  // parent messages (dimension De)
+  const T* nu_p; const T* ze_p; int64_t Mp;
+  T* R; int64_t S;      // marginal slots of dimension De (nullable)
+  T* marg; const int64_t* marg_off;  // per-cluster marginal output (nullable)
+  double* scal;         // per library cluster id: F_beta or lambda_min
+  double* scal2;        // per library cluster id: certify margin (MODE_CERTIFY)
+  double beta;          // inverse temperature (MODE_GIBBS)
+  double theta;         // extrapolation weight when ze_* != nullptr
+  double tau_rel;       // ground-space threshold (MODE_GROUND)
+  int max_sweeps;
+  double tol;           // relative off-diagonal tolerance
+  unsigned long long* noconv;
+  unsigned long long* nonfinite;
+  // ---- fused update of the previous iteration (register kernel only) ----
+  const FusedParams* fp;      // device pointer, nullptr: no fused update
+  const T* nu_c_prev; const T* ze_c_prev; const T* Tprev_c; const T* Rprev_c;
+  const int32_t* rslot_of_msg_c; int64_t Sc;
+  T* nu_c_new; T* ze_c_new;   // written by the parent (this cluster)
+  const T* nu_p_prev; const T* ze_p_prev; const T* Tprev_p; const T* Rprev_p;
+  int fused_first;            // 1: iteration 0 of a call, state already current
+};
+
+template <typename T>
+struct MsgArgs {
+  int64_t M, comps, S;
+  const int32_t* rslot;   // [M] child's marginal slot
+  const int32_t* inst;    // [M] instance
+  const T* R; const T* Tm;
+  T* nu; T* ze; T* nu_best; T* grad;
+  const T* nu_src; const T* ze_src;  // state read from here (nullptr: nu / ze, in place)
+  const int32_t* improved;  // [n_inst] (subgradient best tracking)
+  double alpha, theta, inv_thL;
+  const FusedParams* fp;    // if set, theta/inv_thL come from here (theta_prev)
+};
+
+// ---- launchers (lrh_kernels.hip) ----
+template <typename T>
+hipError_t launch_cluster(const ClusterArgs<T>& a, bool cplx, int mode, int block, hipStream_t s);
+template <typename T>
+hipError_t launch_msg(const MsgArgs<T>& a, int mode, int block, hipStream_t s);
+hipError_t launch_reduce(const double* scal, const int64_t* inst_ptr, int64_t n_inst, double* out,
+                         const double* scal2, double* out2, double* q_best, int32_t* improved,
+                         double* q_hist, hipStream_t s);
+constexpr int kFusedTableMax = 65;
+struct FusedTable { FusedParams p[kFusedTableMax]; };
+hipError_t launch_set_fused(FusedParams* dst, const FusedTable& v, int n, hipStream_t s);
+hipError_t launch_widen(double* dst, const float* src, int64_t n, hipStream_t s);
+// two-bucket fused/plain launch for 2-local problems: edges (De=4, Dc=2) and sites (De=2)
+template <typename T>
+hipError_t launch_cluster_pair(const ClusterArgs<T>& edges, const ClusterArgs<T>& sites, bool cplx,
+                               int mode, int block, hipStream_t s);
+template <typename T>
+hipError_t launch_copy(T* dst, const T* src, int64_t n, hipStream_t s);
+
+}  // namespace lrh

@@ -1,0 +1,351 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Every case prints its name before touching the GPU.  Tolerances: FP64 results to 1e-9
+per site on dual values and 1e-10 on every message / marginal entry (rounding-level
+agreement is expected: both sides are backward-stable eigen-solvers in FP64); FP32
+iterations against the FP64 oracle at the stated FP32 tolerances.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import lrh_workloads as W
+from oracle import lrh_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_40336_amd import lrh
+    lrh.load()
+
+
+def lrhmod():
+    from paper_2609_40336_amd import lrh
+    return lrh
+
+
+def sites_per_instance(desc):
+    return np.bincount(desc.site_instance, minlength=desc.n_instances).astype(np.float64)
+
+
+def oracle_marginals(R, marg):
+    out = {}
+    for D, ids in R.cgroups.items():
+        for j, e in enumerate(ids):
+            out[R.clusters[e]] = marg[D][j]
+    return out
+
+
+def max_pair_err(got, want):
+    assert set(got) == set(want)
+    return max(float(np.abs(got[k] - want[k]).max()) for k in want)
+
+
+PROBLEMS = {
+    "c1_tfim16_complex": lambda: W.workload_c1(),
+    "heis_square4": lambda: W.heisenberg_square(4),
+    "heis_chain_field": lambda: W.heisenberg_chain(9, field_x=0.5),
+    "randchain_Y3": lambda: W.random_chain(8, seed=1, top_len=3, subintervals=True),
+    "randchain_Y4": lambda: W.random_chain(8, seed=2, top_len=4, subintervals=True),
+    "gue_Y5": lambda: W.interval_chain_gue(9, 5, 0.1, seed=3),
+    "randchain_Y6": lambda: W.random_chain(7, seed=3, top_len=6, subintervals=True),
+    "plaq_batch_ragged": lambda: W.tfim_plaquette_batch([3, 4, 5], [0.7, 2.0, 3.5]),
+    "xxz_tri3": lambda: W.xxz_triangular(3, 0.5, seed=5),
+    "ising_tree_rot": lambda: W.classical_ising_tree(9, 4, rotate=True),
+}
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+@pytest.mark.parametrize("beta", [0.0, 0.7, 6.0])
+def test_dual_eval_fp64(name, beta):
+    lrh = lrhmod()
+    say(f"[dual_eval fp64] {name} beta={beta}")
+    d = PROBLEMS[name]()
+    P = lrh.Problem(d, 0)
+    R = O.Relaxation(d)
+    nu_o = R.draw(11, 0.5)
+    nu = P.from_dense(R.to_pairs(nu_o))
+    q, g, m = P.dual_eval(nu, beta, grad=True, marg=True)
+    torch.cuda.synchronize()
+    if beta > 0:
+        q_o, g_o = R.grad_beta(nu_o, beta)
+        _, rho = R.gibbs(nu_o, beta)
+    else:
+        q_o, g_o = R.subgrad(nu_o)
+        _, rho = R.ground(nu_o)
+    n = sites_per_instance(d)
+    assert np.all(np.abs(q.cpu().numpy() - q_o) <= 1e-9 * n)
+    assert max_pair_err(P.to_dense(g), R.to_pairs(g_o)) < 1e-10
+    assert max_pair_err(P.marg_dense(m), oracle_marginals(R, rho)) < 1e-10
+    assert P.check() == (0, 0)
+
+
+@pytest.mark.parametrize("name", ["c1_tfim16_complex", "randchain_Y4", "plaq_batch_ragged", "gue_Y5"])
+def test_dual_eval_fp32(name):
+    """FP32 iteration arithmetic: values within 2e-5 per site, gradients within 5e-5."""
+    lrh = lrhmod()
+    say(f"[dual_eval fp32] {name}")
+    d = PROBLEMS[name]()
+    P = lrh.Problem(d, 0)
+    R = O.Relaxation(d)
+    nu_o = R.draw(12, 0.5)
+    nu32 = P.from_dense(R.to_pairs(nu_o), f32=True)
+    nu_o = R.from_pairs(P.to_dense(nu32))   # the oracle sees the float-rounded messages
+    q, g, _ = P.dual_eval(nu32, 2.0, grad=True)
+    torch.cuda.synchronize()
+    q_o, g_o = R.grad_beta(nu_o, 2.0)
+    n = sites_per_instance(d)
+    assert np.all(np.abs(q.cpu().numpy() - q_o) <= 2e-5 * n)
+    assert max_pair_err(P.to_dense(g), R.to_pairs(g_o)) < 5e-5
+
+
+@pytest.mark.parametrize("name", ["c1_tfim16_complex", "randchain_Y6", "plaq_batch_ragged", "xxz_tri3"])
+def test_certify_fp64_and_from_fp32(name):
+    lrh = lrhmod()
+    say(f"[certify] {name}")
+    d = PROBLEMS[name]()
+    P = lrh.Problem(d, 0)
+    R = O.Relaxation(d)
+    nu_o = R.draw(13, 0.4)
+    nu = P.from_dense(R.to_pairs(nu_o))
+    q, mg, lm = P.certify(nu, lmin=True)
+    torch.cuda.synchronize()
+    q_o, mg_o = R.certify(nu_o)
+    n = sites_per_instance(d)
+    assert np.all(np.abs(q.cpu().numpy() - q_o) <= 1e-9 * n)
+    np.testing.assert_allclose(mg.cpu().numpy(), mg_o, rtol=1e-9)
+    # per-cluster lambda_min in library order
+    lmo = {}
+    for D, vals in R.lambda_min(nu_o).items():
+        for j, e in enumerate(R.cgroups[D]):
+            lmo[R.clusters[e]] = vals[j]
+    lmg = lm.cpu().numpy()
+    assert max(abs(lmg[c] - lmo[s]) for c, s in enumerate(P.clusters)) < 1e-11
+    # from float messages: the bound is for the float-rounded nu, evaluated in FP64
+    nu32 = P.from_dense(R.to_pairs(nu_o), f32=True)
+    q32, _, _ = P.certify(nu32)
+    torch.cuda.synchronize()
+    q_o32, _ = R.certify(R.from_pairs(P.to_dense(nu32)))
+    assert np.all(np.abs(q32.cpu().numpy() - q_o32) <= 1e-9 * n)
+
+
+def test_subgradient_c1_trajectory():
+    """Algorithm 1 on the 16-site TFIM chain, 2000 steps of 1/sqrt(k+1).
+
+    The iteration is chaotic in its first steps: a 1e-15 perturbation of nu^0 grows about
+    1e3-fold per step from k ~ 7 in the oracle itself, so whole trajectories of two
+    rounding-different implementations agree only up to there.  Parity is therefore
+    checked (a) on the whole trajectory for k < 7, (b) one step at a time from the GPU's
+    own states at sampled k (q^k and nu^{k+1} = nu^k + alpha_k g^k), and (c) on the best
+    iterate bookkeeping and the certified bracket Anderson <= q_best <= E0."""
+    lrh = lrhmod()
+    say("[subgradient] c1 2000 steps")
+    d = W.workload_c1()
+    P = lrh.Problem(d, 0)
+    R = O.Relaxation(d)
+    T = 2000
+    sample = set(range(0, T, 97)) | {T - 1}
+    nu = P.zeros()
+    nb = P.zeros()
+    qb = P.qbuf(-math.inf)
+    qh = torch.zeros(T, dtype=torch.float64, device="cuda")
+    snaps = {}
+    k = 0
+    while k < T:
+        if k in sample:
+            before = nu.clone()
+            P.step_subgrad(nu, nb, qb, k, 1, q_hist=qh[k:k + 1])
+            snaps[k] = (before, nu.clone())
+            k += 1
+        else:
+            n = min(T, min([s for s in sample if s > k] + [T])) - k
+            P.step_subgrad(nu, nb, qb, k, n, q_hist=qh[k:k + n])
+            k += n
+    torch.cuda.synchronize()
+    nb_o, qb_o, nT_o, hist_o = O.subgradient(R, 7)
+    n_s = d.n_sites
+    hg = qh.cpu().numpy()
+    assert np.max(np.abs(hg[:7] - hist_o[:, 0])) <= 1e-12 * n_s
+    for k, (before, after) in sorted(snaps.items()):
+        nu_k = R.from_pairs(P.to_dense(before))
+        q_o, g_o = R.subgrad(nu_k)
+        assert abs(hg[k] - q_o[0]) <= 1e-9 * n_s, k
+        step = R.symmetrise({D: nu_k[D] + g_o[D] / math.sqrt(k + 1.0) for D in nu_k})
+        assert max_pair_err(P.to_dense(after), R.to_pairs(step)) < 1e-10, k
+    # best-iterate bookkeeping: q_best is the running max of q^k, and nu_best is the
+    # iterate that produced it (re-evaluated by the oracle)
+    assert qb.item() == hg.max()
+    q_nb, _ = R.subgrad(R.from_pairs(P.to_dense(nb)))
+    assert abs(q_nb[0] - qb.item()) <= 1e-9 * n_s
+    assert -23.0 <= qb.item() <= -16.146050955496804
+    assert qb.item() > -17.19
+
+
+NEST = {
+    "tfim8_complex": (lambda: W.tfim_chain(8, 1.0, 0.7), [(1.0, 30), (4.0, 30)]),
+    "randchain_Y3": (lambda: W.random_chain(7, seed=5, top_len=3, subintervals=True), [(1.0, 25), (3.0, 25)]),
+    "plaq_batch": (lambda: W.tfim_plaquette_batch([3, 4], [1.0, 2.5]), [(2.0, 40)]),
+    "xxz_tri3": (lambda: W.xxz_triangular(3, 0.5, seed=2), [(4.0, 40)]),
+}
+
+
+@pytest.mark.parametrize("name", list(NEST))
+def test_nesterov_plain_fp64(name):
+    lrh = lrhmod()
+    say(f"[nesterov fp64] {name}")
+    mk, sched = NEST[name]
+    d = mk()
+    P = lrh.Problem(d, 0)
+    R = O.Relaxation(d)
+    nu = P.zeros()
+    ze = P.zeros()
+    for beta, K in sched:
+        st = P.new_nesterov_state(beta, R.lipschitz(beta))
+        P.step_nesterov(nu, ze, st, K)
+    torch.cuda.synchronize()
+    ref = O.nesterov(R, sched)
+    assert max_pair_err(P.to_dense(nu), R.to_pairs(ref)) < 1e-9
+    q, _, _ = P.certify(nu)
+    torch.cuda.synchronize()
+    assert np.all(np.abs(q.cpu().numpy() - R.Q(ref)) <= 1e-9 * sites_per_instance(d))
+
+
+@pytest.mark.parametrize("f32", [False, True])
+@pytest.mark.parametrize("name", ["heis_field", "tfim_complex"])
+def test_fused_equals_plain_bitwise(name, f32):
+    """The fused single-launch iteration (graph-replayed) performs the same arithmetic as the
+    plain two-kernel iteration: identical bits, across graph chunks and a remainder."""
+    lrh = lrhmod()
+    say(f"[fused==plain] {name} f32={f32}")
+    d = (W.heisenberg_chain(12, field_x=0.5) if name == "heis_field"
+         else W.tfim_chain(10, 1.0, 0.9, complex_storage=True))
+    P = lrh.Problem(d, 0)
+    res = []
+    for fused in (False, True):
+        nu = P.zeros(f32)
+        ze = P.zeros(f32)
+        for beta, K in [(1.0, 70), (2.0, 64), (4.0, 3)]:
+            st = P.new_nesterov_state(beta)
+            P.step_nesterov(nu, ze, st, K, fused=fused)
+        torch.cuda.synchronize()
+        res.append((nu.clone(), ze.clone()))
+    assert torch.equal(res[0][0], res[1][0])
+    assert torch.equal(res[0][1], res[1][1])
+    assert float(res[0][0].abs().max()) > 1e-3
+
+
+def test_heisenberg_32x32_fp32_fused_certified():
+    """The 32x32 Heisenberg workload, FP32 fused iterations with beta doubling 1 -> 1024 over
+    5000 iterations, FP64 certification: the certified bound equals the closed form -6144
+    (singlets on every bond) to 1e-6 per site, and the oracle agrees at the same messages."""
+    lrh = lrhmod()
+    say("[c2 full] fp32 fused 5000 iterations")
+    d = W.workload_c2(32)
+    P = lrh.Problem(d, 0)
+    nu = P.zeros(True)
+    ze = P.zeros(True)
+    for beta, K in lrh.nesterov_schedule(1.0, 1024.0, 5000):
+        st = P.new_nesterov_state(beta)
+        P.step_nesterov(nu, ze, st, K, fused=True)
+    q, mg, _ = P.certify(nu)
+    torch.cuda.synchronize()
+    assert P.check() == (0, 0)
+    bound = q.item() - mg.item()
+    assert abs(bound - (-6144.0)) <= 1e-6 * 1024
+    R = O.Relaxation(d)
+    q_o, _ = R.certify(R.from_pairs(P.to_dense(nu)))
+    assert abs(q.item() - q_o[0]) <= 1e-9 * 1024
+
+
+def test_heisenberg_32x32_fp64_plain_vs_oracle():
+    lrh = lrhmod()
+    say("[c2 full] fp64 plain 20 iterations vs oracle")
+    d = W.workload_c2(32)
+    P = lrh.Problem(d, 0)
+    R = O.Relaxation(d)
+    nu0 = R.draw(5, 0.05)   # start away from the symmetric optimum
+    nu = P.from_dense(R.to_pairs(nu0))
+    ze = P.zeros()
+    st = P.new_nesterov_state(1.0, R.lipschitz(1.0))
+    P.step_nesterov(nu, ze, st, 20)
+    torch.cuda.synchronize()
+    ref = O.nesterov(R, [(1.0, 20)], nu0=nu0)
+    assert max_pair_err(P.to_dense(nu), R.to_pairs(ref)) < 1e-10
+
+
+def test_fp32_fused_vs_fp64_oracle_trajectory():
+    """FP32 fused iterations track the FP64 oracle: certified values within 1e-6 per site."""
+    lrh = lrhmod()
+    say("[fp32 fused vs oracle] tfim chain")
+    d = W.tfim_chain(12, 1.0, 1.0, complex_storage=False)
+    P = lrh.Problem(d, 0)
+    R = O.Relaxation(d)
+    sched = [(1.0, 100), (4.0, 100), (16.0, 100)]
+    nu = P.zeros(True)
+    ze = P.zeros(True)
+    for beta, K in sched:
+        st = P.new_nesterov_state(beta, R.lipschitz(beta))
+        P.step_nesterov(nu, ze, st, K, fused=True)
+    q, _, _ = P.certify(nu)
+    torch.cuda.synchronize()
+    ref = O.nesterov(R, sched)
+    assert abs(q.item() - R.Q(ref)[0]) <= 1e-6 * d.n_sites
+
+
+def test_batched_instances_match_single_instances():
+    lrh = lrhmod()
+    say("[batch] ragged plaquette instances vs single builds")
+    Ls, hs = [3, 4, 5, 3], [0.6, 1.4, 2.2, 3.9]
+    d = W.tfim_plaquette_batch(Ls, hs)
+    P = lrh.Problem(d, 0)
+    nu = P.zeros()
+    ze = P.zeros()
+    st = P.new_nesterov_state(2.0)
+    P.step_nesterov(nu, ze, st, 30)
+    qb, _, _ = P.certify(nu)
+    torch.cuda.synchronize()
+    for i, (L, h) in enumerate(zip(Ls, hs)):
+        di = W.tfim_plaquette_batch([L], [h])
+        Pi = lrh.Problem(di, 0)
+        nui = Pi.zeros()
+        zei = Pi.zeros()
+        sti = Pi.new_nesterov_state(2.0, 2.0 * P.Lambda / 2.0)
+        Pi.step_nesterov(nui, zei, sti, 30)
+        qi, _, _ = Pi.certify(nui)
+        torch.cuda.synchronize()
+        assert abs(qi.item() - qb[i].item()) <= 1e-11 * L * L
+
+
+def test_health_flags():
+    lrh = lrhmod()
+    say("[health] sweep cap and non-finite detection")
+    d = W.random_chain(8, seed=7, top_len=3, subintervals=True)
+    P = lrh.Problem(d, 0)
+    R = O.Relaxation(d)
+    nu = P.from_dense(R.to_pairs(R.draw(1, 0.5)))
+    P.set_jacobi(0)
+    P.certify(nu)
+    with pytest.raises(lrh.LrhError) as e:
+        P.check()
+    assert e.value.code == 5
+    P.set_jacobi(30)
+    P.certify(nu)
+    assert P.check() == (0, 0)
+    bad = nu.clone()
+    bad[3] = float("nan")
+    q, _, _ = P.certify(bad)
+    with pytest.raises(lrh.LrhError) as e:
+        P.check()
+    assert e.value.code == 6
+    assert math.isnan(q.item())
