@@ -28,6 +28,10 @@ TOTAL_ITERS = 5000
 BETA0, BETA_MAX = 1.0, 1024.0
 Q_REF = -6144.0            # closed form: -3 J per bond, 2048 bonds (singlet on every bond)
 HBM_PEAK_GBS = 8000.0
+# HBM-side bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by
+# a 64 MiB copy (profiles/k_cluster_pair_heisenberg32x32_traffic.md), keyed by the hash of the kernel
+# sources they were taken with; reported as null once the sources change.
+TRAFFIC_BYTES = {"f8271996583633e9": 1038336}
 FP32_VALU_PEAK_TFLOPS = 157.3
 
 
@@ -133,6 +137,15 @@ def algorithmic_work(P):
     return B, F
 
 
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("lrh_kernels.hip", "lrh_host.cpp", "lrh_internal.h"):
+        with open(os.path.join(ROOT, "paper_2609_40336_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def cpu_baseline(desc, budget_s=15.0):
     """The FP64 oracle, untuned, on one core: Algorithm 2 iterations of the same workload
     until the time budget is spent (at least 2)."""
@@ -177,6 +190,9 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--profile-traffic", action="store_true",
+                    help="short run for hardware counters: 4 fused graph chunks, then a 64 MiB "
+                         "device copy (a plain copy kernel of known size, for calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the path is single-GPU; --gpus {args.gpus} "
@@ -189,6 +205,16 @@ def main():
     desc = W.workload_c2(32)
     P = lrh.Problem(desc, 0)
     schedule = lrh.nesterov_schedule(BETA0, BETA_MAX, TOTAL_ITERS)
+    if args.profile_traffic:
+        S = Solver(P, True, True, [(BETA0, 10 ** 9)])
+        for _ in range(4):
+            S.run(64)
+        src = torch.ones(16 * 2 ** 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_traffic": "done", "copy_bytes": src.numel() * 4}))
+        return
     print(f"[bench] workload {desc.name}: {P.n_clusters} clusters, {P.n_msgs} messages", file=sys.stderr,
           flush=True)
     fused = timed_solve(P, True, True, args.steps, args.warmup, schedule, torch)
@@ -206,7 +232,7 @@ def main():
     else:
         roof = dict(bound="alu", achieved=F / t_it / 1e12, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = TRAFFIC_BYTES.get(kernel_sources_hash())
     roof["kernel"] = "k_cluster_pair<float,false,MODE_GIBBS> (one fused iteration)"
     roof["per_launch"] = dict(bytes=B, flops=F, seconds=t_it)
     updates = P.n_clusters * fused["iters"]
