@@ -241,13 +241,16 @@ class Relaxation:
         return nu
 
     # ---- theta_e (definition of the local augmented Hamiltonian) -----------------
-    def thetas(self, nu) -> Dict[int, np.ndarray]:
+    def thetas(self, nu, with_h: bool = True, h=None) -> Dict[int, np.ndarray]:
+        """theta_e for every cluster; with_h=False gives the linear part (B nu)_e alone."""
+        hh = self.h if h is None else h
         th = {}
         for D, ids in self.cgroups.items():
             t = np.zeros((len(ids), D, D), dtype=np.complex128)
-            for j, e in enumerate(ids):
-                if int(e) in self.h:
-                    t[j] = self.h[int(e)]
+            if with_h:
+                for j, e in enumerate(ids):
+                    if int(e) in hh:
+                        t[j] = hh[int(e)]
             th[D] = t
         for (dims_e, pos), ms in self.patterns.items():
             De = int(np.prod(dims_e))
@@ -476,3 +479,144 @@ def gibbs_vjp(theta: np.ndarray, beta: float, rho_bar: np.ndarray) -> np.ndarray
     M = U.conj().T @ rho_bar @ U
     out = U @ (G * M) @ U.conj().T + beta * np.real(np.vdot(rho, rho_bar)) * rho
     return herm(out)
+
+
+# --------------------------------------------------------------------------------------
+# parametrised terms and reverse mode (gradient checks of the certified bound)
+# --------------------------------------------------------------------------------------
+
+def term_params(R: Relaxation):
+    """[(cluster id, parameter index, d h_t / d c)] for every parametrised term."""
+    d = R.desc
+    out = []
+    if d.term_param is None:
+        return out
+    for t in range(d.n_terms):
+        p = int(d.term_param[t])
+        if p >= 0:
+            sites, _ = d.term(t)
+            out.append((R.index[sites], p, d.dterm(t)))
+    return out
+
+
+def h_at_params(R: Relaxation, params) -> Dict[int, np.ndarray]:
+    """h_e with every parametrised term h_t = c_p * dh_t/dc moved to the new parameters."""
+    h = {e: v.copy() for e, v in R.h.items()}
+    c0 = R.desc.params
+    for e, p, B in term_params(R):
+        h[e] = h[e] + (params[p] - c0[p]) * B
+    return h
+
+
+def gibbs_vjp_batch(theta: np.ndarray, beta: float, Xbar: np.ndarray) -> np.ndarray:
+    """gibbs_vjp over a stack of clusters."""
+    return np.stack([gibbs_vjp(theta[j], beta, Xbar[j]) for j in range(len(theta))])
+
+
+def dual_vjp(R: Relaxation, nu, beta: float, qbar, gbar=None, params=None):
+    """Cotangents (qbar per instance, gbar per message) of (Q_beta(nu), grad Q_beta(nu)) ->
+    (nu_bar, param_bar).  With B the linear map messages -> augmented Hamiltonians
+    (B nu)_e = -sum_children 1 (x) nu + sum_parents nu, grad Q_beta = B^* rho (chain rule of
+    the Lipschitz lemma), so with Y_e = qbar rho_e + D rho_e[(B gbar)_e]:
+    nu_bar = B^* Y (Y_f - Tr_{e\\f} Y_e) and param_bar_p = sum_t <Y_e(t), dh_t/dc_p>.
+    beta = 0: Q itself, Y_e = qbar mu_e (ground projector), gbar must be None."""
+    h = None if params is None else h_at_params(R, params)
+    th = R.thetas(nu, h=h)
+    if gbar is not None:
+        X = R.thetas(gbar, with_h=False)
+    Y = {}
+    for D, ids in R.cgroups.items():
+        qb = np.asarray(qbar, dtype=np.float64)[R.inst[ids]]
+        if beta > 0:
+            lam, U = np.linalg.eigh(th[D])
+            w = np.exp(-beta * (lam - lam[:, :1]))
+            p = w / w.sum(axis=1, keepdims=True)
+            rho = herm(np.einsum('nik,nk,njk->nij', U, p, U.conj()))
+            Yd = qb[:, None, None] * rho
+            if gbar is not None:
+                Yd = Yd + gibbs_vjp_batch(th[D], beta, X[D])
+        else:
+            if gbar is not None:
+                raise ValueError("the subgradient has no derivative: gbar must be None at beta = 0")
+            lam, U = np.linalg.eigh(th[D])
+            tau = 1e-9 * np.maximum(1.0, np.linalg.norm(th[D], axis=(1, 2)))
+            sel = (lam <= lam[:, :1] + tau[:, None]).astype(np.float64)
+            mu = herm(np.einsum('nik,nk,njk->nij', U, sel / sel.sum(axis=1, keepdims=True), U.conj()))
+            Yd = qb[:, None, None] * mu
+        Y[D] = Yd
+    nu_bar = R._grad_from_marginals(Y)
+    npar = 0 if R.desc.params is None else len(R.desc.params)
+    pbar = np.zeros(npar)
+    for e, p, B in term_params(R):
+        D = int(R.D[e])
+        pbar[p] += float(np.real(np.vdot(Y[D][R.cslot[e]], B)))
+    return nu_bar, pbar
+
+
+def unrolled_bound(R: Relaxation, beta: float, T: int, params=None, nu0=None, L=None):
+    """B_T = Q(nu^T) per instance, nu^T = T steps of Algorithm 2 at fixed beta from nu0
+    (zeta0 = nu0, theta0 = 1), everything at parameters `params`."""
+    h = None if params is None else h_at_params(R, params)
+    L = R.lipschitz(beta) if L is None else L
+    nu = R.zeros() if nu0 is None else R.copy(nu0)
+    ze = R.copy(nu)
+    th = 1.0
+    for _ in range(T):
+        eta = R.axpby(1.0 - th, nu, th, ze)
+        g = _grad_beta_h(R, eta, beta, h)
+        ze = R.symmetrise({k: ze[k] + g[k] / (th * L) for k in ze})
+        nu = R.symmetrise(R.axpby(1.0 - th, nu, th, ze))
+        th = theta_next(th)
+    lm = {D: np.linalg.eigvalsh(t)[:, 0] for D, t in R.thetas(nu, h=h).items()}
+    return R._per_instance(lm), nu
+
+
+def _grad_beta_h(R, eta, beta, h):
+    th = R.thetas(eta, h=h)
+    rho = {}
+    for D, t in th.items():
+        lam, U = np.linalg.eigh(t)
+        w = np.exp(-beta * (lam - lam[:, :1]))
+        p = w / w.sum(axis=1, keepdims=True)
+        rho[D] = herm(np.einsum('nik,nk,njk->nij', U, p, U.conj()))
+    return R._grad_from_marginals(rho)
+
+
+def unrolled_bound_grad(R: Relaxation, beta: float, T: int, params=None, nu0=None, qbar=None, L=None):
+    """Reverse mode through `unrolled_bound`: returns (B_T, d<qbar, B_T>/d params, d/d nu0).
+
+    Backward of one step (eta = (1-th) nu + th ze; g = grad Q_beta(eta); ze' = ze + g/(th L);
+    nu' = (1-th) nu + th ze') with cotangents (a, b) of (nu', ze'):
+        b_tot = b + th a;  g_bar = b_tot / (th L);  (eta_bar, c_bar) = VJP of g at eta;
+        a <- (1-th)(a + eta_bar);  b <- b_tot + th eta_bar.
+    At the start of the stage zeta0 = nu0, so nu0_bar = a + b."""
+    L = R.lipschitz(beta) if L is None else L
+    h = None if params is None else h_at_params(R, params)
+    qbar = np.ones(R.n_inst) if qbar is None else np.asarray(qbar, dtype=np.float64)
+    nu = R.zeros() if nu0 is None else R.copy(nu0)
+    ze = R.copy(nu)
+    th = 1.0
+    etas, ths = [], []
+    for _ in range(T):
+        eta = R.axpby(1.0 - th, nu, th, ze)
+        etas.append(eta)
+        ths.append(th)
+        g = _grad_beta_h(R, eta, beta, h)
+        ze = R.symmetrise({k: ze[k] + g[k] / (th * L) for k in ze})
+        nu = R.symmetrise(R.axpby(1.0 - th, nu, th, ze))
+        th = theta_next(th)
+    lm = {D: np.linalg.eigvalsh(t)[:, 0] for D, t in R.thetas(nu, h=h).items()}
+    bound = R._per_instance(lm)
+    a, cbar = dual_vjp(R, nu, 0.0, qbar, None, params)
+    b = R.zeros()
+    zero_q = np.zeros(R.n_inst)
+    for k in range(T - 1, -1, -1):
+        th = ths[k]
+        btot = R.axpby(1.0, b, th, a)
+        gbar = {D: v / (th * L) for D, v in btot.items()}
+        etabar, cb = dual_vjp(R, etas[k], beta, zero_q, gbar, params)
+        cbar = cbar + cb
+        a = {D: (1.0 - th) * (a[D] + etabar[D]) for D in a}
+        b = R.axpby(1.0, btot, th, etabar)
+    nu0bar = R.axpby(1.0, a, 1.0, b)
+    return bound, cbar, nu0bar

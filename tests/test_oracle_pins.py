@@ -474,3 +474,64 @@ def test_interval_hierarchy_monotone_and_exact_at_full_length():
     for a, c in zip(vals, vals[1:]):
         assert c >= a - 2e-3
     assert vals[-1] == pytest.approx(E0, abs=5e-3)
+
+
+# ------------------------------------------------------------------------------------------
+# reverse mode (gradient of the certified bound with respect to couplings)
+# ------------------------------------------------------------------------------------------
+
+def test_unrolled_bound_gradient_zero_steps_is_hellmann_feynman():
+    """T = 0: B_0 = Anderson bound = sum_e J_e lambda_min(XX+YY+Delta ZZ); each bond's
+    derivative is lambda_min(XX+YY+Delta ZZ) = -(2 + Delta)."""
+    d = W.xxz_triangular(3, 0.5, seed=5)
+    R = O.Relaxation(d)
+    B, cb, _ = O.unrolled_bound_grad(R, 4.0, 0)
+    np.testing.assert_allclose(cb, -2.5, atol=1e-12)
+    assert B[0] == pytest.approx(-2.5 * d.params.sum(), abs=1e-10)
+
+
+@pytest.mark.parametrize("T", [3, 8])
+def test_unrolled_bound_gradient_matches_central_differences(T):
+    d = W.xxz_triangular(3, 0.5, seed=5, n_bonds=5)
+    R = O.Relaxation(d)
+    _, cb, _ = O.unrolled_bound_grad(R, 4.0, T)
+    c0 = d.params.copy()
+    h = 1e-6
+    for p in d.meta["bonds"]:
+        cp, cm = c0.copy(), c0.copy()
+        cp[p] += h
+        cm[p] -= h
+        fd = (O.unrolled_bound(R, 4.0, T, cp)[0][0] - O.unrolled_bound(R, 4.0, T, cm)[0][0]) / (2 * h)
+        assert cb[p] == pytest.approx(fd, abs=1e-7)
+
+
+def test_unrolled_bound_gradient_wrt_initial_messages():
+    d = W.random_chain(5, seed=3)
+    R = O.Relaxation(d)
+    nu0 = R.draw(1, 0.3)
+    _, _, n0b = O.unrolled_bound_grad(R, 2.0, 5, nu0=nu0)
+    X = R.draw(2, 1.0)
+    t = 1e-6
+    fp = O.unrolled_bound(R, 2.0, 5, nu0=R.axpby(1, nu0, t, X))[0][0]
+    fm = O.unrolled_bound(R, 2.0, 5, nu0=R.axpby(1, nu0, -t, X))[0][0]
+    assert (fp - fm) / (2 * t) == pytest.approx(_inner(R, n0b, X), abs=1e-7)
+
+
+def test_dual_vjp_is_the_transposed_hessian():
+    """<gbar, d grad Q_beta[X]> = <VJP(gbar), X> and the qbar part is qbar * grad."""
+    d = W.random_chain(5, seed=7, top_len=3, subintervals=True)
+    R = O.Relaxation(d)
+    beta = 1.3
+    nu = R.draw(3, 0.4)
+    gbar = R.draw(4, 1.0)
+    X = R.draw(5, 1.0)
+    vb, _ = O.dual_vjp(R, nu, beta, np.zeros(1), gbar)
+    t = 1e-6
+    _, gp = R.grad_beta(R.axpby(1, nu, t, X), beta)
+    _, gm = R.grad_beta(R.axpby(1, nu, -t, X), beta)
+    fd = (_inner(R, gbar, gp) - _inner(R, gbar, gm)) / (2 * t)
+    assert fd == pytest.approx(_inner(R, vb, X), abs=1e-7)
+    vq, _ = O.dual_vjp(R, nu, beta, np.array([2.5]), None)
+    _, g = R.grad_beta(nu, beta)
+    for k in g:
+        np.testing.assert_allclose(vq[k], 2.5 * g[k], atol=1e-13)
