@@ -60,6 +60,10 @@ typedef enum {
 #define LRH_FUSED  0x2u   /* fused iteration: one launch per iteration (message update of
                              the previous step folded into the cluster kernel), replayed
                              from a captured HIP graph                                     */
+#define LRH_PACKED_COTANGENT 0x4u  /* message cotangents (gbar in, nu_bar out) are taken with
+                             respect to the packed storage components instead of the
+                             Frobenius inner product of the Hermitian matrices (they differ by
+                             a factor 2 on off-diagonal components)                        */
 
 typedef struct lrh_problem_s* lrh_problem;   /* opaque; owned by the library */
 
@@ -87,6 +91,15 @@ typedef struct {
   const int32_t* top_sites;
   const int32_t* site_instance;   /* [n_sites] or NULL                                   */
   uint32_t flags;                 /* LRH_SUBINTERVALS                                    */
+  /* Optional linear parametrisation of terms (for gradients with respect to couplings):
+   * term t with term_param[t] = p >= 0 is h_t(c) = h_t + (c_p - params[p]) * dterm_t, with
+   * dterm_t = d h_t / d c_p stored like the terms (term_off, dterm_im NULL for a real
+   * problem).  n_params = 0 and NULL pointers: no parameters. */
+  int32_t n_params;
+  const int32_t* term_param;      /* [n_terms], -1: constant term                       */
+  const double* dterm_re;
+  const double* dterm_im;
+  const double* params;           /* [n_params] values the term blocks were given at    */
 } lrh_problem_desc;
 
 #define LRH_MAX_BUCKETS 8
@@ -107,6 +120,7 @@ typedef struct {
   double Lambda_G;                         /* Lipschitz factor: L = beta * Lambda_G / 2 */
   double Gamma_G;                          /* sum_e log D_e (smoothing-error lemma)     */
   int32_t max_sweeps;                      /* Jacobi sweep cap in use                   */
+  int32_t n_params;                        /* parameters of the term parametrisation    */
 } lrh_layout;
 
 /* Build the cluster poset, message layout and device-resident problem data on HIP
@@ -187,6 +201,40 @@ lrh_status lrh_step_nesterov(lrh_problem p, void* nu, void* zeta, lrh_nesterov_s
  * Errors: LRH_E_INVALID (null nu/q/margin). */
 lrh_status lrh_certify(lrh_problem p, const void* nu, uint32_t flags, double* q_dev,
                        double* margin_dev, double* lmin_dev, hipStream_t stream);
+
+/* Move the parametrised terms to new parameter values (device double[n_params]):
+ * h_e = sum of the constant terms + sum_t params[p_t] * dterm_t, recomputed on the device.
+ * Errors: LRH_E_INVALID (no parameters, null pointer). */
+lrh_status lrh_set_params(lrh_problem p, const double* params_dev, hipStream_t stream);
+
+/* Adjoint of lrh_dual_eval (FP64): cotangents qbar (device double[n_instances], NULL = 0) of
+ * the per-instance dual values and gbar (device, nu_len doubles, NULL = 0) of the gradient
+ * are pulled back to the messages and to the parameters:
+ *   Y_e = qbar rho_e + D rho_e[(B gbar)_e],  nu_bar = B^* Y = Y_f - Tr_{e\f} Y_e,
+ *   param_bar[p] = sum over the parameter's terms of <Y_e, dterm_t>,
+ * with B the linear map from messages to augmented Hamiltonians (grad Q_beta = B^* rho,
+ * Sec. 4.1.2 / Lipschitz lemma) and D rho the Daleckii-Krein derivative of the Gibbs state.
+ * beta == 0 differentiates Q itself with the ground projector (gbar must be NULL).
+ * nu_bar_dev: device, nu_len doubles (or NULL); param_bar_dev: device double[n_params] or NULL.
+ * flags: LRH_PACKED_COTANGENT; LRH_F32 is not supported (LRH_E_UNSUPPORTED), nor complex
+ * clusters with D_e = 64.
+ * Errors: LRH_E_INVALID (null nu, beta < 0, gbar with beta == 0). */
+lrh_status lrh_dual_vjp(lrh_problem p, const void* nu, uint32_t flags, double beta, const double* qbar_dev,
+                        const void* gbar_dev, void* nu_bar_dev, double* param_bar_dev, hipStream_t stream);
+
+/* Certified value after T accelerated steps and its gradient (FP64):
+ *   B_T = Q(nu^T) per instance, nu^T = T steps of Algorithm 2 at fixed beta and Lipschitz L
+ *   from nu0 (zeta0 = nu0, theta0 = 1; nu0 == NULL: zero messages),
+ * and the reverse-mode derivative of sum_i qbar_i B_T,i (qbar NULL: all ones) with respect to
+ * the parameters (param_bar_dev, double[n_params]) and to nu0 (nu0_bar_dev, nu_len doubles,
+ * LRH_PACKED_COTANGENT applies).  The forward pass keeps every extrapolated point (T * nu_len
+ * doubles of workspace); each reverse step is one lrh_dual_vjp at that point.  The rounding
+ * margin of lrh_certify is not included in B_T.
+ * Errors: LRH_E_INVALID (beta <= 0, L <= 0, T < 0, null bound_dev), LRH_E_UNSUPPORTED as for
+ * lrh_dual_vjp. */
+lrh_status lrh_unrolled_bound_grad(lrh_problem p, const double* nu0_dev, double beta, double L, int32_t T,
+                                   const double* qbar_dev, double* bound_dev, double* param_bar_dev,
+                                   double* nu0_bar_dev, uint32_t flags, hipStream_t stream);
 
 /* Synchronise `stream` and report the eigen-solver health flags accumulated since the
  * last lrh_check: *noconv = clusters that hit the sweep cap, *nonfinite = clusters with

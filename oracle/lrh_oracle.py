@@ -509,8 +509,20 @@ def h_at_params(R: Relaxation, params) -> Dict[int, np.ndarray]:
 
 
 def gibbs_vjp_batch(theta: np.ndarray, beta: float, Xbar: np.ndarray) -> np.ndarray:
-    """gibbs_vjp over a stack of clusters."""
-    return np.stack([gibbs_vjp(theta[j], beta, Xbar[j]) for j in range(len(theta))])
+    """gibbs_vjp over a stack of clusters (the same formula with a leading batch axis)."""
+    lam, U = np.linalg.eigh(theta)
+    w = np.exp(-beta * (lam - lam[:, :1]))
+    p = w / w.sum(axis=1, keepdims=True)
+    la, lb = lam[:, :, None], lam[:, None, :]
+    p_lo = np.where(la <= lb, p[:, :, None], p[:, None, :])
+    dl = np.abs(la - lb)
+    safe = np.where(dl == 0.0, 1.0, dl)
+    G = np.where(dl == 0.0, -beta * p_lo, p_lo * np.expm1(-beta * dl) / safe)
+    rho = np.einsum('nik,nk,njk->nij', U, p, U.conj())
+    M = np.einsum('nki,nkl,nlj->nij', U.conj(), Xbar, U)
+    out = np.einsum('nik,nkl,njl->nij', U, G * M, U.conj())
+    rx = np.real(np.einsum('nij,nij->n', rho.conj(), Xbar))
+    return herm(out + beta * rx[:, None, None] * rho)
 
 
 def dual_vjp(R: Relaxation, nu, beta: float, qbar, gbar=None, params=None):

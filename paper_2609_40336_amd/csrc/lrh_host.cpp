@@ -132,11 +132,26 @@ struct lrh_problem_s {
   int32_t* improved = nullptr;
   double* nu64_tmp = nullptr;            // widened copy of a float nu for certify
   FusedParams* fp = nullptr;             // [kFusedTableMax]
+  // ---- parametrised terms (adjoint) ----
+  int64_t n_params = 0;
+  double* hfix = nullptr;                // h without the parametrised parts, packed like h
+  double* dterm = nullptr;               // packed d h_t / d c blocks
+  int64_t n_pc = 0;                      // clusters carrying parametrised terms (CSR)
+  int64_t *pc_hoff = nullptr, *pc_ptr = nullptr, *pc_doff = nullptr;
+  int32_t *pc_param = nullptr, *pc_ncomp = nullptr;
+  int64_t *pp_ptr = nullptr, *pp_yoff = nullptr, *pp_doff = nullptr;  // parameters -> terms (CSR)
+  int32_t* pp_D = nullptr;
+  int32_t* cinst = nullptr;              // instance of every library cluster
+  double* ywork = nullptr;               // per-cluster cotangent Y (marg layout)
+  double* ones = nullptr;                // [n_inst] of 1.0
+  std::vector<double*> adj_ws;           // reverse-mode workspace
+  int64_t adj_T = -1;
   Work<float> w32;
   Work<double> w64;
   hipStream_t cap_stream = nullptr;
   std::map<GraphKey, hipGraphExec_t> graphs;
   std::vector<void*> allocs;
+  std::vector<int32_t> pp_tmp_g;
 
   ~lrh_problem_s() {
     if (host_only) return;
@@ -504,6 +519,76 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
         for (int j = i + 1; j < D; ++j) hpack.push_back(0.5 * (H[i * D + j].imag() - H[j * D + i].imag()));
   }
 
+  // ---- parametrised terms ----
+  std::vector<double> hfix_pack, dterm_pack;
+  std::vector<int64_t> pc_hoff, pc_ptr, pc_doff, pp_ptr, pp_yoff, pp_doff;
+  std::vector<int32_t> pc_param, pc_ncomp, pp_D;
+  if (d->n_params < 0) return fail(LRH_E_INVALID, "negative n_params");
+  P->n_params = d->n_params;
+  if (d->n_params > 0) {
+    if (!d->term_param || !d->dterm_re || !d->params) return fail(LRH_E_INVALID, "null parameter arrays");
+    if (P->cplx != (d->dterm_im != nullptr)) return fail(LRH_E_INVALID, "dterm_im must match term_im");
+    hfix_pack = hpack;
+    struct PT { int32_t g; int32_t p; int32_t t; int64_t doff; };
+    std::vector<PT> pts;
+    for (int t = 0; t < d->n_terms; ++t) {
+      const int32_t pidx = d->term_param[t];
+      if (pidx < 0) continue;
+      if (pidx >= d->n_params) return fail(LRH_E_INVALID, "term_param out of range");
+      const int32_t g = gid_of[term_cluster[t]];
+      const int D = P->c_D[g];
+      const double* re = d->dterm_re + d->term_off[t];
+      const double* im = d->dterm_im ? d->dterm_im + d->term_off[t] : nullptr;
+      for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) {
+          std::complex<double> a(re[i * D + j], im ? im[i * D + j] : 0.0);
+          std::complex<double> b(re[j * D + i], im ? -im[j * D + i] : 0.0);
+          if (std::abs(a - b) > 1e-12 * std::max(1.0, std::abs(a))) return fail(LRH_E_INVALID, "dterm is not Hermitian");
+        }
+      const int64_t doff = (int64_t)dterm_pack.size();
+      for (int i = 0; i < D; ++i)
+        for (int j = i; j < D; ++j) dterm_pack.push_back(0.5 * (re[i * D + j] + re[j * D + i]));
+      if (P->cplx)
+        for (int i = 0; i < D; ++i)
+          for (int j = i + 1; j < D; ++j) dterm_pack.push_back(0.5 * (im[i * D + j] - im[j * D + i]));
+      // constant part of the cluster: subtract params[p] * dterm
+      const int64_t ho = h_hoff[cb_of[g]][pos_in_cb[g]];
+      const int nco = comps_of(D, P->cplx);
+      for (int k = 0; k < nco; ++k) hfix_pack[ho + k] -= d->params[pidx] * dterm_pack[doff + k];
+      pts.push_back({g, pidx, t, doff});
+    }
+    // clusters -> terms
+    std::vector<PT> byc = pts;
+    std::stable_sort(byc.begin(), byc.end(), [](const PT& a, const PT& b) { return a.g < b.g; });
+    for (size_t i = 0; i < byc.size(); ++i) {
+      if (i == 0 || byc[i].g != byc[i - 1].g) {
+        pc_ptr.push_back((int64_t)i);
+        const int32_t g = byc[i].g;
+        pc_hoff.push_back(h_hoff[cb_of[g]][pos_in_cb[g]]);
+        pc_ncomp.push_back(comps_of(P->c_D[g], P->cplx));
+      }
+      pc_param.push_back(byc[i].p);
+      pc_doff.push_back(byc[i].doff);
+    }
+    pc_ptr.push_back((int64_t)byc.size());
+    P->n_pc = (int64_t)pc_hoff.size();
+    // parameters -> terms
+    std::vector<PT> byp = pts;
+    std::stable_sort(byp.begin(), byp.end(), [](const PT& a, const PT& b) { return a.p < b.p; });
+    pp_ptr.assign(d->n_params + 1, 0);
+    for (auto& x : byp) pp_ptr[x.p + 1]++;
+    for (int q = 0; q < d->n_params; ++q) pp_ptr[q + 1] += pp_ptr[q];
+    for (auto& x : byp) {
+      pp_doff.push_back(x.doff);
+      pp_D.push_back(P->c_D[x.g]);
+      pp_yoff.push_back(-1);  // filled below once marginal offsets are known
+    }
+    // remember the cluster of each entry for the Y offset
+    std::vector<int32_t> pp_g;
+    for (auto& x : byp) pp_g.push_back(x.g);
+    P->pp_tmp_g.swap(pp_g);
+  }
+
   // ---- per-instance cluster ranges, marginal offsets ----
   std::vector<int64_t> inst_ptr(n_inst + 1, 0);
   for (int64_t g = 0; g < nc; ++g) inst_ptr[P->c_inst[g] + 1]++;
@@ -515,6 +600,7 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
     moff += comps_of(P->c_D[g], P->cplx);
   }
   P->marg_len = moff;
+  for (size_t i = 0; i < pp_yoff.size(); ++i) pp_yoff[i] = marg_off[P->pp_tmp_g[i]];
 
   // ---- Lipschitz factor Lambda_G and Gamma_G ----
   bool two_local = true;
@@ -574,6 +660,20 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
   if (hpack.empty()) hpack.push_back(0.0);
   UP(P->h, hpack);
   UP(P->inst_ptr, inst_ptr);
+  UP(P->cinst, P->c_inst);
+  if (P->n_params > 0) {
+    UP(P->hfix, hfix_pack);
+    UP(P->dterm, dterm_pack);
+    UP(P->pc_hoff, pc_hoff);
+    UP(P->pc_ptr, pc_ptr);
+    UP(P->pc_param, pc_param);
+    UP(P->pc_doff, pc_doff);
+    UP(P->pc_ncomp, pc_ncomp);
+    UP(P->pp_ptr, pp_ptr);
+    UP(P->pp_yoff, pp_yoff);
+    UP(P->pp_doff, pp_doff);
+    UP(P->pp_D, pp_D);
+  }
   UP(P->marg_off, marg_off);
   st = P->dalloc(&P->scal, nc);
   if (st != LRH_OK) return st;
@@ -892,6 +992,138 @@ lrh_status nesterov_t(lrh_problem_s* P, T* nu, T* ze, lrh_nesterov_state* stt, i
   return nesterov_plain<T>(P, nu, ze, stt, n_iter, s);
 }
 
+
+// ------------------------------------------------------------------------------------------
+// adjoint drivers
+// ------------------------------------------------------------------------------------------
+
+lrh_status ensure_adjoint(lrh_problem_s* P) {
+  lrh_status st = ensure_work<double>(P, false);
+  if (st != LRH_OK) return st;
+  if (!P->ywork) {
+    if ((st = P->dalloc(&P->ywork, std::max<int64_t>(P->marg_len, 1))) != LRH_OK) return st;
+    if ((st = P->dalloc(&P->ones, std::max<int64_t>(P->n_inst, 1))) != LRH_OK) return st;
+    std::vector<double> one(std::max<int64_t>(P->n_inst, 1), 1.0);
+    HIP_TRY(hipMemcpy(P->ones, one.data(), one.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  return LRH_OK;
+}
+
+// One VJP pass over every cluster: Y_e into the marginal slots, the partial traces and ywork.
+lrh_status vjp_pass(lrh_problem_s* P, const double* nu, double beta, const double* qbar, const double* gbar,
+                    double gb_offscale, hipStream_t s) {
+  Work<double>& w = P->w64;
+  for (const CBucket& B : P->cb) {
+    ClusterArgs<double> a = base_args<double>(P, B);
+    a.tol = P->tol_override > 0 ? P->tol_override : default_tol<double>();
+    if (B.mb_child >= 0) {
+      const MBucket& M = P->mb[B.mb_child];
+      a.nu_c = nu + M.offset;
+      a.gb_c = gbar ? gbar + M.offset : nullptr;
+      a.Tout = w.Tb[0] + M.offset;
+    }
+    if (B.mb_self >= 0) {
+      const MBucket& M = P->mb[B.mb_self];
+      a.nu_p = nu + M.offset;
+      a.gb_p = gbar ? gbar + M.offset : nullptr;
+      a.R = w.Rb[0] + M.roff;
+    }
+    a.gb_offscale = gb_offscale;
+    a.qbar = qbar;
+    a.cinst = P->cinst;
+    a.marg = P->ywork;
+    a.marg_off = P->marg_off;
+    a.beta = beta;
+    hipError_t e = launch_cluster_vjp(a, P->cplx, beta > 0 ? MODE_GIBBS : MODE_GROUND, s);
+    if (e == hipErrorInvalidValue) return fail(LRH_E_UNSUPPORTED, "adjoint of complex clusters with D_e = 64");
+    HIP_TRY(e);
+  }
+  return LRH_OK;
+}
+
+lrh_status scatter_grad(lrh_problem_s* P, double* out, hipStream_t s) {
+  for (const MBucket& M : P->mb) {
+    MsgArgs<double> a = msg_args<double>(P, M);
+    a.grad = out + M.offset;
+    HIP_TRY(launch_msg<double>(a, MSG_GRAD, 256, s));
+  }
+  return LRH_OK;
+}
+
+lrh_status to_packed(lrh_problem_s* P, double* x, hipStream_t s) {
+  for (const MBucket& M : P->mb) HIP_TRY(launch_scale_offdiag(x + M.offset, M.M, M.D, P->cplx, 2.0, s));
+  return LRH_OK;
+}
+
+lrh_status param_bar(lrh_problem_s* P, double* out, int accumulate, hipStream_t s) {
+  if (!out || P->n_params == 0) return LRH_OK;
+  HIP_TRY(launch_param_bar(out, accumulate, P->n_params, P->pp_ptr, P->pp_yoff, P->pp_doff, P->pp_D, P->ywork,
+                           P->dterm, P->cplx, s));
+  return LRH_OK;
+}
+
+lrh_status unrolled_grad(lrh_problem_s* P, const double* nu0, double beta, double L, int T, const double* qbar,
+                         double* bound, double* pbar, double* nu0bar, bool packed, hipStream_t s) {
+  lrh_status st = ensure_adjoint(P);
+  if (st != LRH_OK) return st;
+  const int64_t n = std::max<int64_t>(P->nu_len, 1);
+  const int64_t need = 7 + (int64_t)T;
+  if ((int64_t)P->adj_ws.size() < need) {
+    for (int64_t i = (int64_t)P->adj_ws.size(); i < need; ++i) {
+      double* b = nullptr;
+      if ((st = P->dalloc(&b, n)) != LRH_OK) return st;
+      P->adj_ws.push_back(b);
+    }
+  }
+  double* nu = P->adj_ws[0];
+  double* ze = P->adj_ws[1];
+  double* a = P->adj_ws[2];
+  double* b = P->adj_ws[3];
+  double* btot = P->adj_ws[4];
+  double* gb = P->adj_ws[5];
+  double* eb = P->adj_ws[6];
+  auto eta = [&](int k) { return P->adj_ws[7 + k]; };
+  if (nu0) HIP_TRY(launch_copy<double>(nu, nu0, P->nu_len, s));
+  else HIP_TRY(hipMemsetAsync(nu, 0, n * sizeof(double), s));
+  HIP_TRY(launch_copy<double>(ze, nu, P->nu_len, s));
+  std::vector<double> ths;
+  double th = 1.0;
+  for (int k = 0; k < T; ++k) {
+    HIP_TRY(launch_extrap<double>(eta(k), nu, ze, th, P->nu_len, s));
+    if ((st = cluster_pass<double>(P, eta(k), nullptr, 0.0, MODE_GIBBS, beta, nullptr, s)) != LRH_OK) return st;
+    for (const MBucket& M : P->mb) {
+      MsgArgs<double> m = msg_args<double>(P, M);
+      m.nu = nu + M.offset;
+      m.ze = ze + M.offset;
+      m.theta = th;
+      m.inv_thL = 1.0 / (th * L);
+      HIP_TRY(launch_msg<double>(m, MSG_NESTEROV, 256, s));
+    }
+    ths.push_back(th);
+    th = theta_next(th);
+  }
+  // B_T = Q(nu^T) and its cotangent
+  if ((st = cluster_pass<double>(P, nu, nullptr, 0.0, MODE_GROUND, 0.0, nullptr, s)) != LRH_OK) return st;
+  HIP_TRY(launch_reduce(P->scal, P->inst_ptr, P->n_inst, bound, nullptr, nullptr, nullptr, nullptr, nullptr, s));
+  const double* qb = qbar ? qbar : P->ones;
+  if ((st = vjp_pass(P, nu, 0.0, qb, nullptr, 1.0, s)) != LRH_OK) return st;
+  if ((st = scatter_grad(P, a, s)) != LRH_OK) return st;
+  if ((st = param_bar(P, pbar, 0, s)) != LRH_OK) return st;
+  HIP_TRY(hipMemsetAsync(b, 0, n * sizeof(double), s));
+  for (int k = T - 1; k >= 0; --k) {
+    const double t = ths[k];
+    HIP_TRY(launch_adj_pre(a, b, btot, gb, t, 1.0 / (t * L), P->nu_len, s));
+    if ((st = vjp_pass(P, eta(k), beta, nullptr, gb, 1.0, s)) != LRH_OK) return st;
+    if ((st = scatter_grad(P, eb, s)) != LRH_OK) return st;
+    if ((st = param_bar(P, pbar, 1, s)) != LRH_OK) return st;
+    HIP_TRY(launch_adj_post(a, b, btot, eb, t, P->nu_len, s));
+  }
+  if (nu0bar) {
+    HIP_TRY(launch_adj_pre(a, b, nu0bar, gb, 1.0, 0.0, P->nu_len, s));  // nu0_bar = a + b
+    if (packed && (st = to_packed(P, nu0bar, s)) != LRH_OK) return st;
+  }
+  return LRH_OK;
+}
 }  // namespace
 
 // ------------------------------------------------------------------------------------------
@@ -950,6 +1182,7 @@ lrh_status lrh_query(lrh_problem p, lrh_layout* out) {
   out->Lambda_G = p->Lambda;
   out->Gamma_G = p->Gamma;
   out->max_sweeps = p->max_sweeps;
+  out->n_params = (int32_t)p->n_params;
   return LRH_OK;
 }
 
@@ -1037,6 +1270,49 @@ lrh_status lrh_certify(lrh_problem p, const void* nu, uint32_t flags, double* q_
                         stream));
   if (lmin_dev) HIP_TRY(launch_copy<double>(lmin_dev, p->scal, p->n_clusters, stream));
   return LRH_OK;
+}
+
+lrh_status lrh_set_params(lrh_problem p, const double* params_dev, hipStream_t stream) {
+  if (!p || !params_dev) return fail(LRH_E_INVALID, "null argument");
+  if (p->host_only) return fail(LRH_E_INVALID, "problem was built without a device");
+  if (p->n_params == 0) return fail(LRH_E_INVALID, "problem has no parameters");
+  DeviceGuard guard(p->device);
+  HIP_TRY(launch_set_params(p->h, p->hfix, p->pc_hoff, p->pc_ptr, p->pc_param, p->pc_doff, p->dterm, p->pc_ncomp,
+                            p->n_pc, params_dev, stream));
+  return LRH_OK;
+}
+
+lrh_status lrh_dual_vjp(lrh_problem p, const void* nu, uint32_t flags, double beta, const double* qbar_dev,
+                        const void* gbar_dev, void* nu_bar_dev, double* param_bar_dev, hipStream_t stream) {
+  if (!p || !nu) return fail(LRH_E_INVALID, "null argument");
+  if (p->host_only) return fail(LRH_E_INVALID, "problem was built without a device");
+  if (!(beta >= 0.0)) return fail(LRH_E_INVALID, "beta must be >= 0");
+  if (beta == 0.0 && gbar_dev) return fail(LRH_E_INVALID, "the subgradient has no derivative (gbar with beta = 0)");
+  if (flags & LRH_F32) return fail(LRH_E_UNSUPPORTED, "the adjoint runs in FP64 only");
+  DeviceGuard guard(p->device);
+  lrh_status st = ensure_adjoint(p);
+  if (st != LRH_OK) return st;
+  const bool packed = (flags & LRH_PACKED_COTANGENT) != 0;
+  if ((st = vjp_pass(p, (const double*)nu, beta, qbar_dev, (const double*)gbar_dev, packed ? 0.5 : 1.0, stream)) !=
+      LRH_OK)
+    return st;
+  if (nu_bar_dev) {
+    if ((st = scatter_grad(p, (double*)nu_bar_dev, stream)) != LRH_OK) return st;
+    if (packed && (st = to_packed(p, (double*)nu_bar_dev, stream)) != LRH_OK) return st;
+  }
+  return param_bar(p, param_bar_dev, 0, stream);
+}
+
+lrh_status lrh_unrolled_bound_grad(lrh_problem p, const double* nu0_dev, double beta, double L, int32_t T,
+                                   const double* qbar_dev, double* bound_dev, double* param_bar_dev,
+                                   double* nu0_bar_dev, uint32_t flags, hipStream_t stream) {
+  if (!p || !bound_dev) return fail(LRH_E_INVALID, "null argument");
+  if (p->host_only) return fail(LRH_E_INVALID, "problem was built without a device");
+  if (!(beta > 0.0) || !(L > 0.0) || T < 0) return fail(LRH_E_INVALID, "beta, L must be positive and T >= 0");
+  if (flags & LRH_F32) return fail(LRH_E_UNSUPPORTED, "the adjoint runs in FP64 only");
+  DeviceGuard guard(p->device);
+  return unrolled_grad(p, nu0_dev, beta, L, T, qbar_dev, bound_dev, param_bar_dev, nu0_bar_dev,
+                       (flags & LRH_PACKED_COTANGENT) != 0, stream);
 }
 
 lrh_status lrh_check(lrh_problem p, hipStream_t stream, int64_t* noconv, int64_t* nonfinite) {

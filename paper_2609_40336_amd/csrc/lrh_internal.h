@@ -76,6 +76,11 @@ struct ClusterArgs {
   T* nu_c_new; T* ze_c_new;   // written by the parent (this cluster)
   const T* nu_p_prev; const T* ze_p_prev; const T* Tprev_p; const T* Rprev_p;
   int fused_first;            // 1: iteration 0 of a call, state already current
+  // ---- adjoint (k_cluster_vjp) ----
+  const T* gb_c; const T* gb_p;  // gradient cotangent gbar, child / parent buckets (nullable)
+  double gb_offscale;            // scale of off-diagonal gbar elements (1, or 1/2 for packed coords)
+  const double* qbar;            // [n_inst] cotangent of Q per instance (nullable: 0)
+  const int32_t* cinst;          // [n_clusters] instance of every library cluster
 };
 
 template <typename T>
@@ -109,5 +114,25 @@ hipError_t launch_cluster_pair(const ClusterArgs<T>& edges, const ClusterArgs<T>
                                int mode, int block, hipStream_t s);
 template <typename T>
 hipError_t launch_copy(T* dst, const T* src, int64_t n, hipStream_t s);
+
+// ---- adjoint helpers ----
+hipError_t launch_cluster_vjp(const ClusterArgs<double>& a, bool cplx, int mode, hipStream_t s);
+// h_e = hfix_e + sum_t params[p_t] * dterm_t for the clusters listed in (pc_gid... CSR)
+hipError_t launch_set_params(double* h, const double* hfix, const int64_t* pc_hoff, const int64_t* pc_ptr,
+                             const int32_t* pc_param, const int64_t* pc_doff, const double* dterm,
+                             const int32_t* pc_ncomp, int64_t n_pc, const double* params, hipStream_t s);
+// param_bar[p] (+)= sum over the parameter's terms of <Y_e, dterm_t> (Y per cluster, packed)
+hipError_t launch_param_bar(double* out, int accumulate, int64_t n_params, const int64_t* pp_ptr,
+                            const int64_t* pp_yoff, const int64_t* pp_doff, const int32_t* pp_D, const double* Y,
+                            const double* dterm, bool cplx, hipStream_t s);
+// reverse Nesterov step on message vectors (length n)
+hipError_t launch_adj_pre(const double* a, const double* b, double* btot, double* gbar, double th, double invthL,
+                          int64_t n, hipStream_t s);
+hipError_t launch_adj_post(double* a, double* b, const double* btot, const double* etabar, double th, int64_t n,
+                           hipStream_t s);
+template <typename T>
+hipError_t launch_extrap(T* dst, const T* nu, const T* ze, double th, int64_t n, hipStream_t s);
+// scale the off-diagonal components of every message of a bucket by f
+hipError_t launch_scale_offdiag(double* x, int64_t M, int D, bool cplx, double f, hipStream_t s);
 
 }  // namespace lrh

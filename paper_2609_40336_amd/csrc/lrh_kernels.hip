@@ -490,26 +490,20 @@ __device__ __forceinline__ void herm_elem(Get get, int a, int b, int D, bool cpl
   }
 }
 
-template <typename T, bool CPLX, int DE, int MODE>
-__global__ __launch_bounds__(64) void k_cluster_lds(ClusterArgs<T> A) {
+// ---- shared pieces of the LDS kernels ----
+
+// theta_e = [h_e] - sum_children 1 (x) x_{e->f} + sum_parents x_{g->e}, written to (dr, di) with
+// leading dimension DE+1; x = extrap(nu, zeta, th) when zeta is given.  Off-diagonal message
+// elements are scaled by `offs` (packed-coordinate cotangents use 1/2).  Returns this lane's
+// share of the squared Frobenius norm.
+template <typename T, bool CPLX, int DE>
+__device__ T lds_assemble(const ClusterArgs<T>& A, int64_t c, const T* xc, const T* zc, const T* xp, const T* zp,
+                          T th, bool with_h, T offs, T* dr, T* di) {
   constexpr int LD = DE + 1;
-  constexpr bool VEC = (MODE != MODE_CERTIFY);
-  constexpr int NP = DE / 2;
   constexpr int NB = log2i(DE);
-  __shared__ T sar[DE * LD];
-  __shared__ T sai[CPLX ? DE * LD : 1];
-  __shared__ T sur[VEC ? DE * LD : 1];
-  __shared__ T sui[(VEC && CPLX) ? DE * LD : 1];
-  __shared__ T cs_c[NP], cs_s[NP], cs_er[NP], cs_ei[NP], cs_app[NP], cs_aqq[NP];
-  __shared__ int cs_p[NP], cs_q[NP];
-  __shared__ T sp[DE];
-  const int64_t c = blockIdx.x;
-  if (c >= A.n) return;
   const int tid = threadIdx.x;
-  const T th = (T)A.theta;
-  const int64_t ho = A.hoff[c];
+  const int64_t ho = with_h ? A.hoff[c] : -1;
   const int Dc = A.Dc;
-  // ---- a2: assemble theta_e ----
   T my_n2 = T(0);
   for (int idx = tid; idx < DE * DE; idx += 64) {
     const int i = idx / DE, j = idx % DE;
@@ -525,41 +519,53 @@ __global__ __launch_bounds__(64) void k_cluster_lds(ClusterArgs<T> A) {
       if (((i ^ j) & ~mask & (DE - 1)) != 0) continue;
       const int a = pext_rt(i, mask, NB), b = pext_rt(j, mask, NB);
       T er, ei;
-      if (A.ze_c)
+      if (zc)
         herm_elem<T>([&](int k) { const int64_t o = (int64_t)k * A.Mc + m;
-                                  return extrap<T>(A.nu_c[o], A.ze_c[o], th); }, a, b, Dc, CPLX, er, ei);
+                                  return extrap<T>(xc[o], zc[o], th); }, a, b, Dc, CPLX, er, ei);
       else
-        herm_elem<T>([&](int k) { return A.nu_c[(int64_t)k * A.Mc + m]; }, a, b, Dc, CPLX, er, ei);
-      vr -= er;
-      vi -= ei;
+        herm_elem<T>([&](int k) { return xc[(int64_t)k * A.Mc + m]; }, a, b, Dc, CPLX, er, ei);
+      const T sc = (a == b) ? T(1) : offs;
+      vr -= sc * er;
+      vi -= sc * ei;
     }
     for (int s = 0; s < A.maxpar; ++s) {
       const int m = A.par[(int64_t)s * A.n + c];
       if (m < 0) continue;
       T er, ei;
-      if (A.ze_p)
+      if (zp)
         herm_elem<T>([&](int k) { const int64_t o = (int64_t)k * A.Mp + m;
-                                  return extrap<T>(A.nu_p[o], A.ze_p[o], th); }, i, j, DE, CPLX, er, ei);
+                                  return extrap<T>(xp[o], zp[o], th); }, i, j, DE, CPLX, er, ei);
       else
-        herm_elem<T>([&](int k) { return A.nu_p[(int64_t)k * A.Mp + m]; }, i, j, DE, CPLX, er, ei);
-      vr += er;
-      vi += ei;
+        herm_elem<T>([&](int k) { return xp[(int64_t)k * A.Mp + m]; }, i, j, DE, CPLX, er, ei);
+      const T sc = (i == j) ? T(1) : offs;
+      vr += sc * er;
+      vi += sc * ei;
     }
-    sar[i * LD + j] = vr;
-    if constexpr (CPLX) sai[i * LD + j] = vi;
-    if constexpr (VEC) {
-      sur[i * LD + j] = (i == j) ? T(1) : T(0);
-      if constexpr (CPLX) sui[i * LD + j] = T(0);
-    }
+    dr[i * LD + j] = vr;
+    if constexpr (CPLX) di[i * LD + j] = vi;
     my_n2 = dfma<T>(vr, vr, my_n2);
     if constexpr (CPLX) my_n2 = dfma<T>(vi, vi, my_n2);
   }
-  const T nrm2 = wave_sum(my_n2);
-  __syncthreads();
-  // ---- a3: parallel cyclic Jacobi (round-robin ordering) ----
-  const T tol2 = (T)(A.tol * A.tol) * nrm2;
-  bool conv = false;
-  for (int sweep = 0; sweep <= A.max_sweeps; ++sweep) {
+  return my_n2;
+}
+
+// Rotation scratch of the round-robin parallel Jacobi.
+template <typename T, int NP>
+struct JacobiScratch {
+  T c[NP], s[NP], er[NP], ei[NP], app[NP], aqq[NP];
+  int p[NP], q[NP];
+};
+
+// Cyclic two-sided Jacobi on the LDS matrix (sar, sai) with eigenvectors accumulated in
+// (sur, sui) when VEC.  Each round applies the DE/2 disjoint rotations of a round-robin
+// tournament in parallel: columns (A G, U G), then rows (G^H A), then the exact 2x2 blocks.
+// Returns true when the off-diagonal norm fell below tol2 within max_sweeps sweeps.
+template <typename T, bool CPLX, int DE, bool VEC>
+__device__ bool lds_jacobi(T* sar, T* sai, T* sur, T* sui, JacobiScratch<T, DE / 2>& J, T tol2, int max_sweeps) {
+  constexpr int LD = DE + 1;
+  constexpr int NP = DE / 2;
+  const int tid = threadIdx.x;
+  for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
     T off = T(0);
     for (int idx = tid; idx < DE * DE; idx += 64) {
       const int i = idx / DE, j = idx % DE;
@@ -569,8 +575,8 @@ __global__ __launch_bounds__(64) void k_cluster_lds(ClusterArgs<T> A) {
       }
     }
     off = wave_sum(off);
-    if (off <= tol2) { conv = true; break; }
-    if (sweep == A.max_sweeps) break;
+    if (off <= tol2) return true;
+    if (sweep == max_sweeps) break;
     for (int r = 0; r < DE - 1; ++r) {
       if (tid < NP) {
         int p, q;
@@ -585,17 +591,17 @@ __global__ __launch_bounds__(64) void k_cluster_lds(ClusterArgs<T> A) {
           er = xr / rr;
           ei = CPLX ? -xi / rr : T(0);
         }
-        cs_p[tid] = p; cs_q[tid] = q;
-        cs_c[tid] = cc; cs_s[tid] = ss; cs_er[tid] = er; cs_ei[tid] = ei;
-        cs_app[tid] = app - t * rr;
-        cs_aqq[tid] = aqq + t * rr;
+        J.p[tid] = p; J.q[tid] = q;
+        J.c[tid] = cc; J.s[tid] = ss; J.er[tid] = er; J.ei[tid] = ei;
+        J.app[tid] = app - t * rr;
+        J.aqq[tid] = aqq + t * rr;
       }
       __syncthreads();
       // columns: A <- A G, U <- U G  (w = x_q e^{-i phi})
       for (int idx = tid; idx < DE * NP; idx += 64) {
         const int i = idx % DE, k = idx / DE;
-        const int p = cs_p[k], q = cs_q[k];
-        const T cc = cs_c[k], ss = cs_s[k], er = cs_er[k], ei = cs_ei[k];
+        const int p = J.p[k], q = J.q[k];
+        const T cc = J.c[k], ss = J.s[k], er = J.er[k], ei = J.ei[k];
         {
           T pr = sar[i * LD + p], qr = sar[i * LD + q];
           T pi = CPLX ? sai[i * LD + p] : T(0), qi = CPLX ? sai[i * LD + q] : T(0);
@@ -625,8 +631,8 @@ __global__ __launch_bounds__(64) void k_cluster_lds(ClusterArgs<T> A) {
       // rows: A <- G^H A  (w = x_q e^{+i phi})
       for (int idx = tid; idx < DE * NP; idx += 64) {
         const int j = idx % DE, k = idx / DE;
-        const int p = cs_p[k], q = cs_q[k];
-        const T cc = cs_c[k], ss = cs_s[k], er = cs_er[k], ei = -cs_ei[k];
+        const int p = J.p[k], q = J.q[k];
+        const T cc = J.c[k], ss = J.s[k], er = J.er[k], ei = -J.ei[k];
         T pr = sar[p * LD + j], qr = sar[q * LD + j];
         T pi = CPLX ? sai[p * LD + j] : T(0), qi = CPLX ? sai[q * LD + j] : T(0);
         T wr = CPLX ? qr * er - qi * ei : qr * er;
@@ -640,9 +646,9 @@ __global__ __launch_bounds__(64) void k_cluster_lds(ClusterArgs<T> A) {
       }
       __syncthreads();
       if (tid < NP) {
-        const int p = cs_p[tid], q = cs_q[tid];
-        sar[p * LD + p] = cs_app[tid];
-        sar[q * LD + q] = cs_aqq[tid];
+        const int p = J.p[tid], q = J.q[tid];
+        sar[p * LD + p] = J.app[tid];
+        sar[q * LD + q] = J.aqq[tid];
         sar[p * LD + q] = T(0);
         sar[q * LD + p] = T(0);
         if constexpr (CPLX) {
@@ -653,8 +659,128 @@ __global__ __launch_bounds__(64) void k_cluster_lds(ClusterArgs<T> A) {
       __syncthreads();
     }
   }
+  return false;
+}
+
+// component k of a packed D x D Hermitian -> (i, j, imaginary?)
+__device__ __forceinline__ void decode_comp(int k, int D, int& i, int& j, bool& im) {
+  im = false;
+  i = 0;
+  if (k >= D * (D + 1) / 2) { im = true; k -= D * (D + 1) / 2; }
+  const int rowlen0 = im ? D - 1 : D;
+  while (k >= rowlen0 - i) { k -= rowlen0 - i; ++i; }
+  j = i + k + (im ? 1 : 0);
+}
+
+// Write a cluster matrix Y (LDS) to its consumers: own marginal slot (if it has parents),
+// the per-cluster output buffer, and the partial traces onto every child.
+template <typename T, bool CPLX, int DE>
+__device__ void lds_outputs(const ClusterArgs<T>& A, int64_t c, int32_t gid, const T* yr, const T* yi) {
+  constexpr int LD = DE + 1;
+  constexpr int NB = log2i(DE);
+  const int tid = threadIdx.x;
+  const int64_t rs_self = A.rslot ? A.rslot[c] : -1;
+  constexpr int NCE = n_comps(DE, CPLX);
+  for (int k = tid; k < NCE; k += 64) {
+    int i, j;
+    bool im;
+    decode_comp(k, DE, i, j, im);
+    const T v = im ? yi[i * LD + j] : yr[i * LD + j];
+    if (rs_self >= 0 && A.R) A.R[(int64_t)k * A.S + rs_self] = v;
+    if (A.marg) A.marg[A.marg_off[gid] + k] = v;
+  }
+  const int Dc = A.Dc;
+  if (A.Tout && Dc > 0) {
+    const int NR = DE / Dc;
+    const int NCC = CPLX ? Dc * Dc : Dc * (Dc + 1) / 2;
+    for (int s = 0; s < A.maxch; ++s) {
+      const int m = A.ch[(int64_t)s * A.n + c];
+      if (m < 0) continue;
+      const int mask = A.chmask[(int64_t)s * A.n + c];
+      for (int k = tid; k < NCC; k += 64) {
+        int a, b;
+        bool im;
+        decode_comp(k, Dc, a, b, im);
+        T sum = T(0);
+        for (int x = 0; x < NR; ++x) {
+          const int i = pdep_rt(a, x, mask, NB), j = pdep_rt(b, x, mask, NB);
+          sum += im ? yi[i * LD + j] : yr[i * LD + j];
+        }
+        A.Tout[(int64_t)k * A.Mc + m] = sum;
+      }
+    }
+  }
+}
+
+// Marginal weights from the eigenvalues on the diagonal of sar: Gibbs p (returns F_beta) or the
+// normalised ground-space indicator (returns lambda_min).  Weights go to sp[].
+template <typename T, int DE, int MODE>
+__device__ T lds_weights(const T* sar, T* sp, T lmin, T beta, T tau) {
+  constexpr int LD = DE + 1;
+  const int tid = threadIdx.x;
+  T w = T(0);
+  if constexpr (MODE == MODE_GIBBS) {
+    for (int k = tid; k < DE; k += 64) { T v = dexp<T>(-beta * (sar[k * LD + k] - lmin)); sp[k] = v; w += v; }
+  } else {
+    for (int k = tid; k < DE; k += 64) { T v = (sar[k * LD + k] <= lmin + tau) ? T(1) : T(0); sp[k] = v; w += v; }
+  }
+  const T Z = wave_sum(w);
+  __syncthreads();
+  for (int k = tid; k < DE; k += 64) sp[k] /= Z;
+  __syncthreads();
+  if constexpr (MODE == MODE_GIBBS) return lmin - dlog<T>(Z) / beta;
+  else return lmin;
+}
+
+// (yr, yi) = U diag(sp) U^H
+template <typename T, bool CPLX, int DE>
+__device__ void lds_rebuild(const T* sur, const T* sui, const T* sp, T* yr, T* yi) {
+  constexpr int LD = DE + 1;
+  for (int idx = threadIdx.x; idx < DE * DE; idx += 64) {
+    const int i = idx / DE, j = idx % DE;
+    T sr = T(0), si = T(0);
+    for (int k = 0; k < DE; ++k) {
+      const T a_r = sur[i * LD + k] * sp[k];
+      const T a_i = CPLX ? sui[i * LD + k] * sp[k] : T(0);
+      sr = dfma<T>(a_r, sur[j * LD + k], sr);
+      if constexpr (CPLX) {
+        sr = dfma<T>(a_i, sui[j * LD + k], sr);
+        si = dfma<T>(a_i, sur[j * LD + k], si);
+        si = dfma<T>(-a_r, sui[j * LD + k], si);
+      }
+    }
+    yr[i * LD + j] = sr;
+    if constexpr (CPLX) yi[i * LD + j] = (i == j) ? T(0) : si;
+  }
+}
+
+template <typename T, bool CPLX, int DE, int MODE>
+__global__ __launch_bounds__(64) void k_cluster_lds(ClusterArgs<T> A) {
+  constexpr int LD = DE + 1;
+  constexpr bool VEC = (MODE != MODE_CERTIFY);
+  __shared__ T sar[DE * LD];
+  __shared__ T sai[CPLX ? DE * LD : 1];
+  __shared__ T sur[VEC ? DE * LD : 1];
+  __shared__ T sui[(VEC && CPLX) ? DE * LD : 1];
+  __shared__ JacobiScratch<T, DE / 2> J;
+  __shared__ T sp[DE];
+  const int64_t c = blockIdx.x;
+  if (c >= A.n) return;
+  const int tid = threadIdx.x;
+  // ---- a1/a2: assemble theta_e at eta ----
+  const T nrm2 = wave_sum(lds_assemble<T, CPLX, DE>(A, c, A.nu_c, A.ze_c, A.nu_p, A.ze_p, (T)A.theta, true,
+                                                    T(1), sar, sai));
+  if constexpr (VEC) {
+    for (int idx = tid; idx < DE * DE; idx += 64) {
+      const int i = idx / DE, j = idx % DE;
+      sur[i * LD + j] = (i == j) ? T(1) : T(0);
+      if constexpr (CPLX) sui[i * LD + j] = T(0);
+    }
+  }
+  __syncthreads();
+  // ---- a3: parallel cyclic Jacobi ----
+  const bool conv = lds_jacobi<T, CPLX, DE, VEC>(sar, sai, sur, sui, J, (T)(A.tol * A.tol) * nrm2, A.max_sweeps);
   if (!conv && tid == 0 && A.noconv) atomicAdd(A.noconv, 1ull);
-  // ---- eigenvalues ----
   T lmin = T(INFINITY);
   for (int k = tid; k < DE; k += 64) lmin = fmin(lmin, sar[k * LD + k]);
   lmin = wave_min(lmin);
@@ -667,82 +793,177 @@ __global__ __launch_bounds__(64) void k_cluster_lds(ClusterArgs<T> A) {
     }
     return;
   } else {
-    // ---- a4: weights ----
-    T w = T(0);
-    if constexpr (MODE == MODE_GIBBS) {
-      const T b = (T)A.beta;
-      for (int k = tid; k < DE; k += 64) { T v = dexp<T>(-b * (sar[k * LD + k] - lmin)); sp[k] = v; w += v; }
-      const T Z = wave_sum(w);
-      __syncthreads();
-      for (int k = tid; k < DE; k += 64) sp[k] /= Z;
-      if (tid == 0) A.scal[gid] = (double)(lmin - dlog<T>(Z) / b);
-    } else {
-      const T tau = (T)A.tau_rel * fmax(T(1), dsqrt<T>(nrm2));
-      for (int k = tid; k < DE; k += 64) { T v = (sar[k * LD + k] <= lmin + tau) ? T(1) : T(0); sp[k] = v; w += v; }
-      const T g = wave_sum(w);
-      __syncthreads();
-      for (int k = tid; k < DE; k += 64) sp[k] /= g;
-      if (tid == 0) A.scal[gid] = (double)lmin;
+    // ---- a4: weights and the marginal U diag(p) U^H (over A) ----
+    const T val = lds_weights<T, DE, MODE>(sar, sp, lmin, (T)A.beta,
+                                           (T)A.tau_rel * fmax(T(1), dsqrt<T>(nrm2)));
+    if (tid == 0) A.scal[gid] = (double)val;
+    lds_rebuild<T, CPLX, DE>(sur, sui, sp, sar, sai);
+    __syncthreads();
+    // ---- a5: outputs ----
+    lds_outputs<T, CPLX, DE>(A, c, gid, sar, sai);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// adjoint (a9): VJP of (Q_beta, grad Q_beta) through one cluster
+// ------------------------------------------------------------------------------------------
+//
+// grad Q_beta = B^* rho_beta(B nu + h) with B the linear map from messages to augmented
+// Hamiltonians (chain rule of the Lipschitz lemma, Sec. 4.1.2).  For cotangents qbar (per
+// instance) and gbar (per message) the cluster's cotangent is
+//     Y_e = qbar rho_e + D rho_e[(B gbar)_e],
+// with the Daleckii-Krein derivative of the normalised matrix exponential
+//     D rho[X] = U [Gamma o (U^H X U)] U^H + beta <rho, X> rho,
+//     Gamma_ab = (p_a - p_b)/(l_a - l_b) = p_lo expm1(-beta (l_hi - l_lo)) / (l_hi - l_lo),
+//     Gamma_aa = -beta p_a.
+// nu_bar = B^* Y is then the message kernel's gradient stage (Y_f - Tr_{e\f} Y_e).  At beta = 0
+// the cotangent of Q is Y_e = qbar mu_e (the ground projector; gbar must be absent).
+template <typename T, bool CPLX, int DE, int MODE>
+__global__ __launch_bounds__(64) void k_cluster_vjp(ClusterArgs<T> A) {
+  constexpr int LD = DE + 1;
+  __shared__ T sar[DE * LD];
+  __shared__ T sai[CPLX ? DE * LD : 1];
+  __shared__ T sur[DE * LD];
+  __shared__ T sui[CPLX ? DE * LD : 1];
+  __shared__ T sxr[DE * LD];
+  __shared__ T sxi[CPLX ? DE * LD : 1];
+  __shared__ T str[DE * LD];
+  __shared__ T sti[CPLX ? DE * LD : 1];
+  __shared__ JacobiScratch<T, DE / 2> J;
+  __shared__ T sp[DE];
+  __shared__ T slam[DE];
+  const int64_t c = blockIdx.x;
+  if (c >= A.n) return;
+  const int tid = threadIdx.x;
+  const bool has_g = (A.gb_c != nullptr || A.gb_p != nullptr);
+  const T nrm2 = wave_sum(lds_assemble<T, CPLX, DE>(A, c, A.nu_c, nullptr, A.nu_p, nullptr, T(0), true, T(1),
+                                                    sar, sai));
+  if (has_g) lds_assemble<T, CPLX, DE>(A, c, A.gb_c, nullptr, A.gb_p, nullptr, T(0), false, (T)A.gb_offscale,
+                                       sxr, sxi);
+  for (int idx = tid; idx < DE * DE; idx += 64) {
+    const int i = idx / DE, j = idx % DE;
+    sur[i * LD + j] = (i == j) ? T(1) : T(0);
+    if constexpr (CPLX) sui[i * LD + j] = T(0);
+  }
+  __syncthreads();
+  const bool conv = lds_jacobi<T, CPLX, DE, true>(sar, sai, sur, sui, J, (T)(A.tol * A.tol) * nrm2, A.max_sweeps);
+  if (!conv && tid == 0 && A.noconv) atomicAdd(A.noconv, 1ull);
+  T lmin = T(INFINITY);
+  for (int k = tid; k < DE; k += 64) {
+    slam[k] = sar[k * LD + k];
+    lmin = fmin(lmin, sar[k * LD + k]);
+  }
+  lmin = wave_min(lmin);
+  const T beta = (T)A.beta;
+  lds_weights<T, DE, MODE>(sar, sp, lmin, beta, (T)A.tau_rel * fmax(T(1), dsqrt<T>(nrm2)));
+  // rho (or mu) over A
+  lds_rebuild<T, CPLX, DE>(sur, sui, sp, sar, sai);
+  __syncthreads();
+  const int32_t gid = A.gid[c];
+  const T qb = A.qbar ? (T)A.qbar[A.cinst[gid]] : T(0);
+  if (MODE == MODE_GIBBS && has_g) {
+    // <rho, X>
+    T rx = T(0);
+    for (int idx = tid; idx < DE * DE; idx += 64) {
+      rx = dfma<T>(sar[idx / DE * LD + idx % DE], sxr[idx / DE * LD + idx % DE], rx);
+      if constexpr (CPLX) rx = dfma<T>(sai[idx / DE * LD + idx % DE], sxi[idx / DE * LD + idx % DE], rx);
+    }
+    rx = wave_sum(rx);
+    // Tm = U^H X
+    for (int idx = tid; idx < DE * DE; idx += 64) {
+      const int a = idx / DE, j = idx % DE;
+      T sr = T(0), si = T(0);
+      for (int k = 0; k < DE; ++k) {
+        const T ur = sur[k * LD + a], ui = CPLX ? -sui[k * LD + a] : T(0);  // conj(U_ka)
+        const T xr = sxr[k * LD + j], xi = CPLX ? sxi[k * LD + j] : T(0);
+        sr = dfma<T>(ur, xr, sr);
+        if constexpr (CPLX) {
+          sr = dfma<T>(-ui, xi, sr);
+          si = dfma<T>(ur, xi, si);
+          si = dfma<T>(ui, xr, si);
+        }
+      }
+      str[a * LD + j] = sr;
+      if constexpr (CPLX) sti[a * LD + j] = si;
     }
     __syncthreads();
-    // rho = U diag(p) U^H, written over A
+    // M = (U^H X) U, then Gamma o M (into X)
+    for (int idx = tid; idx < DE * DE; idx += 64) {
+      const int a = idx / DE, b = idx % DE;
+      T sr = T(0), si = T(0);
+      for (int k = 0; k < DE; ++k) {
+        const T tr = str[a * LD + k], ti = CPLX ? sti[a * LD + k] : T(0);
+        const T ur = sur[k * LD + b], ui = CPLX ? sui[k * LD + b] : T(0);
+        sr = dfma<T>(tr, ur, sr);
+        if constexpr (CPLX) {
+          sr = dfma<T>(-ti, ui, sr);
+          si = dfma<T>(tr, ui, si);
+          si = dfma<T>(ti, ur, si);
+        }
+      }
+      const int hi = slam[a] >= slam[b] ? a : b, lo = slam[a] >= slam[b] ? b : a;
+      const T dl = slam[hi] - slam[lo];
+      const T g = (dl == T(0)) ? -beta * sp[lo] : sp[lo] * (T)expm1((double)(-beta * dl)) / dl;
+      sxr[a * LD + b] = g * sr;
+      if constexpr (CPLX) sxi[a * LD + b] = g * si;
+    }
+    __syncthreads();
+    // Tm = U (Gamma o M)
+    for (int idx = tid; idx < DE * DE; idx += 64) {
+      const int i = idx / DE, b = idx % DE;
+      T sr = T(0), si = T(0);
+      for (int k = 0; k < DE; ++k) {
+        const T ur = sur[i * LD + k], ui = CPLX ? sui[i * LD + k] : T(0);
+        const T mr = sxr[k * LD + b], mi = CPLX ? sxi[k * LD + b] : T(0);
+        sr = dfma<T>(ur, mr, sr);
+        if constexpr (CPLX) {
+          sr = dfma<T>(-ui, mi, sr);
+          si = dfma<T>(ur, mi, si);
+          si = dfma<T>(ui, mr, si);
+        }
+      }
+      str[i * LD + b] = sr;
+      if constexpr (CPLX) sti[i * LD + b] = si;
+    }
+    __syncthreads();
+    // Y = Tm U^H + (beta <rho,X> + qbar) rho  (into X)
+    const T w = beta * rx + qb;
     for (int idx = tid; idx < DE * DE; idx += 64) {
       const int i = idx / DE, j = idx % DE;
       T sr = T(0), si = T(0);
       for (int k = 0; k < DE; ++k) {
-        const T a_r = sur[i * LD + k] * sp[k];
-        const T a_i = CPLX ? sui[i * LD + k] * sp[k] : T(0);
-        sr = dfma<T>(a_r, sur[j * LD + k], sr);
+        const T tr = str[i * LD + k], ti = CPLX ? sti[i * LD + k] : T(0);
+        const T ur = sur[j * LD + k], ui = CPLX ? -sui[j * LD + k] : T(0);  // conj(U_jk)
+        sr = dfma<T>(tr, ur, sr);
         if constexpr (CPLX) {
-          sr = dfma<T>(a_i, sui[j * LD + k], sr);
-          si = dfma<T>(a_i, sur[j * LD + k], si);
-          si = dfma<T>(-a_r, sui[j * LD + k], si);
+          sr = dfma<T>(-ti, ui, sr);
+          si = dfma<T>(tr, ui, si);
+          si = dfma<T>(ti, ur, si);
         }
       }
-      sar[i * LD + j] = sr;
-      if constexpr (CPLX) sai[i * LD + j] = (i == j) ? T(0) : si;
+      sxr[i * LD + j] = dfma<T>(w, sar[i * LD + j], sr);
+      if constexpr (CPLX) sxi[i * LD + j] = dfma<T>(w, sai[i * LD + j], si);
     }
     __syncthreads();
-    // ---- outputs ----
-    const int64_t rs_self = A.rslot ? A.rslot[c] : -1;
-    constexpr int NCE = n_comps(DE, CPLX);
-    for (int k = tid; k < NCE; k += 64) {
-      // decode component k -> (i, j)
-      int i = 0, j = 0;
-      bool im = false;
-      int kk = k;
-      if (kk >= DE * (DE + 1) / 2) { im = true; kk -= DE * (DE + 1) / 2; }
-      const int rowlen0 = im ? DE - 1 : DE;
-      while (kk >= rowlen0 - i) { kk -= rowlen0 - i; ++i; }
-      j = i + kk + (im ? 1 : 0);
-      const T v = im ? sai[i * LD + j] : sar[i * LD + j];
-      if (rs_self >= 0 && A.R) A.R[(int64_t)k * A.S + rs_self] = v;
-      if (A.marg) A.marg[A.marg_off[gid] + k] = v;
-    }
-    if (A.Tout && Dc > 0) {
-      const int NR = DE / Dc;
-      const int NCC = CPLX ? Dc * Dc : Dc * (Dc + 1) / 2;
-      for (int s = 0; s < A.maxch; ++s) {
-        const int m = A.ch[(int64_t)s * A.n + c];
-        if (m < 0) continue;
-        const int mask = A.chmask[(int64_t)s * A.n + c];
-        for (int k = tid; k < NCC; k += 64) {
-          int a = 0, b = 0;
-          bool im = false;
-          int kk = k;
-          if (kk >= Dc * (Dc + 1) / 2) { im = true; kk -= Dc * (Dc + 1) / 2; }
-          const int rowlen0 = im ? Dc - 1 : Dc;
-          while (kk >= rowlen0 - a) { kk -= rowlen0 - a; ++a; }
-          b = a + kk + (im ? 1 : 0);
-          T sum = T(0);
-          for (int x = 0; x < NR; ++x) {
-            const int i = pdep_rt(a, x, mask, NB), j = pdep_rt(b, x, mask, NB);
-            sum += im ? sai[i * LD + j] : sar[i * LD + j];
-          }
-          A.Tout[(int64_t)k * A.Mc + m] = sum;
-        }
+    // symmetrise (Y is Hermitian up to rounding): keep the upper triangle mirrored
+    for (int idx = tid; idx < DE * DE; idx += 64) {
+      const int i = idx / DE, j = idx % DE;
+      if (i < j) {
+        sxr[j * LD + i] = sxr[i * LD + j];
+        if constexpr (CPLX) sxi[j * LD + i] = -sxi[i * LD + j];
       }
+      if constexpr (CPLX) { if (i == j) sxi[i * LD + i] = T(0); }
     }
+    __syncthreads();
+    lds_outputs<T, CPLX, DE>(A, c, gid, sxr, sxi);
+  } else {
+    for (int idx = tid; idx < DE * DE; idx += 64) {
+      const int i = idx / DE, j = idx % DE;
+      sxr[i * LD + j] = qb * sar[i * LD + j];
+      if constexpr (CPLX) sxi[i * LD + j] = qb * sai[i * LD + j];
+    }
+    __syncthreads();
+    lds_outputs<T, CPLX, DE>(A, c, gid, sxr, sxi);
   }
 }
 
@@ -843,6 +1064,82 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_copy(T* dst, const T* src, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_extrap(T* dst, const T* nu, const T* ze, double th, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = extrap<T>(nu[i], ze[i], (T)th);
+}
+
+__global__ __launch_bounds__(256) void k_set_params(double* h, const double* hfix, const int64_t* pc_hoff,
+                                                    const int64_t* pc_ptr, const int32_t* pc_param,
+                                                    const int64_t* pc_doff, const double* dterm,
+                                                    const int32_t* pc_ncomp, int64_t n_pc, const double* params) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_pc) return;
+  const int64_t ho = pc_hoff[c];
+  const int nc = pc_ncomp[c];
+  for (int k = 0; k < nc; ++k) {
+    double v = hfix[ho + k];
+    for (int64_t t = pc_ptr[c]; t < pc_ptr[c + 1]; ++t) v = fma(params[pc_param[t]], dterm[pc_doff[t] + k], v);
+    h[ho + k] = v;
+  }
+}
+
+// <Y, B> for packed Hermitian D x D matrices: diagonal once, off-diagonal (real and imaginary) twice.
+__device__ __forceinline__ double packed_inner(const double* y, const double* b, int D, bool cplx) {
+  double s = 0.0;
+  int k = 0;
+  for (int i = 0; i < D; ++i)
+    for (int j = i; j < D; ++j, ++k) s = fma((i == j) ? 1.0 : 2.0, y[k] * b[k], s);
+  if (cplx) {
+    const int n = D * (D - 1) / 2;
+    for (int q = 0; q < n; ++q, ++k) s = fma(2.0, y[k] * b[k], s);
+  }
+  return s;
+}
+
+__global__ __launch_bounds__(256) void k_param_bar(double* out, int accumulate, int64_t n_params,
+                                                   const int64_t* pp_ptr, const int64_t* pp_yoff,
+                                                   const int64_t* pp_doff, const int32_t* pp_D, const double* Y,
+                                                   const double* dterm, int cplx) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_params) return;
+  double s = 0.0;
+  for (int64_t t = pp_ptr[p]; t < pp_ptr[p + 1]; ++t)
+    s += packed_inner(Y + pp_yoff[t], dterm + pp_doff[t], pp_D[t], cplx != 0);
+  out[p] = accumulate ? out[p] + s : s;
+}
+
+__global__ __launch_bounds__(256) void k_adj_pre(const double* a, const double* b, double* btot, double* gbar,
+                                                 double th, double invthL, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double bt = fma(th, a[i], b[i]);
+  btot[i] = bt;
+  gbar[i] = bt * invthL;
+}
+
+__global__ __launch_bounds__(256) void k_adj_post(double* a, double* b, const double* btot, const double* etabar,
+                                                  double th, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  a[i] = (1.0 - th) * (a[i] + etabar[i]);
+  b[i] = fma(th, etabar[i], btot[i]);
+}
+
+__global__ __launch_bounds__(256) void k_scale_offdiag(double* x, int64_t M, int D, int cplx, double f) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  int k = 0;
+  for (int i = 0; i < D; ++i)
+    for (int j = i; j < D; ++j, ++k)
+      if (i != j) x[(int64_t)k * M + m] *= f;
+  if (cplx) {
+    const int n = D * (D - 1) / 2;
+    for (int q = 0; q < n; ++q, ++k) x[(int64_t)k * M + m] *= f;
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -948,6 +1245,81 @@ hipError_t launch_copy(T* dst, const T* src, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_cluster_vjp(const ClusterArgs<double>& a, bool cplx, int mode, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  const dim3 g((unsigned)a.n), b(64);
+#define VJP_CASE(DE)                                                                                   \
+  if (a.De == DE) {                                                                                    \
+    if (mode == MODE_GIBBS) {                                                                          \
+      if (cplx) hipLaunchKernelGGL((k_cluster_vjp<double, true, DE, MODE_GIBBS>), g, b, 0, s, a);      \
+      else hipLaunchKernelGGL((k_cluster_vjp<double, false, DE, MODE_GIBBS>), g, b, 0, s, a);          \
+    } else {                                                                                           \
+      if (cplx) hipLaunchKernelGGL((k_cluster_vjp<double, true, DE, MODE_GROUND>), g, b, 0, s, a);     \
+      else hipLaunchKernelGGL((k_cluster_vjp<double, false, DE, MODE_GROUND>), g, b, 0, s, a);         \
+    }                                                                                                  \
+    return hipGetLastError();                                                                          \
+  }
+  VJP_CASE(2)
+  VJP_CASE(4)
+  VJP_CASE(8)
+  VJP_CASE(16)
+  VJP_CASE(32)
+  if (a.De == 64 && !cplx) {
+    if (mode == MODE_GIBBS) hipLaunchKernelGGL((k_cluster_vjp<double, false, 64, MODE_GIBBS>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_cluster_vjp<double, false, 64, MODE_GROUND>), g, b, 0, s, a);
+    return hipGetLastError();
+  }
+#undef VJP_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_set_params(double* h, const double* hfix, const int64_t* pc_hoff, const int64_t* pc_ptr,
+                             const int32_t* pc_param, const int64_t* pc_doff, const double* dterm,
+                             const int32_t* pc_ncomp, int64_t n_pc, const double* params, hipStream_t s) {
+  if (n_pc == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_params, dim3(grid_for(n_pc, 256)), dim3(256), 0, s, h, hfix, pc_hoff, pc_ptr, pc_param,
+                     pc_doff, dterm, pc_ncomp, n_pc, params);
+  return hipGetLastError();
+}
+
+hipError_t launch_param_bar(double* out, int accumulate, int64_t n_params, const int64_t* pp_ptr,
+                            const int64_t* pp_yoff, const int64_t* pp_doff, const int32_t* pp_D, const double* Y,
+                            const double* dterm, bool cplx, hipStream_t s) {
+  if (n_params == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_param_bar, dim3(grid_for(n_params, 256)), dim3(256), 0, s, out, accumulate, n_params, pp_ptr,
+                     pp_yoff, pp_doff, pp_D, Y, dterm, cplx ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_pre(const double* a, const double* b, double* btot, double* gbar, double th, double invthL,
+                          int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_pre, dim3(grid_for(n, 256)), dim3(256), 0, s, a, b, btot, gbar, th, invthL, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_post(double* a, double* b, const double* btot, const double* etabar, double th, int64_t n,
+                           hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_post, dim3(grid_for(n, 256)), dim3(256), 0, s, a, b, btot, etabar, th, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_extrap(T* dst, const T* nu, const T* ze, double th, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_extrap<T>), dim3(grid_for(n, 256)), dim3(256), 0, s, dst, nu, ze, th, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_offdiag(double* x, int64_t M, int D, bool cplx, double f, hipStream_t s) {
+  if (M == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_offdiag, dim3(grid_for(M, 256)), dim3(256), 0, s, x, M, D, cplx ? 1 : 0, f);
+  return hipGetLastError();
+}
+
+template hipError_t launch_extrap<float>(float*, const float*, const float*, double, int64_t, hipStream_t);
+template hipError_t launch_extrap<double>(double*, const double*, const double*, double, int64_t, hipStream_t);
 template hipError_t launch_cluster<float>(const ClusterArgs<float>&, bool, int, int, hipStream_t);
 template hipError_t launch_cluster<double>(const ClusterArgs<double>&, bool, int, int, hipStream_t);
 template hipError_t launch_msg<float>(const MsgArgs<float>&, int, int, hipStream_t);

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(HERE, "liblrh.so")
 LRH_SUBINTERVALS = 0x1
 LRH_F32 = 0x1
 LRH_FUSED = 0x2
+LRH_PACKED_COTANGENT = 0x4
 LRH_MAX_BUCKETS = 8
 
 STATUS = {0: "LRH_OK", 1: "LRH_E_INVALID", 2: "LRH_E_UNSUPPORTED", 3: "LRH_E_NOMEM",
@@ -42,7 +43,9 @@ class ProblemDesc(C.Structure):
                 ("term_re", C.POINTER(C.c_double)), ("term_im", C.POINTER(C.c_double)),
                 ("n_top", C.c_int32), ("top_ptr", C.POINTER(C.c_int64)),
                 ("top_sites", C.POINTER(C.c_int32)), ("site_instance", C.POINTER(C.c_int32)),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("n_params", C.c_int32), ("term_param", C.POINTER(C.c_int32)),
+                ("dterm_re", C.POINTER(C.c_double)), ("dterm_im", C.POINTER(C.c_double)),
+                ("params", C.POINTER(C.c_double))]
 
 
 class Layout(C.Structure):
@@ -53,7 +56,8 @@ class Layout(C.Structure):
                 ("bucket_comps", C.c_int64 * LRH_MAX_BUCKETS),
                 ("bucket_offset", C.c_int64 * LRH_MAX_BUCKETS),
                 ("nu_len", C.c_int64), ("marg_len", C.c_int64),
-                ("Lambda_G", C.c_double), ("Gamma_G", C.c_double), ("max_sweeps", C.c_int32)]
+                ("Lambda_G", C.c_double), ("Gamma_G", C.c_double), ("max_sweeps", C.c_int32),
+                ("n_params", C.c_int32)]
 
 
 class NesterovState(C.Structure):
@@ -64,7 +68,8 @@ _lib = None
 
 EXPORTS = ["lrh_build_clusters", "lrh_query", "lrh_export_clusters", "lrh_export_messages",
            "lrh_dual_eval", "lrh_step_subgrad", "lrh_step_nesterov", "lrh_certify", "lrh_check",
-           "lrh_set_jacobi", "lrh_destroy", "lrh_last_error"]
+           "lrh_set_jacobi", "lrh_destroy", "lrh_last_error", "lrh_set_params", "lrh_dual_vjp",
+           "lrh_unrolled_bound_grad"]
 
 
 def load(path: str = LIB_PATH):
@@ -87,6 +92,9 @@ def load(path: str = LIB_PATH):
         "lrh_certify": (i32, [vp, vp, u32, vp, vp, vp, vp]),
         "lrh_check": (i32, [vp, vp, C.POINTER(i64), C.POINTER(i64)]),
         "lrh_set_jacobi": (i32, [vp, i32, dbl]),
+        "lrh_set_params": (i32, [vp, vp, vp]),
+        "lrh_dual_vjp": (i32, [vp, vp, u32, dbl, vp, vp, vp, vp, vp]),
+        "lrh_unrolled_bound_grad": (i32, [vp, vp, dbl, dbl, i32, vp, vp, vp, vp, u32, vp]),
         "lrh_destroy": (None, [vp]),
         "lrh_last_error": (C.c_char_p, []),
     }
@@ -141,6 +149,12 @@ def lrh_build_clusters(desc, hip_device: int = 0):
         top_sites=np.ascontiguousarray(desc.top_sites, dtype=np.int32),
         site_instance=np.ascontiguousarray(desc.site_instance, dtype=np.int32),
     )
+    npar = 0 if getattr(desc, "params", None) is None else len(desc.params)
+    if npar:
+        keep["term_param"] = np.ascontiguousarray(desc.term_param, dtype=np.int32)
+        keep["dterm_re"] = np.ascontiguousarray(desc.dterm_re, dtype=np.float64)
+        keep["dterm_im"] = None if desc.dterm_im is None else np.ascontiguousarray(desc.dterm_im, np.float64)
+        keep["params"] = np.ascontiguousarray(desc.params, dtype=np.float64)
     d = ProblemDesc()
     d.n_sites = int(desc.n_sites)
     d.site_dim = _ptr(keep["site_dim"], C.c_int32)
@@ -155,6 +169,12 @@ def lrh_build_clusters(desc, hip_device: int = 0):
     d.top_sites = _ptr(keep["top_sites"], C.c_int32)
     d.site_instance = _ptr(keep["site_instance"], C.c_int32)
     d.flags = LRH_SUBINTERVALS if desc.subintervals else 0
+    d.n_params = npar
+    if npar:
+        d.term_param = _ptr(keep["term_param"], C.c_int32)
+        d.dterm_re = _ptr(keep["dterm_re"], C.c_double)
+        d.dterm_im = None if keep["dterm_im"] is None else _ptr(keep["dterm_im"], C.c_double)
+        d.params = _ptr(keep["params"], C.c_double)
     h = C.c_void_p()
     _check(lib.lrh_build_clusters(C.byref(d), int(hip_device), C.byref(h)))
     return h
@@ -195,6 +215,22 @@ def lrh_check(h, stream=None) -> Tuple[int, int]:
 
 def lrh_set_jacobi(h, max_sweeps: int, rel_tol: float = 0.0):
     _check(load().lrh_set_jacobi(h, int(max_sweeps), float(rel_tol)))
+
+
+def lrh_set_params(h, params, stream=None):
+    _check(load().lrh_set_params(h, _dptr(params), _stream(stream)))
+
+
+def lrh_dual_vjp(h, nu, flags, beta, qbar=None, gbar=None, nu_bar=None, param_bar=None, stream=None):
+    _check(load().lrh_dual_vjp(h, _dptr(nu), flags, float(beta), _dptr(qbar), _dptr(gbar), _dptr(nu_bar),
+                               _dptr(param_bar), _stream(stream)))
+
+
+def lrh_unrolled_bound_grad(h, nu0, beta, L, T, qbar, bound, param_bar=None, nu0_bar=None, flags=0,
+                            stream=None):
+    _check(load().lrh_unrolled_bound_grad(h, _dptr(nu0), float(beta), float(L), int(T), _dptr(qbar),
+                                          _dptr(bound), _dptr(param_bar), _dptr(nu0_bar), flags,
+                                          _stream(stream)))
 
 
 def lrh_destroy(h):
@@ -369,6 +405,32 @@ class Problem:
     def check(self, stream=None):
         return lrh_check(self.h, stream)
 
+    # ---- parameters and adjoint ----
+    @property
+    def n_params(self) -> int:
+        return int(self.layout.n_params)
+
+    def set_params(self, params, stream=None):
+        lrh_set_params(self.h, params.contiguous(), stream)
+
+    def dual_vjp(self, nu, beta: float, qbar=None, gbar=None, packed: bool = False, stream=None):
+        nu_bar = self.torch.empty_like(nu)
+        pbar = (self.torch.empty(self.n_params, dtype=self.torch.float64, device=self.device)
+                if self.n_params else None)
+        lrh_dual_vjp(self.h, nu, LRH_PACKED_COTANGENT if packed else 0, beta, qbar, gbar, nu_bar, pbar, stream)
+        return nu_bar, pbar
+
+    def unrolled_bound_grad(self, beta: float, T: int, L: Optional[float] = None, nu0=None, qbar=None,
+                            want_nu0_bar: bool = False, packed: bool = False, stream=None):
+        L = float(beta) * self.Lambda / 2.0 if L is None else float(L)
+        bound = self.qbuf()
+        pbar = (self.torch.empty(self.n_params, dtype=self.torch.float64, device=self.device)
+                if self.n_params else None)
+        n0b = self.zeros() if want_nu0_bar else None
+        lrh_unrolled_bound_grad(self.h, nu0, beta, L, T, qbar, bound, pbar, n0b,
+                                LRH_PACKED_COTANGENT if packed else 0, stream)
+        return bound, pbar, n0b
+
     def set_jacobi(self, max_sweeps: int, rel_tol: float = 0.0):
         lrh_set_jacobi(self.h, max_sweeps, rel_tol)
 
@@ -384,3 +446,66 @@ def nesterov_schedule(beta0: float, beta_max: float, total_iters: int):
     sched = [(bb, per) for bb in betas]
     sched[-1] = (betas[-1], total_iters - per * (len(betas) - 1))
     return sched
+
+
+# ---- autograd wrappers (the arithmetic of both passes runs in the library) ------------------
+
+def _autograd():
+    import torch
+
+    class SmoothedDual(torch.autograd.Function):
+        """(nu, params) -> (Q_beta per instance, grad Q_beta).
+
+        grad Q_beta is the Hermitian gradient matrix of every message (Frobenius inner product)
+        stored in the message layout.  Cotangents follow torch's convention (with respect to the
+        stored components); the library converts them (LRH_PACKED_COTANGENT).  Forward:
+        lrh_set_params + lrh_dual_eval.  Backward: lrh_dual_vjp, which applies the
+        Daleckii-Krein derivative of every Gibbs state."""
+
+        @staticmethod
+        def forward(ctx, nu, params, problem, beta):
+            if params is not None and problem.n_params:
+                problem.set_params(params.detach())
+            q, g, _ = problem.dual_eval(nu.detach(), beta, grad=True)
+            ctx.problem, ctx.beta = problem, beta
+            ctx.save_for_backward(nu.detach())
+            return q, g
+
+        @staticmethod
+        def backward(ctx, qbar, gbar):
+            (nu,) = ctx.saved_tensors
+            P = ctx.problem
+            qb = None if qbar is None else qbar.contiguous().double()
+            gb = None if gbar is None else gbar.contiguous().double()
+            nu_bar, pbar = P.dual_vjp(nu, ctx.beta, qb, gb, packed=True)
+            return nu_bar, pbar, None, None
+
+    class UnrolledBound(torch.autograd.Function):
+        """params -> B_T per instance (T accelerated steps at fixed beta from zero messages,
+        then Q).  Backward re-runs the forward and the reverse sweep in the library."""
+
+        @staticmethod
+        def forward(ctx, params, problem, beta, T, L):
+            problem.set_params(params.detach())
+            b, _, _ = problem.unrolled_bound_grad(beta, T, L)
+            ctx.problem, ctx.beta, ctx.T, ctx.L = problem, beta, T, L
+            ctx.save_for_backward(params.detach())
+            return b
+
+        @staticmethod
+        def backward(ctx, bbar):
+            (params,) = ctx.saved_tensors
+            P = ctx.problem
+            P.set_params(params)
+            _, pbar, _ = P.unrolled_bound_grad(ctx.beta, ctx.T, ctx.L, qbar=bbar.contiguous().double())
+            return pbar, None, None, None, None
+
+    return SmoothedDual, UnrolledBound
+
+
+def smoothed_dual(nu, params, problem, beta):
+    return _autograd()[0].apply(nu, params, problem, beta)
+
+
+def unrolled_bound(params, problem, beta, T, L=None):
+    return _autograd()[1].apply(params, problem, beta, T, L)

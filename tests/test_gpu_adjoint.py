@@ -1,0 +1,186 @@
+"""GPU adjoint (form 3): the VJP of the smoothed dual and the gradient of the certified
+value after T accelerated steps, through the C ABI, against the FP64 oracle's reverse mode,
+central finite differences, and torch.autograd.gradcheck of the autograd wrappers."""
+import math
+
+import numpy as np
+import pytest
+
+import lrh_workloads as W
+from oracle import lrh_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_40336_amd import lrh
+    lrh.load()
+
+
+def lrhmod():
+    from paper_2609_40336_amd import lrh
+    return lrh
+
+
+def max_pair_err(got, want):
+    assert set(got) == set(want)
+    return max(float(np.abs(got[k] - want[k]).max()) for k in want)
+
+
+VJP_PROBLEMS = {
+    "xxz_tri3": lambda: W.xxz_triangular(3, 0.5, seed=5),
+    "randchain_Y3_complex": lambda: W.random_chain(7, seed=2, top_len=3, subintervals=True),
+    "tfim16_complex": lambda: W.workload_c1(),
+    "plaq_L3": lambda: W.tfim_plaquette_batch([3, 4], [0.8, 2.0]),
+    "randchain_Y5_complex": lambda: W.random_chain(7, seed=4, top_len=5, subintervals=True),
+}
+
+
+@pytest.mark.parametrize("name", list(VJP_PROBLEMS))
+@pytest.mark.parametrize("beta", [0.0, 1.7])
+def test_dual_vjp_matches_oracle(name, beta):
+    lrh = lrhmod()
+    say(f"[dual_vjp] {name} beta={beta}")
+    d = VJP_PROBLEMS[name]()
+    P = lrh.Problem(d, 0)
+    R = O.Relaxation(d)
+    nu_o = R.draw(21, 0.4)
+    gbar_o = R.draw(22, 1.0) if beta > 0 else None
+    qbar = np.linspace(0.5, 1.5, R.n_inst)
+    nu = P.from_dense(R.to_pairs(nu_o))
+    gb = P.from_dense(R.to_pairs(gbar_o)) if gbar_o is not None else None
+    qb = torch.tensor(qbar, dtype=torch.float64, device="cuda")
+    nb, pb = P.dual_vjp(nu, beta, qb, gb)
+    torch.cuda.synchronize()
+    nb_o, pb_o = O.dual_vjp(R, nu_o, beta, qbar, gbar_o)
+    assert max_pair_err(P.to_dense(nb), R.to_pairs(nb_o)) < 1e-10
+    if pb is not None:
+        assert np.max(np.abs(pb.cpu().numpy() - pb_o)) < 1e-10
+    assert P.check() == (0, 0)
+
+
+def test_set_params_moves_the_terms():
+    lrh = lrhmod()
+    say("[set_params] xxz L=3")
+    d = W.xxz_triangular(3, 0.5, seed=5)
+    P = lrh.Problem(d, 0)
+    R = O.Relaxation(d)
+    c = d.params * np.linspace(0.7, 1.3, len(d.params))
+    P.set_params(torch.tensor(c, dtype=torch.float64, device="cuda"))
+    q, _, _ = P.certify(P.zeros())
+    torch.cuda.synchronize()
+    assert q.item() == pytest.approx(-2.5 * c.sum(), abs=1e-10)
+    nu_o = R.draw(3, 0.3)
+    q2, _, _ = P.dual_eval(P.from_dense(R.to_pairs(nu_o)), 2.0)
+    torch.cuda.synchronize()
+    F = R.thetas(nu_o, h=O.h_at_params(R, c))
+    ref = 0.0
+    for D, t in F.items():
+        lam = np.linalg.eigvalsh(t)
+        ref += float(np.sum(lam[:, 0] - np.log(np.exp(-2.0 * (lam - lam[:, :1])).sum(axis=1)) / 2.0))
+    assert q2.item() == pytest.approx(ref, abs=1e-9 * d.n_sites)
+
+
+@pytest.mark.parametrize("T", [0, 5, 16])
+def test_unrolled_bound_grad_matches_oracle(T):
+    lrh = lrhmod()
+    say(f"[unrolled grad] xxz L=4 T={T}")
+    d = W.xxz_triangular(4, 0.5, seed=5)
+    P = lrh.Problem(d, 0)
+    R = O.Relaxation(d)
+    beta = 4.0
+    L = R.lipschitz(beta)
+    b, pb, n0b = P.unrolled_bound_grad(beta, T, L, want_nu0_bar=True)
+    torch.cuda.synchronize()
+    b_o, pb_o, n0b_o = O.unrolled_bound_grad(R, beta, T, L=L)
+    assert abs(b.item() - b_o[0]) <= 1e-9 * d.n_sites
+    assert np.max(np.abs(pb.cpu().numpy() - pb_o)) < 1e-9
+    assert max_pair_err(P.to_dense(n0b), R.to_pairs(n0b_o)) < 1e-9
+
+
+@pytest.mark.parametrize("T", [0, 16, 128])
+def test_xxz_64x64_bound_gradient_vs_central_differences(T):
+    """The full workload: XXZ on the 64x64 periodic triangular lattice, Delta = 0.5, J ~
+    U[0.8, 1.2], up and down triangles, fixed beta = 4.  The adjoint gradient of B_T with respect
+    to 32 seeded bonds against central differences (h = 1e-6, FP64) of the same forward:
+    |err| <= 1e-6 or relative 1e-5 (difference rounding is about eps |B| / h ~ 1e-6)."""
+    lrh = lrhmod()
+    say(f"[xxz 64x64] adjoint vs central differences, T={T}")
+    d = W.workload_c5()
+    P = lrh.Problem(d, 0)
+    beta = 4.0
+    L = beta * P.Lambda / 2.0
+    c0 = torch.tensor(d.params, dtype=torch.float64, device="cuda")
+    P.set_params(c0)
+    b, pb, _ = P.unrolled_bound_grad(beta, T, L)
+    torch.cuda.synchronize()
+    g = pb.cpu().numpy()
+    h = 1e-6
+    for p in d.meta["bonds"]:
+        cp = c0.clone()
+        cp[p] += h
+        P.set_params(cp)
+        bp, _, _ = P.unrolled_bound_grad(beta, T, L)
+        cm = c0.clone()
+        cm[p] -= h
+        P.set_params(cm)
+        bm, _, _ = P.unrolled_bound_grad(beta, T, L)
+        torch.cuda.synchronize()
+        fd = (bp.item() - bm.item()) / (2 * h)
+        assert abs(g[p] - fd) <= max(1e-6, 1e-5 * abs(fd)), (p, g[p], fd)
+    if T == 0:
+        np.testing.assert_allclose(g, -2.5, atol=1e-12)   # Hellmann-Feynman closed form
+    P.set_params(c0)
+
+
+def test_xxz_64x64_bound_gradient_vs_oracle():
+    """Full size against the oracle's reverse mode at T = 16 (all 12288 bonds)."""
+    lrh = lrhmod()
+    say("[xxz 64x64] adjoint vs oracle, T=16")
+    d = W.workload_c5()
+    P = lrh.Problem(d, 0)
+    R = O.Relaxation(d)
+    beta = 4.0
+    L = R.lipschitz(beta)
+    b, pb, _ = P.unrolled_bound_grad(beta, 16, L)
+    torch.cuda.synchronize()
+    b_o, pb_o, _ = O.unrolled_bound_grad(R, beta, 16, L=L)
+    assert abs(b.item() - b_o[0]) <= 1e-9 * d.n_sites
+    assert np.max(np.abs(pb.cpu().numpy() - pb_o)) < 1e-9
+
+
+def test_autograd_smoothed_dual_gradcheck():
+    """torch.autograd.gradcheck of (nu, params) -> (Q_beta, grad Q_beta): exercises the
+    packed-coordinate cotangents and the Daleckii-Krein second derivative."""
+    lrh = lrhmod()
+    say("[autograd] SmoothedDual gradcheck")
+    d = W.xxz_triangular(3, 0.5, seed=5)
+    P = lrh.Problem(d, 0)
+    R = O.Relaxation(d)
+    nu = P.from_dense(R.to_pairs(R.draw(7, 0.3))).requires_grad_(True)
+    c = torch.tensor(d.params, dtype=torch.float64, device="cuda", requires_grad=True)
+
+    def f(nu_, c_):
+        return lrh.smoothed_dual(nu_, c_, P, 1.5)
+    assert torch.autograd.gradcheck(f, (nu, c), eps=1e-6, atol=1e-6, rtol=1e-5, fast_mode=True)
+
+
+def test_autograd_unrolled_bound_gradcheck():
+    lrh = lrhmod()
+    say("[autograd] UnrolledBound gradcheck")
+    d = W.xxz_triangular(3, 0.5, seed=6)
+    P = lrh.Problem(d, 0)
+    c = torch.tensor(d.params, dtype=torch.float64, device="cuda", requires_grad=True)
+
+    def f(c_):
+        return lrh.unrolled_bound(c_, P, 4.0, 6)
+    assert torch.autograd.gradcheck(f, (c,), eps=1e-6, atol=1e-6, rtol=1e-5)

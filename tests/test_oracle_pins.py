@@ -535,3 +535,12 @@ def test_dual_vjp_is_the_transposed_hessian():
     _, g = R.grad_beta(nu, beta)
     for k in g:
         np.testing.assert_allclose(vq[k], 2.5 * g[k], atol=1e-13)
+
+
+def test_batched_gibbs_vjp_equals_single():
+    rng = np.random.default_rng(9)
+    K = np.stack([W.gue(rng, 8) for _ in range(5)] + [np.kron(np.kron(W.X, W.X) + np.kron(W.Y, W.Y), np.eye(2))])
+    X = np.stack([W.gue(rng, 8) for _ in range(6)])
+    got = O.gibbs_vjp_batch(K, 2.3, X)
+    for j in range(len(K)):
+        np.testing.assert_allclose(got[j], O.gibbs_vjp(K[j], 2.3, X[j]), atol=1e-12)
