@@ -57,9 +57,11 @@ typedef enum {
 /* flags for the compute calls */
 #define LRH_F32    0x1u   /* state buffers (nu, zeta, grad, marginals) are float, and the
                              iterations compute in FP32; certification stays FP64          */
-#define LRH_FUSED  0x2u   /* fused iteration: one launch per iteration (message update of
-                             the previous step folded into the cluster kernel), replayed
-                             from a captured HIP graph                                     */
+#define LRH_FUSED  0x2u   /* graph-replayed iterations: for 2-local problems one launch per
+                             iteration (the message update of the previous step folded into
+                             the cluster kernel); otherwise the plain launches of each
+                             iteration, driven by a device table of per-iteration scalars.
+                             Either form is captured once per 64-iteration chunk            */
 #define LRH_PACKED_COTANGENT 0x4u  /* message cotangents (gbar in, nu_bar out) are taken with
                              respect to the packed storage components instead of the
                              Frobenius inner product of the Hermitian matrices (they differ by
@@ -241,6 +243,22 @@ lrh_status lrh_unrolled_bound_grad(lrh_problem p, const double* nu0_dev, double 
  * a NaN/Inf eigenvalue.  Returns LRH_E_NONFINITE or LRH_E_NOCONV when either is
  * non-zero (NONFINITE first), LRH_OK otherwise.  Either pointer may be NULL. */
 lrh_status lrh_check(lrh_problem p, hipStream_t stream, int64_t* noconv, int64_t* nonfinite);
+
+/* Launch-shape autotuner (form 2): for every cluster bucket, time the Gibbs pass of the
+ * candidate shapes -- threads per block {64, 128, 256} for the register kernels (D_e <= 4),
+ * lanes per cluster for the LDS kernels (64/W clusters share a wave; W in {8, 16, 64} for
+ * D_e = 8, {16, 32, 64} for 16, {32, 64} for 32, 64 for 64) -- in the precision of `flags`
+ * (LRH_F32 or FP64) and keep the fastest.  cache_path (may be NULL) names a JSON file of
+ * earlier choices keyed by (D_e, D_child, real/complex, precision, bucket size): cached
+ * buckets are not re-measured, and the file is rewritten with every choice.  Synchronous.
+ * Results are identical for every shape (the same arithmetic per cluster). */
+lrh_status lrh_autotune(lrh_problem p, uint32_t flags, const char* cache_path, hipStream_t stream);
+
+/* Launch shapes in use, one entry per cluster bucket (at most `cap` written; *count = number
+ * of buckets): dimensions, cluster count, block / lanes-per-cluster, measured microseconds
+ * (0 when not measured).  Host arrays, any may be NULL except count. */
+lrh_status lrh_get_shapes(lrh_problem p, int32_t cap, int32_t* De, int32_t* Dc, int64_t* n, int32_t* block,
+                          int32_t* W, double* us, int32_t* count);
 
 /* Jacobi sweep cap (default 30) and relative off-diagonal tolerance (0 = default:
  * 4 eps of the iteration precision). */

@@ -64,6 +64,9 @@ struct KeyHash {
 
 struct CBucket {
   int De = 0, Dc = 0, maxch = 0, maxpar = 0;
+  int block = 64;     // threads per block (register kernels)
+  int W = 64;         // lanes per cluster (LDS kernels)
+  double tuned_us = 0.0;
   int64_t n = 0;
   int mb_child = -1;  // message bucket of the children (dimension Dc)
   int mb_self = -1;   // message bucket of dimension De (messages received from parents)
@@ -379,6 +382,8 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
     P->cb[b].h_gid.push_back((int32_t)g);
   }
   for (auto& B : P->cb) {
+    int shapes[8];
+    if (lds_shapes(B.De, shapes) > 0) B.W = shapes[0];
     B.n = (int64_t)B.h_gid.size();
     for (int32_t g : B.h_gid) {
       B.maxch = std::max<int>(B.maxch, (int)children[g].size());
@@ -750,7 +755,7 @@ ClusterArgs<T> base_args(lrh_problem_s* P, const CBucket& B) {
 // One plain pass of the cluster kernels over every bucket at (nu, zeta, theta).
 template <typename T>
 lrh_status cluster_pass(lrh_problem_s* P, const T* nu, const T* ze, double theta, int mode, double beta,
-                        T* marg, hipStream_t s) {
+                        T* marg, hipStream_t s, const FusedParams* tab = nullptr) {
   Work<T>& w = P->work<T>();
   for (const CBucket& B : P->cb) {
     ClusterArgs<T> a = base_args<T>(P, B);
@@ -770,7 +775,8 @@ lrh_status cluster_pass(lrh_problem_s* P, const T* nu, const T* ze, double theta
     a.marg_off = P->marg_off;
     a.beta = beta;
     a.theta = theta;
-    HIP_TRY(launch_cluster<T>(a, P->cplx, mode, 64, s));
+    a.tab = tab;
+    HIP_TRY(launch_cluster<T>(a, P->cplx, mode, B.block, B.W, s));
   }
   return LRH_OK;
 }
@@ -905,7 +911,7 @@ lrh_status fused_enqueue(lrh_problem_s* P, T* nu, T* ze, int n, hipStream_t s) {
     sa.S = M.S;
     // non-null plain pointers keep the (unused) plain path well-defined
     ea.nu_c = ea.nu_c_prev; sa.nu_p = sa.nu_p_prev;
-    HIP_TRY(launch_cluster_pair<T>(ea, sa, P->cplx, MODE_GIBBS, 64, s));
+    HIP_TRY(launch_cluster_pair<T>(ea, sa, P->cplx, MODE_GIBBS, E ? E->block : 64, s));
   }
   MsgArgs<T> a{};
   a.M = M.M;
@@ -977,6 +983,74 @@ lrh_status nesterov_fused(lrh_problem_s* P, T* nu, T* ze, lrh_nesterov_state* st
   return LRH_OK;
 }
 
+// Plain iterations driven from the device parameter table (row j: theta_k, 1/(theta_k L), beta),
+// so that a chunk can be captured once and replayed for any stage.
+template <typename T>
+lrh_status table_enqueue(lrh_problem_s* P, T* nu, T* ze, int n, hipStream_t s) {
+  lrh_status st;
+  for (int j = 0; j < n; ++j) {
+    if ((st = cluster_pass<T>(P, nu, ze, 0.0, MODE_GIBBS, 0.0, nullptr, s, P->fp + j)) != LRH_OK) return st;
+    for (const MBucket& M : P->mb) {
+      MsgArgs<T> a = msg_args<T>(P, M);
+      a.nu = nu + M.offset;
+      a.ze = ze + M.offset;
+      a.fp = P->fp + j;
+      a.fp_cur = 1;
+      HIP_TRY(launch_msg<T>(a, MSG_NESTEROV, 256, s));
+    }
+  }
+  return LRH_OK;
+}
+
+template <typename T>
+lrh_status nesterov_graph(lrh_problem_s* P, T* nu, T* ze, lrh_nesterov_state* stt, int n_iter, hipStream_t s) {
+  lrh_status st = ensure_work<T>(P, false);
+  if (st != LRH_OK) return st;
+  constexpr int CH = kFusedTableMax - 1;
+  const int prec = (sizeof(T) == 4 ? 32 : 64) + 1000;  // distinct key space from the fused graphs
+  int done = 0;
+  while (done < n_iter) {
+    const int n = std::min(CH, n_iter - done);
+    FusedTable tab{};
+    double th = stt->theta;
+    for (int j = 0; j < n; ++j) {
+      tab.p[j].theta_cur = th;
+      tab.p[j].inv_thL_cur = 1.0 / (th * stt->L);
+      tab.p[j].beta = stt->beta;
+      th = theta_next(th);
+    }
+    HIP_TRY(launch_set_fused(P->fp, tab, n, s));
+    if (n == CH) {
+      GraphKey key{prec, nu, ze};
+      auto it = P->graphs.find(key);
+      if (it == P->graphs.end()) {
+        if (!P->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeRelaxed));
+        lrh_status est = table_enqueue<T>(P, nu, ze, n, P->cap_stream);
+        hipGraph_t graph = nullptr;
+        hipError_t ee = hipStreamEndCapture(P->cap_stream, &graph);
+        if (est != LRH_OK) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return est;
+        }
+        if (ee != hipSuccess) return fail(LRH_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+        hipGraphExec_t exec = nullptr;
+        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) return fail(LRH_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+        it = P->graphs.emplace(key, exec).first;
+      }
+      HIP_TRY(hipGraphLaunch(it->second, s));
+    } else {
+      if ((st = table_enqueue<T>(P, nu, ze, n, s)) != LRH_OK) return st;
+    }
+    for (int j = 0; j < n; ++j) stt->theta = theta_next(stt->theta);
+    stt->k += n;
+    done += n;
+  }
+  return LRH_OK;
+}
+
 template <typename T>
 lrh_status nesterov_t(lrh_problem_s* P, T* nu, T* ze, lrh_nesterov_state* stt, int n_iter, bool fused,
                       hipStream_t s) {
@@ -986,8 +1060,8 @@ lrh_status nesterov_t(lrh_problem_s* P, T* nu, T* ze, lrh_nesterov_state* stt, i
   }
   if (n_iter == 0) return LRH_OK;
   if (fused) {
-    if (!fusable(P)) return fail(LRH_E_UNSUPPORTED, "fused iteration needs a 2-local problem (edges and sites)");
-    return nesterov_fused<T>(P, nu, ze, stt, n_iter, s);
+    if (fusable(P)) return nesterov_fused<T>(P, nu, ze, stt, n_iter, s);
+    return nesterov_graph<T>(P, nu, ze, stt, n_iter, s);
   }
   return nesterov_plain<T>(P, nu, ze, stt, n_iter, s);
 }
@@ -1122,6 +1196,115 @@ lrh_status unrolled_grad(lrh_problem_s* P, const double* nu0, double beta, doubl
     HIP_TRY(launch_adj_pre(a, b, nu0bar, gb, 1.0, 0.0, P->nu_len, s));  // nu0_bar = a + b
     if (packed && (st = to_packed(P, nu0bar, s)) != LRH_OK) return st;
   }
+  return LRH_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// autotuner: per cluster bucket, the launch shape (threads per block of the register kernels,
+// lanes per cluster of the LDS kernels) with the shortest measured Gibbs pass
+// ------------------------------------------------------------------------------------------
+
+std::string shape_key(const CBucket& B, bool cplx, int prec) {
+  return std::to_string(B.De) + "," + std::to_string(B.Dc) + "," + (cplx ? "c" : "r") + "," +
+         std::to_string(prec) + "," + std::to_string(B.n);
+}
+
+void read_cache(const char* path, std::map<std::string, std::pair<int, int>>& out) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char line[512];
+  while (std::fgets(line, sizeof(line), f)) {
+    char key[128];
+    int block = 0, W = 0;
+    // line format:   "De,Dc,kind,prec,n": {"block": B, "W": W, ...
+    if (std::sscanf(line, " \"%127[^\"]\": {\"block\": %d, \"W\": %d", key, &block, &W) == 3) out[key] = {block, W};
+  }
+  std::fclose(f);
+}
+
+void write_cache(const char* path, const std::map<std::string, std::tuple<int, int, double>>& rows) {
+  FILE* f = std::fopen(path, "w");
+  if (!f) return;
+  std::fprintf(f, "{\n");
+  size_t i = 0;
+  for (auto& kv : rows) {
+    std::fprintf(f, "  \"%s\": {\"block\": %d, \"W\": %d, \"us\": %.3f}%s\n", kv.first.c_str(), std::get<0>(kv.second),
+                 std::get<1>(kv.second), std::get<2>(kv.second), ++i < rows.size() ? "," : "");
+  }
+  std::fprintf(f, "}\n");
+  std::fclose(f);
+}
+
+template <typename T>
+lrh_status autotune_t(lrh_problem_s* P, const char* cache, hipStream_t s) {
+  lrh_status st = ensure_work<T>(P, false);
+  if (st != LRH_OK) return st;
+  const int prec = sizeof(T) == 4 ? 32 : 64;
+  std::map<std::string, std::pair<int, int>> cached;
+  if (cache) read_cache(cache, cached);
+  T* z = nullptr;
+  if ((st = P->dalloc(&z, std::max<int64_t>(P->nu_len, 1))) != LRH_OK) return st;
+  HIP_TRY(hipMemsetAsync(z, 0, std::max<int64_t>(P->nu_len, 1) * sizeof(T), s));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  Work<T>& w = P->work<T>();
+  std::map<std::string, std::tuple<int, int, double>> rows;
+  for (CBucket& B : P->cb) {
+    const std::string key = shape_key(B, P->cplx, prec);
+    auto it = cached.find(key);
+    if (it != cached.end()) {
+      B.block = it->second.first;
+      B.W = it->second.second;
+      rows[key] = std::make_tuple(B.block, B.W, 0.0);
+      continue;
+    }
+    std::vector<std::pair<int, int>> cands;
+    const bool reg = (B.De == 2 && B.Dc == 0) || (B.De == 4 && B.Dc == 2);
+    if (reg) {
+      for (int b : {64, 128, 256}) cands.push_back({b, B.W});
+    } else {
+      int shapes[8];
+      const int ns = lds_shapes(B.De, shapes);
+      for (int i = 0; i < ns; ++i) cands.push_back({B.block, shapes[i]});
+    }
+    double best = 1e30;
+    std::pair<int, int> pick = cands[0];
+    for (auto& cand : cands) {
+      ClusterArgs<T> a = base_args<T>(P, B);
+      if (B.mb_child >= 0) {
+        const MBucket& M = P->mb[B.mb_child];
+        a.nu_c = z + M.offset;
+        a.Tout = w.Tb[0] + M.offset;
+      }
+      if (B.mb_self >= 0) {
+        const MBucket& M = P->mb[B.mb_self];
+        a.nu_p = z + M.offset;
+        a.R = w.Rb[0] + M.roff;
+      }
+      a.beta = 1.0;
+      HIP_TRY(launch_cluster<T>(a, P->cplx, MODE_GIBBS, cand.first, cand.second, s));  // warm-up
+      const int reps = B.n > 100000 ? 3 : 10;
+      HIP_TRY(hipEventRecord(e0, s));
+      for (int r = 0; r < reps; ++r) HIP_TRY(launch_cluster<T>(a, P->cplx, MODE_GIBBS, cand.first, cand.second, s));
+      HIP_TRY(hipEventRecord(e1, s));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      const double us = 1e3 * ms / reps;
+      if (us < best) {
+        best = us;
+        pick = cand;
+      }
+    }
+    B.block = pick.first;
+    B.W = pick.second;
+    B.tuned_us = best;
+    rows[key] = std::make_tuple(B.block, B.W, best);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (cache) write_cache(cache, rows);
   return LRH_OK;
 }
 }  // namespace
@@ -1264,7 +1447,7 @@ lrh_status lrh_certify(lrh_problem p, const void* nu, uint32_t flags, double* q_
     if (B.mb_child >= 0) a.nu_c = nu64 + p->mb[B.mb_child].offset;
     if (B.mb_self >= 0) a.nu_p = nu64 + p->mb[B.mb_self].offset;
     a.R = nullptr;
-    HIP_TRY(launch_cluster<double>(a, p->cplx, MODE_CERTIFY, 64, stream));
+    HIP_TRY(launch_cluster<double>(a, p->cplx, MODE_CERTIFY, B.block, B.W, stream));
   }
   HIP_TRY(launch_reduce(p->scal, p->inst_ptr, p->n_inst, q_dev, p->scal2, margin_dev, nullptr, nullptr, nullptr,
                         stream));
@@ -1327,6 +1510,30 @@ lrh_status lrh_check(lrh_problem p, hipStream_t stream, int64_t* noconv, int64_t
   if (nonfinite) *nonfinite = (int64_t)h[1];
   if (h[1]) return fail(LRH_E_NONFINITE, "non-finite eigenvalue in " + std::to_string(h[1]) + " cluster solves");
   if (h[0]) return fail(LRH_E_NOCONV, "Jacobi sweep cap reached in " + std::to_string(h[0]) + " cluster solves");
+  return LRH_OK;
+}
+
+lrh_status lrh_autotune(lrh_problem p, uint32_t flags, const char* cache_path, hipStream_t stream) {
+  if (!p) return fail(LRH_E_INVALID, "null problem");
+  if (p->host_only) return fail(LRH_E_INVALID, "problem was built without a device");
+  DeviceGuard guard(p->device);
+  if (flags & LRH_F32) return autotune_t<float>(p, cache_path, stream);
+  return autotune_t<double>(p, cache_path, stream);
+}
+
+lrh_status lrh_get_shapes(lrh_problem p, int32_t cap, int32_t* De, int32_t* Dc, int64_t* n, int32_t* block,
+                          int32_t* W, double* us, int32_t* count) {
+  if (!p || !count) return fail(LRH_E_INVALID, "null argument");
+  *count = (int32_t)p->cb.size();
+  for (int32_t i = 0; i < std::min<int32_t>(cap, *count); ++i) {
+    const CBucket& B = p->cb[i];
+    if (De) De[i] = B.De;
+    if (Dc) Dc[i] = B.Dc;
+    if (n) n[i] = B.n;
+    if (block) block[i] = B.block;
+    if (W) W[i] = B.W;
+    if (us) us[i] = B.tuned_us;
+  }
   return LRH_OK;
 }
 

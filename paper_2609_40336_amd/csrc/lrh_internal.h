@@ -39,6 +39,7 @@ struct FusedParams {
   double inv_thL_prev; // 1 / (theta_{k-1} L)
   double theta_cur;    // theta_k
   double beta;
+  double inv_thL_cur;  // 1 / (theta_k L)
 };
 
 template <typename T>
@@ -65,6 +66,8 @@ struct ClusterArgs {
   double beta;          // inverse temperature (MODE_GIBBS)
   double theta;         // extrapolation weight when ze_* != nullptr
   double tau_rel;       // ground-space threshold (MODE_GROUND)
+  const FusedParams* tab;  // device table row: theta (extrapolation) and beta replace the
+                           // fields above (graph-replayed plain iterations); nullptr: unused
   int max_sweeps;
   double tol;           // relative off-diagonal tolerance
   unsigned long long* noconv;
@@ -93,18 +96,24 @@ struct MsgArgs {
   const T* nu_src; const T* ze_src;  // state read from here (nullptr: nu / ze, in place)
   const int32_t* improved;  // [n_inst] (subgradient best tracking)
   double alpha, theta, inv_thL;
-  const FusedParams* fp;    // if set, theta/inv_thL come from here (theta_prev)
+  const FusedParams* fp;    // if set, theta/inv_thL come from here (theta_prev, or theta_cur
+  int fp_cur;               // when fp_cur is set)
 };
 
 // ---- launchers (lrh_kernels.hip) ----
+// block: threads per block of the register kernels; W: lanes per cluster of the LDS kernels
+// (64/W clusters per wave), one of the shapes listed by lds_shapes()
 template <typename T>
-hipError_t launch_cluster(const ClusterArgs<T>& a, bool cplx, int mode, int block, hipStream_t s);
+hipError_t launch_cluster(const ClusterArgs<T>& a, bool cplx, int mode, int block, int W, hipStream_t s);
+// lanes-per-cluster shapes compiled for an LDS bucket of dimension De (returns the count)
+int lds_shapes(int De, int* out);
 template <typename T>
 hipError_t launch_msg(const MsgArgs<T>& a, int mode, int block, hipStream_t s);
 hipError_t launch_reduce(const double* scal, const int64_t* inst_ptr, int64_t n_inst, double* out,
                          const double* scal2, double* out2, double* q_best, int32_t* improved,
                          double* q_hist, hipStream_t s);
 constexpr int kFusedTableMax = 65;
+constexpr int kTableRows = 65;  // rows of the device parameter table (chunk of 64 + 1)
 struct FusedTable { FusedParams p[kFusedTableMax]; };
 hipError_t launch_set_fused(FusedParams* dst, const FusedTable& v, int n, hipStream_t s);
 hipError_t launch_widen(double* dst, const float* src, int64_t n, hipStream_t s);

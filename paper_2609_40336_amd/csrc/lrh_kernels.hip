@@ -256,7 +256,7 @@ __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
     fc.ithp = (T)A.fp->inv_thL_prev;
     fc.thc = (T)A.fp->theta_cur;
   }
-  const T th = fused ? fc.thc : (T)A.theta;
+  const T th = fused ? fc.thc : (A.tab ? (T)A.tab->theta_cur : (T)A.theta);
   // ---- children: subtract lifted messages ----
   if constexpr (DC > 0) {
     for (int s = 0; s < A.maxch; ++s) {
@@ -364,7 +364,7 @@ __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
     T p[DE];
     if constexpr (MODE == MODE_GIBBS) {
       // fused launches are replayed from a graph across stages: beta comes from the table
-      const T b = fused ? (T)A.fp->beta : (T)A.beta;
+      const T b = fused ? (T)A.fp->beta : (A.tab ? (T)A.tab->beta : (T)A.beta);
       T Z = T(0);
 #pragma unroll
       for (int k = 0; k < DE; ++k) { p[k] = dexp<T>(-b * (lam[k] - lmin)); Z += p[k]; }
@@ -491,21 +491,38 @@ __device__ __forceinline__ void herm_elem(Get get, int a, int b, int D, bool cpl
 }
 
 // ---- shared pieces of the LDS kernels ----
+//
+// A 64-lane wave holds G = 64/W clusters, W lanes each (W is a power of two, 8..64); lane `lt`
+// of a cluster strides over that cluster's entries by W.  Every loop whose trip count depends
+// on the data is made wave-uniform (per-cluster `done` flags, exit on __all), so barriers and
+// cross-lane shuffles always see the whole wave.
+
+template <int W, typename T>
+__device__ __forceinline__ T seg_sum(T v) {
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+template <int W, typename T>
+__device__ __forceinline__ T seg_min(T v) {
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
 
 // theta_e = [h_e] - sum_children 1 (x) x_{e->f} + sum_parents x_{g->e}, written to (dr, di) with
 // leading dimension DE+1; x = extrap(nu, zeta, th) when zeta is given.  Off-diagonal message
 // elements are scaled by `offs` (packed-coordinate cotangents use 1/2).  Returns this lane's
 // share of the squared Frobenius norm.
-template <typename T, bool CPLX, int DE>
-__device__ T lds_assemble(const ClusterArgs<T>& A, int64_t c, const T* xc, const T* zc, const T* xp, const T* zp,
-                          T th, bool with_h, T offs, T* dr, T* di) {
+template <typename T, bool CPLX, int DE, int W>
+__device__ T lds_assemble(const ClusterArgs<T>& A, int64_t c, int lt, const T* xc, const T* zc, const T* xp,
+                          const T* zp, T th, bool with_h, T offs, T* dr, T* di) {
   constexpr int LD = DE + 1;
   constexpr int NB = log2i(DE);
-  const int tid = threadIdx.x;
   const int64_t ho = with_h ? A.hoff[c] : -1;
   const int Dc = A.Dc;
   T my_n2 = T(0);
-  for (int idx = tid; idx < DE * DE; idx += 64) {
+  for (int idx = lt; idx < DE * DE; idx += W) {
     const int i = idx / DE, j = idx % DE;
     T vr = T(0), vi = T(0);
     if (ho >= 0) {
@@ -549,7 +566,7 @@ __device__ T lds_assemble(const ClusterArgs<T>& A, int64_t c, const T* xc, const
   return my_n2;
 }
 
-// Rotation scratch of the round-robin parallel Jacobi.
+// Rotation scratch of the round-robin parallel Jacobi (one per cluster).
 template <typename T, int NP>
 struct JacobiScratch {
   T c[NP], s[NP], er[NP], ei[NP], app[NP], aqq[NP];
@@ -559,107 +576,122 @@ struct JacobiScratch {
 // Cyclic two-sided Jacobi on the LDS matrix (sar, sai) with eigenvectors accumulated in
 // (sur, sui) when VEC.  Each round applies the DE/2 disjoint rotations of a round-robin
 // tournament in parallel: columns (A G, U G), then rows (G^H A), then the exact 2x2 blocks.
+// `done` clusters (converged, capped, or absent) skip the work but keep the wave together.
 // Returns true when the off-diagonal norm fell below tol2 within max_sweeps sweeps.
-template <typename T, bool CPLX, int DE, bool VEC>
-__device__ bool lds_jacobi(T* sar, T* sai, T* sur, T* sui, JacobiScratch<T, DE / 2>& J, T tol2, int max_sweeps) {
+template <typename T, bool CPLX, int DE, bool VEC, int W>
+__device__ bool lds_jacobi(T* sar, T* sai, T* sur, T* sui, JacobiScratch<T, DE / 2>& J, T tol2, int max_sweeps,
+                           int lt, bool active) {
   constexpr int LD = DE + 1;
   constexpr int NP = DE / 2;
-  const int tid = threadIdx.x;
-  for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
+  bool done = !active, conv = false;
+  for (int sweep = 0;; ++sweep) {
     T off = T(0);
-    for (int idx = tid; idx < DE * DE; idx += 64) {
-      const int i = idx / DE, j = idx % DE;
-      if (i != j) {
-        off = dfma<T>(sar[i * LD + j], sar[i * LD + j], off);
-        if constexpr (CPLX) off = dfma<T>(sai[i * LD + j], sai[i * LD + j], off);
+    if (!done) {
+      for (int idx = lt; idx < DE * DE; idx += W) {
+        const int i = idx / DE, j = idx % DE;
+        if (i != j) {
+          off = dfma<T>(sar[i * LD + j], sar[i * LD + j], off);
+          if constexpr (CPLX) off = dfma<T>(sai[i * LD + j], sai[i * LD + j], off);
+        }
       }
     }
-    off = wave_sum(off);
-    if (off <= tol2) return true;
-    if (sweep == max_sweeps) break;
+    off = seg_sum<W>(off);
+    if (!done) {
+      if (off <= tol2) { done = true; conv = true; }
+      else if (sweep >= max_sweeps) { done = true; }
+    }
+    if (__all(done ? 1 : 0)) break;
     for (int r = 0; r < DE - 1; ++r) {
-      if (tid < NP) {
-        int p, q;
-        rr_pair(r, tid, DE, p, q);
-        const T xr = sar[p * LD + q];
-        const T xi = CPLX ? sai[p * LD + q] : T(0);
-        const T rr = CPLX ? dsqrt<T>(dfma<T>(xr, xr, xi * xi)) : fabs(xr);
-        T t = T(0), cc = T(1), ss = T(0), er = T(1), ei = T(0);
-        const T app = sar[p * LD + p], aqq = sar[q * LD + q];
-        if (rr != T(0)) {
-          rot_params<T>(app, aqq, rr, t, cc, ss);
-          er = xr / rr;
-          ei = CPLX ? -xi / rr : T(0);
+      if (!done) {
+        for (int k = lt; k < NP; k += W) {
+          int p, q;
+          rr_pair(r, k, DE, p, q);
+          const T xr = sar[p * LD + q];
+          const T xi = CPLX ? sai[p * LD + q] : T(0);
+          const T rr = CPLX ? dsqrt<T>(dfma<T>(xr, xr, xi * xi)) : fabs(xr);
+          T t = T(0), cc = T(1), ss = T(0), er = T(1), ei = T(0);
+          const T app = sar[p * LD + p], aqq = sar[q * LD + q];
+          if (rr != T(0)) {
+            rot_params<T>(app, aqq, rr, t, cc, ss);
+            er = xr / rr;
+            ei = CPLX ? -xi / rr : T(0);
+          }
+          J.p[k] = p; J.q[k] = q;
+          J.c[k] = cc; J.s[k] = ss; J.er[k] = er; J.ei[k] = ei;
+          J.app[k] = app - t * rr;
+          J.aqq[k] = aqq + t * rr;
         }
-        J.p[tid] = p; J.q[tid] = q;
-        J.c[tid] = cc; J.s[tid] = ss; J.er[tid] = er; J.ei[tid] = ei;
-        J.app[tid] = app - t * rr;
-        J.aqq[tid] = aqq + t * rr;
       }
       __syncthreads();
-      // columns: A <- A G, U <- U G  (w = x_q e^{-i phi})
-      for (int idx = tid; idx < DE * NP; idx += 64) {
-        const int i = idx % DE, k = idx / DE;
-        const int p = J.p[k], q = J.q[k];
-        const T cc = J.c[k], ss = J.s[k], er = J.er[k], ei = J.ei[k];
-        {
-          T pr = sar[i * LD + p], qr = sar[i * LD + q];
-          T pi = CPLX ? sai[i * LD + p] : T(0), qi = CPLX ? sai[i * LD + q] : T(0);
-          T wr = CPLX ? qr * er - qi * ei : qr * er;
-          T wi = CPLX ? qr * ei + qi * er : T(0);
-          sar[i * LD + p] = cc * pr - ss * wr;
-          sar[i * LD + q] = ss * pr + cc * wr;
-          if constexpr (CPLX) {
-            sai[i * LD + p] = cc * pi - ss * wi;
-            sai[i * LD + q] = ss * pi + cc * wi;
+      if (!done) {
+        // columns: A <- A G, U <- U G  (w = x_q e^{-i phi})
+        for (int idx = lt; idx < DE * NP; idx += W) {
+          const int i = idx % DE, k = idx / DE;
+          const int p = J.p[k], q = J.q[k];
+          const T cc = J.c[k], ss = J.s[k], er = J.er[k], ei = J.ei[k];
+          {
+            T pr = sar[i * LD + p], qr = sar[i * LD + q];
+            T pi = CPLX ? sai[i * LD + p] : T(0), qi = CPLX ? sai[i * LD + q] : T(0);
+            T wr = CPLX ? qr * er - qi * ei : qr * er;
+            T wi = CPLX ? qr * ei + qi * er : T(0);
+            sar[i * LD + p] = cc * pr - ss * wr;
+            sar[i * LD + q] = ss * pr + cc * wr;
+            if constexpr (CPLX) {
+              sai[i * LD + p] = cc * pi - ss * wi;
+              sai[i * LD + q] = ss * pi + cc * wi;
+            }
+          }
+          if constexpr (VEC) {
+            T pr = sur[i * LD + p], qr = sur[i * LD + q];
+            T pi = CPLX ? sui[i * LD + p] : T(0), qi = CPLX ? sui[i * LD + q] : T(0);
+            T wr = CPLX ? qr * er - qi * ei : qr * er;
+            T wi = CPLX ? qr * ei + qi * er : T(0);
+            sur[i * LD + p] = cc * pr - ss * wr;
+            sur[i * LD + q] = ss * pr + cc * wr;
+            if constexpr (CPLX) {
+              sui[i * LD + p] = cc * pi - ss * wi;
+              sui[i * LD + q] = ss * pi + cc * wi;
+            }
           }
         }
-        if constexpr (VEC) {
-          T pr = sur[i * LD + p], qr = sur[i * LD + q];
-          T pi = CPLX ? sui[i * LD + p] : T(0), qi = CPLX ? sui[i * LD + q] : T(0);
+      }
+      __syncthreads();
+      if (!done) {
+        // rows: A <- G^H A  (w = x_q e^{+i phi})
+        for (int idx = lt; idx < DE * NP; idx += W) {
+          const int j = idx % DE, k = idx / DE;
+          const int p = J.p[k], q = J.q[k];
+          const T cc = J.c[k], ss = J.s[k], er = J.er[k], ei = -J.ei[k];
+          T pr = sar[p * LD + j], qr = sar[q * LD + j];
+          T pi = CPLX ? sai[p * LD + j] : T(0), qi = CPLX ? sai[q * LD + j] : T(0);
           T wr = CPLX ? qr * er - qi * ei : qr * er;
           T wi = CPLX ? qr * ei + qi * er : T(0);
-          sur[i * LD + p] = cc * pr - ss * wr;
-          sur[i * LD + q] = ss * pr + cc * wr;
+          sar[p * LD + j] = cc * pr - ss * wr;
+          sar[q * LD + j] = ss * pr + cc * wr;
           if constexpr (CPLX) {
-            sui[i * LD + p] = cc * pi - ss * wi;
-            sui[i * LD + q] = ss * pi + cc * wi;
+            sai[p * LD + j] = cc * pi - ss * wi;
+            sai[q * LD + j] = ss * pi + cc * wi;
           }
         }
       }
       __syncthreads();
-      // rows: A <- G^H A  (w = x_q e^{+i phi})
-      for (int idx = tid; idx < DE * NP; idx += 64) {
-        const int j = idx % DE, k = idx / DE;
-        const int p = J.p[k], q = J.q[k];
-        const T cc = J.c[k], ss = J.s[k], er = J.er[k], ei = -J.ei[k];
-        T pr = sar[p * LD + j], qr = sar[q * LD + j];
-        T pi = CPLX ? sai[p * LD + j] : T(0), qi = CPLX ? sai[q * LD + j] : T(0);
-        T wr = CPLX ? qr * er - qi * ei : qr * er;
-        T wi = CPLX ? qr * ei + qi * er : T(0);
-        sar[p * LD + j] = cc * pr - ss * wr;
-        sar[q * LD + j] = ss * pr + cc * wr;
-        if constexpr (CPLX) {
-          sai[p * LD + j] = cc * pi - ss * wi;
-          sai[q * LD + j] = ss * pi + cc * wi;
-        }
-      }
-      __syncthreads();
-      if (tid < NP) {
-        const int p = J.p[tid], q = J.q[tid];
-        sar[p * LD + p] = J.app[tid];
-        sar[q * LD + q] = J.aqq[tid];
-        sar[p * LD + q] = T(0);
-        sar[q * LD + p] = T(0);
-        if constexpr (CPLX) {
-          sai[p * LD + p] = T(0); sai[q * LD + q] = T(0);
-          sai[p * LD + q] = T(0); sai[q * LD + p] = T(0);
+      if (!done) {
+        for (int k = lt; k < NP; k += W) {
+          const int p = J.p[k], q = J.q[k];
+          sar[p * LD + p] = J.app[k];
+          sar[q * LD + q] = J.aqq[k];
+          sar[p * LD + q] = T(0);
+          sar[q * LD + p] = T(0);
+          if constexpr (CPLX) {
+            sai[p * LD + p] = T(0); sai[q * LD + q] = T(0);
+            sai[p * LD + q] = T(0); sai[q * LD + p] = T(0);
+          }
         }
       }
       __syncthreads();
     }
   }
-  return false;
+  return conv;
 }
 
 // component k of a packed D x D Hermitian -> (i, j, imaginary?)
@@ -674,14 +706,13 @@ __device__ __forceinline__ void decode_comp(int k, int D, int& i, int& j, bool& 
 
 // Write a cluster matrix Y (LDS) to its consumers: own marginal slot (if it has parents),
 // the per-cluster output buffer, and the partial traces onto every child.
-template <typename T, bool CPLX, int DE>
-__device__ void lds_outputs(const ClusterArgs<T>& A, int64_t c, int32_t gid, const T* yr, const T* yi) {
+template <typename T, bool CPLX, int DE, int W>
+__device__ void lds_outputs(const ClusterArgs<T>& A, int64_t c, int lt, int32_t gid, const T* yr, const T* yi) {
   constexpr int LD = DE + 1;
   constexpr int NB = log2i(DE);
-  const int tid = threadIdx.x;
   const int64_t rs_self = A.rslot ? A.rslot[c] : -1;
   constexpr int NCE = n_comps(DE, CPLX);
-  for (int k = tid; k < NCE; k += 64) {
+  for (int k = lt; k < NCE; k += W) {
     int i, j;
     bool im;
     decode_comp(k, DE, i, j, im);
@@ -697,7 +728,7 @@ __device__ void lds_outputs(const ClusterArgs<T>& A, int64_t c, int32_t gid, con
       const int m = A.ch[(int64_t)s * A.n + c];
       if (m < 0) continue;
       const int mask = A.chmask[(int64_t)s * A.n + c];
-      for (int k = tid; k < NCC; k += 64) {
+      for (int k = lt; k < NCC; k += W) {
         int a, b;
         bool im;
         decode_comp(k, Dc, a, b, im);
@@ -714,29 +745,31 @@ __device__ void lds_outputs(const ClusterArgs<T>& A, int64_t c, int32_t gid, con
 
 // Marginal weights from the eigenvalues on the diagonal of sar: Gibbs p (returns F_beta) or the
 // normalised ground-space indicator (returns lambda_min).  Weights go to sp[].
-template <typename T, int DE, int MODE>
-__device__ T lds_weights(const T* sar, T* sp, T lmin, T beta, T tau) {
+template <typename T, int DE, int MODE, int W>
+__device__ T lds_weights(const T* sar, T* sp, T lmin, T beta, T tau, int lt, bool active) {
   constexpr int LD = DE + 1;
-  const int tid = threadIdx.x;
   T w = T(0);
-  if constexpr (MODE == MODE_GIBBS) {
-    for (int k = tid; k < DE; k += 64) { T v = dexp<T>(-beta * (sar[k * LD + k] - lmin)); sp[k] = v; w += v; }
-  } else {
-    for (int k = tid; k < DE; k += 64) { T v = (sar[k * LD + k] <= lmin + tau) ? T(1) : T(0); sp[k] = v; w += v; }
+  if (active) {
+    if constexpr (MODE == MODE_GIBBS) {
+      for (int k = lt; k < DE; k += W) { T v = dexp<T>(-beta * (sar[k * LD + k] - lmin)); sp[k] = v; w += v; }
+    } else {
+      for (int k = lt; k < DE; k += W) { T v = (sar[k * LD + k] <= lmin + tau) ? T(1) : T(0); sp[k] = v; w += v; }
+    }
   }
-  const T Z = wave_sum(w);
+  const T Z = seg_sum<W>(w);
   __syncthreads();
-  for (int k = tid; k < DE; k += 64) sp[k] /= Z;
+  if (active)
+    for (int k = lt; k < DE; k += W) sp[k] /= Z;
   __syncthreads();
   if constexpr (MODE == MODE_GIBBS) return lmin - dlog<T>(Z) / beta;
   else return lmin;
 }
 
 // (yr, yi) = U diag(sp) U^H
-template <typename T, bool CPLX, int DE>
-__device__ void lds_rebuild(const T* sur, const T* sui, const T* sp, T* yr, T* yi) {
+template <typename T, bool CPLX, int DE, int W>
+__device__ void lds_rebuild(const T* sur, const T* sui, const T* sp, T* yr, T* yi, int lt) {
   constexpr int LD = DE + 1;
-  for (int idx = threadIdx.x; idx < DE * DE; idx += 64) {
+  for (int idx = lt; idx < DE * DE; idx += W) {
     const int i = idx / DE, j = idx % DE;
     T sr = T(0), si = T(0);
     for (int k = 0; k < DE; ++k) {
@@ -754,53 +787,67 @@ __device__ void lds_rebuild(const T* sur, const T* sui, const T* sp, T* yr, T* y
   }
 }
 
-template <typename T, bool CPLX, int DE, int MODE>
+// W lanes per cluster, 64/W clusters per single-wave block.
+template <typename T, bool CPLX, int DE, int MODE, int W>
 __global__ __launch_bounds__(64) void k_cluster_lds(ClusterArgs<T> A) {
   constexpr int LD = DE + 1;
+  constexpr int G = 64 / W;
+  constexpr int SZ = DE * LD;
   constexpr bool VEC = (MODE != MODE_CERTIFY);
-  __shared__ T sar[DE * LD];
-  __shared__ T sai[CPLX ? DE * LD : 1];
-  __shared__ T sur[VEC ? DE * LD : 1];
-  __shared__ T sui[(VEC && CPLX) ? DE * LD : 1];
-  __shared__ JacobiScratch<T, DE / 2> J;
-  __shared__ T sp[DE];
-  const int64_t c = blockIdx.x;
-  if (c >= A.n) return;
-  const int tid = threadIdx.x;
+  __shared__ T sar_[G * SZ];
+  __shared__ T sai_[CPLX ? G * SZ : 1];
+  __shared__ T sur_[VEC ? G * SZ : 1];
+  __shared__ T sui_[(VEC && CPLX) ? G * SZ : 1];
+  __shared__ JacobiScratch<T, DE / 2> J_[G];
+  __shared__ T sp_[G * DE];
+  const int g = threadIdx.x / W, lt = threadIdx.x % W;
+  const int64_t c = (int64_t)blockIdx.x * G + g;
+  const bool active = c < A.n;
+  T* sar = sar_ + g * SZ;
+  T* sai = CPLX ? sai_ + g * SZ : sai_;
+  T* sur = VEC ? sur_ + g * SZ : sur_;
+  T* sui = (VEC && CPLX) ? sui_ + g * SZ : sui_;
+  T* sp = sp_ + g * DE;
+  const T th = A.tab ? (T)A.tab->theta_cur : (T)A.theta;
+  const T beta = A.tab ? (T)A.tab->beta : (T)A.beta;
   // ---- a1/a2: assemble theta_e at eta ----
-  const T nrm2 = wave_sum(lds_assemble<T, CPLX, DE>(A, c, A.nu_c, A.ze_c, A.nu_p, A.ze_p, (T)A.theta, true,
-                                                    T(1), sar, sai));
+  T n2 = T(0);
+  if (active) n2 = lds_assemble<T, CPLX, DE, W>(A, c, lt, A.nu_c, A.ze_c, A.nu_p, A.ze_p, th, true, T(1), sar, sai);
+  const T nrm2 = seg_sum<W>(n2);
   if constexpr (VEC) {
-    for (int idx = tid; idx < DE * DE; idx += 64) {
-      const int i = idx / DE, j = idx % DE;
-      sur[i * LD + j] = (i == j) ? T(1) : T(0);
-      if constexpr (CPLX) sui[i * LD + j] = T(0);
+    if (active) {
+      for (int idx = lt; idx < DE * DE; idx += W) {
+        const int i = idx / DE, j = idx % DE;
+        sur[i * LD + j] = (i == j) ? T(1) : T(0);
+        if constexpr (CPLX) sui[i * LD + j] = T(0);
+      }
     }
   }
   __syncthreads();
   // ---- a3: parallel cyclic Jacobi ----
-  const bool conv = lds_jacobi<T, CPLX, DE, VEC>(sar, sai, sur, sui, J, (T)(A.tol * A.tol) * nrm2, A.max_sweeps);
-  if (!conv && tid == 0 && A.noconv) atomicAdd(A.noconv, 1ull);
+  const bool conv = lds_jacobi<T, CPLX, DE, VEC, W>(sar, sai, sur, sui, J_[g], (T)(A.tol * A.tol) * nrm2,
+                                                    A.max_sweeps, lt, active);
+  if (active && !conv && lt == 0 && A.noconv) atomicAdd(A.noconv, 1ull);
   T lmin = T(INFINITY);
-  for (int k = tid; k < DE; k += 64) lmin = fmin(lmin, sar[k * LD + k]);
-  lmin = wave_min(lmin);
-  if (tid == 0 && !isfinite((double)lmin) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
-  const int32_t gid = A.gid[c];
+  if (active)
+    for (int k = lt; k < DE; k += W) lmin = fmin(lmin, sar[k * LD + k]);
+  lmin = seg_min<W>(lmin);
+  if (active && lt == 0 && !isfinite((double)lmin) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
+  const int32_t gid = active ? A.gid[c] : 0;
   if constexpr (MODE == MODE_CERTIFY) {
-    if (tid == 0) {
+    if (active && lt == 0) {
       A.scal[gid] = (double)lmin;
       A.scal2[gid] = 8.0 * DE * DBL_EPSILON * sqrt((double)nrm2);
     }
-    return;
   } else {
     // ---- a4: weights and the marginal U diag(p) U^H (over A) ----
-    const T val = lds_weights<T, DE, MODE>(sar, sp, lmin, (T)A.beta,
-                                           (T)A.tau_rel * fmax(T(1), dsqrt<T>(nrm2)));
-    if (tid == 0) A.scal[gid] = (double)val;
-    lds_rebuild<T, CPLX, DE>(sur, sui, sp, sar, sai);
+    const T val = lds_weights<T, DE, MODE, W>(sar, sp, lmin, beta, (T)A.tau_rel * fmax(T(1), dsqrt<T>(nrm2)), lt,
+                                              active);
+    if (active && lt == 0 && A.scal) A.scal[gid] = (double)val;
+    if (active) lds_rebuild<T, CPLX, DE, W>(sur, sui, sp, sar, sai, lt);
     __syncthreads();
     // ---- a5: outputs ----
-    lds_outputs<T, CPLX, DE>(A, c, gid, sar, sai);
+    if (active) lds_outputs<T, CPLX, DE, W>(A, c, lt, gid, sar, sai);
   }
 }
 
@@ -836,17 +883,18 @@ __global__ __launch_bounds__(64) void k_cluster_vjp(ClusterArgs<T> A) {
   if (c >= A.n) return;
   const int tid = threadIdx.x;
   const bool has_g = (A.gb_c != nullptr || A.gb_p != nullptr);
-  const T nrm2 = wave_sum(lds_assemble<T, CPLX, DE>(A, c, A.nu_c, nullptr, A.nu_p, nullptr, T(0), true, T(1),
-                                                    sar, sai));
-  if (has_g) lds_assemble<T, CPLX, DE>(A, c, A.gb_c, nullptr, A.gb_p, nullptr, T(0), false, (T)A.gb_offscale,
-                                       sxr, sxi);
+  const T nrm2 = wave_sum(lds_assemble<T, CPLX, DE, 64>(A, c, tid, A.nu_c, nullptr, A.nu_p, nullptr, T(0), true,
+                                                        T(1), sar, sai));
+  if (has_g) lds_assemble<T, CPLX, DE, 64>(A, c, tid, A.gb_c, nullptr, A.gb_p, nullptr, T(0), false,
+                                           (T)A.gb_offscale, sxr, sxi);
   for (int idx = tid; idx < DE * DE; idx += 64) {
     const int i = idx / DE, j = idx % DE;
     sur[i * LD + j] = (i == j) ? T(1) : T(0);
     if constexpr (CPLX) sui[i * LD + j] = T(0);
   }
   __syncthreads();
-  const bool conv = lds_jacobi<T, CPLX, DE, true>(sar, sai, sur, sui, J, (T)(A.tol * A.tol) * nrm2, A.max_sweeps);
+  const bool conv = lds_jacobi<T, CPLX, DE, true, 64>(sar, sai, sur, sui, J, (T)(A.tol * A.tol) * nrm2,
+                                                      A.max_sweeps, tid, true);
   if (!conv && tid == 0 && A.noconv) atomicAdd(A.noconv, 1ull);
   T lmin = T(INFINITY);
   for (int k = tid; k < DE; k += 64) {
@@ -855,9 +903,9 @@ __global__ __launch_bounds__(64) void k_cluster_vjp(ClusterArgs<T> A) {
   }
   lmin = wave_min(lmin);
   const T beta = (T)A.beta;
-  lds_weights<T, DE, MODE>(sar, sp, lmin, beta, (T)A.tau_rel * fmax(T(1), dsqrt<T>(nrm2)));
+  lds_weights<T, DE, MODE, 64>(sar, sp, lmin, beta, (T)A.tau_rel * fmax(T(1), dsqrt<T>(nrm2)), tid, true);
   // rho (or mu) over A
-  lds_rebuild<T, CPLX, DE>(sur, sui, sp, sar, sai);
+  lds_rebuild<T, CPLX, DE, 64>(sur, sui, sp, sar, sai, tid);
   __syncthreads();
   const int32_t gid = A.gid[c];
   const T qb = A.qbar ? (T)A.qbar[A.cinst[gid]] : T(0);
@@ -955,7 +1003,7 @@ __global__ __launch_bounds__(64) void k_cluster_vjp(ClusterArgs<T> A) {
       if constexpr (CPLX) { if (i == j) sxi[i * LD + i] = T(0); }
     }
     __syncthreads();
-    lds_outputs<T, CPLX, DE>(A, c, gid, sxr, sxi);
+    lds_outputs<T, CPLX, DE, 64>(A, c, tid, gid, sxr, sxi);
   } else {
     for (int idx = tid; idx < DE * DE; idx += 64) {
       const int i = idx / DE, j = idx % DE;
@@ -963,7 +1011,7 @@ __global__ __launch_bounds__(64) void k_cluster_vjp(ClusterArgs<T> A) {
       if constexpr (CPLX) sxi[i * LD + j] = qb * sai[i * LD + j];
     }
     __syncthreads();
-    lds_outputs<T, CPLX, DE>(A, c, gid, sxr, sxi);
+    lds_outputs<T, CPLX, DE, 64>(A, c, tid, gid, sxr, sxi);
   }
 }
 
@@ -977,7 +1025,8 @@ __global__ __launch_bounds__(256) void k_msg(MsgArgs<T> A) {
   if (m >= A.M) return;
   const int64_t rs = A.rslot[m];
   T th, ith;
-  if (A.fp) { th = (T)A.fp->theta_prev; ith = (T)A.fp->inv_thL_prev; }
+  if (A.fp && A.fp_cur) { th = (T)A.fp->theta_cur; ith = (T)A.fp->inv_thL_cur; }
+  else if (A.fp) { th = (T)A.fp->theta_prev; ith = (T)A.fp->inv_thL_prev; }
   else { th = (T)A.theta; ith = (T)A.inv_thL; }
   const bool copy_best = (MODE == MSG_SUBGRAD) && A.improved && A.improved[A.inst[m]];
   const T alpha = (T)A.alpha;
@@ -1148,8 +1197,26 @@ __global__ __launch_bounds__(256) void k_scale_offdiag(double* x, int64_t M, int
 
 static inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
+// LDS shapes compiled per dimension (lanes per cluster); the first is the default.
+int lds_shapes(int De, int* out) {
+  switch (De) {
+    case 4: out[0] = 64; return 1;
+    case 8: out[0] = 16; out[1] = 8; out[2] = 64; return 3;
+    case 16: out[0] = 16; out[1] = 32; out[2] = 64; return 3;
+    case 32: out[0] = 32; out[1] = 64; return 2;
+    case 64: out[0] = 64; return 1;
+    default: return 0;
+  }
+}
+
+template <typename T, bool CPLX, int MODE, int DE, int W>
+static void launch_lds_w(const ClusterArgs<T>& a, hipStream_t s) {
+  constexpr int G = 64 / W;
+  hipLaunchKernelGGL((k_cluster_lds<T, CPLX, DE, MODE, W>), dim3((unsigned)((a.n + G - 1) / G)), dim3(64), 0, s, a);
+}
+
 template <typename T, bool CPLX, int MODE>
-static hipError_t launch_cluster_m(const ClusterArgs<T>& a, int block, hipStream_t s) {
+static hipError_t launch_cluster_m(const ClusterArgs<T>& a, int block, int W, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
   if (a.De == 2 && a.Dc == 0) {
     hipLaunchKernelGGL((k_cluster_reg<T, CPLX, 2, 0, MODE>), dim3(grid_for(a.n, block)), dim3(block), 0, s, a);
@@ -1157,16 +1224,26 @@ static hipError_t launch_cluster_m(const ClusterArgs<T>& a, int block, hipStream
     hipLaunchKernelGGL((k_cluster_reg<T, CPLX, 4, 2, MODE>), dim3(grid_for(a.n, block)), dim3(block), 0, s, a);
   } else if (a.fp != nullptr) {
     return hipErrorInvalidValue;  // fused update only in the register kernel
-  } else if (a.De == 4) {
-    hipLaunchKernelGGL((k_cluster_lds<T, CPLX, 4, MODE>), dim3((unsigned)a.n), dim3(64), 0, s, a);
-  } else if (a.De == 8) {
-    hipLaunchKernelGGL((k_cluster_lds<T, CPLX, 8, MODE>), dim3((unsigned)a.n), dim3(64), 0, s, a);
-  } else if (a.De == 16) {
-    hipLaunchKernelGGL((k_cluster_lds<T, CPLX, 16, MODE>), dim3((unsigned)a.n), dim3(64), 0, s, a);
-  } else if (a.De == 32) {
-    hipLaunchKernelGGL((k_cluster_lds<T, CPLX, 32, MODE>), dim3((unsigned)a.n), dim3(64), 0, s, a);
-  } else if (a.De == 64) {
-    hipLaunchKernelGGL((k_cluster_lds<T, CPLX, 64, MODE>), dim3((unsigned)a.n), dim3(64), 0, s, a);
+  } else if (a.De == 4 && W == 64) {
+    launch_lds_w<T, CPLX, MODE, 4, 64>(a, s);
+  } else if (a.De == 8 && W == 16) {
+    launch_lds_w<T, CPLX, MODE, 8, 16>(a, s);
+  } else if (a.De == 8 && W == 8) {
+    launch_lds_w<T, CPLX, MODE, 8, 8>(a, s);
+  } else if (a.De == 8 && W == 64) {
+    launch_lds_w<T, CPLX, MODE, 8, 64>(a, s);
+  } else if (a.De == 16 && W == 16) {
+    launch_lds_w<T, CPLX, MODE, 16, 16>(a, s);
+  } else if (a.De == 16 && W == 32) {
+    launch_lds_w<T, CPLX, MODE, 16, 32>(a, s);
+  } else if (a.De == 16 && W == 64) {
+    launch_lds_w<T, CPLX, MODE, 16, 64>(a, s);
+  } else if (a.De == 32 && W == 32) {
+    launch_lds_w<T, CPLX, MODE, 32, 32>(a, s);
+  } else if (a.De == 32 && W == 64) {
+    launch_lds_w<T, CPLX, MODE, 32, 64>(a, s);
+  } else if (a.De == 64 && W == 64) {
+    launch_lds_w<T, CPLX, MODE, 64, 64>(a, s);
   } else {
     return hipErrorInvalidValue;
   }
@@ -1174,20 +1251,20 @@ static hipError_t launch_cluster_m(const ClusterArgs<T>& a, int block, hipStream
 }
 
 template <typename T>
-hipError_t launch_cluster(const ClusterArgs<T>& a, bool cplx, int mode, int block, hipStream_t s) {
+hipError_t launch_cluster(const ClusterArgs<T>& a, bool cplx, int mode, int block, int W, hipStream_t s) {
   if (mode == MODE_CERTIFY) {
     if constexpr (std::is_same<T, double>::value) {
-      return cplx ? launch_cluster_m<T, true, MODE_CERTIFY>(a, block, s)
-                  : launch_cluster_m<T, false, MODE_CERTIFY>(a, block, s);
+      return cplx ? launch_cluster_m<T, true, MODE_CERTIFY>(a, block, W, s)
+                  : launch_cluster_m<T, false, MODE_CERTIFY>(a, block, W, s);
     } else {
       return hipErrorInvalidValue;
     }
   }
   if (mode == MODE_GIBBS)
-    return cplx ? launch_cluster_m<T, true, MODE_GIBBS>(a, block, s)
-                : launch_cluster_m<T, false, MODE_GIBBS>(a, block, s);
-  return cplx ? launch_cluster_m<T, true, MODE_GROUND>(a, block, s)
-              : launch_cluster_m<T, false, MODE_GROUND>(a, block, s);
+    return cplx ? launch_cluster_m<T, true, MODE_GIBBS>(a, block, W, s)
+                : launch_cluster_m<T, false, MODE_GIBBS>(a, block, W, s);
+  return cplx ? launch_cluster_m<T, true, MODE_GROUND>(a, block, W, s)
+              : launch_cluster_m<T, false, MODE_GROUND>(a, block, W, s);
 }
 
 template <typename T>
@@ -1320,8 +1397,8 @@ hipError_t launch_scale_offdiag(double* x, int64_t M, int D, bool cplx, double f
 
 template hipError_t launch_extrap<float>(float*, const float*, const float*, double, int64_t, hipStream_t);
 template hipError_t launch_extrap<double>(double*, const double*, const double*, double, int64_t, hipStream_t);
-template hipError_t launch_cluster<float>(const ClusterArgs<float>&, bool, int, int, hipStream_t);
-template hipError_t launch_cluster<double>(const ClusterArgs<double>&, bool, int, int, hipStream_t);
+template hipError_t launch_cluster<float>(const ClusterArgs<float>&, bool, int, int, int, hipStream_t);
+template hipError_t launch_cluster<double>(const ClusterArgs<double>&, bool, int, int, int, hipStream_t);
 template hipError_t launch_msg<float>(const MsgArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_msg<double>(const MsgArgs<double>&, int, int, hipStream_t);
 template hipError_t launch_copy<float>(float*, const float*, int64_t, hipStream_t);

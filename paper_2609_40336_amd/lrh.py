@@ -69,7 +69,7 @@ _lib = None
 EXPORTS = ["lrh_build_clusters", "lrh_query", "lrh_export_clusters", "lrh_export_messages",
            "lrh_dual_eval", "lrh_step_subgrad", "lrh_step_nesterov", "lrh_certify", "lrh_check",
            "lrh_set_jacobi", "lrh_destroy", "lrh_last_error", "lrh_set_params", "lrh_dual_vjp",
-           "lrh_unrolled_bound_grad"]
+           "lrh_unrolled_bound_grad", "lrh_autotune", "lrh_get_shapes"]
 
 
 def load(path: str = LIB_PATH):
@@ -93,6 +93,8 @@ def load(path: str = LIB_PATH):
         "lrh_check": (i32, [vp, vp, C.POINTER(i64), C.POINTER(i64)]),
         "lrh_set_jacobi": (i32, [vp, i32, dbl]),
         "lrh_set_params": (i32, [vp, vp, vp]),
+        "lrh_autotune": (i32, [vp, u32, C.c_char_p, vp]),
+        "lrh_get_shapes": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, C.POINTER(i32)]),
         "lrh_dual_vjp": (i32, [vp, vp, u32, dbl, vp, vp, vp, vp, vp]),
         "lrh_unrolled_bound_grad": (i32, [vp, vp, dbl, dbl, i32, vp, vp, vp, vp, u32, vp]),
         "lrh_destroy": (None, [vp]),
@@ -231,6 +233,23 @@ def lrh_unrolled_bound_grad(h, nu0, beta, L, T, qbar, bound, param_bar=None, nu0
     _check(load().lrh_unrolled_bound_grad(h, _dptr(nu0), float(beta), float(L), int(T), _dptr(qbar),
                                           _dptr(bound), _dptr(param_bar), _dptr(nu0_bar), flags,
                                           _stream(stream)))
+
+
+def lrh_autotune(h, flags=0, cache_path: Optional[str] = None, stream=None):
+    _check(load().lrh_autotune(h, flags, None if cache_path is None else cache_path.encode(), _stream(stream)))
+
+
+def lrh_get_shapes(h):
+    cnt = C.c_int32(0)
+    _check(load().lrh_get_shapes(h, 0, None, None, None, None, None, None, C.byref(cnt)))
+    n = cnt.value
+    De, Dc, blk, W = (np.zeros(n, np.int32) for _ in range(4))
+    nn = np.zeros(n, np.int64)
+    us = np.zeros(n, np.float64)
+    _check(load().lrh_get_shapes(h, n, De.ctypes.data, Dc.ctypes.data, nn.ctypes.data, blk.ctypes.data,
+                                 W.ctypes.data, us.ctypes.data, C.byref(cnt)))
+    return [dict(De=int(De[i]), Dc=int(Dc[i]), n=int(nn[i]), block=int(blk[i]), W=int(W[i]), us=float(us[i]))
+            for i in range(n)]
 
 
 def lrh_destroy(h):
@@ -433,6 +452,13 @@ class Problem:
 
     def set_jacobi(self, max_sweeps: int, rel_tol: float = 0.0):
         lrh_set_jacobi(self.h, max_sweeps, rel_tol)
+
+    def autotune(self, f32: bool = False, cache_path: Optional[str] = None, stream=None):
+        lrh_autotune(self.h, LRH_F32 if f32 else 0, cache_path, stream)
+        return self.shapes()
+
+    def shapes(self):
+        return lrh_get_shapes(self.h)
 
 
 def nesterov_schedule(beta0: float, beta_max: float, total_iters: int):

@@ -349,3 +349,48 @@ def test_health_flags():
         P.check()
     assert e.value.code == 6
     assert math.isnan(q.item())
+
+
+@pytest.mark.parametrize("f32", [False, True])
+@pytest.mark.parametrize("name", ["plaq", "interval_Y4"])
+def test_graph_replayed_general_problem_equals_plain(name, f32):
+    """LRH_FUSED on a problem with larger clusters replays the plain launches from a captured
+    graph with per-iteration scalars in device memory: identical bits to the plain loop."""
+    lrh = lrhmod()
+    say(f"[graph==plain] {name} f32={f32}")
+    d = (W.tfim_plaquette_batch([3, 4, 5], [0.9, 2.1, 3.3]) if name == "plaq"
+         else W.interval_chain_gue(10, 4, 0.1, seed=3))
+    P = lrh.Problem(d, 0)
+    res = []
+    for fused in (False, True):
+        nu = P.zeros(f32)
+        ze = P.zeros(f32)
+        for beta, K in [(1.0, 70), (2.0, 64), (4.0, 5)]:
+            st = P.new_nesterov_state(beta)
+            P.step_nesterov(nu, ze, st, K, fused=fused)
+        torch.cuda.synchronize()
+        res.append((nu.clone(), ze.clone()))
+    assert torch.equal(res[0][0], res[1][0])
+    assert torch.equal(res[0][1], res[1][1])
+
+
+def test_autotuned_shapes_agree_and_cache_round_trip(tmp_path):
+    """Every launch shape computes the same cluster arithmetic: after autotuning, dual values
+    agree with the default shapes to rounding, and a second build reads the cached choice."""
+    lrh = lrhmod()
+    say("[autotune] plaquettes + triangles")
+    for d in [W.tfim_plaquette_batch([6, 5], [1.0, 2.0]), W.xxz_triangular(6, 0.5, seed=1),
+              W.random_chain(12, seed=3, top_len=5, subintervals=True)]:
+        P = lrh.Problem(d, 0)
+        R = O.Relaxation(d)
+        nu = P.from_dense(R.to_pairs(R.draw(4, 0.4)))
+        q0, g0, _ = P.dual_eval(nu, 1.3, grad=True)
+        cache = str(tmp_path / "shapes.json")
+        shapes = P.autotune(False, cache)
+        q1, g1, _ = P.dual_eval(nu, 1.3, grad=True)
+        torch.cuda.synchronize()
+        assert torch.allclose(q0, q1, rtol=0, atol=1e-12 * d.n_sites)
+        assert torch.allclose(g0, g1, rtol=0, atol=1e-12)
+        P2 = lrh.Problem(d, 0)
+        shapes2 = P2.autotune(False, cache)
+        assert [(s["block"], s["W"]) for s in shapes] == [(s["block"], s["W"]) for s in shapes2]
