@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -182,6 +184,64 @@ def cpu_baseline(desc, budget_s=15.0):
                        f"one thread), {dt:.1f} s")
 
 
+def bench_rate(workload, args, torch):
+    """Per-iteration rate of the batched Algorithm 2 on a large workload (cluster updates/s),
+    FP32 iterations replayed from captured graphs with autotuned launch shapes, one FP64
+    certification per step.  beta doubles every 250 iterations from 1 (no closed-form
+    reference energy, so no time-to-gap is reported for these workloads)."""
+    import lrh_workloads as W
+    from paper_2609_40336_amd import lrh
+    t0 = time.perf_counter()
+    if workload == "c4":
+        desc = W.workload_c4()
+        name = "tfim_plaquette_sweep_512_L8to64_h0.5to4_nesterov_fp32"
+    elif workload.startswith("c3k"):
+        k = int(workload[3:])
+        desc = W.workload_c3(k)
+        name = f"interval_chain_gue_n4096_eps0.1_Y{k}_nesterov_fp32"
+    else:
+        raise SystemExit(f"unknown workload {workload}")
+    P = lrh.Problem(desc, 0)
+    t_build = time.perf_counter() - t0
+    print(f"[bench] {desc.name}: {P.n_clusters} clusters, {P.n_msgs} messages, built in {t_build:.1f} s",
+          file=sys.stderr, flush=True)
+    shapes = P.autotune(True, os.path.join(os.environ.get("TMPDIR", "/tmp"), "lrh_shapes.json"))
+    print(f"[bench] shapes {shapes}", file=sys.stderr, flush=True)
+    sched = [(2.0 ** s, 250) for s in range(64)]
+    S = Solver(P, True, True, sched)
+    for _ in range(args.warmup):
+        S.run(ITERS_PER_STEP)
+    torch.cuda.synchronize()
+    S = Solver(P, True, True, sched)
+    q = torch.zeros((args.steps, P.n_inst), dtype=torch.float64, device="cuda")
+    mg = torch.zeros_like(q)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for k in range(args.steps):
+        S.run(ITERS_PER_STEP)
+        lrh.lrh_certify(P.h, S.nu, lrh.LRH_F32, q[k], mg[k])
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    iters = args.steps * ITERS_PER_STEP
+    nchk, nnf = P.check()
+    n_sites = np.bincount(desc.site_instance, minlength=desc.n_instances)
+    bound = (q[-1] - mg[-1]).cpu().numpy()
+    out = {
+        "metric": "cluster updates/s", "value": P.n_clusters * iters / sec, "unit": "cluster updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 iterations, f64 certify", "data": "synthetic",
+        "config": {"workload": name, "clusters": P.n_clusters, "messages": P.n_msgs,
+                   "instances": P.n_inst, "iters_per_step": ITERS_PER_STEP},
+        "us_per_iteration": sec / iters * 1e6,
+        "mean_certified_bound_per_site": float(np.mean(bound / n_sites)),
+        "shapes": shapes, "jacobi_noconv": nchk, "nonfinite": nnf,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,6 +250,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--workload", default="c2",
+                    help="c2 (default: the 32x32 Heisenberg solve), c4 (512 plaquette lattices), c3k<k>")
     ap.add_argument("--profile-traffic", action="store_true",
                     help="short run for hardware counters: 4 fused graph chunks, then a 64 MiB "
                          "device copy (a plain copy kernel of known size, for calibration)")
@@ -202,6 +264,10 @@ def main():
     import lrh_workloads as W
     from paper_2609_40336_amd import lrh
 
+    if args.workload != "c2":
+        if args.steps == TOTAL_ITERS // ITERS_PER_STEP:
+            args.steps = 4
+        return bench_rate(args.workload, args, torch)
     desc = W.workload_c2(32)
     P = lrh.Problem(desc, 0)
     schedule = lrh.nesterov_schedule(BETA0, BETA_MAX, TOTAL_ITERS)

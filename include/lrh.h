@@ -13,8 +13,8 @@
  *     "device" pointers are HIP device memory owned by the caller; the call
  *     enqueues work on `stream` and returns without waiting: results are valid once
  *     the stream is synchronised.
- *   - Sites are spin-1/2 (d = 2) in this release; clusters hold at most 6 sites
- *     (D_e <= 64).  A cluster's basis is the big-endian product basis of its sites in
+ *   - Sites are spin-1/2 (d = 2) in this release; clusters hold at most 8 sites
+ *     (D_e <= 256).  A cluster's basis is the big-endian product basis of its sites in
  *     ascending order (first site most significant), so A_{s0} (x) B_{s1} = kron(A, B).
  *   - Message layout (structure of arrays).  Messages nu_{e->f} (e a cluster, f one of
  *     its covering children) are grouped into buckets by D_f.  Bucket b holds M_b
@@ -43,7 +43,7 @@ typedef enum {
   LRH_OK = 0,
   LRH_E_INVALID = 1,      /* bad argument: non-Hermitian term, cluster spanning instances,
                              beta <= 0, Lipschitz <= 0, null required pointer, ...          */
-  LRH_E_UNSUPPORTED = 2,  /* D_e > 64, site dimension != 2, mixed child dimensions        */
+  LRH_E_UNSUPPORTED = 2,  /* D_e > 256, site dimension != 2, mixed child dimensions       */
   LRH_E_NOMEM = 3,        /* device or host allocation failed                             */
   LRH_E_DEVICE = 4,       /* a HIP runtime call failed                                    */
   LRH_E_NOCONV = 5,       /* a Jacobi eigen-solve hit its sweep cap (see lrh_check)       */
@@ -131,7 +131,7 @@ typedef struct {
  * call returns LRH_E_INVALID).
  * Errors: LRH_E_INVALID (non-Hermitian term beyond 1e-12 * max|h|, site out of range,
  * unsorted or repeated sites, cluster spanning instances), LRH_E_UNSUPPORTED (site
- * dimension != 2, a cluster with more than 6 sites, a cluster whose children have
+ * dimension != 2, a cluster with more than 8 sites, a cluster whose children have
  * different dimensions), LRH_E_NOMEM, LRH_E_DEVICE.  On success *out owns device
  * memory until lrh_destroy. */
 lrh_status lrh_build_clusters(const lrh_problem_desc* desc, int hip_device, lrh_problem* out);
@@ -219,7 +219,7 @@ lrh_status lrh_set_params(lrh_problem p, const double* params_dev, hipStream_t s
  * beta == 0 differentiates Q itself with the ground projector (gbar must be NULL).
  * nu_bar_dev: device, nu_len doubles (or NULL); param_bar_dev: device double[n_params] or NULL.
  * flags: LRH_PACKED_COTANGENT; LRH_F32 is not supported (LRH_E_UNSUPPORTED), nor complex
- * clusters with D_e = 64.
+ * clusters with D_e = 64, nor any cluster with D_e > 64.
  * Errors: LRH_E_INVALID (null nu, beta < 0, gbar with beta == 0). */
 lrh_status lrh_dual_vjp(lrh_problem p, const void* nu, uint32_t flags, double beta, const double* qbar_dev,
                         const void* gbar_dev, void* nu_bar_dev, double* param_bar_dev, hipStream_t stream);

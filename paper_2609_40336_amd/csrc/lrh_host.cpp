@@ -39,7 +39,7 @@ lrh_status fail(lrh_status s, const std::string& msg) {
       return fail(LRH_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e__));        \
   } while (0)
 
-constexpr int kMaxSites = 6;  // D_e <= 64 for spin-1/2 sites
+constexpr int kMaxSites = 8;  // D_e <= 256 for spin-1/2 sites
 
 struct Key {
   int k = 0;
@@ -89,6 +89,8 @@ struct MBucket {
 
 template <typename T>
 struct Work {
+  T* big = nullptr;               // scratch slabs of the large-cluster kernel
+  int64_t big_slab = 0, big_blocks = 0;
   T* Tb[2] = {nullptr, nullptr};  // partial traces, message layout
   T* Rb[2] = {nullptr, nullptr};  // marginals of clusters with parents
   T* W[4] = {nullptr, nullptr, nullptr, nullptr};  // fused ping-pong state: nu1, ze1, nu2, ze2
@@ -235,7 +237,7 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
   std::vector<Key> keys;
   auto make_key = [&](const int32_t* s, int k, Key& key) -> lrh_status {
     if (k <= 0) return fail(LRH_E_INVALID, "empty cluster or term support");
-    if (k > kMaxSites) return fail(LRH_E_UNSUPPORTED, "cluster with more than 6 sites (D_e > 64)");
+    if (k > kMaxSites) return fail(LRH_E_UNSUPPORTED, "cluster with more than 8 sites (D_e > 256)");
     key.k = k;
     for (int i = 0; i < k; ++i) {
       if (s[i] < 0 || s[i] >= n) return fail(LRH_E_INVALID, "site index out of range");
@@ -703,6 +705,20 @@ template <typename T>
 lrh_status ensure_work(lrh_problem_s* P, bool fused) {
   Work<T>& w = P->work<T>();
   lrh_status st;
+  if (!w.big) {
+    int64_t nbig = 0;
+    int Dmax = 0;
+    for (const CBucket& B : P->cb)
+      if (B.De >= 128) {
+        nbig = std::max<int64_t>(nbig, B.n);
+        Dmax = std::max(Dmax, B.De);
+      }
+    if (nbig > 0) {
+      w.big_slab = (int64_t)(P->cplx ? 6 : 3) * Dmax * Dmax;
+      w.big_blocks = std::min<int64_t>(nbig, 512);
+      if ((st = P->dalloc(&w.big, w.big_slab * w.big_blocks)) != LRH_OK) return st;
+    }
+  }
   if (!w.Tb[0]) {
     if ((st = P->dalloc(&w.Tb[0], std::max<int64_t>(P->nu_len, 1))) != LRH_OK) return st;
     if ((st = P->dalloc(&w.Rb[0], std::max<int64_t>(P->R_len, 1))) != LRH_OK) return st;
@@ -748,6 +764,12 @@ ClusterArgs<T> base_args(lrh_problem_s* P, const CBucket& B) {
   if (B.mb_self >= 0) {
     a.Mp = P->mb[B.mb_self].M;
     a.S = P->mb[B.mb_self].S;
+  }
+  if (B.De >= 128) {
+    Work<T>& w = P->work<T>();
+    a.big_scratch = w.big;
+    a.big_slab = w.big_slab;
+    a.big_blocks = w.big_blocks;
   }
   return a;
 }
@@ -1109,7 +1131,7 @@ lrh_status vjp_pass(lrh_problem_s* P, const double* nu, double beta, const doubl
     a.marg_off = P->marg_off;
     a.beta = beta;
     hipError_t e = launch_cluster_vjp(a, P->cplx, beta > 0 ? MODE_GIBBS : MODE_GROUND, s);
-    if (e == hipErrorInvalidValue) return fail(LRH_E_UNSUPPORTED, "adjoint of complex clusters with D_e = 64");
+    if (e == hipErrorInvalidValue) return fail(LRH_E_UNSUPPORTED, "adjoint of complex clusters with D_e = 64 or of D_e > 64");
     HIP_TRY(e);
   }
   return LRH_OK;
@@ -1432,6 +1454,10 @@ lrh_status lrh_certify(lrh_problem p, const void* nu, uint32_t flags, double* q_
   if (!p || !nu || !q_dev || !margin_dev) return fail(LRH_E_INVALID, "null argument");
   if (p->host_only) return fail(LRH_E_INVALID, "problem was built without a device");
   DeviceGuard guard(p->device);
+  {
+    lrh_status wst = ensure_work<double>(p, false);
+    if (wst != LRH_OK) return wst;
+  }
   const double* nu64 = (const double*)nu;
   if (flags & LRH_F32) {
     if (!p->nu64_tmp) {

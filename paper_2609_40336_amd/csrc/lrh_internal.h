@@ -84,6 +84,10 @@ struct ClusterArgs {
   double gb_offscale;            // scale of off-diagonal gbar elements (1, or 1/2 for packed coords)
   const double* qbar;            // [n_inst] cotangent of Q per instance (nullable: 0)
   const int32_t* cinst;          // [n_clusters] instance of every library cluster
+  // ---- large clusters (De >= 128): per-workgroup scratch slab in device memory ----
+  void* big_scratch;             // big_blocks slabs of big_slab elements of T
+  int64_t big_slab;
+  int64_t big_blocks;
 };
 
 template <typename T>

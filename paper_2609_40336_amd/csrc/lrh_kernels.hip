@@ -22,8 +22,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <type_traits>
 
 namespace lrh {
 
@@ -852,6 +854,320 @@ __global__ __launch_bounds__(64) void k_cluster_lds(ClusterArgs<T> A) {
 }
 
 // ------------------------------------------------------------------------------------------
+// large clusters (De = 128, 256): one 1024-thread workgroup per cluster
+// ------------------------------------------------------------------------------------------
+//
+// A De x De complex matrix and its eigenvectors do not fit one CU's LDS, so theta_e, U and
+// rho live in a per-workgroup scratch slab in HBM (the workgroup walks clusters with a grid
+// stride); the round-robin parallel Jacobi applies De/2 disjoint rotations per round with all
+// 1024 threads.  The reconstruction rho = W W^H with W = U diag(sqrt p) is a dense contraction
+// and runs on the matrix cores: v_mfma_f32_32x32x2_f32 (FP32) / v_mfma_f64_16x16x4_f64 (FP64),
+// four real products per complex tile.
+
+typedef float mfma_f32x16 __attribute__((ext_vector_type(16)));
+typedef double mfma_f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  T s = T(0);
+  const int nw = blockDim.x / 64;
+  for (int i = 0; i < nw; ++i) s += red[i];
+  __syncthreads();
+  return s;
+}
+template <typename T>
+__device__ __forceinline__ T block_min(T v, T* red) {
+  v = wave_min(v);
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  T s = red[0];
+  const int nw = blockDim.x / 64;
+  for (int i = 1; i < nw; ++i) s = fmin(s, red[i]);
+  __syncthreads();
+  return s;
+}
+
+// rho tile accumulation on the matrix cores; (wr, wi) = W rows, rho written to (orr, ori)
+template <typename T, bool CPLX>
+__device__ void mfma_rebuild(const T* ur, const T* ui, const T* sq, T* orr, T* ori, int D) {
+  const int wave = threadIdx.x / 64, l = threadIdx.x % 64, nw = blockDim.x / 64;
+  if constexpr (std::is_same<T, float>::value) {
+    const int nt = D / 32;
+    for (int tile = wave; tile < nt * nt; tile += nw) {
+      const int I = tile / nt, J = tile % nt;
+      mfma_f32x16 cr = {0}, ci = {0};
+      const int i = I * 32 + (l % 32), j = J * 32 + (l % 32);
+      for (int k0 = 0; k0 < D; k0 += 2) {
+        const int k = k0 + l / 32;
+        const float s = sq[k];
+        const float ar = ur[(int64_t)i * D + k] * s, br = ur[(int64_t)j * D + k] * s;
+        cr = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, cr, 0, 0, 0);
+        if constexpr (CPLX) {
+          const float ai = ui[(int64_t)i * D + k] * s, bi = ui[(int64_t)j * D + k] * s;
+          cr = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bi, cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, ci, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_32x32x2f32(-ar, bi, ci, 0, 0, 0);
+        }
+      }
+      for (int r = 0; r < 16; ++r) {
+        const int row = I * 32 + 8 * (r / 4) + 4 * (l / 32) + (r % 4), col = J * 32 + (l % 32);
+        orr[(int64_t)row * D + col] = cr[r];
+        if constexpr (CPLX) ori[(int64_t)row * D + col] = (row == col) ? 0.f : ci[r];
+      }
+    }
+  } else {
+    const int nt = D / 16;
+    for (int tile = wave; tile < nt * nt; tile += nw) {
+      const int I = tile / nt, J = tile % nt;
+      mfma_f64x4 cr = {0}, ci = {0};
+      const int i = I * 16 + (l % 16), j = J * 16 + (l % 16);
+      for (int k0 = 0; k0 < D; k0 += 4) {
+        const int k = k0 + l / 16;
+        const double s = sq[k];
+        const double ar = ur[(int64_t)i * D + k] * s, br = ur[(int64_t)j * D + k] * s;
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, cr, 0, 0, 0);
+        if constexpr (CPLX) {
+          const double ai = ui[(int64_t)i * D + k] * s, bi = ui[(int64_t)j * D + k] * s;
+          cr = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, ci, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar, bi, ci, 0, 0, 0);
+        }
+      }
+      for (int r = 0; r < 4; ++r) {
+        const int row = I * 16 + 4 * r + (l / 16), col = J * 16 + (l % 16);
+        orr[(int64_t)row * D + col] = cr[r];
+        if constexpr (CPLX) ori[(int64_t)row * D + col] = (row == col) ? 0.0 : ci[r];
+      }
+    }
+  }
+}
+
+template <typename T, bool CPLX, int MODE>
+__global__ __launch_bounds__(1024) void k_cluster_big(ClusterArgs<T> A, T* scratch, int64_t slab) {
+  constexpr bool VEC = (MODE != MODE_CERTIFY);
+  __shared__ T cs_c[128], cs_s[128], cs_er[128], cs_ei[128], cs_app[128], cs_aqq[128];
+  __shared__ int cs_p[128], cs_q[128];
+  __shared__ T red[16];
+  __shared__ T sp[256];
+  const int D = A.De;
+  const int NB = log2i(D);
+  const int NP = D / 2;
+  const int64_t DD = (int64_t)D * D;
+  T* ar = scratch + (int64_t)blockIdx.x * slab;
+  T* ai = ar + DD;   // unused for real problems
+  T* ur = ar + (CPLX ? 2 : 1) * DD;
+  T* ui = ur + DD;
+  T* rr_ = ar + (CPLX ? 4 : 2) * DD;
+  T* ri_ = rr_ + DD;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const T th = A.tab ? (T)A.tab->theta_cur : (T)A.theta;
+  const T beta = A.tab ? (T)A.tab->beta : (T)A.beta;
+  for (int64_t c = blockIdx.x; c < A.n; c += gridDim.x) {
+    // ---- a2: assemble theta_e ----
+    const int64_t ho = A.hoff[c];
+    const int Dc = A.Dc;
+    T my_n2 = T(0);
+    for (int64_t idx = tid; idx < DD; idx += nth) {
+      const int i = (int)(idx / D), j = (int)(idx % D);
+      T vr = T(0), vi = T(0);
+      if (ho >= 0) herm_elem<T>([&](int k) { return (T)A.h[ho + k]; }, i, j, D, CPLX, vr, vi);
+      for (int s = 0; s < A.maxch; ++s) {
+        const int m = A.ch[(int64_t)s * A.n + c];
+        if (m < 0) continue;
+        const int mask = A.chmask[(int64_t)s * A.n + c];
+        if (((i ^ j) & ~mask & (D - 1)) != 0) continue;
+        const int a = pext_rt(i, mask, NB), b = pext_rt(j, mask, NB);
+        T er, ei;
+        if (A.ze_c)
+          herm_elem<T>([&](int k) { const int64_t o = (int64_t)k * A.Mc + m;
+                                    return extrap<T>(A.nu_c[o], A.ze_c[o], th); }, a, b, Dc, CPLX, er, ei);
+        else
+          herm_elem<T>([&](int k) { return A.nu_c[(int64_t)k * A.Mc + m]; }, a, b, Dc, CPLX, er, ei);
+        vr -= er;
+        vi -= ei;
+      }
+      for (int s = 0; s < A.maxpar; ++s) {
+        const int m = A.par[(int64_t)s * A.n + c];
+        if (m < 0) continue;
+        T er, ei;
+        if (A.ze_p)
+          herm_elem<T>([&](int k) { const int64_t o = (int64_t)k * A.Mp + m;
+                                    return extrap<T>(A.nu_p[o], A.ze_p[o], th); }, i, j, D, CPLX, er, ei);
+        else
+          herm_elem<T>([&](int k) { return A.nu_p[(int64_t)k * A.Mp + m]; }, i, j, D, CPLX, er, ei);
+        vr += er;
+        vi += ei;
+      }
+      ar[idx] = vr;
+      if constexpr (CPLX) ai[idx] = vi;
+      if constexpr (VEC) {
+        ur[idx] = (i == j) ? T(1) : T(0);
+        if constexpr (CPLX) ui[idx] = T(0);
+      }
+      my_n2 = dfma<T>(vr, vr, my_n2);
+      if constexpr (CPLX) my_n2 = dfma<T>(vi, vi, my_n2);
+    }
+    const T nrm2 = block_sum(my_n2, red);
+    // ---- a3: parallel cyclic Jacobi over the slab ----
+    const T tol2 = (T)(A.tol * A.tol) * nrm2;
+    bool conv = false;
+    for (int sweep = 0; sweep <= A.max_sweeps; ++sweep) {
+      T off = T(0);
+      for (int64_t idx = tid; idx < DD; idx += nth) {
+        if (idx / D != idx % D) {
+          off = dfma<T>(ar[idx], ar[idx], off);
+          if constexpr (CPLX) off = dfma<T>(ai[idx], ai[idx], off);
+        }
+      }
+      off = block_sum(off, red);
+      if (off <= tol2) { conv = true; break; }
+      if (sweep == A.max_sweeps) break;
+      for (int r = 0; r < D - 1; ++r) {
+        if (tid < NP) {
+          int p, q;
+          rr_pair(r, tid, D, p, q);
+          const T xr = ar[(int64_t)p * D + q];
+          const T xi = CPLX ? ai[(int64_t)p * D + q] : T(0);
+          const T rr = CPLX ? dsqrt<T>(dfma<T>(xr, xr, xi * xi)) : fabs(xr);
+          T t = T(0), cc = T(1), ss = T(0), er = T(1), ei = T(0);
+          const T app = ar[(int64_t)p * D + p], aqq = ar[(int64_t)q * D + q];
+          if (rr != T(0)) {
+            rot_params<T>(app, aqq, rr, t, cc, ss);
+            er = xr / rr;
+            ei = CPLX ? -xi / rr : T(0);
+          }
+          cs_p[tid] = p; cs_q[tid] = q;
+          cs_c[tid] = cc; cs_s[tid] = ss; cs_er[tid] = er; cs_ei[tid] = ei;
+          cs_app[tid] = app - t * rr;
+          cs_aqq[tid] = aqq + t * rr;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < D * NP; idx += nth) {
+          const int i = idx % D, k = idx / D;
+          const int p = cs_p[k], q = cs_q[k];
+          const T cc = cs_c[k], ss = cs_s[k], er = cs_er[k], ei = cs_ei[k];
+          {
+            const int64_t op = (int64_t)i * D + p, oq = (int64_t)i * D + q;
+            T pr = ar[op], qr = ar[oq];
+            T pi = CPLX ? ai[op] : T(0), qi = CPLX ? ai[oq] : T(0);
+            T wr = CPLX ? qr * er - qi * ei : qr * er;
+            T wi = CPLX ? qr * ei + qi * er : T(0);
+            ar[op] = cc * pr - ss * wr;
+            ar[oq] = ss * pr + cc * wr;
+            if constexpr (CPLX) { ai[op] = cc * pi - ss * wi; ai[oq] = ss * pi + cc * wi; }
+          }
+          if constexpr (VEC) {
+            const int64_t op = (int64_t)i * D + p, oq = (int64_t)i * D + q;
+            T pr = ur[op], qr = ur[oq];
+            T pi = CPLX ? ui[op] : T(0), qi = CPLX ? ui[oq] : T(0);
+            T wr = CPLX ? qr * er - qi * ei : qr * er;
+            T wi = CPLX ? qr * ei + qi * er : T(0);
+            ur[op] = cc * pr - ss * wr;
+            ur[oq] = ss * pr + cc * wr;
+            if constexpr (CPLX) { ui[op] = cc * pi - ss * wi; ui[oq] = ss * pi + cc * wi; }
+          }
+        }
+        __syncthreads();
+        for (int idx = tid; idx < D * NP; idx += nth) {
+          const int j = idx % D, k = idx / D;
+          const int p = cs_p[k], q = cs_q[k];
+          const T cc = cs_c[k], ss = cs_s[k], er = cs_er[k], ei = -cs_ei[k];
+          const int64_t op = (int64_t)p * D + j, oq = (int64_t)q * D + j;
+          T pr = ar[op], qr = ar[oq];
+          T pi = CPLX ? ai[op] : T(0), qi = CPLX ? ai[oq] : T(0);
+          T wr = CPLX ? qr * er - qi * ei : qr * er;
+          T wi = CPLX ? qr * ei + qi * er : T(0);
+          ar[op] = cc * pr - ss * wr;
+          ar[oq] = ss * pr + cc * wr;
+          if constexpr (CPLX) { ai[op] = cc * pi - ss * wi; ai[oq] = ss * pi + cc * wi; }
+        }
+        __syncthreads();
+        if (tid < NP) {
+          const int p = cs_p[tid], q = cs_q[tid];
+          ar[(int64_t)p * D + p] = cs_app[tid];
+          ar[(int64_t)q * D + q] = cs_aqq[tid];
+          ar[(int64_t)p * D + q] = T(0);
+          ar[(int64_t)q * D + p] = T(0);
+          if constexpr (CPLX) {
+            ai[(int64_t)p * D + p] = T(0); ai[(int64_t)q * D + q] = T(0);
+            ai[(int64_t)p * D + q] = T(0); ai[(int64_t)q * D + p] = T(0);
+          }
+        }
+        __syncthreads();
+      }
+    }
+    if (!conv && tid == 0 && A.noconv) atomicAdd(A.noconv, 1ull);
+    T lmin = T(INFINITY);
+    for (int k = tid; k < D; k += nth) lmin = fmin(lmin, ar[(int64_t)k * D + k]);
+    lmin = block_min(lmin, red);
+    if (tid == 0 && !isfinite((double)lmin) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
+    const int32_t gid = A.gid[c];
+    if constexpr (MODE == MODE_CERTIFY) {
+      if (tid == 0) {
+        A.scal[gid] = (double)lmin;
+        A.scal2[gid] = 8.0 * D * DBL_EPSILON * sqrt((double)nrm2);
+      }
+    } else {
+      // ---- a4: weights (sqrt stored for the W W^H product) ----
+      T w = T(0);
+      for (int k = tid; k < D; k += nth) {
+        const T lk = ar[(int64_t)k * D + k];
+        T v;
+        if constexpr (MODE == MODE_GIBBS) v = dexp<T>(-beta * (lk - lmin));
+        else v = (lk <= lmin + (T)A.tau_rel * fmax(T(1), dsqrt<T>(nrm2))) ? T(1) : T(0);
+        sp[k] = v;
+        w += v;
+      }
+      const T Z = block_sum(w, red);
+      for (int k = tid; k < D; k += nth) sp[k] = dsqrt<T>(sp[k] / Z);
+      if (tid == 0 && A.scal) A.scal[gid] = (MODE == MODE_GIBBS) ? (double)(lmin - dlog<T>(Z) / beta) : (double)lmin;
+      __syncthreads();
+      mfma_rebuild<T, CPLX>(ur, ui, sp, rr_, ri_, D);
+      __syncthreads();
+      // ---- a5: outputs ----
+      const int64_t rs_self = A.rslot ? A.rslot[c] : -1;
+      const int NCE = CPLX ? D * D : D * (D + 1) / 2;
+      for (int k = tid; k < NCE; k += nth) {
+        int i, j;
+        bool im;
+        decode_comp(k, D, i, j, im);
+        const T v = im ? ri_[(int64_t)i * D + j] : rr_[(int64_t)i * D + j];
+        if (rs_self >= 0 && A.R) A.R[(int64_t)k * A.S + rs_self] = v;
+        if (A.marg) A.marg[A.marg_off[gid] + k] = v;
+      }
+      if (A.Tout && Dc > 0) {
+        const int NR = D / Dc;
+        const int NCC = CPLX ? Dc * Dc : Dc * (Dc + 1) / 2;
+        for (int s = 0; s < A.maxch; ++s) {
+          const int m = A.ch[(int64_t)s * A.n + c];
+          if (m < 0) continue;
+          const int mask = A.chmask[(int64_t)s * A.n + c];
+          for (int k = tid; k < NCC; k += nth) {
+            int a, b;
+            bool im;
+            decode_comp(k, Dc, a, b, im);
+            T sum = T(0);
+            for (int x = 0; x < NR; ++x) {
+              const int i = pdep_rt(a, x, mask, NB), j = pdep_rt(b, x, mask, NB);
+              sum += im ? ri_[(int64_t)i * D + j] : rr_[(int64_t)i * D + j];
+            }
+            A.Tout[(int64_t)k * A.Mc + m] = sum;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // adjoint (a9): VJP of (Q_beta, grad Q_beta) through one cluster
 // ------------------------------------------------------------------------------------------
 //
@@ -1205,6 +1521,8 @@ int lds_shapes(int De, int* out) {
     case 16: out[0] = 16; out[1] = 32; out[2] = 64; return 3;
     case 32: out[0] = 32; out[1] = 64; return 2;
     case 64: out[0] = 64; return 1;
+    case 128: out[0] = 1024; return 1;
+    case 256: out[0] = 1024; return 1;
     default: return 0;
   }
 }
@@ -1244,6 +1562,10 @@ static hipError_t launch_cluster_m(const ClusterArgs<T>& a, int block, int W, hi
     launch_lds_w<T, CPLX, MODE, 32, 64>(a, s);
   } else if (a.De == 64 && W == 64) {
     launch_lds_w<T, CPLX, MODE, 64, 64>(a, s);
+  } else if ((a.De == 128 || a.De == 256) && a.big_scratch != nullptr) {
+    const unsigned grid = (unsigned)std::min<int64_t>(a.n, a.big_blocks);
+    hipLaunchKernelGGL((k_cluster_big<T, CPLX, MODE>), dim3(grid), dim3(1024), 0, s, a, (T*)a.big_scratch,
+                       a.big_slab);
   } else {
     return hipErrorInvalidValue;
   }

@@ -63,6 +63,10 @@ PROBLEMS = {
     "plaq_batch_ragged": lambda: W.tfim_plaquette_batch([3, 4, 5], [0.7, 2.0, 3.5]),
     "xxz_tri3": lambda: W.xxz_triangular(3, 0.5, seed=5),
     "ising_tree_rot": lambda: W.classical_ising_tree(9, 4, rotate=True),
+    "gue_Y7": lambda: W.interval_chain_gue(9, 7, 0.1, seed=3),
+    "gue_Y8": lambda: W.interval_chain_gue(10, 8, 0.1, seed=3),
+    "randchain_Y7_real": lambda: W.with_tops(W.heisenberg_chain(9, field_x=0.4),
+                                             [tuple(range(i, i + 7)) for i in range(3)], subintervals=True),
 }
 
 
@@ -91,7 +95,7 @@ def test_dual_eval_fp64(name, beta):
     assert P.check() == (0, 0)
 
 
-@pytest.mark.parametrize("name", ["c1_tfim16_complex", "randchain_Y4", "plaq_batch_ragged", "gue_Y5"])
+@pytest.mark.parametrize("name", ["c1_tfim16_complex", "randchain_Y4", "plaq_batch_ragged", "gue_Y5", "gue_Y8"])
 def test_dual_eval_fp32(name):
     """FP32 iteration arithmetic: values within 2e-5 per site, gradients within 5e-5."""
     lrh = lrhmod()
@@ -110,7 +114,7 @@ def test_dual_eval_fp32(name):
     assert max_pair_err(P.to_dense(g), R.to_pairs(g_o)) < 5e-5
 
 
-@pytest.mark.parametrize("name", ["c1_tfim16_complex", "randchain_Y6", "plaq_batch_ragged", "xxz_tri3"])
+@pytest.mark.parametrize("name", ["c1_tfim16_complex", "randchain_Y6", "plaq_batch_ragged", "xxz_tri3", "gue_Y8"])
 def test_certify_fp64_and_from_fp32(name):
     lrh = lrhmod()
     say(f"[certify] {name}")
@@ -197,6 +201,7 @@ NEST = {
     "randchain_Y3": (lambda: W.random_chain(7, seed=5, top_len=3, subintervals=True), [(1.0, 25), (3.0, 25)]),
     "plaq_batch": (lambda: W.tfim_plaquette_batch([3, 4], [1.0, 2.5]), [(2.0, 40)]),
     "xxz_tri3": (lambda: W.xxz_triangular(3, 0.5, seed=2), [(4.0, 40)]),
+    "gue_Y8": (lambda: W.interval_chain_gue(9, 8, 0.1, seed=3), [(2.0, 6), (8.0, 6)]),
 }
 
 

@@ -91,8 +91,8 @@ def test_validation_errors():
     sp.site_instance = np.array([0, 0, 1, 1], dtype=np.int32)
     sp.n_instances = 2
     _expect(1, lambda: lrh.Problem(sp, -1))
-    # 7-site cluster
-    big = W.with_tops(W.tfim_chain(8, 1.0, 0.5), [tuple(range(7))])
+    # 9-site cluster (D_e = 512)
+    big = W.with_tops(W.tfim_chain(10, 1.0, 0.5), [tuple(range(9))])
     _expect(2, lambda: lrh.Problem(big, -1))
     # unsorted top cluster
     uns = W.tfim_chain(4, 1.0, 0.5)
