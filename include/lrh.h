@@ -260,6 +260,13 @@ lrh_status lrh_autotune(lrh_problem p, uint32_t flags, const char* cache_path, h
 lrh_status lrh_get_shapes(lrh_problem p, int32_t cap, int32_t* De, int32_t* Dc, int64_t* n, int32_t* block,
                           int32_t* W, double* us, int32_t* count);
 
+/* Force the launch shape of every cluster bucket of dimension De for the precision of `flags`
+ * (LRH_F32: FP32 iterations, else FP64): block = threads per block of the register kernel
+ * (64, 128, 256), W = 1 for one lane per cluster (register kernel) or the lanes per cluster of
+ * the LDS kernel.  Errors: LRH_E_INVALID (no such bucket, bad block), LRH_E_UNSUPPORTED (shape
+ * not compiled for that bucket). */
+lrh_status lrh_set_shape(lrh_problem p, int32_t De, int32_t block, int32_t W, uint32_t flags);
+
 /* Jacobi sweep cap (default 30) and relative off-diagonal tolerance (0 = default:
  * 4 eps of the iteration precision). */
 lrh_status lrh_set_jacobi(lrh_problem p, int32_t max_sweeps, double rel_tol);

@@ -65,7 +65,8 @@ struct KeyHash {
 struct CBucket {
   int De = 0, Dc = 0, maxch = 0, maxpar = 0;
   int block = 64;     // threads per block (register kernels)
-  int W = 64;         // lanes per cluster (LDS kernels)
+  int W = 64;         // FP32 iterations: lanes per cluster (1 = register kernel, else LDS kernel)
+  int W64 = 64;       // FP64 iterations
   double tuned_us = 0.0;
   int64_t n = 0;
   int mb_child = -1;  // message bucket of the children (dimension Dc)
@@ -385,7 +386,8 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
   }
   for (auto& B : P->cb) {
     int shapes[8];
-    if (lds_shapes(B.De, shapes) > 0) B.W = shapes[0];
+    if (cluster_shapes(B.De, B.Dc, false, P->cplx, MODE_GIBBS, shapes) > 0) B.W = shapes[0];
+    if (cluster_shapes(B.De, B.Dc, true, P->cplx, MODE_GIBBS, shapes) > 0) B.W64 = shapes[0];
     B.n = (int64_t)B.h_gid.size();
     for (int32_t g : B.h_gid) {
       B.maxch = std::max<int>(B.maxch, (int)children[g].size());
@@ -738,6 +740,16 @@ double default_tol();
 template <> double default_tol<float>() { return 4.0 * 1.1920928955078125e-07; }
 template <> double default_tol<double>() { return 4.0 * 2.220446049250313e-16; }
 
+// The bucket's chosen shape if it is compiled for this precision / mode, else the first that is.
+int shape_for(const lrh_problem_s* P, const CBucket& B, bool dbl, int mode) {
+  int shapes[8];
+  const int n = cluster_shapes(B.De, B.Dc, dbl, P->cplx, mode, shapes);
+  const int want = dbl ? B.W64 : B.W;
+  for (int i = 0; i < n; ++i)
+    if (shapes[i] == want) return want;
+  return n > 0 ? shapes[0] : 64;
+}
+
 template <typename T>
 ClusterArgs<T> base_args(lrh_problem_s* P, const CBucket& B) {
   ClusterArgs<T> a{};
@@ -798,7 +810,7 @@ lrh_status cluster_pass(lrh_problem_s* P, const T* nu, const T* ze, double theta
     a.beta = beta;
     a.theta = theta;
     a.tab = tab;
-    HIP_TRY(launch_cluster<T>(a, P->cplx, mode, B.block, B.W, s));
+    HIP_TRY(launch_cluster<T>(a, P->cplx, mode, B.block, shape_for(P, B, sizeof(T) == 8, mode), s));
   }
   return LRH_OK;
 }
@@ -1264,9 +1276,10 @@ lrh_status autotune_t(lrh_problem_s* P, const char* cache, hipStream_t s) {
   const int prec = sizeof(T) == 4 ? 32 : 64;
   std::map<std::string, std::pair<int, int>> cached;
   if (cache) read_cache(cache, cached);
+  // non-trivial seeded messages, so every candidate runs full Jacobi sweeps
   T* z = nullptr;
   if ((st = P->dalloc(&z, std::max<int64_t>(P->nu_len, 1))) != LRH_OK) return st;
-  HIP_TRY(hipMemsetAsync(z, 0, std::max<int64_t>(P->nu_len, 1) * sizeof(T), s));
+  HIP_TRY(launch_fill_noise<T>(z, P->nu_len, 0.3, 12345u, s));
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
@@ -1274,21 +1287,25 @@ lrh_status autotune_t(lrh_problem_s* P, const char* cache, hipStream_t s) {
   std::map<std::string, std::tuple<int, int, double>> rows;
   for (CBucket& B : P->cb) {
     const std::string key = shape_key(B, P->cplx, prec);
+    const bool dbl = sizeof(T) == 8;
+    int& Wsel = dbl ? B.W64 : B.W;
     auto it = cached.find(key);
     if (it != cached.end()) {
       B.block = it->second.first;
-      B.W = it->second.second;
-      rows[key] = std::make_tuple(B.block, B.W, 0.0);
+      Wsel = it->second.second;
+      rows[key] = std::make_tuple(B.block, Wsel, 0.0);
       continue;
     }
     std::vector<std::pair<int, int>> cands;
-    const bool reg = (B.De == 2 && B.Dc == 0) || (B.De == 4 && B.Dc == 2);
-    if (reg) {
-      for (int b : {64, 128, 256}) cands.push_back({b, B.W});
-    } else {
+    {
       int shapes[8];
-      const int ns = lds_shapes(B.De, shapes);
-      for (int i = 0; i < ns; ++i) cands.push_back({B.block, shapes[i]});
+      const int ns = cluster_shapes(B.De, B.Dc, dbl, P->cplx, MODE_GIBBS, shapes);
+      for (int i = 0; i < ns; ++i) {
+        if (shapes[i] == 1 || B.De <= 4)
+          for (int b : {64, 128, 256}) cands.push_back({b, shapes[i]});
+        else
+          cands.push_back({B.block, shapes[i]});
+      }
     }
     double best = 1e30;
     std::pair<int, int> pick = cands[0];
@@ -1320,9 +1337,9 @@ lrh_status autotune_t(lrh_problem_s* P, const char* cache, hipStream_t s) {
       }
     }
     B.block = pick.first;
-    B.W = pick.second;
+    Wsel = pick.second;
     B.tuned_us = best;
-    rows[key] = std::make_tuple(B.block, B.W, best);
+    rows[key] = std::make_tuple(B.block, Wsel, best);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1473,7 +1490,7 @@ lrh_status lrh_certify(lrh_problem p, const void* nu, uint32_t flags, double* q_
     if (B.mb_child >= 0) a.nu_c = nu64 + p->mb[B.mb_child].offset;
     if (B.mb_self >= 0) a.nu_p = nu64 + p->mb[B.mb_self].offset;
     a.R = nullptr;
-    HIP_TRY(launch_cluster<double>(a, p->cplx, MODE_CERTIFY, B.block, B.W, stream));
+    HIP_TRY(launch_cluster<double>(a, p->cplx, MODE_CERTIFY, B.block, shape_for(p, B, true, MODE_CERTIFY), stream));
   }
   HIP_TRY(launch_reduce(p->scal, p->inst_ptr, p->n_inst, q_dev, p->scal2, margin_dev, nullptr, nullptr, nullptr,
                         stream));
@@ -1557,9 +1574,29 @@ lrh_status lrh_get_shapes(lrh_problem p, int32_t cap, int32_t* De, int32_t* Dc, 
     if (Dc) Dc[i] = B.Dc;
     if (n) n[i] = B.n;
     if (block) block[i] = B.block;
-    if (W) W[i] = B.W;
+    if (W) W[i] = B.W;  // FP32 iteration shape
     if (us) us[i] = B.tuned_us;
   }
+  return LRH_OK;
+}
+
+lrh_status lrh_set_shape(lrh_problem p, int32_t De, int32_t block, int32_t W, uint32_t flags) {
+  if (!p) return fail(LRH_E_INVALID, "null problem");
+  if (block != 64 && block != 128 && block != 256) return fail(LRH_E_INVALID, "block must be 64, 128 or 256");
+  const bool dbl = !(flags & LRH_F32);
+  bool any = false;
+  for (CBucket& B : p->cb) {
+    if (B.De != De) continue;
+    int shapes[8];
+    const int n = cluster_shapes(B.De, B.Dc, dbl, p->cplx, MODE_GIBBS, shapes);
+    bool ok = false;
+    for (int i = 0; i < n; ++i) ok = ok || shapes[i] == W;
+    if (!ok) return fail(LRH_E_UNSUPPORTED, "launch shape not compiled for this bucket");
+    B.block = block;
+    (dbl ? B.W64 : B.W) = W;
+    any = true;
+  }
+  if (!any) return fail(LRH_E_INVALID, "no cluster bucket with that dimension");
   return LRH_OK;
 }
 

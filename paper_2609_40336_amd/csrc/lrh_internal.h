@@ -111,6 +111,9 @@ template <typename T>
 hipError_t launch_cluster(const ClusterArgs<T>& a, bool cplx, int mode, int block, int W, hipStream_t s);
 // lanes-per-cluster shapes compiled for an LDS bucket of dimension De (returns the count)
 int lds_shapes(int De, int* out);
+// every launch shape available for a bucket in a given precision / field / mode, best guess
+// first: 1 = one lane per cluster (register kernel), otherwise lanes per cluster of the LDS kernel
+int cluster_shapes(int De, int Dc, bool dbl, bool cplx, int mode, int* out);
 template <typename T>
 hipError_t launch_msg(const MsgArgs<T>& a, int mode, int block, hipStream_t s);
 hipError_t launch_reduce(const double* scal, const int64_t* inst_ptr, int64_t n_inst, double* out,
@@ -143,6 +146,9 @@ hipError_t launch_adj_pre(const double* a, const double* b, double* btot, double
                           int64_t n, hipStream_t s);
 hipError_t launch_adj_post(double* a, double* b, const double* btot, const double* etabar, double th, int64_t n,
                            hipStream_t s);
+// x[i] = scale * (uniform(-1, 1) from a 64-bit mix of (seed, i))
+template <typename T>
+hipError_t launch_fill_noise(T* x, int64_t n, double scale, uint32_t seed, hipStream_t s);
 template <typename T>
 hipError_t launch_extrap(T* dst, const T* nu, const T* ze, double th, int64_t n, hipStream_t s);
 // scale the off-diagonal components of every message of a bucket by f

@@ -26,6 +26,7 @@
 #include <cfloat>
 #include <cmath>
 #include <type_traits>
+#include <utility>
 
 namespace lrh {
 
@@ -81,135 +82,189 @@ __host__ __device__ constexpr int pext_bits(int i, int mask, int nbits) {
 __host__ __device__ constexpr int log2i(int D) { return D <= 1 ? 0 : 1 + log2i(D / 2); }
 
 // ------------------------------------------------------------------------------------------
-// register-resident cluster kernel (De <= 4)
+// register-resident cluster kernel (one lane per cluster, D_e <= 8)
 // ------------------------------------------------------------------------------------------
 
-template <typename T, bool CPLX, int D, typename Get>
-__device__ __forceinline__ void unpack(Get get, T (&xr)[D][D], T (&xi)[D][D]) {
-#pragma unroll
-  for (int i = 0; i < D; ++i)
-#pragma unroll
-    for (int j = i; j < D; ++j) {
-      T v = get(tri_index(i, j, D));
-      xr[i][j] = v;
-      xr[j][i] = v;
+// Hermitian D x D matrix kept as its packed upper triangle (real parts and imaginary parts);
+// every index is a compile-time constant after unrolling, so the storage lives in registers
+// and each independent entry is carried once across the sweep loop.
+template <typename T, bool CPLX, int D>
+struct HMat {
+  static constexpr int NT = D * (D + 1) / 2;
+  T r[NT];
+  T i[CPLX ? NT : 1];
+  __device__ __forceinline__ T re(int a, int b) const {
+    return a <= b ? r[tri_index(a, b, D)] : r[tri_index(b, a, D)];
+  }
+  __device__ __forceinline__ T im(int a, int b) const {
+    if constexpr (!CPLX) return T(0);
+    else return a < b ? i[tri_index(a, b, D)] : (a > b ? -i[tri_index(b, a, D)] : T(0));
+  }
+  __device__ __forceinline__ void set(int a, int b, T vr, T vi) {
+    if (a <= b) {
+      r[tri_index(a, b, D)] = vr;
+      if constexpr (CPLX) i[tri_index(a, b, D)] = (a == b) ? T(0) : vi;
+    } else {
+      r[tri_index(b, a, D)] = vr;
+      if constexpr (CPLX) i[tri_index(b, a, D)] = -vi;
     }
+  }
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      r[k] = T(0);
+      if constexpr (CPLX) i[k] = T(0);
+    }
+  }
+};
+
+// packed message / term components <-> HMat (layout: real upper triangle row-major, then the
+// imaginary strict upper triangle)
+template <typename T, bool CPLX, int D, typename Get>
+__device__ __forceinline__ void unpack(Get get, HMat<T, CPLX, D>& M) {
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = a; b < D; ++b) M.r[tri_index(a, b, D)] = get(tri_index(a, b, D));
   if constexpr (CPLX) {
 #pragma unroll
-    for (int i = 0; i < D; ++i) {
-      xi[i][i] = T(0);
+    for (int a = 0; a < D; ++a) {
+      M.i[tri_index(a, a, D)] = T(0);
 #pragma unroll
-      for (int j = i + 1; j < D; ++j) {
-        T v = get(D * (D + 1) / 2 + stri_index(i, j, D));
-        xi[i][j] = v;
-        xi[j][i] = -v;
-      }
+      for (int b = a + 1; b < D; ++b) M.i[tri_index(a, b, D)] = get(D * (D + 1) / 2 + stri_index(a, b, D));
     }
+  }
+}
+
+template <typename T, bool CPLX, int D, typename Get>
+__device__ __forceinline__ void unpack_add(Get get, HMat<T, CPLX, D>& M) {
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = a; b < D; ++b) M.r[tri_index(a, b, D)] += get(tri_index(a, b, D));
+  if constexpr (CPLX) {
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = a + 1; b < D; ++b) M.i[tri_index(a, b, D)] += get(D * (D + 1) / 2 + stri_index(a, b, D));
   }
 }
 
 template <typename T, bool CPLX, int D, typename Put>
-__device__ __forceinline__ void pack(Put put, const T (&xr)[D][D], const T (&xi)[D][D]) {
+__device__ __forceinline__ void pack(Put put, const HMat<T, CPLX, D>& M) {
 #pragma unroll
-  for (int i = 0; i < D; ++i)
+  for (int a = 0; a < D; ++a)
 #pragma unroll
-    for (int j = i; j < D; ++j) put(tri_index(i, j, D), xr[i][j]);
+    for (int b = a; b < D; ++b) put(tri_index(a, b, D), M.r[tri_index(a, b, D)]);
   if constexpr (CPLX) {
 #pragma unroll
-    for (int i = 0; i < D; ++i)
+    for (int a = 0; a < D; ++a)
 #pragma unroll
-      for (int j = i + 1; j < D; ++j) put(D * (D + 1) / 2 + stri_index(i, j, D), xi[i][j]);
+      for (int b = a + 1; b < D; ++b) put(D * (D + 1) / 2 + stri_index(a, b, D), M.i[tri_index(a, b, D)]);
   }
+}
+
+// Calls f(integral_constant<int, M>) for the compile-time mask M == mask among the masks that
+// select log2(DC) of the log2(DE) site bits (the positions a child can occupy in its parent).
+// A flat fold over the candidate masks (no recursion), so everything inlines into the caller.
+template <int DE, int DC, int M, typename F>
+__device__ __forceinline__ void mask_case(int mask, F& f) {
+  if constexpr (__builtin_popcount(M) == log2i(DC)) {
+    if (mask == M) f(std::integral_constant<int, M>{});
+  }
+}
+template <int DE, int DC, typename F, int... I>
+__device__ __forceinline__ void mask_dispatch_seq(int mask, F& f, std::integer_sequence<int, I...>) {
+  (mask_case<DE, DC, I + 1>(mask, f), ...);
+}
+template <int DE, int DC, typename F>
+__device__ __forceinline__ void mask_dispatch(int mask, F&& f) {
+  mask_dispatch_seq<DE, DC>(mask, f, std::make_integer_sequence<int, DE - 1>{});
 }
 
 // theta_e -= 1_{e\f} (x) X for a child whose sites occupy bit mask MASK of e's index.
 template <typename T, bool CPLX, int DE, int DC, int MASK>
-__device__ __forceinline__ void lift_sub(T (&ar)[DE][DE], T (&ai)[DE][DE], const T (&xr)[DC][DC],
-                                         const T (&xi)[DC][DC]) {
+__device__ __forceinline__ void lift_sub(HMat<T, CPLX, DE>& A, const HMat<T, CPLX, DC>& X) {
   constexpr int NB = log2i(DE);
 #pragma unroll
-  for (int i = 0; i < DE; ++i)
+  for (int a = 0; a < DE; ++a)
 #pragma unroll
-    for (int j = 0; j < DE; ++j) {
-      if (((i ^ j) & ~MASK & (DE - 1)) == 0) {
-        ar[i][j] -= xr[pext_bits(i, MASK, NB)][pext_bits(j, MASK, NB)];
-        if constexpr (CPLX) ai[i][j] -= xi[pext_bits(i, MASK, NB)][pext_bits(j, MASK, NB)];
+    for (int b = a; b < DE; ++b) {
+      if (((a ^ b) & ~MASK & (DE - 1)) == 0) {
+        const int x = pext_bits(a, MASK, NB), y = pext_bits(b, MASK, NB);
+        A.r[tri_index(a, b, DE)] -= X.re(x, y);
+        if constexpr (CPLX) A.i[tri_index(a, b, DE)] -= X.im(x, y);
       }
     }
 }
 
 // T = Tr_{e\f} rho for a child at mask MASK.
 template <typename T, bool CPLX, int DE, int DC, int MASK>
-__device__ __forceinline__ void ptrace_reg(const T (&rr)[DE][DE], const T (&ri)[DE][DE],
-                                           T (&tr)[DC][DC], T (&ti)[DC][DC]) {
+__device__ __forceinline__ void ptrace_reg(const HMat<T, CPLX, DE>& Rh, HMat<T, CPLX, DC>& Tm) {
   constexpr int NB = log2i(DE);
   constexpr int NR = DE / DC;
 #pragma unroll
   for (int a = 0; a < DC; ++a)
 #pragma unroll
-    for (int b = 0; b < DC; ++b) {
+    for (int b = a; b < DC; ++b) {
       T sr = T(0), si = T(0);
 #pragma unroll
       for (int x = 0; x < NR; ++x) {
-        sr += rr[pdep_bits(a, x, MASK, NB)][pdep_bits(b, x, MASK, NB)];
-        if constexpr (CPLX) si += ri[pdep_bits(a, x, MASK, NB)][pdep_bits(b, x, MASK, NB)];
+        sr += Rh.re(pdep_bits(a, x, MASK, NB), pdep_bits(b, x, MASK, NB));
+        if constexpr (CPLX) si += Rh.im(pdep_bits(a, x, MASK, NB), pdep_bits(b, x, MASK, NB));
       }
-      tr[a][b] = sr;
-      ti[a][b] = si;
+      Tm.set(a, b, sr, si);
     }
 }
 
 // One cyclic sweep of two-sided Jacobi rotations over all pairs (p < q), row-cyclic order.
+// Branch-free: a pair with a_pq == 0 gets the identity rotation (t = 0, c = 1, s = 0), so the
+// unrolled sweep is straight-line code.
 template <typename T, bool CPLX, int D, bool VEC>
-__device__ __forceinline__ void jacobi_sweep_reg(T (&ar)[D][D], T (&ai)[D][D], T (&ur)[D][D],
-                                                 T (&ui)[D][D]) {
+__device__ __forceinline__ void jacobi_sweep_reg(HMat<T, CPLX, D>& A, T (&ur)[D][D], T (&ui)[D][D]) {
 #pragma unroll
   for (int p = 0; p < D - 1; ++p)
 #pragma unroll
     for (int q = p + 1; q < D; ++q) {
-      T xr = ar[p][q];
-      T xi = CPLX ? ai[p][q] : T(0);
-      T r = CPLX ? dsqrt<T>(dfma<T>(xr, xr, xi * xi)) : fabs(xr);
-      if (r != T(0)) {
-        T t, c, s;
-        // e^{-i phi} with a_pq = r e^{i phi}; real case: sign(a_pq)
-        T er = xr / r, ei = CPLX ? -xi / r : T(0);
-        rot_params<T>(ar[p][p], ar[q][q], r, t, c, s);
-        T app = ar[p][p], aqq = ar[q][q];
+      const T xr = A.re(p, q);
+      const T xi = A.im(p, q);
+      const T r = CPLX ? dsqrt<T>(dfma<T>(xr, xr, xi * xi)) : fabs(xr);
+      const bool nz = (r != T(0));
+      const T rs = nz ? r : T(1);
+      // e^{-i phi} with a_pq = r e^{i phi}; real case: sign(a_pq)
+      const T er = nz ? xr / rs : T(1), ei = (CPLX && nz) ? -xi / rs : T(0);
+      const T app = A.re(p, p), aqq = A.re(q, q);
+      T t, c, s;
+      rot_params<T>(app, aqq, rs, t, c, s);
+      t = nz ? t : T(0);
+      c = nz ? c : T(1);
+      s = nz ? s : T(0);
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        if (k == p || k == q) continue;
+        // column update (A G): w = a_kq e^{-i phi}; rows follow by Hermitian symmetry
+        const T pr = A.re(k, p), pi = A.im(k, p);
+        const T qr = A.re(k, q), qi = A.im(k, q);
+        const T wr = CPLX ? (qr * er - qi * ei) : qr * er;
+        const T wi = CPLX ? (qr * ei + qi * er) : T(0);
+        A.set(k, p, c * pr - s * wr, c * pi - s * wi);
+        A.set(k, q, s * pr + c * wr, s * pi + c * wi);
+      }
+      A.set(p, p, app - t * r, T(0));
+      A.set(q, q, aqq + t * r, T(0));
+      A.set(p, q, nz ? T(0) : xr, nz ? T(0) : xi);
+      if constexpr (VEC) {
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-          if (k == p || k == q) continue;
-          // column update (A G): w = a_kq e^{-i phi}
-          T pr = ar[k][p], pi = CPLX ? ai[k][p] : T(0);
-          T qr = ar[k][q], qi = CPLX ? ai[k][q] : T(0);
-          T wr = CPLX ? (qr * er - qi * ei) : qr * er;
-          T wi = CPLX ? (qr * ei + qi * er) : T(0);
-          T npr = c * pr - s * wr, npi = c * pi - s * wi;
-          T nqr = s * pr + c * wr, nqi = s * pi + c * wi;
-          ar[k][p] = npr; ar[p][k] = npr;
-          ar[k][q] = nqr; ar[q][k] = nqr;
+          const T pr = ur[k][p], pi = CPLX ? ui[k][p] : T(0);
+          const T qr = ur[k][q], qi = CPLX ? ui[k][q] : T(0);
+          const T wr = CPLX ? (qr * er - qi * ei) : qr * er;
+          const T wi = CPLX ? (qr * ei + qi * er) : T(0);
+          ur[k][p] = c * pr - s * wr;
+          ur[k][q] = s * pr + c * wr;
           if constexpr (CPLX) {
-            ai[k][p] = npi; ai[p][k] = -npi;
-            ai[k][q] = nqi; ai[q][k] = -nqi;
-          }
-        }
-        ar[p][p] = app - t * r;
-        ar[q][q] = aqq + t * r;
-        ar[p][q] = T(0); ar[q][p] = T(0);
-        if constexpr (CPLX) { ai[p][q] = T(0); ai[q][p] = T(0); }
-        if constexpr (VEC) {
-#pragma unroll
-          for (int k = 0; k < D; ++k) {
-            T pr = ur[k][p], pi = CPLX ? ui[k][p] : T(0);
-            T qr = ur[k][q], qi = CPLX ? ui[k][q] : T(0);
-            T wr = CPLX ? (qr * er - qi * ei) : qr * er;
-            T wi = CPLX ? (qr * ei + qi * er) : T(0);
-            ur[k][p] = c * pr - s * wr;
-            ur[k][q] = s * pr + c * wr;
-            if constexpr (CPLX) {
-              ui[k][p] = c * pi - s * wi;
-              ui[k][q] = s * pi + c * wi;
-            }
+            ui[k][p] = c * pi - s * wi;
+            ui[k][q] = s * pi + c * wi;
           }
         }
       }
@@ -217,39 +272,32 @@ __device__ __forceinline__ void jacobi_sweep_reg(T (&ar)[D][D], T (&ai)[D][D], T
 }
 
 template <typename T, bool CPLX, int D>
-__device__ __forceinline__ T offdiag2(const T (&ar)[D][D], const T (&ai)[D][D]) {
+__device__ __forceinline__ T offdiag2(const HMat<T, CPLX, D>& A) {
   T s = T(0);
 #pragma unroll
-  for (int i = 0; i < D; ++i)
+  for (int a = 0; a < D; ++a)
 #pragma unroll
-    for (int j = 0; j < D; ++j)
-      if (i != j) {
-        s = dfma<T>(ar[i][j], ar[i][j], s);
-        if constexpr (CPLX) s = dfma<T>(ai[i][j], ai[i][j], s);
-      }
-  return s;
+    for (int b = a + 1; b < D; ++b) {
+      s = dfma<T>(A.r[tri_index(a, b, D)], A.r[tri_index(a, b, D)], s);
+      if constexpr (CPLX) s = dfma<T>(A.i[tri_index(a, b, D)], A.i[tri_index(a, b, D)], s);
+    }
+  return T(2) * s;
 }
 
-// Loads component k of message m with the Algorithm 2 state handling of this launch:
-// plain:  eta = extrap(nu, zeta, theta) (or nu when there is no zeta);
-// fused:  first apply the previous iteration's update from (nu, zeta, rho_f, T_{e->f}).
 template <typename T>
 struct FusedCoef { T thp, ithp, thc; };
 
 template <typename T, bool CPLX, int DE, int DC, int MODE>
 __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
   constexpr bool VEC = (MODE != MODE_CERTIFY);
-  T ar[DE][DE], ai[DE][DE];
+  HMat<T, CPLX, DE> H;
   // ---- a2: h_e ----
   const int64_t ho = A.hoff[c];
   if (ho >= 0) {
     const double* h = A.h + ho;
-    unpack<T, CPLX, DE>([&](int k) { return (T)h[k]; }, ar, ai);
+    unpack<T, CPLX, DE>([&](int k) { return (T)h[k]; }, H);
   } else {
-#pragma unroll
-    for (int i = 0; i < DE; ++i)
-#pragma unroll
-      for (int j = 0; j < DE; ++j) { ar[i][j] = T(0); ai[i][j] = T(0); }
+    H.zero();
   }
   const bool fused = (A.fp != nullptr);
   FusedCoef<T> fc{};
@@ -265,7 +313,7 @@ __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
       const int m = A.ch[(int64_t)s * A.n + c];
       if (m < 0) continue;
       const int mask = A.chmask[(int64_t)s * A.n + c];
-      T xr[DC][DC], xi[DC][DC];
+      HMat<T, CPLX, DC> X;
       if (fused) {
         const int64_t rs = A.rslot_of_msg_c[m];
         unpack<T, CPLX, DC>([&](int k) {
@@ -279,19 +327,18 @@ __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
             A.ze_c_new[o] = ze0;
           }
           return extrap<T>(nu0, ze0, th);
-        }, xr, xi);
+        }, X);
       } else if (A.ze_c) {
         unpack<T, CPLX, DC>([&](int k) {
           const int64_t o = (int64_t)k * A.Mc + m;
           return extrap<T>(A.nu_c[o], A.ze_c[o], th);
-        }, xr, xi);
+        }, X);
       } else {
-        unpack<T, CPLX, DC>([&](int k) { return A.nu_c[(int64_t)k * A.Mc + m]; }, xr, xi);
+        unpack<T, CPLX, DC>([&](int k) { return A.nu_c[(int64_t)k * A.Mc + m]; }, X);
       }
-      if constexpr (DE == 4 && DC == 2) {
-        if (mask == 2) lift_sub<T, CPLX, DE, DC, 2>(ar, ai, xr, xi);
-        else lift_sub<T, CPLX, DE, DC, 1>(ar, ai, xr, xi);
-      }
+      mask_dispatch<DE, DC>(mask, [&](auto mc) __attribute__((always_inline)) {
+        lift_sub<T, CPLX, DE, DC, decltype(mc)::value>(H, X);
+      });
     }
   }
   // ---- parents: add messages received ----
@@ -299,9 +346,8 @@ __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
   for (int s = 0; s < A.maxpar; ++s) {
     const int m = A.par[(int64_t)s * A.n + c];
     if (m < 0) continue;
-    T xr[DE][DE], xi[DE][DE];
     if (fused) {
-      unpack<T, CPLX, DE>([&](int k) {
+      unpack_add<T, CPLX, DE>([&](int k) {
         const int64_t o = (int64_t)k * A.Mp + m;
         T nu0 = A.nu_p_prev[o], ze0 = A.ze_p_prev[o];
         if (!A.fused_first) {
@@ -310,51 +356,47 @@ __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
           nu0 = extrap<T>(nu0, ze0, fc.thp);
         }
         return extrap<T>(nu0, ze0, th);
-      }, xr, xi);
+      }, H);
     } else if (A.ze_p) {
-      unpack<T, CPLX, DE>([&](int k) {
+      unpack_add<T, CPLX, DE>([&](int k) {
         const int64_t o = (int64_t)k * A.Mp + m;
         return extrap<T>(A.nu_p[o], A.ze_p[o], th);
-      }, xr, xi);
+      }, H);
     } else {
-      unpack<T, CPLX, DE>([&](int k) { return A.nu_p[(int64_t)k * A.Mp + m]; }, xr, xi);
+      unpack_add<T, CPLX, DE>([&](int k) { return A.nu_p[(int64_t)k * A.Mp + m]; }, H);
     }
-#pragma unroll
-    for (int i = 0; i < DE; ++i)
-#pragma unroll
-      for (int j = 0; j < DE; ++j) {
-        ar[i][j] += xr[i][j];
-        if constexpr (CPLX) ai[i][j] += xi[i][j];
-      }
   }
   // ---- a3: cyclic Jacobi ----
-  T nrm2 = T(0);
+  T dg = T(0);
 #pragma unroll
-  for (int i = 0; i < DE; ++i)
-#pragma unroll
-    for (int j = 0; j < DE; ++j) {
-      nrm2 = dfma<T>(ar[i][j], ar[i][j], nrm2);
-      if constexpr (CPLX) nrm2 = dfma<T>(ai[i][j], ai[i][j], nrm2);
-    }
-  T ur[DE][DE], ui[DE][DE];
+  for (int k = 0; k < DE; ++k) dg = dfma<T>(H.r[tri_index(k, k, DE)], H.r[tri_index(k, k, DE)], dg);
+  const T nrm2 = dg + offdiag2<T, CPLX, DE>(H);
+  T ur[DE][DE], ui[DE][DE];  // eigenvectors (unused, and removed, without VEC / CPLX)
   if constexpr (VEC) {
 #pragma unroll
     for (int i = 0; i < DE; ++i)
 #pragma unroll
-      for (int j = 0; j < DE; ++j) { ur[i][j] = (i == j) ? T(1) : T(0); ui[i][j] = T(0); }
+      for (int j = 0; j < DE; ++j) {
+        ur[i][j] = (i == j) ? T(1) : T(0);
+        if constexpr (CPLX) ui[i][j] = T(0);
+      }
   }
   const T tol2 = (T)(A.tol * A.tol) * nrm2;
   bool conv = false;
   for (int sweep = 0; sweep <= A.max_sweeps; ++sweep) {
-    if (offdiag2<T, CPLX, DE>(ar, ai) <= tol2) { conv = true; break; }
+    if (offdiag2<T, CPLX, DE>(H) <= tol2) { conv = true; break; }
     if (sweep == A.max_sweeps) break;
-    jacobi_sweep_reg<T, CPLX, DE, VEC>(ar, ai, ur, ui);
+    if constexpr (VEC) jacobi_sweep_reg<T, CPLX, DE, true>(H, ur, ui);
+    else {
+      T dr[DE][DE], di[DE][DE];
+      jacobi_sweep_reg<T, CPLX, DE, false>(H, dr, di);
+    }
   }
   if (!conv && A.noconv) atomicAdd(A.noconv, 1ull);
   T lam[DE];
-  T lmin = ar[0][0];
+  T lmin = H.r[0];
 #pragma unroll
-  for (int k = 0; k < DE; ++k) { lam[k] = ar[k][k]; lmin = fmin(lmin, lam[k]); }
+  for (int k = 0; k < DE; ++k) { lam[k] = H.r[tri_index(k, k, DE)]; lmin = fmin(lmin, lam[k]); }
   if (!isfinite((double)lmin) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
   const int32_t gid = A.gid[c];
   if constexpr (MODE == MODE_CERTIFY) {
@@ -373,7 +415,7 @@ __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
       const T iZ = T(1) / Z;
 #pragma unroll
       for (int k = 0; k < DE; ++k) p[k] *= iZ;
-      A.scal[gid] = (double)(lmin - dlog<T>(Z) / b);
+      if (A.scal) A.scal[gid] = (double)(lmin - dlog<T>(Z) / b);
     } else {
       const T tau = (T)A.tau_rel * fmax(T(1), dsqrt<T>(nrm2));
       T g = T(0);
@@ -382,9 +424,9 @@ __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
       const T ig = T(1) / g;
 #pragma unroll
       for (int k = 0; k < DE; ++k) p[k] *= ig;
-      A.scal[gid] = (double)lmin;
+      if (A.scal) A.scal[gid] = (double)lmin;
     }
-    // rho = U diag(p) U^H  (reuse ar/ai)
+    // rho = U diag(p) U^H  (reuse H)
 #pragma unroll
     for (int i = 0; i < DE; ++i)
 #pragma unroll
@@ -392,7 +434,7 @@ __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
         T sr = T(0), si = T(0);
 #pragma unroll
         for (int k = 0; k < DE; ++k) {
-          T a_r = ur[i][k] * p[k], a_i = CPLX ? ui[i][k] * p[k] : T(0);
+          const T a_r = ur[i][k] * p[k], a_i = CPLX ? ui[i][k] * p[k] : T(0);
           // (a_r + i a_i) * conj(u_jk)
           sr = dfma<T>(a_r, ur[j][k], sr);
           if constexpr (CPLX) {
@@ -401,20 +443,15 @@ __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
             si = dfma<T>(-a_r, ui[j][k], si);
           }
         }
-        ar[i][j] = sr; ar[j][i] = sr;
-        if constexpr (CPLX) { ai[i][j] = si; ai[j][i] = (i == j) ? T(0) : -si; }
+        H.set(i, j, sr, si);
       }
-    if constexpr (CPLX) {
-#pragma unroll
-      for (int i = 0; i < DE; ++i) ai[i][i] = T(0);
-    }
     // ---- outputs: own marginal ----
     if (rs_self >= 0 && A.R) {
-      pack<T, CPLX, DE>([&](int k, T v) { A.R[(int64_t)k * A.S + rs_self] = v; }, ar, ai);
+      pack<T, CPLX, DE>([&](int k, T v) { A.R[(int64_t)k * A.S + rs_self] = v; }, H);
     }
     if (A.marg) {
       T* mo = A.marg + A.marg_off[gid];
-      pack<T, CPLX, DE>([&](int k, T v) { mo[k] = v; }, ar, ai);
+      pack<T, CPLX, DE>([&](int k, T v) { mo[k] = v; }, H);
     }
     // ---- a5: partial traces onto the children ----
     if constexpr (DC > 0) {
@@ -423,12 +460,11 @@ __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
           const int m = A.ch[(int64_t)s * A.n + c];
           if (m < 0) continue;
           const int mask = A.chmask[(int64_t)s * A.n + c];
-          T tr[DC][DC], ti[DC][DC];
-          if constexpr (DE == 4 && DC == 2) {
-            if (mask == 2) ptrace_reg<T, CPLX, DE, DC, 2>(ar, ai, tr, ti);
-            else ptrace_reg<T, CPLX, DE, DC, 1>(ar, ai, tr, ti);
-          }
-          pack<T, CPLX, DC>([&](int k, T v) { A.Tout[(int64_t)k * A.Mc + m] = v; }, tr, ti);
+          HMat<T, CPLX, DC> Tm;
+          mask_dispatch<DE, DC>(mask, [&](auto mc) __attribute__((always_inline)) {
+            ptrace_reg<T, CPLX, DE, DC, decltype(mc)::value>(H, Tm);
+          });
+          pack<T, CPLX, DC>([&](int k, T v) { A.Tout[(int64_t)k * A.Mc + m] = v; }, Tm);
         }
       }
     }
@@ -1432,6 +1468,20 @@ __global__ __launch_bounds__(256) void k_copy(T* dst, const T* src, int64_t n) {
 }
 
 template <typename T>
+__global__ __launch_bounds__(256) void k_fill_noise(T* x, int64_t n, double scale, uint32_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  // splitmix64 finaliser of (seed, i)
+  uint64_t z = ((uint64_t)seed << 32) ^ (uint64_t)i;
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  z ^= z >> 31;
+  const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);  // [0, 1)
+  x[i] = (T)(scale * (2.0 * u - 1.0));
+}
+
+template <typename T>
 __global__ __launch_bounds__(256) void k_extrap(T* dst, const T* nu, const T* ze, double th, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = extrap<T>(nu[i], ze[i], (T)th);
@@ -1513,6 +1563,34 @@ __global__ __launch_bounds__(256) void k_scale_offdiag(double* x, int64_t M, int
 
 static inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
+// Register (one lane per cluster) instantiations: which (De, precision, field, mode) fit the
+// register file (the whole De x De matrix and, with vectors, U live in one lane's VGPRs).
+template <typename T, bool CPLX, int DE, int MODE>
+constexpr bool reg_ok() {
+  constexpr bool dbl = std::is_same<T, double>::value;
+  if constexpr (DE <= 4) return true;
+  if constexpr (DE == 8) return !(dbl && CPLX && MODE != MODE_CERTIFY);
+  return false;  // D_e = 16: H + U exceed the arch VGPR file of one lane; the LDS kernel takes it
+}
+
+static bool reg_pair(int De, int Dc) {
+  return (De == 2 && Dc == 0) || (De == 4 && Dc == 2) || (De == 8 && (Dc == 4 || Dc == 2));
+}
+
+int cluster_shapes(int De, int Dc, bool dbl, bool cplx, int mode, int* out) {
+  int n = 0;
+  bool reg = reg_pair(De, Dc);
+  if (reg && De >= 8) {
+    if (De == 8) reg = !(dbl && cplx && mode != MODE_CERTIFY);
+  }
+  if (reg) out[n++] = 1;
+  int lds[8];
+  const int nl = lds_shapes(De, lds);
+  if (!(De <= 4 && reg))
+    for (int i = 0; i < nl; ++i) out[n++] = lds[i];
+  return n;
+}
+
 // LDS shapes compiled per dimension (lanes per cluster); the first is the default.
 int lds_shapes(int De, int* out) {
   switch (De) {
@@ -1533,9 +1611,24 @@ static void launch_lds_w(const ClusterArgs<T>& a, hipStream_t s) {
   hipLaunchKernelGGL((k_cluster_lds<T, CPLX, DE, MODE, W>), dim3((unsigned)((a.n + G - 1) / G)), dim3(64), 0, s, a);
 }
 
+template <typename T, bool CPLX, int MODE, int DE, int DC>
+static hipError_t launch_reg(const ClusterArgs<T>& a, int block, hipStream_t s) {
+  if constexpr (reg_ok<T, CPLX, DE, MODE>()) {
+    hipLaunchKernelGGL((k_cluster_reg<T, CPLX, DE, DC, MODE>), dim3(grid_for(a.n, block)), dim3(block), 0, s, a);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
 template <typename T, bool CPLX, int MODE>
 static hipError_t launch_cluster_m(const ClusterArgs<T>& a, int block, int W, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
+  if (W == 1 && a.De >= 8) {
+    if (a.De == 8 && a.Dc == 4) return launch_reg<T, CPLX, MODE, 8, 4>(a, block, s);
+    if (a.De == 8 && a.Dc == 2) return launch_reg<T, CPLX, MODE, 8, 2>(a, block, s);
+    return hipErrorInvalidValue;
+  }
   if (a.De == 2 && a.Dc == 0) {
     hipLaunchKernelGGL((k_cluster_reg<T, CPLX, 2, 0, MODE>), dim3(grid_for(a.n, block)), dim3(block), 0, s, a);
   } else if (a.De == 4 && a.Dc == 2) {
@@ -1717,6 +1810,14 @@ hipError_t launch_scale_offdiag(double* x, int64_t M, int D, bool cplx, double f
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_fill_noise(T* x, int64_t n, double scale, uint32_t seed, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_fill_noise<T>), dim3(grid_for(n, 256)), dim3(256), 0, s, x, n, scale, seed);
+  return hipGetLastError();
+}
+template hipError_t launch_fill_noise<float>(float*, int64_t, double, uint32_t, hipStream_t);
+template hipError_t launch_fill_noise<double>(double*, int64_t, double, uint32_t, hipStream_t);
 template hipError_t launch_extrap<float>(float*, const float*, const float*, double, int64_t, hipStream_t);
 template hipError_t launch_extrap<double>(double*, const double*, const double*, double, int64_t, hipStream_t);
 template hipError_t launch_cluster<float>(const ClusterArgs<float>&, bool, int, int, int, hipStream_t);

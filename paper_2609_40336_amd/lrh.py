@@ -69,7 +69,7 @@ _lib = None
 EXPORTS = ["lrh_build_clusters", "lrh_query", "lrh_export_clusters", "lrh_export_messages",
            "lrh_dual_eval", "lrh_step_subgrad", "lrh_step_nesterov", "lrh_certify", "lrh_check",
            "lrh_set_jacobi", "lrh_destroy", "lrh_last_error", "lrh_set_params", "lrh_dual_vjp",
-           "lrh_unrolled_bound_grad", "lrh_autotune", "lrh_get_shapes"]
+           "lrh_unrolled_bound_grad", "lrh_autotune", "lrh_get_shapes", "lrh_set_shape"]
 
 
 def load(path: str = LIB_PATH):
@@ -94,6 +94,7 @@ def load(path: str = LIB_PATH):
         "lrh_set_jacobi": (i32, [vp, i32, dbl]),
         "lrh_set_params": (i32, [vp, vp, vp]),
         "lrh_autotune": (i32, [vp, u32, C.c_char_p, vp]),
+        "lrh_set_shape": (i32, [vp, i32, i32, i32, u32]),
         "lrh_get_shapes": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, C.POINTER(i32)]),
         "lrh_dual_vjp": (i32, [vp, vp, u32, dbl, vp, vp, vp, vp, vp]),
         "lrh_unrolled_bound_grad": (i32, [vp, vp, dbl, dbl, i32, vp, vp, vp, vp, u32, vp]),
@@ -237,6 +238,10 @@ def lrh_unrolled_bound_grad(h, nu0, beta, L, T, qbar, bound, param_bar=None, nu0
 
 def lrh_autotune(h, flags=0, cache_path: Optional[str] = None, stream=None):
     _check(load().lrh_autotune(h, flags, None if cache_path is None else cache_path.encode(), _stream(stream)))
+
+
+def lrh_set_shape(h, De, block, W, flags=0):
+    _check(load().lrh_set_shape(h, int(De), int(block), int(W), flags))
 
 
 def lrh_get_shapes(h):
@@ -459,6 +464,10 @@ class Problem:
 
     def shapes(self):
         return lrh_get_shapes(self.h)
+
+    def force_shape(self, De: int, W: int, block: int = 64, f32=None):
+        for flag in ([LRH_F32, 0] if f32 is None else [LRH_F32 if f32 else 0]):
+            lrh_set_shape(self.h, De, block, W, flag)
 
 
 def nesterov_schedule(beta0: float, beta_max: float, total_iters: int):

@@ -383,7 +383,7 @@ def test_autotuned_shapes_agree_and_cache_round_trip(tmp_path):
     """Every launch shape computes the same cluster arithmetic: after autotuning, dual values
     agree with the default shapes to rounding, and a second build reads the cached choice."""
     lrh = lrhmod()
-    say("[autotune] plaquettes + triangles")
+    say("[autotune] plaquettes + triangles + intervals")
     for d in [W.tfim_plaquette_batch([6, 5], [1.0, 2.0]), W.xxz_triangular(6, 0.5, seed=1),
               W.random_chain(12, seed=3, top_len=5, subintervals=True)]:
         P = lrh.Problem(d, 0)
@@ -399,3 +399,29 @@ def test_autotuned_shapes_agree_and_cache_round_trip(tmp_path):
         P2 = lrh.Problem(d, 0)
         shapes2 = P2.autotune(False, cache)
         assert [(s["block"], s["W"]) for s in shapes] == [(s["block"], s["W"]) for s in shapes2]
+
+
+@pytest.mark.parametrize("shape", ["register", "lds16", "lds8", "lds64"])
+def test_triangle_clusters_every_shape(shape):
+    """D = 8 clusters (XXZ triangles) through the one-lane register kernel and through the LDS
+    kernel with 16, 8 and 64 lanes per cluster: each matches the oracle."""
+    lrh = lrhmod()
+    say(f"[shapes] D=8 {shape}")
+    d = W.xxz_triangular(4, 0.5, seed=2)
+    P = lrh.Problem(d, 0)
+    R = O.Relaxation(d)
+    Wsel = {"register": 1, "lds16": 16, "lds8": 8, "lds64": 64}[shape]
+    P.force_shape(8, Wsel)
+    nu_o = R.draw(31, 0.4)
+    for beta in (0.0, 2.0):
+        q, g, m = P.dual_eval(P.from_dense(R.to_pairs(nu_o)), beta, grad=True, marg=True)
+        torch.cuda.synchronize()
+        q_o, g_o = (R.grad_beta(nu_o, beta) if beta > 0 else R.subgrad(nu_o))
+        assert abs(q.item() - q_o[0]) <= 1e-9 * d.n_sites
+        assert max_pair_err(P.to_dense(g), R.to_pairs(g_o)) < 1e-10
+    nu32 = P.from_dense(R.to_pairs(nu_o), f32=True)
+    q32, g32, _ = P.dual_eval(nu32, 2.0, grad=True)
+    torch.cuda.synchronize()
+    q_o, g_o = R.grad_beta(R.from_pairs(P.to_dense(nu32)), 2.0)
+    assert abs(q32.item() - q_o[0]) <= 2e-5 * d.n_sites
+    assert max_pair_err(P.to_dense(g32), R.to_pairs(g_o)) < 5e-5
