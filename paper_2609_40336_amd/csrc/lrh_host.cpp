@@ -92,6 +92,8 @@ template <typename T>
 struct Work {
   T* big = nullptr;               // scratch slabs of the large-cluster kernel
   int64_t big_slab = 0, big_blocks = 0;
+  double* xbig = nullptr;         // FP64 slabs of the scaling-and-squaring kernel (De >= 64)
+  int64_t xslab = 0, xblocks = 0;
   T* Tb[2] = {nullptr, nullptr};  // partial traces, message layout
   T* Rb[2] = {nullptr, nullptr};  // marginals of clusters with parents
   T* W[4] = {nullptr, nullptr, nullptr, nullptr};  // fused ping-pong state: nu1, ze1, nu2, ze2
@@ -721,6 +723,20 @@ lrh_status ensure_work(lrh_problem_s* P, bool fused) {
       if ((st = P->dalloc(&w.big, w.big_slab * w.big_blocks)) != LRH_OK) return st;
     }
   }
+  if (!w.xbig) {
+    int64_t nx = 0;
+    int Dmax = 0;
+    for (const CBucket& B : P->cb)
+      if (B.De >= 64) {
+        nx = std::max<int64_t>(nx, B.n);
+        Dmax = std::max(Dmax, B.De);
+      }
+    if (nx > 0) {
+      w.xslab = (int64_t)5 * (P->cplx ? 2 : 1) * Dmax * Dmax;
+      w.xblocks = std::min<int64_t>(nx, Dmax >= 256 ? 512 : 1024);
+      if ((st = P->dalloc(&w.xbig, w.xslab * w.xblocks)) != LRH_OK) return st;
+    }
+  }
   if (!w.Tb[0]) {
     if ((st = P->dalloc(&w.Tb[0], std::max<int64_t>(P->nu_len, 1))) != LRH_OK) return st;
     if ((st = P->dalloc(&w.Rb[0], std::max<int64_t>(P->R_len, 1))) != LRH_OK) return st;
@@ -782,6 +798,12 @@ ClusterArgs<T> base_args(lrh_problem_s* P, const CBucket& B) {
     a.big_scratch = w.big;
     a.big_slab = w.big_slab;
     a.big_blocks = w.big_blocks;
+  }
+  if (B.De >= 64) {
+    Work<T>& w = P->work<T>();
+    a.expm_scratch = w.xbig;
+    a.expm_slab = w.xslab;
+    a.expm_blocks = w.xblocks;
   }
   return a;
 }
@@ -1300,7 +1322,9 @@ lrh_status autotune_t(lrh_problem_s* P, const char* cache, hipStream_t s) {
     {
       int shapes[8];
       const int ns = cluster_shapes(B.De, B.Dc, dbl, P->cplx, MODE_GIBBS, shapes);
+      const bool has_expm = std::find(shapes, shapes + ns, 0) != shapes + ns;
       for (int i = 0; i < ns; ++i) {
+        if (has_expm && B.De >= 128 && shapes[i] != 0) continue;  // slab Jacobi: orders of magnitude slower
         if (shapes[i] == 1 || B.De <= 4)
           for (int b : {64, 128, 256}) cands.push_back({b, shapes[i]});
         else
@@ -1322,7 +1346,13 @@ lrh_status autotune_t(lrh_problem_s* P, const char* cache, hipStream_t s) {
         a.R = w.Rb[0] + M.roff;
       }
       a.beta = 1.0;
+      HIP_TRY(hipEventRecord(e0, s));
       HIP_TRY(launch_cluster<T>(a, P->cplx, MODE_GIBBS, cand.first, cand.second, s));  // warm-up
+      HIP_TRY(hipEventRecord(e1, s));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms0 = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms0, e0, e1));
+      if (1e3 * ms0 > 4.0 * best) continue;   // clearly slower than the best so far
       const int reps = B.n > 100000 ? 3 : 10;
       HIP_TRY(hipEventRecord(e0, s));
       for (int r = 0; r < reps; ++r) HIP_TRY(launch_cluster<T>(a, P->cplx, MODE_GIBBS, cand.first, cand.second, s));

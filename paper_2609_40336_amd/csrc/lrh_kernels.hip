@@ -985,6 +985,99 @@ __device__ void mfma_rebuild(const T* ur, const T* ui, const T* sq, T* orr, T* o
   }
 }
 
+// theta_e of cluster c assembled element by element into a row-major D x D slab (ar, ai) of
+// element type S; with VEC the slab (ur, ui) is set to the identity.  Returns this thread's
+// share of ||theta||_F^2.
+template <typename T, typename S, bool CPLX, bool VEC>
+__device__ T big_assemble(const ClusterArgs<T>& A, int64_t c, int D, S* ar, S* ai, S* ur, S* ui, T th, int tid,
+                          int nth) {
+  const int NB = log2i(D);
+  const int64_t DD = (int64_t)D * D;
+  const int64_t ho = A.hoff[c];
+  const int Dc = A.Dc;
+  T my_n2 = T(0);
+  for (int64_t idx = tid; idx < DD; idx += nth) {
+    const int i = (int)(idx / D), j = (int)(idx % D);
+    T vr = T(0), vi = T(0);
+    if (ho >= 0) herm_elem<T>([&](int k) { return (T)A.h[ho + k]; }, i, j, D, CPLX, vr, vi);
+    for (int s = 0; s < A.maxch; ++s) {
+      const int m = A.ch[(int64_t)s * A.n + c];
+      if (m < 0) continue;
+      const int mask = A.chmask[(int64_t)s * A.n + c];
+      if (((i ^ j) & ~mask & (D - 1)) != 0) continue;
+      const int a = pext_rt(i, mask, NB), b = pext_rt(j, mask, NB);
+      T er, ei;
+      if (A.ze_c)
+        herm_elem<T>([&](int k) { const int64_t o = (int64_t)k * A.Mc + m;
+                                  return extrap<T>(A.nu_c[o], A.ze_c[o], th); }, a, b, Dc, CPLX, er, ei);
+      else
+        herm_elem<T>([&](int k) { return A.nu_c[(int64_t)k * A.Mc + m]; }, a, b, Dc, CPLX, er, ei);
+      vr -= er;
+      vi -= ei;
+    }
+    for (int s = 0; s < A.maxpar; ++s) {
+      const int m = A.par[(int64_t)s * A.n + c];
+      if (m < 0) continue;
+      T er, ei;
+      if (A.ze_p)
+        herm_elem<T>([&](int k) { const int64_t o = (int64_t)k * A.Mp + m;
+                                  return extrap<T>(A.nu_p[o], A.ze_p[o], th); }, i, j, D, CPLX, er, ei);
+      else
+        herm_elem<T>([&](int k) { return A.nu_p[(int64_t)k * A.Mp + m]; }, i, j, D, CPLX, er, ei);
+      vr += er;
+      vi += ei;
+    }
+    ar[idx] = (S)vr;
+    if constexpr (CPLX) ai[idx] = (S)vi;
+    if constexpr (VEC) {
+      ur[idx] = (i == j) ? S(1) : S(0);
+      if constexpr (CPLX) ui[idx] = S(0);
+    }
+    my_n2 = dfma<T>(vr, vr, my_n2);
+    if constexpr (CPLX) my_n2 = dfma<T>(vi, vi, my_n2);
+  }
+  return my_n2;
+}
+
+// Outputs of a cluster whose marginal scale * (rr, ri) sits in a row-major slab: own marginal
+// slot, per-cluster marginal, partial traces onto every child.
+template <typename T, typename S, bool CPLX>
+__device__ void big_outputs(const ClusterArgs<T>& A, int64_t c, int D, int32_t gid, const S* rr_, const S* ri_,
+                            S scale, int tid, int nth) {
+  const int NB = log2i(D);
+  const int Dc = A.Dc;
+  const int64_t rs_self = A.rslot ? A.rslot[c] : -1;
+  const int NCE = CPLX ? D * D : D * (D + 1) / 2;
+  for (int k = tid; k < NCE; k += nth) {
+    int i, j;
+    bool im;
+    decode_comp(k, D, i, j, im);
+    const T v = (T)(scale * (im ? ri_[(int64_t)i * D + j] : rr_[(int64_t)i * D + j]));
+    if (rs_self >= 0 && A.R) A.R[(int64_t)k * A.S + rs_self] = v;
+    if (A.marg) A.marg[A.marg_off[gid] + k] = v;
+  }
+  if (A.Tout && Dc > 0) {
+    const int NR = D / Dc;
+    const int NCC = CPLX ? Dc * Dc : Dc * (Dc + 1) / 2;
+    for (int s = 0; s < A.maxch; ++s) {
+      const int m = A.ch[(int64_t)s * A.n + c];
+      if (m < 0) continue;
+      const int mask = A.chmask[(int64_t)s * A.n + c];
+      for (int k = tid; k < NCC; k += nth) {
+        int a, b;
+        bool im;
+        decode_comp(k, Dc, a, b, im);
+        S sum = S(0);
+        for (int x = 0; x < NR; ++x) {
+          const int i = pdep_rt(a, x, mask, NB), j = pdep_rt(b, x, mask, NB);
+          sum += im ? ri_[(int64_t)i * D + j] : rr_[(int64_t)i * D + j];
+        }
+        A.Tout[(int64_t)k * A.Mc + m] = (T)(scale * sum);
+      }
+    }
+  }
+}
+
 template <typename T, bool CPLX, int MODE>
 __global__ __launch_bounds__(1024) void k_cluster_big(ClusterArgs<T> A, T* scratch, int64_t slab) {
   constexpr bool VEC = (MODE != MODE_CERTIFY);
@@ -1007,49 +1100,8 @@ __global__ __launch_bounds__(1024) void k_cluster_big(ClusterArgs<T> A, T* scrat
   const T beta = A.tab ? (T)A.tab->beta : (T)A.beta;
   for (int64_t c = blockIdx.x; c < A.n; c += gridDim.x) {
     // ---- a2: assemble theta_e ----
-    const int64_t ho = A.hoff[c];
     const int Dc = A.Dc;
-    T my_n2 = T(0);
-    for (int64_t idx = tid; idx < DD; idx += nth) {
-      const int i = (int)(idx / D), j = (int)(idx % D);
-      T vr = T(0), vi = T(0);
-      if (ho >= 0) herm_elem<T>([&](int k) { return (T)A.h[ho + k]; }, i, j, D, CPLX, vr, vi);
-      for (int s = 0; s < A.maxch; ++s) {
-        const int m = A.ch[(int64_t)s * A.n + c];
-        if (m < 0) continue;
-        const int mask = A.chmask[(int64_t)s * A.n + c];
-        if (((i ^ j) & ~mask & (D - 1)) != 0) continue;
-        const int a = pext_rt(i, mask, NB), b = pext_rt(j, mask, NB);
-        T er, ei;
-        if (A.ze_c)
-          herm_elem<T>([&](int k) { const int64_t o = (int64_t)k * A.Mc + m;
-                                    return extrap<T>(A.nu_c[o], A.ze_c[o], th); }, a, b, Dc, CPLX, er, ei);
-        else
-          herm_elem<T>([&](int k) { return A.nu_c[(int64_t)k * A.Mc + m]; }, a, b, Dc, CPLX, er, ei);
-        vr -= er;
-        vi -= ei;
-      }
-      for (int s = 0; s < A.maxpar; ++s) {
-        const int m = A.par[(int64_t)s * A.n + c];
-        if (m < 0) continue;
-        T er, ei;
-        if (A.ze_p)
-          herm_elem<T>([&](int k) { const int64_t o = (int64_t)k * A.Mp + m;
-                                    return extrap<T>(A.nu_p[o], A.ze_p[o], th); }, i, j, D, CPLX, er, ei);
-        else
-          herm_elem<T>([&](int k) { return A.nu_p[(int64_t)k * A.Mp + m]; }, i, j, D, CPLX, er, ei);
-        vr += er;
-        vi += ei;
-      }
-      ar[idx] = vr;
-      if constexpr (CPLX) ai[idx] = vi;
-      if constexpr (VEC) {
-        ur[idx] = (i == j) ? T(1) : T(0);
-        if constexpr (CPLX) ui[idx] = T(0);
-      }
-      my_n2 = dfma<T>(vr, vr, my_n2);
-      if constexpr (CPLX) my_n2 = dfma<T>(vi, vi, my_n2);
-    }
+    const T my_n2 = big_assemble<T, T, CPLX, VEC>(A, c, D, ar, ai, ur, ui, th, tid, nth);
     const T nrm2 = block_sum(my_n2, red);
     // ---- a3: parallel cyclic Jacobi over the slab ----
     const T tol2 = (T)(A.tol * A.tol) * nrm2;
@@ -1168,37 +1220,418 @@ __global__ __launch_bounds__(1024) void k_cluster_big(ClusterArgs<T> A, T* scrat
       mfma_rebuild<T, CPLX>(ur, ui, sp, rr_, ri_, D);
       __syncthreads();
       // ---- a5: outputs ----
-      const int64_t rs_self = A.rslot ? A.rslot[c] : -1;
-      const int NCE = CPLX ? D * D : D * (D + 1) / 2;
-      for (int k = tid; k < NCE; k += nth) {
-        int i, j;
-        bool im;
-        decode_comp(k, D, i, j, im);
-        const T v = im ? ri_[(int64_t)i * D + j] : rr_[(int64_t)i * D + j];
-        if (rs_self >= 0 && A.R) A.R[(int64_t)k * A.S + rs_self] = v;
-        if (A.marg) A.marg[A.marg_off[gid] + k] = v;
+      big_outputs<T, T, CPLX>(A, c, D, gid, rr_, ri_, T(1), tid, nth);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Gibbs state by scaling and squaring on the matrix cores (accelerated iteration, De = 16, 32)
+// ------------------------------------------------------------------------------------------
+//
+// The smoothed dual needs rho_e = exp(-beta theta_e) / Z and F_beta = -(1/beta) log Z only
+// (Sec. 4.1.2); the eigenvectors are not needed for that.  With mu = Tr(theta)/D and
+// X = beta (theta - mu), the scaling s is the least s >= 0 with ||X||_F / 2^s <= 1/2, and
+//     E0 = T12(-X / 2^s)                (degree-12 Taylor polynomial, Paterson-Stockmeyer, p = 3)
+//     Y0 = E0 / Tr E0,  Y_j = Y_{j-1}^2 / Tr(Y_{j-1}^2)    (j = 1..s)
+//     rho = Y_s,  log Z = 2^s log Tr E0 + sum_j 2^(s-j) log Tr(Y_{j-1}^2)  (Horner: L <- 2L + log tau)
+// The truncation error of T12 at norm 1/2 is below 2e-14 relative, i.e. a backward error of
+// about 7e-14 ||X|| in X that the squarings do not amplify; all of it runs in FP64 on
+// v_mfma_f64_16x16x4_f64 whatever the message precision.
+//
+// One wavefront per cluster.  A matrix is NB x NB blocks of 16 x 16 held in the MFMA result
+// layout: lane l, register r of block (I, J) is element (16 I + 4 r + l/16, 16 J + l%16).
+// Every matrix here is Hermitian (a polynomial in X), so the A operand of block (I, K) at
+// k-step kk, element (16 I + l%16, 16 K + 4 kk + l/16), is the conjugate of register kk of
+// block (K, I): both operands come straight from the registers, with no data movement.
+template <int NB, bool CPLX>
+struct XMat {
+  double re[NB][NB][4];
+  double im[CPLX ? NB : 1][CPLX ? NB : 1][4];
+};
+
+// C (+)= X Y for Hermitian X; C accumulates onto its contents, column block by column block,
+// so C may alias Y (never X).
+template <int NB, bool CPLX>
+__device__ __forceinline__ void xmm(const XMat<NB, CPLX>& X, const XMat<NB, CPLX>& Y, XMat<NB, CPLX>& C) {
+#pragma unroll
+  for (int J = 0; J < NB; ++J) {
+    mfma_f64x4 cr[NB], ci[NB];
+#pragma unroll
+    for (int I = 0; I < NB; ++I) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        cr[I][r] = C.re[I][J][r];
+        if constexpr (CPLX) ci[I][r] = C.im[I][J][r];
       }
-      if (A.Tout && Dc > 0) {
-        const int NR = D / Dc;
-        const int NCC = CPLX ? Dc * Dc : Dc * (Dc + 1) / 2;
-        for (int s = 0; s < A.maxch; ++s) {
-          const int m = A.ch[(int64_t)s * A.n + c];
-          if (m < 0) continue;
-          const int mask = A.chmask[(int64_t)s * A.n + c];
-          for (int k = tid; k < NCC; k += nth) {
-            int a, b;
-            bool im;
-            decode_comp(k, Dc, a, b, im);
-            T sum = T(0);
-            for (int x = 0; x < NR; ++x) {
-              const int i = pdep_rt(a, x, mask, NB), j = pdep_rt(b, x, mask, NB);
-              sum += im ? ri_[(int64_t)i * D + j] : rr_[(int64_t)i * D + j];
-            }
-            A.Tout[(int64_t)k * A.Mc + m] = sum;
+#pragma unroll
+      for (int K = 0; K < NB; ++K)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          cr[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(X.re[K][I][kk], Y.re[K][J][kk], cr[I], 0, 0, 0);
+          if constexpr (CPLX) {
+            cr[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(X.im[K][I][kk], Y.im[K][J][kk], cr[I], 0, 0, 0);
+            ci[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(X.re[K][I][kk], Y.im[K][J][kk], ci[I], 0, 0, 0);
+            ci[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(-X.im[K][I][kk], Y.re[K][J][kk], ci[I], 0, 0, 0);
           }
         }
+    }
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        C.re[I][J][r] = cr[I][r];
+        if constexpr (CPLX) C.im[I][J][r] = ci[I][r];
+      }
+  }
+}
+
+// lane-local diagonal test for register r of a diagonal block
+__device__ __forceinline__ bool xdiag(int r, int l) { return 4 * r + (l >> 4) == (l & 15); }
+
+template <int NB, bool CPLX>
+__device__ __forceinline__ void xzero(XMat<NB, CPLX>& M) {
+#pragma unroll
+  for (int I = 0; I < NB; ++I)
+#pragma unroll
+    for (int J = 0; J < NB; ++J)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        M.re[I][J][r] = 0.0;
+        if constexpr (CPLX) M.im[I][J][r] = 0.0;
+      }
+}
+
+template <int NB, bool CPLX>
+__device__ __forceinline__ double xtrace(const XMat<NB, CPLX>& M, int l) {
+  double t = 0.0;
+#pragma unroll
+  for (int I = 0; I < NB; ++I)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (xdiag(r, l)) t += M.re[I][I][r];
+  return wave_sum(t);
+}
+
+// D = a I + b A + c A2 (+ d A3)
+template <int NB, bool CPLX, bool WITH3>
+__device__ __forceinline__ void xpoly(XMat<NB, CPLX>& D, double a, double b, double c, double d,
+                                      const XMat<NB, CPLX>& A1, const XMat<NB, CPLX>& A2,
+                                      const XMat<NB, CPLX>& A3, int l) {
+#pragma unroll
+  for (int I = 0; I < NB; ++I)
+#pragma unroll
+    for (int J = 0; J < NB; ++J)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double v = fma(c, A2.re[I][J][r], b * A1.re[I][J][r]);
+        if constexpr (WITH3) v = fma(d, A3.re[I][J][r], v);
+        if (I == J && xdiag(r, l)) v += a;
+        D.re[I][J][r] = v;
+        if constexpr (CPLX) {
+          double w = fma(c, A2.im[I][J][r], b * A1.im[I][J][r]);
+          if constexpr (WITH3) w = fma(d, A3.im[I][J][r], w);
+          D.im[I][J][r] = w;
+        }
+      }
+}
+
+template <typename T, bool CPLX, int DE>
+__global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
+  constexpr int LD = DE + 1;
+  constexpr int NB = DE / 16;
+  __shared__ T sar[DE * LD];
+  __shared__ T sai[CPLX ? DE * LD : 1];
+  const int64_t c = blockIdx.x;
+  const int l = threadIdx.x;
+  const T th = A.tab ? (T)A.tab->theta_cur : (T)A.theta;
+  const double beta = A.tab ? A.tab->beta : A.beta;
+  // ---- a1/a2: assemble theta_e at eta ----
+  lds_assemble<T, CPLX, DE, 64>(A, c, l, A.nu_c, A.ze_c, A.nu_p, A.ze_p, th, true, T(1), sar, sai);
+  __syncthreads();
+  XMat<NB, CPLX> X, P2, P3, M;
+#pragma unroll
+  for (int I = 0; I < NB; ++I)
+#pragma unroll
+    for (int J = 0; J < NB; ++J)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int o = (16 * I + 4 * r + (l >> 4)) * LD + 16 * J + (l & 15);
+        X.re[I][J][r] = (double)sar[o];
+        if constexpr (CPLX) X.im[I][J][r] = (double)sai[o];
+      }
+  // ---- shift, scale ----
+  const double mu = xtrace(X, l) / DE;
+  double n2 = 0.0;
+#pragma unroll
+  for (int I = 0; I < NB; ++I)
+#pragma unroll
+    for (int J = 0; J < NB; ++J)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double v = X.re[I][J][r];
+        if (I == J && xdiag(r, l)) v -= mu;
+        X.re[I][J][r] = v;
+        n2 = fma(v, v, n2);
+        if constexpr (CPLX) n2 = fma(X.im[I][J][r], X.im[I][J][r], n2);
+      }
+  const double nrm = beta * sqrt(wave_sum(n2));
+  int s = 0;
+  while (s < 200 && nrm > ldexp(0.5, s)) ++s;   // wave-uniform: every lane holds the same nrm
+  const double sc = -ldexp(beta, -s);
+#pragma unroll
+  for (int I = 0; I < NB; ++I)
+#pragma unroll
+    for (int J = 0; J < NB; ++J)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        X.re[I][J][r] *= sc;
+        if constexpr (CPLX) X.im[I][J][r] *= sc;
+      }
+  // ---- E0 = T12(X): powers X^2, X^3 and a Horner recursion in X^3 ----
+  constexpr double c0 = 1.0, c1 = 1.0, c2 = 1.0 / 2, c3 = 1.0 / 6, c4 = 1.0 / 24, c5 = 1.0 / 120,
+                   c6 = 1.0 / 720, c7 = 1.0 / 5040, c8 = 1.0 / 40320, c9 = 1.0 / 362880, c10 = 1.0 / 3628800,
+                   c11 = 1.0 / 39916800, c12 = 1.0 / 479001600;
+  xzero(P2);
+  xmm(X, X, P2);
+  xzero(P3);
+  xmm(X, P2, P3);
+  xpoly<NB, CPLX, true>(M, c9, c10, c11, c12, X, P2, P3, l);    // B3
+  {
+    XMat<NB, CPLX> B;
+    xpoly<NB, CPLX, false>(B, c6, c7, c8, 0.0, X, P2, P3, l);   // B2 + X^3 B3
+    xmm(P3, M, B);
+    M = B;
+    xpoly<NB, CPLX, false>(B, c3, c4, c5, 0.0, X, P2, P3, l);   // B1 + X^3 (...)
+    xmm(P3, M, B);
+    M = B;
+    xpoly<NB, CPLX, false>(B, c0, c1, c2, 0.0, X, P2, P3, l);   // B0 + X^3 (...)
+    xmm(P3, M, B);
+    M = B;
+  }
+  // ---- normalise and square s times ----
+  double t = xtrace(M, l);
+  double L = log(t);
+  {
+    const double it = 1.0 / t;
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+      for (int J = 0; J < NB; ++J)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          M.re[I][J][r] *= it;
+          if constexpr (CPLX) M.im[I][J][r] *= it;
+        }
+  }
+  for (int j = 0; j < s; ++j) {
+    xzero(X);
+    xmm(M, M, X);
+    t = xtrace(X, l);
+    L = fma(2.0, L, log(t));
+    const double it = 1.0 / t;
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+      for (int J = 0; J < NB; ++J)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          M.re[I][J][r] = X.re[I][J][r] * it;
+          if constexpr (CPLX) M.im[I][J][r] = X.im[I][J][r] * it;
+        }
+  }
+  const double F = mu - L / beta;
+  const int32_t gid = A.gid[c];
+  if (l == 0) {
+    if (A.scal) A.scal[gid] = F;
+    if (!isfinite(F) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
+  }
+  // ---- a5: rho back to LDS, then the outputs ----
+  __syncthreads();
+#pragma unroll
+  for (int I = 0; I < NB; ++I)
+#pragma unroll
+    for (int J = 0; J < NB; ++J)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int o = (16 * I + 4 * r + (l >> 4)) * LD + 16 * J + (l & 15);
+        sar[o] = (T)M.re[I][J][r];
+        if constexpr (CPLX) sai[o] = (T)M.im[I][J][r];
+      }
+  __syncthreads();
+  lds_outputs<T, CPLX, DE, 64>(A, c, l, gid, sar, sai);
+}
+
+// Workgroup variant for De = 64, 128, 256: five matrices (X, X^2, X^3 and two Horner / squaring
+// buffers) in a per-workgroup FP64 slab, row-major, real plane then imaginary plane; four
+// waves, each computing 32 x 32 output tiles (2 x 2 blocks of the 16 x 16 MFMA).  The A operand
+// of block (I, K) is read as the conjugate of block (K, I), which keeps both operand reads as
+// rows of 16 consecutive doubles.
+struct GInit {
+  double a, b, c;             // C = a I + b X + c P + scale * (A B)
+  const double* xr; const double* xi;
+  const double* pr; const double* pi;
+};
+
+template <bool CPLX, int DE>
+__device__ double gmm(const double* xr, const double* xi, const double* yr, const double* yi, double* cr_,
+                      double* ci_, double scale, const GInit& in, int tid) {
+  constexpr int NB = DE / 16, NT = NB / 2;
+  const int wave = tid / 64, l = tid % 64;
+  const int lr = l >> 4, lc = l & 15;
+  double tr = 0.0;
+  for (int t = wave; t < NT * NT; t += 4) {
+    const int TI = t / NT, TJ = t % NT;
+    mfma_f64x4 accr[2][2], acci[2][2];
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        accr[ii][jj] = mfma_f64x4{0.0, 0.0, 0.0, 0.0};
+        acci[ii][jj] = mfma_f64x4{0.0, 0.0, 0.0, 0.0};
+      }
+#pragma unroll 1
+    for (int K = 0; K < NB; ++K) {
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int64_t row = (int64_t)(16 * K + 4 * kk + lr) * DE;
+        double a_r[2], a_i[2], b_r[2], b_i[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int ca = 16 * (2 * TI + q) + lc, cb = 16 * (2 * TJ + q) + lc;
+          a_r[q] = xr[row + ca];
+          b_r[q] = yr[row + cb];
+          if constexpr (CPLX) {
+            a_i[q] = xi[row + ca];
+            b_i[q] = yi[row + cb];
+          }
+        }
+#pragma unroll
+        for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj) {
+            accr[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[ii], b_r[jj], accr[ii][jj], 0, 0, 0);
+            if constexpr (CPLX) {
+              accr[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[ii], b_i[jj], accr[ii][jj], 0, 0, 0);
+              acci[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[ii], b_i[jj], acci[ii][jj], 0, 0, 0);
+              acci[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_i[ii], b_r[jj], acci[ii][jj], 0, 0, 0);
+            }
+          }
       }
     }
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * (2 * TI + ii) + 4 * r + lr, j = 16 * (2 * TJ + jj) + lc;
+          const int64_t o = (int64_t)i * DE + j;
+          double vr = scale * accr[ii][jj][r];
+          if (in.b != 0.0) vr = fma(in.b, in.xr[o], vr);
+          if (in.c != 0.0) vr = fma(in.c, in.pr[o], vr);
+          if (i == j) {
+            vr += in.a;
+            tr += vr;
+          }
+          cr_[o] = vr;
+          if constexpr (CPLX) {
+            double vi = scale * acci[ii][jj][r];
+            if (in.b != 0.0) vi = fma(in.b, in.xi[o], vi);
+            if (in.c != 0.0) vi = fma(in.c, in.pi[o], vi);
+            ci_[o] = (i == j) ? 0.0 : vi;
+          }
+        }
+  }
+  return tr;
+}
+
+template <typename T, bool CPLX, int DE>
+__global__ __launch_bounds__(256) void k_cluster_expm_wg(ClusterArgs<T> A, double* scratch, int64_t slab) {
+  constexpr int64_t DD = (int64_t)DE * DE;
+  constexpr int NPL = CPLX ? 2 : 1;
+  __shared__ double red[8];
+  const int tid = threadIdx.x, nth = blockDim.x;
+  double* base = scratch + (int64_t)blockIdx.x * slab;
+  double* mr[5];
+  double* mi[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    mr[k] = base + (int64_t)k * NPL * DD;
+    mi[k] = CPLX ? mr[k] + DD : nullptr;
+  }
+  double *Xr = mr[0], *Xi = mi[0], *P2r = mr[1], *P2i = mi[1], *P3r = mr[2], *P3i = mi[2];
+  const T th = A.tab ? (T)A.tab->theta_cur : (T)A.theta;
+  const double beta = A.tab ? A.tab->beta : A.beta;
+  constexpr double c0 = 1.0, c1 = 1.0, c2 = 1.0 / 2, c3 = 1.0 / 6, c4 = 1.0 / 24, c5 = 1.0 / 120,
+                   c6 = 1.0 / 720, c7 = 1.0 / 5040, c8 = 1.0 / 40320, c9 = 1.0 / 362880, c10 = 1.0 / 3628800,
+                   c11 = 1.0 / 39916800, c12 = 1.0 / 479001600;
+  const GInit zero{0.0, 0.0, 0.0, nullptr, nullptr, nullptr, nullptr};
+  for (int64_t c = blockIdx.x; c < A.n; c += gridDim.x) {
+    double *Mr = mr[3], *Mi = mi[3], *Br = mr[4], *Bi = mi[4];
+    // ---- a1/a2: assemble theta_e at eta ----
+    big_assemble<T, double, CPLX, false>(A, c, DE, Xr, Xi, (double*)nullptr, (double*)nullptr, th, tid, nth);
+    __syncthreads();
+    // ---- shift and scale: X = -(beta / 2^s) (theta - mu) ----
+    double tr = 0.0;
+    for (int k = tid; k < DE; k += nth) tr += Xr[(int64_t)k * DE + k];
+    const double mu = block_sum(tr, red) / DE;
+    double n2 = 0.0;
+    for (int64_t idx = tid; idx < DD; idx += nth) {
+      const double v = Xr[idx] - ((idx / DE == idx % DE) ? mu : 0.0);
+      n2 = fma(v, v, n2);
+      if constexpr (CPLX) n2 = fma(Xi[idx], Xi[idx], n2);
+    }
+    const double nrm = beta * sqrt(block_sum(n2, red));
+    int s = 0;
+    while (s < 200 && nrm > ldexp(0.5, s)) ++s;   // block-uniform
+    const double sc = -ldexp(beta, -s);
+    for (int64_t idx = tid; idx < DD; idx += nth) {
+      Xr[idx] = sc * (Xr[idx] - ((idx / DE == idx % DE) ? mu : 0.0));
+      if constexpr (CPLX) Xi[idx] *= sc;
+    }
+    __syncthreads();
+    // ---- E0 = T12(X) ----
+    gmm<CPLX, DE>(Xr, Xi, Xr, Xi, P2r, P2i, 1.0, zero, tid);
+    __syncthreads();
+    gmm<CPLX, DE>(Xr, Xi, P2r, P2i, P3r, P3i, 1.0, zero, tid);
+    __syncthreads();
+    for (int64_t idx = tid; idx < DD; idx += nth) {
+      double v = fma(c12, P3r[idx], fma(c11, P2r[idx], c10 * Xr[idx]));
+      if (idx / DE == idx % DE) v += c9;
+      Mr[idx] = v;
+      if constexpr (CPLX) Mi[idx] = fma(c12, P3i[idx], fma(c11, P2i[idx], c10 * Xi[idx]));
+    }
+    __syncthreads();
+    const double hc[3][3] = {{c6, c7, c8}, {c3, c4, c5}, {c0, c1, c2}};
+    double trp = 0.0;
+    for (int h = 0; h < 3; ++h) {
+      const GInit in{hc[h][0], hc[h][1], hc[h][2], Xr, Xi, P2r, P2i};
+      trp = gmm<CPLX, DE>(P3r, P3i, Mr, Mi, Br, Bi, 1.0, in, tid);
+      __syncthreads();
+      double* tp = Mr; Mr = Br; Br = tp;
+      tp = Mi; Mi = Bi; Bi = tp;
+    }
+    // ---- normalise and square: Z_{j+1} = Z_j^2 / (Tr Z_j)^2 ----
+    double t = block_sum(trp, red);
+    double L = log(t);
+    for (int j = 0; j < s; ++j) {
+      trp = gmm<CPLX, DE>(Mr, Mi, Mr, Mi, Br, Bi, 1.0 / (t * t), zero, tid);
+      __syncthreads();
+      double* tp = Mr; Mr = Br; Br = tp;
+      tp = Mi; Mi = Bi; Bi = tp;
+      t = block_sum(trp, red);
+      L = fma(2.0, L, log(t));
+    }
+    const double F = mu - L / beta;
+    const int32_t gid = A.gid[c];
+    if (tid == 0) {
+      if (A.scal) A.scal[gid] = F;
+      if (!isfinite(F) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
+    }
+    // ---- a5: outputs of rho = Z_s / Tr Z_s ----
+    big_outputs<T, double, CPLX>(A, c, DE, gid, Mr, Mi, 1.0 / t, tid, nth);
     __syncthreads();
   }
 }
@@ -1573,6 +2006,9 @@ constexpr bool reg_ok() {
   return false;  // D_e = 16: H + U exceed the arch VGPR file of one lane; the LDS kernel takes it
 }
 
+// Scaling-and-squaring Gibbs kernel (shape code W = 0): dimensions and fields compiled.
+static bool expm_ok(int De, bool cplx) { return De == 16 || (De == 32 && !cplx) || De == 64 || De == 128 || De == 256; }
+
 static bool reg_pair(int De, int Dc) {
   return (De == 2 && Dc == 0) || (De == 4 && Dc == 2) || (De == 8 && (Dc == 4 || Dc == 2));
 }
@@ -1584,6 +2020,7 @@ int cluster_shapes(int De, int Dc, bool dbl, bool cplx, int mode, int* out) {
     if (De == 8) reg = !(dbl && cplx && mode != MODE_CERTIFY);
   }
   if (reg) out[n++] = 1;
+  if (mode == MODE_GIBBS && expm_ok(De, cplx)) out[n++] = 0;
   int lds[8];
   const int nl = lds_shapes(De, lds);
   if (!(De <= 4 && reg))
@@ -1624,6 +2061,29 @@ static hipError_t launch_reg(const ClusterArgs<T>& a, int block, hipStream_t s) 
 template <typename T, bool CPLX, int MODE>
 static hipError_t launch_cluster_m(const ClusterArgs<T>& a, int block, int W, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
+  if (W == 0) {
+    if constexpr (MODE == MODE_GIBBS) {
+      if (a.fp != nullptr || a.n > 0x7fffffff) return hipErrorInvalidValue;
+      if (a.De == 16)
+        hipLaunchKernelGGL((k_cluster_expm<T, CPLX, 16>), dim3((unsigned)a.n), dim3(64), 0, s, a);
+      else if (a.De == 32 && !CPLX)
+        hipLaunchKernelGGL((k_cluster_expm<T, false, 32>), dim3((unsigned)a.n), dim3(64), 0, s, a);
+      else if (a.De >= 64 && a.De <= 256 && a.expm_scratch != nullptr && a.expm_blocks > 0) {
+        const unsigned grid = (unsigned)std::min<int64_t>(a.n, a.expm_blocks);
+        if (a.De == 64)
+          hipLaunchKernelGGL((k_cluster_expm_wg<T, CPLX, 64>), dim3(grid), dim3(256), 0, s, a, a.expm_scratch, a.expm_slab);
+        else if (a.De == 128)
+          hipLaunchKernelGGL((k_cluster_expm_wg<T, CPLX, 128>), dim3(grid), dim3(256), 0, s, a, a.expm_scratch, a.expm_slab);
+        else if (a.De == 256)
+          hipLaunchKernelGGL((k_cluster_expm_wg<T, CPLX, 256>), dim3(grid), dim3(256), 0, s, a, a.expm_scratch, a.expm_slab);
+        else
+          return hipErrorInvalidValue;
+      } else
+        return hipErrorInvalidValue;
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
   if (W == 1 && a.De >= 8) {
     if (a.De == 8 && a.Dc == 4) return launch_reg<T, CPLX, MODE, 8, 4>(a, block, s);
     if (a.De == 8 && a.Dc == 2) return launch_reg<T, CPLX, MODE, 8, 2>(a, block, s);

@@ -425,3 +425,70 @@ def test_triangle_clusters_every_shape(shape):
     q_o, g_o = R.grad_beta(R.from_pairs(P.to_dense(nu32)), 2.0)
     assert abs(q32.item() - q_o[0]) <= 2e-5 * d.n_sites
     assert max_pair_err(P.to_dense(g32), R.to_pairs(g_o)) < 5e-5
+
+
+EXPM_PROBLEMS = {
+    "plaq_batch_ragged": (lambda: W.tfim_plaquette_batch([3, 4, 5], [0.7, 2.0, 3.5]), [16]),
+    "randchain_Y4_complex": (lambda: W.random_chain(8, seed=2, top_len=4, subintervals=True), [16]),
+    "heis_Y5_real": (lambda: W.with_tops(W.heisenberg_chain(9, field_x=0.4),
+                                         [tuple(range(i, i + 5)) for i in range(5)], subintervals=True), [16, 32]),
+    "randchain_Y6_complex": (lambda: W.random_chain(7, seed=3, top_len=6, subintervals=True), [16, 64]),
+    "heis_Y7_real": (lambda: W.with_tops(W.heisenberg_chain(9, field_x=0.4),
+                                         [tuple(range(i, i + 7)) for i in range(3)], subintervals=True),
+                     [16, 32, 64, 128]),
+    "gue_Y8_complex": (lambda: W.interval_chain_gue(10, 8, 0.1, seed=3), [16, 64, 128, 256]),
+}
+
+
+@pytest.mark.parametrize("name", list(EXPM_PROBLEMS))
+@pytest.mark.parametrize("beta", [0.7, 6.0, 300.0])
+def test_gibbs_by_scaling_and_squaring_matches_oracle(name, beta):
+    """The matrix-core Gibbs kernel (shape W = 0: exp(-beta theta) by scaling and squaring, no
+    eigenvectors) against the oracle's eigen-decomposition, FP64 and FP32 messages.  beta = 300
+    takes about 12 squarings."""
+    lrh = lrhmod()
+    say(f"[expm] {name} beta={beta}")
+    make, dims = EXPM_PROBLEMS[name]
+    d = make()
+    P = lrh.Problem(d, 0)
+    R = O.Relaxation(d)
+    for De in dims:
+        P.force_shape(De, 0)
+    nu_o = R.draw(41, 0.5)
+    q, g, m = P.dual_eval(P.from_dense(R.to_pairs(nu_o)), beta, grad=True, marg=True)
+    torch.cuda.synchronize()
+    q_o, g_o = R.grad_beta(nu_o, beta)
+    _, rho = R.gibbs(nu_o, beta)
+    n = sites_per_instance(d)
+    tol = 1e-10 if beta < 10 else 2e-9
+    assert np.all(np.abs(q.cpu().numpy() - q_o) <= 1e-9 * n)
+    assert max_pair_err(P.to_dense(g), R.to_pairs(g_o)) < tol
+    assert max_pair_err(P.marg_dense(m), oracle_marginals(R, rho)) < tol
+    nu32 = P.from_dense(R.to_pairs(nu_o), f32=True)
+    q32, g32, _ = P.dual_eval(nu32, beta, grad=True)
+    torch.cuda.synchronize()
+    q_o, g_o = R.grad_beta(R.from_pairs(P.to_dense(nu32)), beta)
+    assert np.all(np.abs(q32.cpu().numpy() - q_o) <= 2e-5 * n)
+    assert max_pair_err(P.to_dense(g32), R.to_pairs(g_o)) < 5e-5
+    assert P.check() == (0, 0)
+
+
+def test_gibbs_kernels_agree_in_accelerated_loop():
+    """Algorithm 2 on the plaquette batch through graph replay: the scaling-and-squaring
+    kernel and the Jacobi (LDS) kernel give the same certified bounds to 1e-9 per site."""
+    lrh = lrhmod()
+    say("[expm] plaquette batch, 200 accelerated iterations, expm vs jacobi")
+    d = W.tfim_plaquette_batch([3, 4, 5], [0.7, 2.0, 3.5])
+    out = []
+    for Wsel in (0, 16):
+        P = lrh.Problem(d, 0)
+        P.force_shape(16, Wsel)
+        nu, ze = P.zeros(), P.zeros()
+        st = P.new_nesterov_state(4.0)
+        P.step_nesterov(nu, ze, st, 200, fused=True)
+        b, mg, _ = P.certify(nu)
+        torch.cuda.synchronize()
+        out.append((b - mg).cpu().numpy())
+        assert P.check() == (0, 0)
+    n = sites_per_instance(d)
+    assert np.all(np.abs(out[0] - out[1]) <= 1e-9 * n)
