@@ -184,61 +184,293 @@ def cpu_baseline(desc, budget_s=15.0):
                        f"one thread), {dt:.1f} s")
 
 
+FP64_MFMA_PEAK_TFLOPS = 78.6
+FP64_VALU_PEAK_TFLOPS = 78.6
+
+
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def dominant_kernel_roofline(P, nu, beta, f32, torch, reps=3):
+    """Roofline of the slowest cluster-kernel launch of one pass at messages nu: the bucket's
+    algorithmic flops (11 D^3 real / 44 D^3 complex per cluster, Sec. 8(d) of the design
+    notes) over its launch duration timed live with HIP events on the launch stream.  The
+    scaling-and-squaring kernel (shape 0) runs in FP64 on the matrix cores, the others on the
+    vector ALUs in the iteration precision."""
+    us = P.time_buckets(nu, beta, reps)
+    shapes = P.shapes()
+    b = int(np.argmax(us))
+    sh = shapes[b]
+    D, n = sh["De"], sh["n"]
+    F = (11 if P.is_real else 44) * D ** 3 * n
+    t = us[b] * 1e-6
+    W = sh["W"] if f32 else sh.get("W", 0)
+    if W == 0 and D >= 16 and beta > 0:
+        bound, peak, kind = "mfma", FP64_MFMA_PEAK_TFLOPS, "scaling-and-squaring Gibbs kernel (FP64 MFMA)"
+    else:
+        bound = "alu"
+        peak = FP32_VALU_PEAK_TFLOPS if f32 else FP64_VALU_PEAK_TFLOPS
+        kind = "Jacobi cluster kernel (vector ALU)"
+    ach = F / t / 1e12
+    return dict(bound=bound, achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak, traffic=None,
+                kernel=f"{kind}, bucket D={D} (n={n}), beta={beta:g}",
+                per_launch=dict(flops=F, seconds=t), all_buckets_us=[round(u, 3) for u in us])
+
+
+def oracle_rate(desc, budget_s, beta=1.0):
+    """The FP64 oracle, untuned, on one core: Algorithm 2 iterations at fixed beta until the
+    budget is spent (at least 2).  Returns (cluster updates/s, iterations, seconds)."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    from oracle import lrh_oracle as O
+    ctx = threadpool_limits(1) if threadpool_limits else None
+    try:
+        R = O.Relaxation(desc)
+        nu = R.zeros()
+        ze = R.copy(nu)
+        L = R.lipschitz(beta)
+        th = 1.0
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            eta = R.axpby(1.0 - th, nu, th, ze)
+            _, g = R.grad_beta(eta, beta)
+            ze = R.symmetrise({k: ze[k] + g[k] / (th * L) for k in ze})
+            nu = R.symmetrise(R.axpby(1.0 - th, nu, th, ze))
+            th = O.theta_next(th)
+            n += 1
+            if n >= 2 and time.perf_counter() - t0 > budget_s:
+                break
+        dt = time.perf_counter() - t0
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+    return R.n_clusters * n / dt, n, dt
+
+
+def _line(metric_value, args, name, P, extra):
+    out = {
+        "metric": "cluster updates/s", "value": metric_value, "unit": "cluster updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "data": "synthetic",
+        "config": {"workload": name, "clusters": P.n_clusters, "messages": P.n_msgs, "instances": P.n_inst},
+    }
+    out.update(extra)
+    return out
+
+
 def bench_rate(workload, args, torch):
-    """Per-iteration rate of the batched Algorithm 2 on a large workload (cluster updates/s),
-    FP32 iterations replayed from captured graphs with autotuned launch shapes, one FP64
-    certification per step.  beta doubles every 250 iterations from 1 (no closed-form
-    reference energy, so no time-to-gap is reported for these workloads)."""
+    """Batched Algorithm 2 on a large workload: FP32 iterations replayed from captured graphs
+    with autotuned launch shapes, beta doubling 1 -> 1024 over 11 stages of
+    --iters-per-stage iterations, FP64 certification after every stage; then the plain FP64
+    form (one launch per phase, no graph) for a few iterations at beta = 64.  No closed-form
+    reference energy exists for these workloads, so no time-to-gap is reported."""
     import lrh_workloads as W
     from paper_2609_40336_amd import lrh
     t0 = time.perf_counter()
     if workload == "c4":
         desc = W.workload_c4()
+        sample = W.workload_c4(n_inst=2)
         name = "tfim_plaquette_sweep_512_L8to64_h0.5to4_nesterov_fp32"
+        sample_txt = "a 2-instance plaquette sweep drawn the same way"
+        ips = 50
     elif workload.startswith("c3k"):
         k = int(workload[3:])
         desc = W.workload_c3(k)
+        sample = W.interval_chain_gue(24, k, 0.1, seed=3)
         name = f"interval_chain_gue_n4096_eps0.1_Y{k}_nesterov_fp32"
+        sample_txt = f"the same interval hierarchy Y{k} on a 24-site chain"
+        ips = 10 if k >= 8 else 50
     else:
         raise SystemExit(f"unknown workload {workload}")
+    if args.iters_per_stage:
+        ips = args.iters_per_stage
     P = lrh.Problem(desc, 0)
     t_build = time.perf_counter() - t0
     print(f"[bench] {desc.name}: {P.n_clusters} clusters, {P.n_msgs} messages, built in {t_build:.1f} s",
           file=sys.stderr, flush=True)
-    shapes = P.autotune(True, os.path.join(os.environ.get("TMPDIR", "/tmp"), "lrh_shapes.json"))
+    cache = os.path.join(os.environ.get("TMPDIR", "/tmp"), "lrh_shapes.json")
+    shapes = P.autotune(True, cache)
+    P.autotune(False, cache)
     print(f"[bench] shapes {shapes}", file=sys.stderr, flush=True)
-    sched = [(2.0 ** s, 250) for s in range(64)]
-    S = Solver(P, True, True, sched)
+    sched = [(2.0 ** s, ips) for s in range(11)]
     for _ in range(args.warmup):
-        S.run(ITERS_PER_STEP)
+        Solver(P, True, True, sched).run(ips)
     torch.cuda.synchronize()
     S = Solver(P, True, True, sched)
-    q = torch.zeros((args.steps, P.n_inst), dtype=torch.float64, device="cuda")
+    q = torch.zeros((len(sched), P.n_inst), dtype=torch.float64, device="cuda")
     mg = torch.zeros_like(q)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [_events(torch)[0] for _ in range(len(sched) + 1)]
     torch.cuda.synchronize()
-    e0.record()
-    for k in range(args.steps):
-        S.run(ITERS_PER_STEP)
+    ev[0].record()
+    for k in range(len(sched)):
+        S.run(ips)
         lrh.lrh_certify(P.h, S.nu, lrh.LRH_F32, q[k], mg[k])
-    e1.record()
+        ev[k + 1].record()
     torch.cuda.synchronize()
-    sec = e0.elapsed_time(e1) / 1e3
-    iters = args.steps * ITERS_PER_STEP
+    sec = ev[0].elapsed_time(ev[-1]) / 1e3
+    stage_ms = [ev[k].elapsed_time(ev[k + 1]) / ips for k in range(len(sched))]
+    iters = len(sched) * ips
+    print(f"[bench] fused fp32: {sec:.3f} s for {iters} iterations", file=sys.stderr, flush=True)
     nchk, nnf = P.check()
     n_sites = np.bincount(desc.site_instance, minlength=desc.n_instances)
     bound = (q[-1] - mg[-1]).cpu().numpy()
-    out = {
-        "metric": "cluster updates/s", "value": P.n_clusters * iters / sec, "unit": "cluster updates/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": sec / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32 iterations, f64 certify", "data": "synthetic",
-        "config": {"workload": name, "clusters": P.n_clusters, "messages": P.n_msgs,
-                   "instances": P.n_inst, "iters_per_step": ITERS_PER_STEP},
+    roof = dominant_kernel_roofline(P, S.nu, 64.0, True, torch)
+    # plain FP64 form
+    n_plain = 3 if P.n_clusters * max(sh["De"] for sh in shapes) ** 3 > 5e10 else 10
+    Sp = Solver(P, False, False, [(64.0, 10 ** 9)])
+    Sp.run(1)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record()
+    Sp.run(n_plain)
+    e1.record()
+    torch.cuda.synchronize()
+    sec_plain = e0.elapsed_time(e1) / 1e3
+    print(f"[bench] plain fp64: {sec_plain:.3f} s for {n_plain} iterations", file=sys.stderr, flush=True)
+    extra = {
+        "ms_per_step": sec / len(sched) * 1e3, "dtype": "f32 iterations, f64 certify",
         "us_per_iteration": sec / iters * 1e6,
+        "schedule": f"beta = 2^s, s = 0..10, {ips} iterations per stage, FP64 certify after each stage",
+        "ms_per_iteration_by_stage": [round(x, 4) for x in stage_ms],
         "mean_certified_bound_per_site": float(np.mean(bound / n_sites)),
-        "shapes": shapes, "jacobi_noconv": nchk, "nonfinite": nnf,
+        "plain_fp64": {"value": P.n_clusters * n_plain / sec_plain, "unit": "cluster updates/s",
+                       "iterations": n_plain, "beta": 64.0},
+        "shapes": shapes, "jacobi_noconv": nchk, "nonfinite": nnf, "roofline": roof,
     }
+    if not args.no_cpu:
+        v, n, dt = oracle_rate(sample, args.cpu_budget)
+        extra["cpu_baseline"] = dict(value=v, unit="cluster updates/s", cores=1, kind="oracle",
+                                     sample=f"{n} Algorithm 2 iterations (beta = 1) of {sample_txt} "
+                                            f"(FP64 NumPy, one thread), {dt:.1f} s")
+    out = _line(P.n_clusters * iters / sec, args, name, P, extra)
+    out["config"]["iters_per_stage"] = ips
+    print(json.dumps(out))
+
+
+E0_TFIM16 = -16.146050955496804   # open TFIM chain n = 16, J = 1, h = 0.5 (free-fermion closed form)
+
+
+def bench_c1(args, torch):
+    """Algorithm 1 on the open TFIM chain n = 16 (complex storage, FP64): 2000 subgradient
+    iterations with alpha_k = 1/sqrt(k+1), one launch per phase; best certified bound and the
+    bracket against the exact ground energy."""
+    import lrh_workloads as W
+    from paper_2609_40336_amd import lrh
+    desc = W.workload_c1()
+    P = lrh.Problem(desc, 0)
+    K = 2000
+
+    def run(n):
+        nu, nb = P.zeros(), P.zeros()
+        qb = torch.full((P.n_inst,), -math.inf, dtype=torch.float64, device="cuda")
+        P.step_subgrad(nu, nb, qb, 0, n)
+        return nu, nb, qb
+    for _ in range(args.warmup):
+        run(50)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record()
+    nu, nb, qb = run(K)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    b, mg, _ = P.certify(nb)
+    torch.cuda.synchronize()
+    cert = float((b - mg).item())
+    nchk, nnf = P.check()
+    B = 16 * (3 * sum(bk["M"] * bk["comps"] for bk in P.buckets))
+    t_it = sec / K
+    extra = {
+        "ms_per_step": sec * 1e3, "dtype": "complex f64", "us_per_iteration": t_it * 1e6,
+        "q_best": float(qb.item()), "certified_bound": cert, "exact_E0": E0_TFIM16, "anderson_bound": -23.0,
+        "bracket_ok": bool(-23.0 - 1e-9 <= cert <= E0_TFIM16 + 1e-9),
+        "jacobi_noconv": nchk, "nonfinite": nnf,
+        "roofline": dict(bound="hbm", achieved=B / t_it / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                         frac=B / t_it / 1e9 / HBM_PEAK_GBS, traffic=None,
+                         kernel="one Algorithm 1 iteration (cluster kernels + reduce + message update)",
+                         per_launch=dict(bytes=B, seconds=t_it)),
+    }
+    if not args.no_cpu:
+        from oracle import lrh_oracle as O
+        R = O.Relaxation(desc)
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            n += 50
+            O.subgradient(R, n)
+            if time.perf_counter() - t0 > args.cpu_budget / 2:
+                break
+        dt = time.perf_counter() - t0
+        tot = sum(range(50, n + 1, 50))
+        extra["cpu_baseline"] = dict(value=R.n_clusters * tot / dt, unit="cluster updates/s", cores=1, kind="oracle",
+                                     sample=f"{tot} Algorithm 1 iterations on the same chain (FP64 NumPy, one "
+                                            f"thread), {dt:.1f} s")
+    out = _line(P.n_clusters * K / sec, args, "tfim_open_chain_n16_h0.5_level1_subgradient_2000it_fp64", P, extra)
+    out["steps"] = 1
+    print(json.dumps(out))
+
+
+def bench_c5(args, torch):
+    """Forward and adjoint on the 64x64 triangular XXZ lattice (FP64, beta = 4): T = 16
+    accelerated steps plus the certified value, then the reverse pass giving the gradient of
+    that value with respect to all 12288 couplings."""
+    import lrh_workloads as W
+    from paper_2609_40336_amd import lrh
+    desc = W.workload_c5()
+    P = lrh.Problem(desc, 0)
+    beta, T = 4.0, 16
+    L = beta * P.Lambda / 2.0
+
+    def forward():
+        nu, ze = P.zeros(), P.zeros()
+        st = P.new_nesterov_state(beta, L=L)
+        P.step_nesterov(nu, ze, st, T, fused=False)
+        b, mg, _ = P.certify(nu)
+        return nu, b
+    for _ in range(max(args.warmup, 1)):
+        forward()
+        P.unrolled_bound_grad(beta, T, L)
+    torch.cuda.synchronize()
+    reps = 5
+    e0, e1 = _events(torch)
+    e0.record()
+    for _ in range(reps):
+        nu, b = forward()
+    e1.record()
+    torch.cuda.synchronize()
+    t_fwd = e0.elapsed_time(e1) / 1e3 / reps
+    e0.record()
+    for _ in range(reps):
+        bb, pb, _ = P.unrolled_bound_grad(beta, T, L)
+    e1.record()
+    torch.cuda.synchronize()
+    t_grad = e0.elapsed_time(e1) / 1e3 / reps
+    roof = dominant_kernel_roofline(P, nu, beta, False, torch)
+    nchk, nnf = P.check()
+    extra = {
+        "ms_per_step": t_fwd * 1e3, "dtype": "f64", "beta": beta, "T": T,
+        "forward_s": t_fwd, "value_and_gradient_s": t_grad, "adjoint_cost_ratio": t_grad / t_fwd,
+        "bound": float(bb.item()), "grad_abs_mean": float(pb.abs().mean().item()),
+        "jacobi_noconv": nchk, "nonfinite": nnf, "roofline": roof,
+    }
+    if not args.no_cpu:
+        from oracle import lrh_oracle as O
+        R = O.Relaxation(desc)
+        t0 = time.perf_counter()
+        O.unrolled_bound_grad(R, beta, 2, L=R.lipschitz(beta))
+        dt = time.perf_counter() - t0
+        extra["cpu_baseline"] = dict(value=R.n_clusters * 2 * 2 / dt, unit="cluster updates/s", cores=1,
+                                     kind="oracle",
+                                     sample=f"value and gradient after T = 2 steps on the full lattice (oracle "
+                                            f"reverse mode, FP64 NumPy, one thread; forward + reverse counted as 2 "
+                                            f"updates per cluster and step), {dt:.1f} s")
+    out = _line(P.n_clusters * T / t_fwd, args, "xxz_triangular_64x64_delta0.5_beta4_T16_value_and_gradient_fp64",
+                P, extra)
+    out["steps"] = reps
     print(json.dumps(out))
 
 
@@ -251,7 +483,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--workload", default="c2",
-                    help="c2 (default: the 32x32 Heisenberg solve), c4 (512 plaquette lattices), c3k<k>")
+                    help="c2 (default: the 32x32 Heisenberg solve), c1 (TFIM chain, Algorithm 1), c3k<k> "
+                         "(interval hierarchy Y_k on the n = 4096 GUE chain), c4 (512 plaquette lattices), "
+                         "c5 (64x64 XXZ value and coupling gradient)")
+    ap.add_argument("--iters-per-stage", type=int, default=0,
+                    help="c3k<k>, c4: iterations per beta stage (default 50; 10 for k = 8)")
     ap.add_argument("--profile-traffic", action="store_true",
                     help="short run for hardware counters: 4 fused graph chunks, then a 64 MiB "
                          "device copy (a plain copy kernel of known size, for calibration)")
@@ -265,8 +501,11 @@ def main():
     from paper_2609_40336_amd import lrh
 
     if args.workload != "c2":
-        if args.steps == TOTAL_ITERS // ITERS_PER_STEP:
-            args.steps = 4
+        args.steps = 1
+        if args.workload == "c1":
+            return bench_c1(args, torch)
+        if args.workload == "c5":
+            return bench_c5(args, torch)
         return bench_rate(args.workload, args, torch)
     desc = W.workload_c2(32)
     P = lrh.Problem(desc, 0)

@@ -267,6 +267,15 @@ lrh_status lrh_get_shapes(lrh_problem p, int32_t cap, int32_t* De, int32_t* Dc, 
  * not compiled for that bucket). */
 lrh_status lrh_set_shape(lrh_problem p, int32_t De, int32_t block, int32_t W, uint32_t flags);
 
+/* Per-bucket kernel timing for roofline accounting: runs reps + 1 launches of every cluster
+ * bucket's kernel (Gibbs state at beta > 0, ground projector at beta = 0) at the messages nu
+ * (device, precision of `flags`), in each bucket's current shape, on `stream`, and writes the
+ * average duration of one launch in microseconds to us[b] (host array, one entry per bucket in
+ * lrh_get_shapes order).  Overwrites the library's workspace; synchronises the stream.
+ * Errors: LRH_E_INVALID (null pointer, reps < 1, beta < 0), LRH_E_DEVICE. */
+lrh_status lrh_time_buckets(lrh_problem p, const void* nu, uint32_t flags, double beta, int32_t reps, double* us,
+                            hipStream_t stream);
+
 /* Jacobi sweep cap (default 30) and relative off-diagonal tolerance (0 = default:
  * 4 eps of the iteration precision). */
 lrh_status lrh_set_jacobi(lrh_problem p, int32_t max_sweeps, double rel_tol);

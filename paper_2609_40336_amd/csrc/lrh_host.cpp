@@ -810,30 +810,65 @@ ClusterArgs<T> base_args(lrh_problem_s* P, const CBucket& B) {
 
 // One plain pass of the cluster kernels over every bucket at (nu, zeta, theta).
 template <typename T>
+ClusterArgs<T> pass_args(lrh_problem_s* P, const CBucket& B, const T* nu, const T* ze, double theta, double beta,
+                         T* marg, const FusedParams* tab) {
+  Work<T>& w = P->work<T>();
+  ClusterArgs<T> a = base_args<T>(P, B);
+  if (B.mb_child >= 0) {
+    const MBucket& M = P->mb[B.mb_child];
+    a.nu_c = nu + M.offset;
+    a.ze_c = ze ? ze + M.offset : nullptr;
+    a.Tout = w.Tb[0] + M.offset;
+  }
+  if (B.mb_self >= 0) {
+    const MBucket& M = P->mb[B.mb_self];
+    a.nu_p = nu + M.offset;
+    a.ze_p = ze ? ze + M.offset : nullptr;
+    a.R = w.Rb[0] + M.roff;
+  }
+  a.marg = marg;
+  a.marg_off = P->marg_off;
+  a.beta = beta;
+  a.theta = theta;
+  a.tab = tab;
+  return a;
+}
+
+template <typename T>
 lrh_status cluster_pass(lrh_problem_s* P, const T* nu, const T* ze, double theta, int mode, double beta,
                         T* marg, hipStream_t s, const FusedParams* tab = nullptr) {
-  Work<T>& w = P->work<T>();
   for (const CBucket& B : P->cb) {
-    ClusterArgs<T> a = base_args<T>(P, B);
-    if (B.mb_child >= 0) {
-      const MBucket& M = P->mb[B.mb_child];
-      a.nu_c = nu + M.offset;
-      a.ze_c = ze ? ze + M.offset : nullptr;
-      a.Tout = w.Tb[0] + M.offset;
-    }
-    if (B.mb_self >= 0) {
-      const MBucket& M = P->mb[B.mb_self];
-      a.nu_p = nu + M.offset;
-      a.ze_p = ze ? ze + M.offset : nullptr;
-      a.R = w.Rb[0] + M.roff;
-    }
-    a.marg = marg;
-    a.marg_off = P->marg_off;
-    a.beta = beta;
-    a.theta = theta;
-    a.tab = tab;
+    ClusterArgs<T> a = pass_args<T>(P, B, nu, ze, theta, beta, marg, tab);
     HIP_TRY(launch_cluster<T>(a, P->cplx, mode, B.block, shape_for(P, B, sizeof(T) == 8, mode), s));
   }
+  return LRH_OK;
+}
+
+// Average duration of one cluster-kernel launch per bucket at messages nu (eta = nu), in the
+// bucket's current shape, timed with events on the caller's stream.
+template <typename T>
+lrh_status time_buckets_t(lrh_problem_s* P, const T* nu, double beta, int reps, double* us, hipStream_t s) {
+  lrh_status st = ensure_work<T>(P, false);
+  if (st != LRH_OK) return st;
+  const int mode = beta > 0 ? MODE_GIBBS : MODE_GROUND;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  for (size_t b = 0; b < P->cb.size(); ++b) {
+    const CBucket& B = P->cb[b];
+    ClusterArgs<T> a = pass_args<T>(P, B, nu, nullptr, 0.0, beta, nullptr, nullptr);
+    const int W = shape_for(P, B, sizeof(T) == 8, mode);
+    HIP_TRY(launch_cluster<T>(a, P->cplx, mode, B.block, W, s));
+    HIP_TRY(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) HIP_TRY(launch_cluster<T>(a, P->cplx, mode, B.block, W, s));
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    us[b] = 1e3 * ms / reps;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   return LRH_OK;
 }
 
@@ -1628,6 +1663,16 @@ lrh_status lrh_set_shape(lrh_problem p, int32_t De, int32_t block, int32_t W, ui
   }
   if (!any) return fail(LRH_E_INVALID, "no cluster bucket with that dimension");
   return LRH_OK;
+}
+
+lrh_status lrh_time_buckets(lrh_problem p, const void* nu, uint32_t flags, double beta, int32_t reps, double* us,
+                            hipStream_t stream) {
+  if (!p || !nu || !us || reps < 1) return fail(LRH_E_INVALID, "null argument or reps < 1");
+  if (p->host_only) return fail(LRH_E_INVALID, "problem was built without a device");
+  if (!(beta >= 0.0) || !std::isfinite(beta)) return fail(LRH_E_INVALID, "beta must be finite and >= 0");
+  DeviceGuard guard(p->device);
+  if (flags & LRH_F32) return time_buckets_t<float>(p, (const float*)nu, beta, reps, us, stream);
+  return time_buckets_t<double>(p, (const double*)nu, beta, reps, us, stream);
 }
 
 lrh_status lrh_set_jacobi(lrh_problem p, int32_t max_sweeps, double rel_tol) {

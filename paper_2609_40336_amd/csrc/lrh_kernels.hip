@@ -1637,6 +1637,150 @@ __global__ __launch_bounds__(256) void k_cluster_expm_wg(ClusterArgs<T> A, doubl
 }
 
 // ------------------------------------------------------------------------------------------
+// certified lambda_min for De >= 64 without eigenvectors (a8)
+// ------------------------------------------------------------------------------------------
+//
+// theta_e (FP64, in a per-workgroup slab) is reduced to a Hermitian tridiagonal matrix by De - 2
+// Householder reflections H = I - tau v v^H acting on the trailing block (A <- H A H with the
+// rank-2 form A - v w^H - w v^H, w = p - (tau/2)(v^H p) v, p = tau A v).  A diagonal unitary
+// makes the off-diagonal real and non-negative, so the eigenvalues are those of the real
+// symmetric tridiagonal (d, |e|).  lambda_min is then bracketed by multisection on Sturm counts
+// (number of eigenvalues below x from the signs of the LDL^T pivots), 256 points per round;
+// the lower end of the final bracket, below which no eigenvalue lies, is returned.
+template <bool CPLX, int DE>
+__global__ __launch_bounds__(256) void k_cluster_tridiag(ClusterArgs<double> A, double* scratch, int64_t slab) {
+  constexpr int64_t DD = (int64_t)DE * DE;
+  __shared__ double vr[DE], vi[DE], pr[DE], pi[DE];
+  __shared__ double dg[DE], e2[DE];
+  __shared__ double red[8];
+  const int tid = threadIdx.x, nth = blockDim.x;
+  double* ar = scratch + (int64_t)blockIdx.x * slab;
+  double* ai = CPLX ? ar + DD : nullptr;
+  for (int64_t c = blockIdx.x; c < A.n; c += gridDim.x) {
+    const double my_n2 = big_assemble<double, double, CPLX, false>(A, c, DE, ar, ai, (double*)nullptr,
+                                                                    (double*)nullptr, 0.0, tid, nth);
+    const double nrm2 = block_sum(my_n2, red);
+    for (int k = 0; k < DE - 2; ++k) {
+      const int m = DE - k - 1;
+      const int64_t rk = (int64_t)k * DE + k + 1;   // x_i = A[k+1+i][k] = conj(A[k][k+1+i])
+      double xs = 0.0;
+      for (int i = tid; i < m; i += nth) {
+        const double xr = ar[rk + i];
+        xs = fma(xr, xr, xs);
+        if constexpr (CPLX) xs = fma(ai[rk + i], ai[rk + i], xs);
+      }
+      const double xn2 = block_sum(xs, red);
+      const double xn = sqrt(xn2);
+      const double x0r = ar[rk], x0i = CPLX ? -ai[rk] : 0.0;
+      const double a0 = sqrt(fma(x0r, x0r, x0i * x0i));
+      if (tid == 0) {
+        dg[k] = ar[(int64_t)k * DE + k];
+        e2[k] = xn2;
+      }
+      const double vn2 = 2.0 * (xn2 + a0 * xn);
+      if (!(vn2 > 0.0)) continue;   // column already reduced (block-uniform)
+      const double ur = a0 > 0.0 ? x0r / a0 : 1.0, ui = a0 > 0.0 ? x0i / a0 : 0.0;
+      const double tau = 2.0 / vn2;
+      for (int i = tid; i < m; i += nth) {
+        double r = ar[rk + i], im = CPLX ? -ai[rk + i] : 0.0;
+        if (i == 0) {
+          r += ur * xn;    // v = x - alpha e1, alpha = -(x0/|x0|) ||x||
+          im += ui * xn;
+        }
+        vr[i] = r;
+        vi[i] = im;
+      }
+      __syncthreads();
+      // p = tau A22 v; A22 is Hermitian, so row i of A22 v reads column i (coalesced across i)
+      for (int i = tid; i < m; i += nth) {
+        double sr = 0.0, si = 0.0;
+        const double* col_r = ar + (int64_t)(k + 1) * DE + (k + 1 + i);
+        const double* col_i = CPLX ? ai + (int64_t)(k + 1) * DE + (k + 1 + i) : nullptr;
+#pragma unroll 4
+        for (int j = 0; j < m; ++j) {
+          const double a_r = col_r[(int64_t)j * DE];
+          sr = fma(a_r, vr[j], sr);
+          if constexpr (CPLX) {
+            const double a_i = -col_i[(int64_t)j * DE];
+            sr = fma(-a_i, vi[j], sr);
+            si = fma(a_r, vi[j], fma(a_i, vr[j], si));
+          }
+        }
+        pr[i] = tau * sr;
+        pi[i] = tau * si;
+      }
+      __syncthreads();
+      double ks = 0.0;
+      for (int i = tid; i < m; i += nth) ks = fma(vr[i], pr[i], fma(vi[i], pi[i], ks));
+      const double K = 0.5 * tau * block_sum(ks, red);
+      for (int i = tid; i < m; i += nth) {
+        pr[i] = fma(-K, vr[i], pr[i]);
+        pi[i] = fma(-K, vi[i], pi[i]);
+      }
+      __syncthreads();
+      // A22 -= v w^H + w v^H
+      for (int idx = tid; idx < m * m; idx += nth) {
+        const int i = idx / m, j = idx % m;
+        const int64_t o = (int64_t)(k + 1 + i) * DE + (k + 1 + j);
+        double re = fma(vr[i], pr[j], fma(vi[i], pi[j], fma(pr[i], vr[j], pi[i] * vi[j])));
+        ar[o] -= re;
+        if constexpr (CPLX) {
+          const double im = fma(vi[i], pr[j], fma(-vr[i], pi[j], fma(pi[i], vr[j], -pr[i] * vi[j])));
+          ai[o] -= im;
+        }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      dg[DE - 2] = ar[(int64_t)(DE - 2) * DE + DE - 2];
+      dg[DE - 1] = ar[(int64_t)(DE - 1) * DE + DE - 1];
+      const double xr = ar[(int64_t)(DE - 2) * DE + DE - 1], xi = CPLX ? ai[(int64_t)(DE - 2) * DE + DE - 1] : 0.0;
+      e2[DE - 2] = fma(xr, xr, xi * xi);
+      e2[DE - 1] = 0.0;
+    }
+    __syncthreads();
+    // Gershgorin bracket (every thread, same order: identical values)
+    double lo = INFINITY, hi = -INFINITY, emax = 0.0;
+    for (int i = 0; i < DE; ++i) {
+      const double r = (i > 0 ? sqrt(e2[i - 1]) : 0.0) + sqrt(e2[i]);
+      lo = fmin(lo, dg[i] - r);
+      hi = fmax(hi, dg[i] + r);
+      emax = fmax(emax, e2[i]);
+    }
+    const double pivmin = DBL_MIN * fmax(1.0, emax);
+    const double span0 = fmax(hi - lo, DBL_MIN);
+    lo -= 2.0 * DBL_EPSILON * fabs(lo) + span0 * DBL_EPSILON;
+    hi += 2.0 * DBL_EPSILON * fabs(hi) + span0 * DBL_EPSILON;
+    for (int round = 0; round < 12; ++round) {
+      const double x = lo + (hi - lo) * (double)(tid + 1) / (double)(nth + 1);
+      int cnt = 0;
+      double q = dg[0] - x;
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0;
+      for (int i = 1; i < DE; ++i) {
+        q = (dg[i] - x) - e2[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += q < 0.0;
+      }
+      const double first = block_min(cnt > 0 ? (double)tid : (double)nth, red);
+      const int t = (int)first;
+      const double nlo = t == 0 ? lo : lo + (hi - lo) * (double)t / (double)(nth + 1);
+      const double nhi = t == nth ? hi : lo + (hi - lo) * (double)(t + 1) / (double)(nth + 1);
+      if (!(nhi - nlo < hi - lo)) break;
+      lo = nlo;
+      hi = nhi;
+    }
+    const int32_t gid = A.gid[c];
+    if (tid == 0) {
+      A.scal[gid] = lo;
+      A.scal2[gid] = 8.0 * DE * DBL_EPSILON * sqrt(nrm2);
+      if (!isfinite(lo) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // adjoint (a9): VJP of (Q_beta, grad Q_beta) through one cluster
 // ------------------------------------------------------------------------------------------
 //
@@ -2021,6 +2165,7 @@ int cluster_shapes(int De, int Dc, bool dbl, bool cplx, int mode, int* out) {
   }
   if (reg) out[n++] = 1;
   if (mode == MODE_GIBBS && expm_ok(De, cplx)) out[n++] = 0;
+  if (mode == MODE_CERTIFY && De >= 64 && De <= 256) out[n++] = 2;
   int lds[8];
   const int nl = lds_shapes(De, lds);
   if (!(De <= 4 && reg))
@@ -2079,6 +2224,22 @@ static hipError_t launch_cluster_m(const ClusterArgs<T>& a, int block, int W, hi
         else
           return hipErrorInvalidValue;
       } else
+        return hipErrorInvalidValue;
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
+  if (W == 2) {
+    if constexpr (MODE == MODE_CERTIFY && std::is_same<T, double>::value) {
+      if (a.expm_scratch == nullptr || a.expm_blocks <= 0) return hipErrorInvalidValue;
+      const unsigned grid = (unsigned)std::min<int64_t>(a.n, a.expm_blocks);
+      if (a.De == 64)
+        hipLaunchKernelGGL((k_cluster_tridiag<CPLX, 64>), dim3(grid), dim3(256), 0, s, a, a.expm_scratch, a.expm_slab);
+      else if (a.De == 128)
+        hipLaunchKernelGGL((k_cluster_tridiag<CPLX, 128>), dim3(grid), dim3(256), 0, s, a, a.expm_scratch, a.expm_slab);
+      else if (a.De == 256)
+        hipLaunchKernelGGL((k_cluster_tridiag<CPLX, 256>), dim3(grid), dim3(256), 0, s, a, a.expm_scratch, a.expm_slab);
+      else
         return hipErrorInvalidValue;
       return hipGetLastError();
     }

@@ -69,7 +69,7 @@ _lib = None
 EXPORTS = ["lrh_build_clusters", "lrh_query", "lrh_export_clusters", "lrh_export_messages",
            "lrh_dual_eval", "lrh_step_subgrad", "lrh_step_nesterov", "lrh_certify", "lrh_check",
            "lrh_set_jacobi", "lrh_destroy", "lrh_last_error", "lrh_set_params", "lrh_dual_vjp",
-           "lrh_unrolled_bound_grad", "lrh_autotune", "lrh_get_shapes", "lrh_set_shape"]
+           "lrh_unrolled_bound_grad", "lrh_autotune", "lrh_get_shapes", "lrh_set_shape", "lrh_time_buckets"]
 
 
 def load(path: str = LIB_PATH):
@@ -95,6 +95,7 @@ def load(path: str = LIB_PATH):
         "lrh_set_params": (i32, [vp, vp, vp]),
         "lrh_autotune": (i32, [vp, u32, C.c_char_p, vp]),
         "lrh_set_shape": (i32, [vp, i32, i32, i32, u32]),
+        "lrh_time_buckets": (i32, [vp, vp, u32, C.c_double, i32, vp, vp]),
         "lrh_get_shapes": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, C.POINTER(i32)]),
         "lrh_dual_vjp": (i32, [vp, vp, u32, dbl, vp, vp, vp, vp, vp]),
         "lrh_unrolled_bound_grad": (i32, [vp, vp, dbl, dbl, i32, vp, vp, vp, vp, u32, vp]),
@@ -242,6 +243,17 @@ def lrh_autotune(h, flags=0, cache_path: Optional[str] = None, stream=None):
 
 def lrh_set_shape(h, De, block, W, flags=0):
     _check(load().lrh_set_shape(h, int(De), int(block), int(W), flags))
+
+
+def lrh_time_buckets(h, nu, beta: float, reps: int = 3, stream=None):
+    import torch
+    cnt = C.c_int32(0)
+    _check(load().lrh_get_shapes(h, 0, None, None, None, None, None, None, C.byref(cnt)))
+    us = np.zeros(max(cnt.value, 1), np.float64)
+    f32 = nu.dtype == torch.float32
+    _check(load().lrh_time_buckets(h, _dptr(nu), LRH_F32 if f32 else 0, float(beta), int(reps), us.ctypes.data,
+                                   _stream(stream)))
+    return [float(u) for u in us[:cnt.value]]
 
 
 def lrh_get_shapes(h):
@@ -464,6 +476,10 @@ class Problem:
 
     def shapes(self):
         return lrh_get_shapes(self.h)
+
+    def time_buckets(self, nu, beta: float, reps: int = 3, stream=None):
+        """Per-bucket cluster-kernel launch durations (us), in shapes() order."""
+        return lrh_time_buckets(self.h, nu, beta, reps, stream)
 
     def force_shape(self, De: int, W: int, block: int = 64, f32=None):
         for flag in ([LRH_F32, 0] if f32 is None else [LRH_F32 if f32 else 0]):

@@ -114,7 +114,8 @@ def test_dual_eval_fp32(name):
     assert max_pair_err(P.to_dense(g), R.to_pairs(g_o)) < 5e-5
 
 
-@pytest.mark.parametrize("name", ["c1_tfim16_complex", "randchain_Y6", "plaq_batch_ragged", "xxz_tri3", "gue_Y8"])
+@pytest.mark.parametrize("name", ["c1_tfim16_complex", "randchain_Y6", "plaq_batch_ragged", "xxz_tri3", "gue_Y7",
+                                  "gue_Y8", "randchain_Y7_real"])
 def test_certify_fp64_and_from_fp32(name):
     lrh = lrhmod()
     say(f"[certify] {name}")
