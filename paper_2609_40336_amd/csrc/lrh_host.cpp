@@ -727,7 +727,7 @@ lrh_status ensure_work(lrh_problem_s* P, bool fused) {
     int64_t nx = 0;
     int Dmax = 0;
     for (const CBucket& B : P->cb)
-      if (B.De >= 64) {
+      if (B.De >= 64 || (B.De == 32 && P->cplx)) {
         nx = std::max<int64_t>(nx, B.n);
         Dmax = std::max(Dmax, B.De);
       }
@@ -799,7 +799,7 @@ ClusterArgs<T> base_args(lrh_problem_s* P, const CBucket& B) {
     a.big_slab = w.big_slab;
     a.big_blocks = w.big_blocks;
   }
-  if (B.De >= 64) {
+  if (B.De >= 64 || (B.De == 32 && P->cplx)) {
     Work<T>& w = P->work<T>();
     a.expm_scratch = w.xbig;
     a.expm_slab = w.xslab;

@@ -528,6 +528,20 @@ __device__ __forceinline__ void herm_elem(Get get, int a, int b, int D, bool cpl
   }
 }
 
+// Element (a, b) of a packed Hermitian without branches: both addresses are always valid, the
+// imaginary part is selected (conjugated below the diagonal, zero on it).
+template <typename T, bool CPLX, typename Get>
+__device__ __forceinline__ void herm_elem_bf(Get get, int a, int b, int D, T& vr, T& vi) {
+  const int lo = min(a, b), hi = max(a, b);
+  vr = get(tri_index(lo, hi, D));
+  if constexpr (CPLX) {
+    const T v = get(D * (D + 1) / 2 + (lo < hi ? stri_index(lo, hi, D) : 0));
+    vi = a < b ? v : (a > b ? -v : T(0));
+  } else {
+    vi = T(0);
+  }
+}
+
 // ---- shared pieces of the LDS kernels ----
 //
 // A 64-lane wave holds G = 64/W clusters, W lanes each (W is a power of two, 8..64); lane `lt`
@@ -1234,8 +1248,9 @@ __global__ __launch_bounds__(1024) void k_cluster_big(ClusterArgs<T> A, T* scrat
 // (Sec. 4.1.2); the eigenvectors are not needed for that.  With mu = Tr(theta)/D and
 // X = beta (theta - mu), the scaling s is the least s >= 0 with ||X||_F / 2^s <= 1/2, and
 //     E0 = T12(-X / 2^s)                (degree-12 Taylor polynomial, Paterson-Stockmeyer, p = 3)
-//     Y0 = E0 / Tr E0,  Y_j = Y_{j-1}^2 / Tr(Y_{j-1}^2)    (j = 1..s)
-//     rho = Y_s,  log Z = 2^s log Tr E0 + sum_j 2^(s-j) log Tr(Y_{j-1}^2)  (Horner: L <- 2L + log tau)
+//     Y0 = E0 / Tr E0,  Y_j = Y_{j-1}^2 / tau_j    (j = 1..s)
+//     rho = Y_s / Tr Y_s,  log Z = 2^s log Tr E0 + sum_j 2^(s-j) log tau_j + log Tr Y_s
+// for any positive rescalings tau_j of the squarings (here exact powers of two).
 // The truncation error of T12 at norm 1/2 is below 2e-14 relative, i.e. a backward error of
 // about 7e-14 ||X|| in X that the squarings do not amplify; all of it runs in FP64 on
 // v_mfma_f64_16x16x4_f64 whatever the message precision.
@@ -1245,6 +1260,8 @@ __global__ __launch_bounds__(1024) void k_cluster_big(ClusterArgs<T> A, T* scrat
 // Every matrix here is Hermitian (a polynomial in X), so the A operand of block (I, K) at
 // k-step kk, element (16 I + l%16, 16 K + 4 kk + l/16), is the conjugate of register kk of
 // block (K, I): both operands come straight from the registers, with no data movement.
+constexpr int kExpmLut = 8;   // children handled through the LDS index tables (more: generic path)
+
 template <int NB, bool CPLX>
 struct XMat {
   double re[NB][NB][4];
@@ -1347,20 +1364,119 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
   const int l = threadIdx.x;
   const T th = A.tab ? (T)A.tab->theta_cur : (T)A.theta;
   const double beta = A.tab ? A.tab->beta : A.beta;
-  // ---- a1/a2: assemble theta_e at eta ----
-  lds_assemble<T, CPLX, DE, 64>(A, c, l, A.nu_c, A.ze_c, A.nu_p, A.ze_p, th, true, T(1), sar, sai);
-  __syncthreads();
+  constexpr int NBITS = log2i(DE);
+  const int Dc = A.Dc;
+  const int nch = A.maxch;
+  const bool lut = nch <= kExpmLut;   // cluster-uniform
+  // per child: pext of every cluster index onto the child's sites, and pdep of (child index a,
+  // complement index x) back to the cluster index, as LDS tables
+  __shared__ unsigned char pextL[kExpmLut][DE], depL[kExpmLut][DE];
+  __shared__ T stc_r[kExpmLut][DE * DE / 4];
+  __shared__ T stc_i[CPLX ? kExpmLut : 1][CPLX ? DE * DE / 4 : 1];
   XMat<NB, CPLX> X, P2, P3, M;
-#pragma unroll
-  for (int I = 0; I < NB; ++I)
-#pragma unroll
-    for (int J = 0; J < NB; ++J)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int o = (16 * I + 4 * r + (l >> 4)) * LD + 16 * J + (l & 15);
-        X.re[I][J][r] = (double)sar[o];
-        if constexpr (CPLX) X.im[I][J][r] = (double)sai[o];
+  // ---- a1/a2: assemble theta_e at eta ----
+  if (lut) {
+    for (int s = 0; s < nch; ++s) {
+      const int mask = A.chmask[(int64_t)s * A.n + c];
+      if (l < DE) {
+        pextL[s][l] = (unsigned char)pext_rt(l, mask, NBITS);
+        const int NR = DE / (Dc > 0 ? Dc : 1);
+        depL[s][l] = (unsigned char)pdep_rt(l / NR, l % NR, mask, NBITS);
       }
+    }
+    __syncthreads();
+    // branch-free element assembly: every candidate element is loaded from a valid address and
+    // then selected, so the lanes of the wave never diverge
+    // (h_e, then the children in slot order, then the parents: the order of the generic path)
+    const int64_t ho = A.hoff[c];
+    T acr[NB][NB][4], aci[NB][NB][4];
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+      for (int J = 0; J < NB; ++J)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * I + 4 * r + (l >> 4), j = 16 * J + (l & 15);
+          double vr = 0.0, vi = 0.0;
+          if (ho >= 0) herm_elem_bf<double, CPLX>([&](int k) { return A.h[ho + k]; }, i, j, DE, vr, vi);
+          acr[I][J][r] = (T)vr;
+          aci[I][J][r] = (T)vi;
+        }
+    // the (extrapolated) child messages, dense D_c x D_c in LDS, one pass over all children
+    for (int idx = l; idx < nch * Dc * Dc; idx += 64) {
+      const int s = idx / (Dc * Dc), ab = idx % (Dc * Dc);
+      const int m = A.ch[(int64_t)s * A.n + c];
+      if (m < 0) continue;
+      T er, ei;
+      if (A.ze_c)
+        herm_elem_bf<T, CPLX>([&](int k) { const int64_t o = (int64_t)k * A.Mc + m;
+                                           return extrap<T>(A.nu_c[o], A.ze_c[o], th); }, ab / Dc, ab % Dc, Dc, er, ei);
+      else
+        herm_elem_bf<T, CPLX>([&](int k) { return A.nu_c[(int64_t)k * A.Mc + m]; }, ab / Dc, ab % Dc, Dc, er, ei);
+      stc_r[s][ab] = er;
+      if constexpr (CPLX) stc_i[s][ab] = ei;
+    }
+    __syncthreads();
+    for (int s = 0; s < nch; ++s) {
+      const int m = A.ch[(int64_t)s * A.n + c];
+      if (m < 0) continue;   // cluster-uniform
+      const int mask = A.chmask[(int64_t)s * A.n + c];
+#pragma unroll
+      for (int I = 0; I < NB; ++I)
+#pragma unroll
+        for (int J = 0; J < NB; ++J)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = 16 * I + 4 * r + (l >> 4), j = 16 * J + (l & 15);
+            const bool ok = ((i ^ j) & ~mask & (DE - 1)) == 0;
+            const int ab = pextL[s][i] * Dc + pextL[s][j];
+            acr[I][J][r] -= ok ? stc_r[s][ab] : T(0);
+            if constexpr (CPLX) aci[I][J][r] -= ok ? stc_i[s][ab] : T(0);
+          }
+    }
+    for (int s = 0; s < A.maxpar; ++s) {
+      const int m = A.par[(int64_t)s * A.n + c];
+      if (m < 0) continue;   // cluster-uniform
+#pragma unroll
+      for (int I = 0; I < NB; ++I)
+#pragma unroll
+        for (int J = 0; J < NB; ++J)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = 16 * I + 4 * r + (l >> 4), j = 16 * J + (l & 15);
+            T er, ei;
+            if (A.ze_p)
+              herm_elem_bf<T, CPLX>([&](int k) { const int64_t o = (int64_t)k * A.Mp + m;
+                                                 return extrap<T>(A.nu_p[o], A.ze_p[o], th); }, i, j, DE, er, ei);
+            else
+              herm_elem_bf<T, CPLX>([&](int k) { return A.nu_p[(int64_t)k * A.Mp + m]; }, i, j, DE, er, ei);
+            acr[I][J][r] += er;
+            aci[I][J][r] += ei;
+          }
+    }
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+      for (int J = 0; J < NB; ++J)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          X.re[I][J][r] = (double)acr[I][J][r];
+          if constexpr (CPLX) X.im[I][J][r] = (double)aci[I][J][r];
+        }
+  } else {
+    lds_assemble<T, CPLX, DE, 64>(A, c, l, A.nu_c, A.ze_c, A.nu_p, A.ze_p, th, true, T(1), sar, sai);
+    __syncthreads();
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+      for (int J = 0; J < NB; ++J)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int o = (16 * I + 4 * r + (l >> 4)) * LD + 16 * J + (l & 15);
+          X.re[I][J][r] = (double)sar[o];
+          if constexpr (CPLX) X.im[I][J][r] = (double)sai[o];
+        }
+  }
   // ---- shift, scale ----
   const double mu = xtrace(X, l) / DE;
   double n2 = 0.0;
@@ -1425,20 +1541,54 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
           if constexpr (CPLX) M.im[I][J][r] *= it;
         }
   }
-  for (int j = 0; j < s; ++j) {
+  // Squarings are rescaled by exact powers of two 2^-e_j, j = 3, 7, 11, ... and the last, chosen
+  // from the trace (for a PSD Y of trace 1, Tr(Y^(2^k)) >= D^(1 - 2^k), so four unscaled
+  // squarings stay far above the FP64 range limit); e_j = 0 elsewhere.  The exponents are
+  // accumulated as an integer, E <- 2E + e_j, so no logarithm or division sits in the loop:
+  //     log Z = 2^s log Tr E0 + E log 2 + log Tr Y_s,   rho = Y_s / Tr Y_s.
+  // X and M alternate as product buffers (the loop is unrolled by two).
+  double E = 0.0;
+  auto post = [&](XMat<NB, CPLX>& Y, int j) {
+    E *= 2.0;
+    if ((j & 3) == 3 || j == s - 1) {
+      const int e = ilogb(xtrace(Y, l));
+      E += (double)e;
+      const double sc2 = ldexp(1.0, -e);
+#pragma unroll
+      for (int I = 0; I < NB; ++I)
+#pragma unroll
+        for (int J = 0; J < NB; ++J)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            Y.re[I][J][r] *= sc2;
+            if constexpr (CPLX) Y.im[I][J][r] *= sc2;
+          }
+    }
+  };
+  for (int j = 0; j < s; j += 2) {
     xzero(X);
     xmm(M, M, X);
-    t = xtrace(X, l);
-    L = fma(2.0, L, log(t));
-    const double it = 1.0 / t;
+    post(X, j);
+    if (j + 1 < s) {
+      xzero(M);
+      xmm(X, X, M);
+      post(M, j + 1);
+    } else {
+      M = X;
+    }
+  }
+  {
+    const double tf = xtrace(M, l);
+    L = fma(ldexp(1.0, s), L, fma(E, 0.69314718055994530942, log(tf)));
+    const double it = 1.0 / tf;
 #pragma unroll
     for (int I = 0; I < NB; ++I)
 #pragma unroll
       for (int J = 0; J < NB; ++J)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          M.re[I][J][r] = X.re[I][J][r] * it;
-          if constexpr (CPLX) M.im[I][J][r] = X.im[I][J][r] * it;
+          M.re[I][J][r] *= it;
+          if constexpr (CPLX) M.im[I][J][r] *= it;
         }
   }
   const double F = mu - L / beta;
@@ -1460,12 +1610,57 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
         if constexpr (CPLX) sai[o] = (T)M.im[I][J][r];
       }
   __syncthreads();
-  lds_outputs<T, CPLX, DE, 64>(A, c, l, gid, sar, sai);
+  if (!lut) {
+    lds_outputs<T, CPLX, DE, 64>(A, c, l, gid, sar, sai);
+    return;
+  }
+  // own marginal slot and per-cluster marginal, straight from the registers (upper triangle)
+  const int64_t rs_self = A.rslot ? A.rslot[c] : -1;
+  if ((rs_self >= 0 && A.R) || A.marg) {
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+      for (int J = 0; J < NB; ++J)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * I + 4 * r + (l >> 4), j = 16 * J + (l & 15);
+          if (i > j) continue;
+          const int kr = tri_index(i, j, DE);
+          const T vr = (T)M.re[I][J][r];
+          if (rs_self >= 0 && A.R) A.R[(int64_t)kr * A.S + rs_self] = vr;
+          if (A.marg) A.marg[A.marg_off[gid] + kr] = vr;
+          if constexpr (CPLX) {
+            if (i < j) {
+              const int ki = DE * (DE + 1) / 2 + stri_index(i, j, DE);
+              const T vi = (T)M.im[I][J][r];
+              if (rs_self >= 0 && A.R) A.R[(int64_t)ki * A.S + rs_self] = vi;
+              if (A.marg) A.marg[A.marg_off[gid] + ki] = vi;
+            }
+          }
+        }
+  }
+  // partial traces onto every child, all (child, component) pairs across the lanes
+  if (A.Tout && Dc > 0) {
+    const int NR = DE / Dc;
+    const int NCC = CPLX ? Dc * Dc : Dc * (Dc + 1) / 2;
+    for (int idx = l; idx < nch * NCC; idx += 64) {
+      const int s = idx / NCC, k = idx % NCC;
+      const int m = A.ch[(int64_t)s * A.n + c];
+      if (m < 0) continue;
+      int a, b;
+      bool im;
+      decode_comp(k, Dc, a, b, im);
+      const T* y = im ? sai : sar;
+      T sum = T(0);
+      for (int x = 0; x < NR; ++x) sum += y[depL[s][a * NR + x] * LD + depL[s][b * NR + x]];
+      A.Tout[(int64_t)k * A.Mc + m] = sum;
+    }
+  }
 }
 
-// Workgroup variant for De = 64, 128, 256: five matrices (X, X^2, X^3 and two Horner / squaring
+// Workgroup variant for De = 32 (complex), 64, 128, 256: five matrices (X, X^2, X^3 and two Horner / squaring
 // buffers) in a per-workgroup FP64 slab, row-major, real plane then imaginary plane; four
-// waves, each computing 32 x 32 output tiles (2 x 2 blocks of the 16 x 16 MFMA).  The A operand
+// waves, each computing 32 x 32 output tiles (2 x 2 blocks of the 16 x 16 MFMA; 16 x 16 at De = 32).  The A operand
 // of block (I, K) is read as the conjugate of block (K, I), which keeps both operand reads as
 // rows of 16 consecutive doubles.
 struct GInit {
@@ -1477,17 +1672,18 @@ struct GInit {
 template <bool CPLX, int DE>
 __device__ double gmm(const double* xr, const double* xi, const double* yr, const double* yi, double* cr_,
                       double* ci_, double scale, const GInit& in, int tid) {
-  constexpr int NB = DE / 16, NT = NB / 2;
+  constexpr int TB = DE >= 64 ? 2 : 1;   // output tile of TB x TB blocks per wave
+  constexpr int NB = DE / 16, NT = NB / TB;
   const int wave = tid / 64, l = tid % 64;
   const int lr = l >> 4, lc = l & 15;
   double tr = 0.0;
   for (int t = wave; t < NT * NT; t += 4) {
     const int TI = t / NT, TJ = t % NT;
-    mfma_f64x4 accr[2][2], acci[2][2];
+    mfma_f64x4 accr[TB][TB], acci[TB][TB];
 #pragma unroll
-    for (int ii = 0; ii < 2; ++ii)
+    for (int ii = 0; ii < TB; ++ii)
 #pragma unroll
-      for (int jj = 0; jj < 2; ++jj) {
+      for (int jj = 0; jj < TB; ++jj) {
         accr[ii][jj] = mfma_f64x4{0.0, 0.0, 0.0, 0.0};
         acci[ii][jj] = mfma_f64x4{0.0, 0.0, 0.0, 0.0};
       }
@@ -1496,10 +1692,10 @@ __device__ double gmm(const double* xr, const double* xi, const double* yr, cons
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int64_t row = (int64_t)(16 * K + 4 * kk + lr) * DE;
-        double a_r[2], a_i[2], b_r[2], b_i[2];
+        double a_r[TB], a_i[TB], b_r[TB], b_i[TB];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int ca = 16 * (2 * TI + q) + lc, cb = 16 * (2 * TJ + q) + lc;
+        for (int q = 0; q < TB; ++q) {
+          const int ca = 16 * (TB * TI + q) + lc, cb = 16 * (TB * TJ + q) + lc;
           a_r[q] = xr[row + ca];
           b_r[q] = yr[row + cb];
           if constexpr (CPLX) {
@@ -1508,9 +1704,9 @@ __device__ double gmm(const double* xr, const double* xi, const double* yr, cons
           }
         }
 #pragma unroll
-        for (int ii = 0; ii < 2; ++ii)
+        for (int ii = 0; ii < TB; ++ii)
 #pragma unroll
-          for (int jj = 0; jj < 2; ++jj) {
+          for (int jj = 0; jj < TB; ++jj) {
             accr[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[ii], b_r[jj], accr[ii][jj], 0, 0, 0);
             if constexpr (CPLX) {
               accr[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[ii], b_i[jj], accr[ii][jj], 0, 0, 0);
@@ -1521,12 +1717,12 @@ __device__ double gmm(const double* xr, const double* xi, const double* yr, cons
       }
     }
 #pragma unroll
-    for (int ii = 0; ii < 2; ++ii)
+    for (int ii = 0; ii < TB; ++ii)
 #pragma unroll
-      for (int jj = 0; jj < 2; ++jj)
+      for (int jj = 0; jj < TB; ++jj)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i = 16 * (2 * TI + ii) + 4 * r + lr, j = 16 * (2 * TJ + jj) + lc;
+          const int i = 16 * (TB * TI + ii) + 4 * r + lr, j = 16 * (TB * TJ + jj) + lc;
           const int64_t o = (int64_t)i * DE + j;
           double vr = scale * accr[ii][jj][r];
           if (in.b != 0.0) vr = fma(in.b, in.xr[o], vr);
@@ -2151,7 +2347,7 @@ constexpr bool reg_ok() {
 }
 
 // Scaling-and-squaring Gibbs kernel (shape code W = 0): dimensions and fields compiled.
-static bool expm_ok(int De, bool cplx) { return De == 16 || (De == 32 && !cplx) || De == 64 || De == 128 || De == 256; }
+static bool expm_ok(int De, bool cplx) { return De == 16 || De == 32 || De == 64 || De == 128 || De == 256; }
 
 static bool reg_pair(int De, int Dc) {
   return (De == 2 && Dc == 0) || (De == 4 && Dc == 2) || (De == 8 && (Dc == 4 || Dc == 2));
@@ -2213,9 +2409,11 @@ static hipError_t launch_cluster_m(const ClusterArgs<T>& a, int block, int W, hi
         hipLaunchKernelGGL((k_cluster_expm<T, CPLX, 16>), dim3((unsigned)a.n), dim3(64), 0, s, a);
       else if (a.De == 32 && !CPLX)
         hipLaunchKernelGGL((k_cluster_expm<T, false, 32>), dim3((unsigned)a.n), dim3(64), 0, s, a);
-      else if (a.De >= 64 && a.De <= 256 && a.expm_scratch != nullptr && a.expm_blocks > 0) {
+      else if (a.De >= 32 && a.De <= 256 && a.expm_scratch != nullptr && a.expm_blocks > 0) {
         const unsigned grid = (unsigned)std::min<int64_t>(a.n, a.expm_blocks);
-        if (a.De == 64)
+        if (a.De == 32)
+          hipLaunchKernelGGL((k_cluster_expm_wg<T, CPLX, 32>), dim3(grid), dim3(256), 0, s, a, a.expm_scratch, a.expm_slab);
+        else if (a.De == 64)
           hipLaunchKernelGGL((k_cluster_expm_wg<T, CPLX, 64>), dim3(grid), dim3(256), 0, s, a, a.expm_scratch, a.expm_slab);
         else if (a.De == 128)
           hipLaunchKernelGGL((k_cluster_expm_wg<T, CPLX, 128>), dim3(grid), dim3(256), 0, s, a, a.expm_scratch, a.expm_slab);

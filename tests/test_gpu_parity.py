@@ -433,7 +433,8 @@ EXPM_PROBLEMS = {
     "randchain_Y4_complex": (lambda: W.random_chain(8, seed=2, top_len=4, subintervals=True), [16]),
     "heis_Y5_real": (lambda: W.with_tops(W.heisenberg_chain(9, field_x=0.4),
                                          [tuple(range(i, i + 5)) for i in range(5)], subintervals=True), [16, 32]),
-    "randchain_Y6_complex": (lambda: W.random_chain(7, seed=3, top_len=6, subintervals=True), [16, 64]),
+    "randchain_Y5_complex": (lambda: W.random_chain(7, seed=4, top_len=5, subintervals=True), [16, 32]),
+    "randchain_Y6_complex": (lambda: W.random_chain(7, seed=3, top_len=6, subintervals=True), [16, 32, 64]),
     "heis_Y7_real": (lambda: W.with_tops(W.heisenberg_chain(9, field_x=0.4),
                                          [tuple(range(i, i + 7)) for i in range(3)], subintervals=True),
                      [16, 32, 64, 128]),
