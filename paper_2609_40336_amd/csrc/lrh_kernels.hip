@@ -1494,7 +1494,8 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
       }
   const double nrm = beta * sqrt(wave_sum(n2));
   int s = 0;
-  while (s < 200 && nrm > ldexp(0.5, s)) ++s;   // wave-uniform: every lane holds the same nrm
+  while (s < 200 && nrm > ldexp(0.5, s)) ++s;
+  s = __builtin_amdgcn_readfirstlane(s);   // every lane holds the same value; make it scalar
   const double sc = -ldexp(beta, -s);
 #pragma unroll
   for (int I = 0; I < NB; ++I)
@@ -1551,7 +1552,7 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
   auto post = [&](XMat<NB, CPLX>& Y, int j) {
     E *= 2.0;
     if ((j & 3) == 3 || j == s - 1) {
-      const int e = ilogb(xtrace(Y, l));
+      const int e = __builtin_amdgcn_readfirstlane(ilogb(xtrace(Y, l)));
       E += (double)e;
       const double sc2 = ldexp(1.0, -e);
 #pragma unroll
