@@ -265,8 +265,8 @@ def _line(metric_value, args, name, P, extra):
 def bench_rate(workload, args, torch):
     """Batched Algorithm 2 on a large workload: FP32 iterations replayed from captured graphs
     with autotuned launch shapes, beta doubling 1 -> 1024 over 11 stages of
-    --iters-per-stage iterations, FP64 certification after every stage; then the plain FP64
-    form (one launch per phase, no graph) for a few iterations at beta = 64.  No closed-form
+    --iters-per-stage iterations, FP64 certification after every stage; then the same
+    schedule in the plain FP64 form (one launch per phase, no graph).  No closed-form
     reference energy exists for these workloads, so no time-to-gap is reported."""
     import lrh_workloads as W
     from paper_2609_40336_amd import lrh
@@ -297,48 +297,44 @@ def bench_rate(workload, args, torch):
     P.autotune(False, cache)
     print(f"[bench] shapes {shapes}", file=sys.stderr, flush=True)
     sched = [(2.0 ** s, ips) for s in range(11)]
-    for _ in range(args.warmup):
-        Solver(P, True, True, sched).run(ips)
-    torch.cuda.synchronize()
-    S = Solver(P, True, True, sched)
-    q = torch.zeros((len(sched), P.n_inst), dtype=torch.float64, device="cuda")
-    mg = torch.zeros_like(q)
-    ev = [_events(torch)[0] for _ in range(len(sched) + 1)]
-    torch.cuda.synchronize()
-    ev[0].record()
-    for k in range(len(sched)):
-        S.run(ips)
-        lrh.lrh_certify(P.h, S.nu, lrh.LRH_F32, q[k], mg[k])
-        ev[k + 1].record()
-    torch.cuda.synchronize()
-    sec = ev[0].elapsed_time(ev[-1]) / 1e3
-    stage_ms = [ev[k].elapsed_time(ev[k + 1]) / ips for k in range(len(sched))]
+
+    def timed_schedule(f32, fused):
+        for _ in range(args.warmup):
+            Solver(P, f32, fused, sched).run(ips)
+        torch.cuda.synchronize()
+        S = Solver(P, f32, fused, sched)
+        q = torch.zeros((len(sched), P.n_inst), dtype=torch.float64, device="cuda")
+        mg = torch.zeros_like(q)
+        ev = [_events(torch)[0] for _ in range(len(sched) + 1)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        for k in range(len(sched)):
+            S.run(ips)
+            lrh.lrh_certify(P.h, S.nu, lrh.LRH_F32 if f32 else 0, q[k], mg[k])
+            ev[k + 1].record()
+        torch.cuda.synchronize()
+        sec = ev[0].elapsed_time(ev[-1]) / 1e3
+        stage_ms = [ev[k].elapsed_time(ev[k + 1]) / ips for k in range(len(sched))]
+        return S, sec, stage_ms, (q[-1] - mg[-1]).cpu().numpy()
+
     iters = len(sched) * ips
+    S, sec, stage_ms, bound = timed_schedule(True, True)
     print(f"[bench] fused fp32: {sec:.3f} s for {iters} iterations", file=sys.stderr, flush=True)
     nchk, nnf = P.check()
     n_sites = np.bincount(desc.site_instance, minlength=desc.n_instances)
-    bound = (q[-1] - mg[-1]).cpu().numpy()
     roof = dominant_kernel_roofline(P, S.nu, 64.0, True, torch)
-    # plain FP64 form
-    n_plain = 3 if P.n_clusters * max(sh["De"] for sh in shapes) ** 3 > 5e10 else 10
-    Sp = Solver(P, False, False, [(64.0, 10 ** 9)])
-    Sp.run(1)
-    torch.cuda.synchronize()
-    e0, e1 = _events(torch)
-    e0.record()
-    Sp.run(n_plain)
-    e1.record()
-    torch.cuda.synchronize()
-    sec_plain = e0.elapsed_time(e1) / 1e3
-    print(f"[bench] plain fp64: {sec_plain:.3f} s for {n_plain} iterations", file=sys.stderr, flush=True)
+    del S
+    _, sec_plain, stage_plain, bound_plain = timed_schedule(False, False)
+    print(f"[bench] plain fp64: {sec_plain:.3f} s for {iters} iterations", file=sys.stderr, flush=True)
     extra = {
         "ms_per_step": sec / len(sched) * 1e3, "dtype": "f32 iterations, f64 certify",
         "us_per_iteration": sec / iters * 1e6,
         "schedule": f"beta = 2^s, s = 0..10, {ips} iterations per stage, FP64 certify after each stage",
         "ms_per_iteration_by_stage": [round(x, 4) for x in stage_ms],
         "mean_certified_bound_per_site": float(np.mean(bound / n_sites)),
-        "plain_fp64": {"value": P.n_clusters * n_plain / sec_plain, "unit": "cluster updates/s",
-                       "iterations": n_plain, "beta": 64.0},
+        "plain_fp64": {"value": P.n_clusters * iters / sec_plain, "unit": "cluster updates/s",
+                       "ms_per_iteration_by_stage": [round(x, 4) for x in stage_plain],
+                       "mean_certified_bound_per_site": float(np.mean(bound_plain / n_sites))},
         "shapes": shapes, "jacobi_noconv": nchk, "nonfinite": nnf, "roofline": roof,
     }
     if not args.no_cpu:

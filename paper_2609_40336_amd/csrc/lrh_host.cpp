@@ -760,6 +760,9 @@ template <> double default_tol<double>() { return 4.0 * 2.220446049250313e-16; }
 int shape_for(const lrh_problem_s* P, const CBucket& B, bool dbl, int mode) {
   int shapes[8];
   const int n = cluster_shapes(B.De, B.Dc, dbl, P->cplx, mode, shapes);
+  if (mode == MODE_CERTIFY)
+    for (int i = 0; i < n; ++i)
+      if (shapes[i] == 2) return 2;   // eigenvalues only: tridiagonalisation whenever compiled
   const int want = dbl ? B.W64 : B.W;
   for (int i = 0; i < n; ++i)
     if (shapes[i] == want) return want;

@@ -1678,8 +1678,15 @@ __device__ double gmm(const double* xr, const double* xi, const double* yr, cons
   const int wave = tid / 64, l = tid % 64;
   const int lr = l >> 4, lc = l & 15;
   double tr = 0.0;
-  for (int t = wave; t < NT * NT; t += 4) {
-    const int TI = t / NT, TJ = t % NT;
+  // C is Hermitian (every product here is a polynomial in one matrix): only the tiles on and
+  // above the diagonal are computed, an off-diagonal tile is also written conjugate-transposed
+  for (int t = wave; t < NT * (NT + 1) / 2; t += 4) {
+    int TI = 0, TJ = t;
+    while (TJ >= NT - TI) {
+      TJ -= NT - TI;
+      ++TI;
+    }
+    TJ += TI;
     mfma_f64x4 accr[TB][TB], acci[TB][TB];
 #pragma unroll
     for (int ii = 0; ii < TB; ++ii)
@@ -1733,11 +1740,14 @@ __device__ double gmm(const double* xr, const double* xi, const double* yr, cons
             tr += vr;
           }
           cr_[o] = vr;
+          const int64_t ot = (int64_t)j * DE + i;
+          if (TI != TJ) cr_[ot] = vr;
           if constexpr (CPLX) {
             double vi = scale * acci[ii][jj][r];
             if (in.b != 0.0) vi = fma(in.b, in.xi[o], vi);
             if (in.c != 0.0) vi = fma(in.c, in.pi[o], vi);
             ci_[o] = (i == j) ? 0.0 : vi;
+            if (TI != TJ) ci_[ot] = -vi;
           }
         }
   }
@@ -1949,6 +1959,7 @@ __global__ __launch_bounds__(256) void k_cluster_tridiag(ClusterArgs<double> A, 
     lo -= 2.0 * DBL_EPSILON * fabs(lo) + span0 * DBL_EPSILON;
     hi += 2.0 * DBL_EPSILON * fabs(hi) + span0 * DBL_EPSILON;
     for (int round = 0; round < 12; ++round) {
+      if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi))) break;   // a few ulps of lambda_min
       const double x = lo + (hi - lo) * (double)(tid + 1) / (double)(nth + 1);
       int cnt = 0;
       double q = dg[0] - x;
@@ -1974,6 +1985,134 @@ __global__ __launch_bounds__(256) void k_cluster_tridiag(ClusterArgs<double> A, 
       if (!isfinite(lo) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
     }
     __syncthreads();
+  }
+}
+
+// One-wave variant for De = 16, 32: the matrix in LDS, the De rows of A22 v split over
+// 64/De lane groups (partial sums over j = g, g + G, ... combined by shuffles), 64 Sturm
+// points per multisection round.
+template <bool CPLX, int DE>
+__global__ __launch_bounds__(64) void k_cluster_tridiag_w(ClusterArgs<double> A) {
+  constexpr int LD = DE + 1;
+  constexpr int G = 64 / DE;
+  __shared__ double ar[DE * LD];
+  __shared__ double ai[CPLX ? DE * LD : 1];
+  __shared__ double vr[DE], vi[DE], pr[DE], pi[DE], dg[DE], e2[DE];
+  const int64_t c = blockIdx.x;
+  const int l = threadIdx.x;
+  const int li = l % DE, lg = l / DE;
+  const double nrm2 =
+      wave_sum(lds_assemble<double, CPLX, DE, 64>(A, c, l, A.nu_c, nullptr, A.nu_p, nullptr, 0.0, true, 1.0, ar, ai));
+  __syncthreads();
+  for (int k = 0; k < DE - 2; ++k) {
+    const int m = DE - k - 1;
+    const int rk = k * LD + k + 1;   // x_i = A[k+1+i][k] = conj(A[k][k+1+i])
+    double xs = 0.0;
+    if (l < m) {
+      xs = ar[rk + l] * ar[rk + l];
+      if constexpr (CPLX) xs = fma(ai[rk + l], ai[rk + l], xs);
+    }
+    const double xn2 = wave_sum(xs);
+    const double xn = sqrt(xn2);
+    const double x0r = ar[rk], x0i = CPLX ? -ai[rk] : 0.0;
+    const double a0 = sqrt(fma(x0r, x0r, x0i * x0i));
+    if (l == 0) {
+      dg[k] = ar[k * LD + k];
+      e2[k] = xn2;
+    }
+    const double vn2 = 2.0 * (xn2 + a0 * xn);
+    if (!(vn2 > 0.0)) continue;   // wave-uniform
+    const double ur = a0 > 0.0 ? x0r / a0 : 1.0, ui = a0 > 0.0 ? x0i / a0 : 0.0;
+    const double tau = 2.0 / vn2;
+    if (l < m) {
+      double r = ar[rk + l], im = CPLX ? -ai[rk + l] : 0.0;
+      if (l == 0) {
+        r += ur * xn;
+        im += ui * xn;
+      }
+      vr[l] = r;
+      vi[l] = im;
+    }
+    __syncthreads();
+    // p = tau A22 v: lane (li, lg) sums j = lg, lg + G, ... of row li (read as column li)
+    double sr = 0.0, si = 0.0;
+    if (li < m) {
+      for (int j = lg; j < m; j += G) {
+        const int o = (k + 1 + j) * LD + (k + 1 + li);
+        const double a_r = ar[o];
+        sr = fma(a_r, vr[j], sr);
+        if constexpr (CPLX) {
+          const double a_i = -ai[o];
+          sr = fma(-a_i, vi[j], sr);
+          si = fma(a_r, vi[j], fma(a_i, vr[j], si));
+        }
+      }
+    }
+#pragma unroll
+    for (int o = DE; o < 64; o <<= 1) {
+      sr += __shfl_xor(sr, o, 64);
+      if constexpr (CPLX) si += __shfl_xor(si, o, 64);
+    }
+    sr *= tau;
+    si *= tau;
+    const double ks = (l < m) ? fma(vr[l], sr, vi[l] * si) : 0.0;
+    const double K = 0.5 * tau * wave_sum(ks);
+    if (l < m) {
+      pr[l] = fma(-K, vr[l], sr);
+      pi[l] = fma(-K, vi[l], si);
+    }
+    __syncthreads();
+    for (int idx = l; idx < m * m; idx += 64) {
+      const int i = idx / m, j = idx % m;
+      const int o = (k + 1 + i) * LD + (k + 1 + j);
+      ar[o] -= fma(vr[i], pr[j], fma(vi[i], pi[j], fma(pr[i], vr[j], pi[i] * vi[j])));
+      if constexpr (CPLX) ai[o] -= fma(vi[i], pr[j], fma(-vr[i], pi[j], fma(pi[i], vr[j], -pr[i] * vi[j])));
+    }
+    __syncthreads();
+  }
+  if (l == 0) {
+    dg[DE - 2] = ar[(DE - 2) * LD + DE - 2];
+    dg[DE - 1] = ar[(DE - 1) * LD + DE - 1];
+    const double xr = ar[(DE - 2) * LD + DE - 1], xi = CPLX ? ai[(DE - 2) * LD + DE - 1] : 0.0;
+    e2[DE - 2] = fma(xr, xr, xi * xi);
+    e2[DE - 1] = 0.0;
+  }
+  __syncthreads();
+  double lo = INFINITY, hi = -INFINITY, emax = 0.0;
+  for (int i = 0; i < DE; ++i) {
+    const double r = (i > 0 ? sqrt(e2[i - 1]) : 0.0) + sqrt(e2[i]);
+    lo = fmin(lo, dg[i] - r);
+    hi = fmax(hi, dg[i] + r);
+    emax = fmax(emax, e2[i]);
+  }
+  const double pivmin = DBL_MIN * fmax(1.0, emax);
+  const double span0 = fmax(hi - lo, DBL_MIN);
+  lo -= 2.0 * DBL_EPSILON * fabs(lo) + span0 * DBL_EPSILON;
+  hi += 2.0 * DBL_EPSILON * fabs(hi) + span0 * DBL_EPSILON;
+  for (int round = 0; round < 14; ++round) {
+    if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi))) break;   // a few ulps of lambda_min
+    const double x = lo + (hi - lo) * (double)(l + 1) / 65.0;
+    int cnt = 0;
+    double q = dg[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+    for (int i = 1; i < DE; ++i) {
+      q = (dg[i] - x) - e2[i - 1] / q;
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0;
+    }
+    const int t = (int)wave_min(cnt > 0 ? (double)l : 64.0);
+    const double nlo = t == 0 ? lo : lo + (hi - lo) * (double)t / 65.0;
+    const double nhi = t == 64 ? hi : lo + (hi - lo) * (double)(t + 1) / 65.0;
+    if (!(nhi - nlo < hi - lo)) break;
+    lo = nlo;
+    hi = nhi;
+  }
+  const int32_t gid = A.gid[c];
+  if (l == 0) {
+    A.scal[gid] = lo;
+    A.scal2[gid] = 8.0 * DE * DBL_EPSILON * sqrt(nrm2);
+    if (!isfinite(lo) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
   }
 }
 
@@ -2362,7 +2501,7 @@ int cluster_shapes(int De, int Dc, bool dbl, bool cplx, int mode, int* out) {
   }
   if (reg) out[n++] = 1;
   if (mode == MODE_GIBBS && expm_ok(De, cplx)) out[n++] = 0;
-  if (mode == MODE_CERTIFY && De >= 64 && De <= 256) out[n++] = 2;
+  if (mode == MODE_CERTIFY && De >= 16 && De <= 256) out[n++] = 2;
   int lds[8];
   const int nl = lds_shapes(De, lds);
   if (!(De <= 4 && reg))
@@ -2430,6 +2569,14 @@ static hipError_t launch_cluster_m(const ClusterArgs<T>& a, int block, int W, hi
   }
   if (W == 2) {
     if constexpr (MODE == MODE_CERTIFY && std::is_same<T, double>::value) {
+      if (a.De == 16 || a.De == 32) {
+        if (a.n > 0x7fffffff) return hipErrorInvalidValue;
+        if (a.De == 16)
+          hipLaunchKernelGGL((k_cluster_tridiag_w<CPLX, 16>), dim3((unsigned)a.n), dim3(64), 0, s, a);
+        else
+          hipLaunchKernelGGL((k_cluster_tridiag_w<CPLX, 32>), dim3((unsigned)a.n), dim3(64), 0, s, a);
+        return hipGetLastError();
+      }
       if (a.expm_scratch == nullptr || a.expm_blocks <= 0) return hipErrorInvalidValue;
       const unsigned grid = (unsigned)std::min<int64_t>(a.n, a.expm_blocks);
       if (a.De == 64)
