@@ -1661,7 +1661,7 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
 
 // Workgroup variant for De = 32 (complex), 64, 128, 256: five matrices (X, X^2, X^3 and two Horner / squaring
 // buffers) in a per-workgroup FP64 slab, row-major, real plane then imaginary plane; four
-// waves, each computing 32 x 32 output tiles (2 x 2 blocks of the 16 x 16 MFMA; 16 x 16 at De = 32).  The A operand
+// waves, each computing 32 x 32 output tiles (2 x 2 blocks of the 16 x 16 MFMA; 16 x 16 below De = 128).  The A operand
 // of block (I, K) is read as the conjugate of block (K, I), which keeps both operand reads as
 // rows of 16 consecutive doubles.
 struct GInit {
@@ -1673,7 +1673,7 @@ struct GInit {
 template <bool CPLX, int DE>
 __device__ double gmm(const double* xr, const double* xi, const double* yr, const double* yi, double* cr_,
                       double* ci_, double scale, const GInit& in, int tid) {
-  constexpr int TB = DE >= 64 ? 2 : 1;   // output tile of TB x TB blocks per wave
+  constexpr int TB = DE >= 128 ? 2 : 1;   // output tile of TB x TB blocks per wave
   constexpr int NB = DE / 16, NT = NB / TB;
   const int wave = tid / 64, l = tid % 64;
   const int lr = l >> 4, lc = l & 15;

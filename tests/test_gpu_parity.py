@@ -443,11 +443,12 @@ EXPM_PROBLEMS = {
 
 
 @pytest.mark.parametrize("name", list(EXPM_PROBLEMS))
-@pytest.mark.parametrize("beta", [0.7, 6.0, 300.0])
+@pytest.mark.parametrize("beta", [0.7, 6.0, 300.0, 5000.0])
 def test_gibbs_by_scaling_and_squaring_matches_oracle(name, beta):
     """The matrix-core Gibbs kernel (shape W = 0: exp(-beta theta) by scaling and squaring, no
     eigenvectors) against the oracle's eigen-decomposition, FP64 and FP32 messages.  beta = 300
-    takes about 12 squarings."""
+    takes about 12 squarings, beta = 5000 about 16.  Entry tolerance: the kernel's backward
+    error (about 1e-13 ||theta||) times the Gibbs state's Lipschitz constant beta / 2."""
     lrh = lrhmod()
     say(f"[expm] {name} beta={beta}")
     make, dims = EXPM_PROBLEMS[name]
@@ -462,7 +463,7 @@ def test_gibbs_by_scaling_and_squaring_matches_oracle(name, beta):
     q_o, g_o = R.grad_beta(nu_o, beta)
     _, rho = R.gibbs(nu_o, beta)
     n = sites_per_instance(d)
-    tol = 1e-10 if beta < 10 else 2e-9
+    tol = 1e-10 if beta < 10 else max(2e-9, 1e-12 * beta)
     assert np.all(np.abs(q.cpu().numpy() - q_o) <= 1e-9 * n)
     assert max_pair_err(P.to_dense(g), R.to_pairs(g_o)) < tol
     assert max_pair_err(P.marg_dense(m), oracle_marginals(R, rho)) < tol
