@@ -470,6 +470,124 @@ def bench_c5(args, torch):
     print(json.dumps(out))
 
 
+EX3_EPS = [0.02, 0.0139, 0.00965, 0.0067, 0.00465, 0.00323, 0.00224, 0.002]
+
+
+def bench_ex3(args, torch):
+    """Iterations to epsilon (the paper's comparison of the subgradient and smooth methods):
+    level-1 relaxation of 16-site open chains (Heisenberg J = 1 with an on-site X field 0.5,
+    anisotropic Heisenberg (2, -3, 0.5), critical TFIM J = h = 1, a seeded random chain).
+
+    * Algorithm 1 with the constant step alpha = eps / (2 Delta_G) (Sec. 4.1.1): since the ground
+      projector is scale-invariant, it is Algorithm 1 with step 1 on H / alpha.
+    * Algorithm 2 at the fixed beta = 2 Gamma / (n eps) of the smoothing-error lemma: it is
+      Algorithm 2 at beta = 1 on beta H, with nu rescaled by beta.
+    So every (model, eps) pair is one instance of a single batched problem per method.
+    Convergence: certified Q(nu^k) within eps per site of the relaxation optimum, taken as the
+    best certified value of a long beta-continuation run (beta up to 2^16) and of every run
+    here.  Exponent p: least-squares fit of log(iterations) against log(1 / eps)."""
+    import lrh_workloads as W
+    from paper_2609_40336_amd import lrh
+    n = 16
+    models = {
+        "heisenberg_field0.5": W.heisenberg_chain(n, field_x=0.5),
+        "xyz_2_-3_0.5": W.anisotropic_heisenberg_chain(n),
+        "tfim_critical": W.tfim_chain(n, 1.0, 1.0, complex_storage=False),
+        "random": W.random_chain(n, seed=7),
+    }
+    names = list(models)
+    descs = [models[k] for k in names]
+    Delta, d = 2, 2
+    Gamma = (n - 1) * math.log(4.0) + n * math.log(2.0)
+    t0 = time.perf_counter()
+    # relaxation optimum: long accelerated run with beta continuation, certified
+    Pr = lrh.Problem(W.batch_scaled(descs, [1.0] * len(descs), "ex3_ref"), 0)
+    Sr = Solver(Pr, False, True, [(2.0 ** s, 800) for s in range(17)])
+    qref = np.full(len(names), -np.inf)
+    for _ in range(17):
+        Sr.run(800)
+        b, mg, _ = Pr.certify(Sr.nu)
+        qref = np.maximum(qref, (b - mg).cpu().numpy())
+    print(f"[ex3] reference optimum per site {qref / n}", file=sys.stderr, flush=True)
+    out_models = {k: {} for k in names}
+    # ---- Algorithm 1 ----
+    inst = [(m, e) for m in range(len(names)) for e in EX3_EPS]
+    alphas = [e / (2.0 * Delta) for (_, e) in inst]
+    P1 = lrh.Problem(W.batch_scaled([descs[m] for (m, _) in inst], [1.0 / a for a in alphas], "ex3_sub"), 0)
+    nu, nb = P1.zeros(), P1.zeros()
+    qb = torch.full((P1.n_inst,), -math.inf, dtype=torch.float64, device="cuda")
+    chunk, kmax = 20000, int(args.ex3_max_iters)
+    first = [None] * len(inst)
+    qbest = np.full(len(inst), -np.inf)
+    k0 = 0
+    while k0 < kmax and any(f is None for f in first):
+        qh = torch.empty((chunk, P1.n_inst), dtype=torch.float64, device="cuda")
+        P1.step_subgrad(nu, nb, qb, k0, chunk, step_kind=1, step_scale=1.0, q_hist=qh)
+        q = qh.cpu().numpy() * np.asarray(alphas)[None, :]
+        qbest = np.maximum(qbest, q.max(axis=0))
+        for i, (m, e) in enumerate(inst):
+            if first[i] is None:
+                hit = np.nonzero((qref[m] - q[:, i]) / n <= e)[0]
+                if len(hit):
+                    first[i] = k0 + int(hit[0]) + 1
+        k0 += chunk
+    # ---- Algorithm 2 ----
+    betas = [2.0 * Gamma / (n * e) for (_, e) in inst]
+    P2 = lrh.Problem(W.batch_scaled([descs[m] for (m, _) in inst], betas, "ex3_smooth"), 0)
+    nu2, ze2 = P2.zeros(), P2.zeros()
+    st = P2.new_nesterov_state(1.0)
+    check, kmax2 = 5, int(args.ex3_max_iters) // 4
+    first2 = [None] * len(inst)
+    qbest2 = np.full(len(inst), -np.inf)
+    k = 0
+    while k < kmax2 and any(f is None for f in first2):
+        P2.step_nesterov(nu2, ze2, st, check, fused=True)
+        k += check
+        b, mg, _ = P2.certify(nu2)
+        q = (b - mg).cpu().numpy() / np.asarray(betas)
+        qbest2 = np.maximum(qbest2, q)
+        for i, (m, e) in enumerate(inst):
+            if first2[i] is None and (qref[m] - q[i]) / n <= e:
+                first2[i] = k
+    torch.cuda.synchronize()
+    # runs that ended above the long run's value raise the reference (it is a lower bound)
+    for i, (m, e) in enumerate(inst):
+        qref[m] = max(qref[m], qbest[i], qbest2[i])
+    secs = time.perf_counter() - t0
+
+    def fit(eps, its):
+        pts = [(e, t) for e, t in zip(eps, its) if t is not None]
+        if len(pts) < 3 or len(set(t for _, t in pts)) == 1:
+            return None, None   # too few points, or no dependence on eps (optimum at the start)
+        x = np.log([1.0 / e for e, _ in pts])
+        y = np.log([float(t) for _, t in pts])
+        p, c = np.polyfit(x, y, 1)
+        r2 = 1.0 - np.sum((y - (p * x + c)) ** 2) / max(np.sum((y - y.mean()) ** 2), 1e-300)
+        return float(p), float(r2)
+    for m, key in enumerate(names):
+        idx = [i for i, (mm, _) in enumerate(inst) if mm == m]
+        eps = [inst[i][1] for i in idx]
+        its1 = [first[i] for i in idx]
+        its2 = [first2[i] for i in idx]
+        p1, r1 = fit(eps, its1)
+        p2, r2 = fit(eps, its2)
+        out_models[key] = {
+            "relaxation_optimum_per_site": float(qref[m] / n),
+            "optimal_at_start": bool(all(t == 1 for t in its1)),
+            "subgradient": {"iterations": its1, "exponent": p1, "r2": r1},
+            "smooth": {"iterations": its2, "exponent": p2, "r2": r2, "checked_every": check},
+        }
+    out = {
+        "metric": "iterations to eps per site (subgradient vs smooth), exponent of 1/eps",
+        "experiment": "eps-scaling of Algorithms 1 and 2 on 16-site chains, level-1 relaxation",
+        "eps": EX3_EPS, "models": out_models, "n_gpus": 1, "seconds": secs, "data": "synthetic",
+        "max_iterations": {"subgradient": int(args.ex3_max_iters), "smooth": kmax2},
+        "paper_context": {"subgradient_exponent": "<= 2 (random), 1.33-1.8 (others)",
+                          "smooth_exponent": "0.8 (random), about 0.5 (others)"},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -481,7 +599,9 @@ def main():
     ap.add_argument("--workload", default="c2",
                     help="c2 (default: the 32x32 Heisenberg solve), c1 (TFIM chain, Algorithm 1), c3k<k> "
                          "(interval hierarchy Y_k on the n = 4096 GUE chain), c4 (512 plaquette lattices), "
-                         "c5 (64x64 XXZ value and coupling gradient)")
+                         "c5 (64x64 XXZ value and coupling gradient), ex3 (iterations-to-eps experiment)")
+    ap.add_argument("--ex3-max-iters", type=float, default=4e5,
+                    help="ex3: iteration cap of Algorithm 1 (Algorithm 2: a quarter of it)")
     ap.add_argument("--iters-per-stage", type=int, default=0,
                     help="c3k<k>, c4: iterations per beta stage (default 50; 10 for k = 8)")
     ap.add_argument("--profile-traffic", action="store_true",
@@ -502,6 +622,8 @@ def main():
             return bench_c1(args, torch)
         if args.workload == "c5":
             return bench_c5(args, torch)
+        if args.workload == "ex3":
+            return bench_ex3(args, torch)
         return bench_rate(args.workload, args, torch)
     desc = W.workload_c2(32)
     P = lrh.Problem(desc, 0)

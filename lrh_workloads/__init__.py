@@ -442,6 +442,30 @@ def with_tops(desc: ProblemDesc, tops: Sequence[Sequence[int]], subintervals=Fal
 # whatever order they enumerate messages in)
 # --------------------------------------------------------------------------------------
 
+def batch_scaled(descs: Sequence[ProblemDesc], scales: Sequence[float], name: str = "batch") -> ProblemDesc:
+    """Independent instances in one problem: instance i is descs[i] with every term multiplied
+    by scales[i] (sites renumbered, top clusters kept).  Parametrised terms are not carried."""
+    n = int(sum(d.n_sites for d in descs))
+    b = _Builder(name, n)
+    off = 0
+    subint = None
+    for i, (d, sc) in enumerate(zip(descs, scales)):
+        if subint is None:
+            subint = d.subintervals
+        elif subint != d.subintervals:
+            raise ValueError("instances disagree on the interval closure")
+        b.site_dim[off:off + d.n_sites] = d.site_dim
+        b.site_instance[off:off + d.n_sites] = i
+        for sites, m in d.terms():
+            b.add_term(tuple(off + x for x in sites), float(sc) * m)
+        for t in d.tops():
+            b.add_top(tuple(off + x for x in t))
+        off += d.n_sites
+    b.n_instances = len(descs)
+    real = all(d.is_real for d in descs)
+    return b.build(real=real, subintervals=bool(subint), meta=dict(model="batch", scales=list(map(float, scales))))
+
+
 def message_draw(seed: int, parent: Sequence[int], child: Sequence[int], D: int,
                  real: bool, scale: float = 1.0) -> np.ndarray:
     """A seeded Hermitian (real symmetric when real=True) D x D matrix for message parent->child."""

@@ -102,3 +102,19 @@ def test_validation_errors():
     # compute on a host-only problem
     P = lrh.Problem(good, -1)
     _expect(1, lambda: lrh._check(lrh.load().lrh_certify(P.h, 8, 0, 8, 8, None, None)))
+
+
+def test_batch_scaled_instances_are_scaled_copies():
+    """The batching helper used by the iterations-to-eps experiment: instance i of the batch is
+    descs[i] with every term times scales[i] (checked on the oracle's Anderson bound Q(0), which
+    is positively homogeneous in H)."""
+    import lrh_workloads as W
+    from oracle import lrh_oracle as O
+    descs = [W.heisenberg_chain(5, field_x=0.5), W.tfim_chain(4, 1.0, 1.0, complex_storage=False),
+             W.random_chain(4, seed=7)]
+    scales = [2.0, 0.25, 3.0]
+    Rb = O.Relaxation(W.batch_scaled(descs, scales))
+    qb = Rb.Q(Rb.zeros())
+    for i, (d, s) in enumerate(zip(descs, scales)):
+        R = O.Relaxation(d)
+        assert abs(qb[i] - s * R.Q(R.zeros())[0]) <= 1e-12 * max(1.0, abs(qb[i]))
