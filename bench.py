@@ -588,6 +588,50 @@ def bench_ex3(args, torch):
     print(json.dumps(out))
 
 
+def bench_ex2(args, torch):
+    """Size dependence of the optimal multiplier norm (the assumption behind both rate
+    theorems): mean Frobenius norm of the messages nu_{e->f} at the end of a long accelerated
+    run (beta = 2^s, s = 0..12, 400 iterations per stage, FP64) on open chains of N sites,
+    N = 8 .. 256, for the isotropic Heisenberg, anisotropic Heisenberg (2, -3, 0.5), critical
+    TFIM and seeded random chains.  All (model, N) pairs run as one batched problem; the
+    certified bound per site is reported beside the norm, and the fitted slope of norm
+    against N measures any size dependence."""
+    import lrh_workloads as W
+    from paper_2609_40336_amd import lrh
+    Ns = [8, 16, 32, 64, 128, 256]
+    makers = {
+        "heisenberg": lambda N: W.heisenberg_chain(N),
+        "xyz_2_-3_0.5": lambda N: W.anisotropic_heisenberg_chain(N),
+        "tfim_critical": lambda N: W.tfim_chain(N, 1.0, 1.0, complex_storage=False),
+        "random": lambda N: W.random_chain(N, seed=11),
+    }
+    inst = [(k, N) for k in makers for N in Ns]
+    desc = W.batch_scaled([makers[k](N) for (k, N) in inst], [1.0] * len(inst), "ex2")
+    t0 = time.perf_counter()
+    P = lrh.Problem(desc, 0)
+    S = Solver(P, False, True, [(2.0 ** s, 400) for s in range(13)])
+    S.run(13 * 400)
+    b, mg, _ = P.certify(S.nu)
+    torch.cuda.synchronize()
+    bound = (b - mg).cpu().numpy()
+    secs = time.perf_counter() - t0
+    norms = [[] for _ in inst]
+    for (par, ch), m in P.to_dense(S.nu).items():
+        norms[int(desc.site_instance[ch[0]])].append(float(np.linalg.norm(m)))
+    out_models = {}
+    for k in makers:
+        idx = [i for i, (kk, _) in enumerate(inst) if kk == k]
+        mean = [float(np.mean(norms[i])) for i in idx]
+        slope = float(np.polyfit(np.asarray(Ns, float), np.asarray(mean), 1)[0])
+        out_models[k] = {"N": Ns, "mean_message_norm": mean, "slope_per_site": slope,
+                         "certified_bound_per_site": [float(bound[i] / inst[i][1]) for i in idx]}
+    out = {"metric": "mean optimal message Frobenius norm vs chain length",
+           "experiment": "size independence of the optimal multipliers, level-1 relaxation of open chains",
+           "models": out_models, "iterations": 13 * 400, "seconds": secs, "n_gpus": 1, "data": "synthetic",
+           "paper_context": "no visible correlation of the average optimal multiplier norm with N"}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -599,7 +643,8 @@ def main():
     ap.add_argument("--workload", default="c2",
                     help="c2 (default: the 32x32 Heisenberg solve), c1 (TFIM chain, Algorithm 1), c3k<k> "
                          "(interval hierarchy Y_k on the n = 4096 GUE chain), c4 (512 plaquette lattices), "
-                         "c5 (64x64 XXZ value and coupling gradient), ex3 (iterations-to-eps experiment)")
+                         "c5 (64x64 XXZ value and coupling gradient), ex3 (iterations-to-eps experiment), "
+                         "ex2 (optimal message norm vs chain length)")
     ap.add_argument("--ex3-max-iters", type=float, default=4e5,
                     help="ex3: iteration cap of Algorithm 1 (Algorithm 2: a quarter of it)")
     ap.add_argument("--iters-per-stage", type=int, default=0,
@@ -624,6 +669,8 @@ def main():
             return bench_c5(args, torch)
         if args.workload == "ex3":
             return bench_ex3(args, torch)
+        if args.workload == "ex2":
+            return bench_ex2(args, torch)
         return bench_rate(args.workload, args, torch)
     desc = W.workload_c2(32)
     P = lrh.Problem(desc, 0)

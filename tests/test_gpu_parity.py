@@ -495,3 +495,37 @@ def test_gibbs_kernels_agree_in_accelerated_loop():
         assert P.check() == (0, 0)
     n = sites_per_instance(d)
     assert np.all(np.abs(out[0] - out[1]) <= 1e-9 * n)
+
+
+def test_scaled_instances_reproduce_step_and_beta_choices():
+    """The iterations-to-eps experiment runs every (model, eps) pair as one instance of a
+    batched problem: Algorithm 1 with constant step alpha on H is Algorithm 1 with step 1 on
+    H / alpha, and Algorithm 2 at beta on H is Algorithm 2 at beta = 1 on beta H (with nu
+    rescaled by beta).  Both are checked against the oracle run on the unscaled H."""
+    lrh = lrhmod()
+    say("[ex3 scaling] heisenberg chain with field, tfim")
+    descs = [W.heisenberg_chain(8, field_x=0.5), W.tfim_chain(8, 1.0, 1.0, complex_storage=False)]
+    alpha, beta = 0.005, 40.0
+    # Algorithm 1: first steps (before the trajectory becomes sensitive), values times alpha
+    P1 = lrh.Problem(W.batch_scaled(descs, [1.0 / alpha] * 2, "sub"), 0)
+    nu, nb = P1.zeros(), P1.zeros()
+    qb = torch.full((P1.n_inst,), -np.inf, dtype=torch.float64, device="cuda")
+    qh = torch.empty((6, P1.n_inst), dtype=torch.float64, device="cuda")
+    P1.step_subgrad(nu, nb, qb, 0, 6, step_kind=1, step_scale=1.0, q_hist=qh)
+    torch.cuda.synchronize()
+    for i, d in enumerate(descs):
+        R = O.Relaxation(d)
+        _, _, _, hist = O.subgradient(R, 6, step=lambda k: alpha)
+        got = qh.cpu().numpy()[:, i] * alpha
+        assert np.max(np.abs(got - np.asarray(hist)[:, 0])) <= 1e-9 * d.n_sites
+    # Algorithm 2: 40 iterations, certified value divided by beta
+    P2 = lrh.Problem(W.batch_scaled(descs, [beta] * 2, "smooth"), 0)
+    nu2, ze2 = P2.zeros(), P2.zeros()
+    P2.step_nesterov(nu2, ze2, P2.new_nesterov_state(1.0), 40, fused=True)
+    b, mg, _ = P2.certify(nu2)
+    torch.cuda.synchronize()
+    for i, d in enumerate(descs):
+        R = O.Relaxation(d)
+        nu_o = O.nesterov(R, [(beta, 40)])
+        q_o, _ = R.certify(nu_o)
+        assert abs(b.cpu().numpy()[i] / beta - q_o[0]) <= 1e-9 * d.n_sites
