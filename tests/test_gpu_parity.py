@@ -52,6 +52,11 @@ def max_pair_err(got, want):
     return max(float(np.abs(got[k] - want[k]).max()) for k in want)
 
 
+def k5_complete():
+    pairs = [(i, j) for i in range(5) for j in range(i + 1, 5)]
+    return W.with_tops(W.heisenberg_graph(5, pairs, 0.7, field_x=0.3), [tuple(range(5))])
+
+
 PROBLEMS = {
     "c1_tfim16_complex": lambda: W.workload_c1(),
     "heis_square4": lambda: W.heisenberg_square(4),
@@ -67,6 +72,7 @@ PROBLEMS = {
     "gue_Y8": lambda: W.interval_chain_gue(10, 8, 0.1, seed=3),
     "randchain_Y7_real": lambda: W.with_tops(W.heisenberg_chain(9, field_x=0.4),
                                              [tuple(range(i, i + 7)) for i in range(3)], subintervals=True),
+    "k5_complete": lambda: k5_complete(),
 }
 
 
@@ -115,7 +121,7 @@ def test_dual_eval_fp32(name):
 
 
 @pytest.mark.parametrize("name", ["c1_tfim16_complex", "randchain_Y6", "plaq_batch_ragged", "xxz_tri3", "gue_Y7",
-                                  "gue_Y8", "randchain_Y7_real"])
+                                  "gue_Y8", "randchain_Y7_real", "k5_complete"])
 def test_certify_fp64_and_from_fp32(name):
     lrh = lrhmod()
     say(f"[certify] {name}")
@@ -439,6 +445,9 @@ EXPM_PROBLEMS = {
                                          [tuple(range(i, i + 7)) for i in range(3)], subintervals=True),
                      [16, 32, 64, 128]),
     "gue_Y8_complex": (lambda: W.interval_chain_gue(10, 8, 0.1, seed=3), [16, 64, 128, 256]),
+    # a 5-site cluster over the complete graph has ten pair children: the generic
+    # (more than eight children) assembly and output path of the one-wave kernel
+    "k5_complete_real": (lambda: k5_complete(), [32]),
 }
 
 
