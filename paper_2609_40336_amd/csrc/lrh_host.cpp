@@ -78,6 +78,7 @@ struct CBucket {
   int32_t* chmask = nullptr;
   int32_t* par = nullptr;
   int32_t* rslot = nullptr;
+  int32_t* chrs = nullptr;   // [maxch][n] marginal slot of each child (-1: none)
 };
 
 struct MBucket {
@@ -644,10 +645,25 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
     st = P->upload(&(dst), vec);          \
     if (st != LRH_OK) return st;          \
   } while (0)
+  // marginal slot of every message's child, per message bucket
+  std::vector<std::vector<int32_t>> h_mrs(nmb);
+  {
+    size_t pos = 0;
+    for (int mbi = 0; mbi < nmb; ++mbi) {
+      h_mrs[mbi].resize(P->mb[mbi].M);
+      for (int64_t m = 0; m < P->mb[mbi].M; ++m, ++pos) h_mrs[mbi][m] = rslot[P->m_child[pos]];
+    }
+  }
   for (int b = 0; b < nb; ++b) {
     CBucket& B = P->cb[b];
     std::vector<int32_t> rs(B.n);
     for (int64_t c = 0; c < B.n; ++c) rs[c] = rslot[B.h_gid[c]];
+    std::vector<int32_t> chrs(h_ch[b].size(), -1);
+    if (B.mb_child >= 0)
+      for (size_t i = 0; i < chrs.size(); ++i)
+        if (h_ch[b][i] >= 0) chrs[i] = h_mrs[B.mb_child][h_ch[b][i]];
+    if (chrs.empty()) chrs.push_back(-1);
+    UP(B.chrs, chrs);
     UP(B.gid, B.h_gid);
     UP(B.hoff, h_hoff[b]);
     UP(B.ch, h_ch[b]);
@@ -781,6 +797,7 @@ ClusterArgs<T> base_args(lrh_problem_s* P, const CBucket& B) {
   a.hoff = B.hoff;
   a.ch = B.ch;
   a.chmask = B.chmask;
+  a.ch_rslot = B.chrs;
   a.par = B.par;
   a.rslot = B.rslot;
   a.h = P->h;

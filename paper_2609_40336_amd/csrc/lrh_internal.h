@@ -76,6 +76,7 @@ struct ClusterArgs {
   const FusedParams* fp;      // device pointer, nullptr: no fused update
   const T* nu_c_prev; const T* ze_c_prev; const T* Tprev_c; const T* Rprev_c;
   const int32_t* rslot_of_msg_c; int64_t Sc;
+  const int32_t* ch_rslot;    // [maxch][n] child's marginal slot by (slot, cluster): read beside ch
   T* nu_c_new; T* ze_c_new;   // written by the parent (this cluster)
   const T* nu_p_prev; const T* ze_p_prev; const T* Tprev_p; const T* Rprev_p;
   int fused_first;            // 1: iteration 0 of a call, state already current

@@ -315,7 +315,8 @@ __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
       const int mask = A.chmask[(int64_t)s * A.n + c];
       HMat<T, CPLX, DC> X;
       if (fused) {
-        const int64_t rs = A.rslot_of_msg_c[m];
+        // by (slot, cluster) when available: the same level of dependent loads as ch itself
+        const int64_t rs = A.ch_rslot ? A.ch_rslot[(int64_t)s * A.n + c] : A.rslot_of_msg_c[m];
         unpack<T, CPLX, DC>([&](int k) {
           const int64_t o = (int64_t)k * A.Mc + m;
           T nu0 = A.nu_c_prev[o], ze0 = A.ze_c_prev[o];
