@@ -244,14 +244,24 @@ lrh_status lrh_unrolled_bound_grad(lrh_problem p, const double* nu0_dev, double 
  * non-zero (NONFINITE first), LRH_OK otherwise.  Either pointer may be NULL. */
 lrh_status lrh_check(lrh_problem p, hipStream_t stream, int64_t* noconv, int64_t* nonfinite);
 
-/* Launch-shape autotuner (form 2): for every cluster bucket, time the Gibbs pass of the
+/* Launch shapes (the W of the calls below), per cluster bucket and precision:
+ *   W = 1      register kernel, one lane per cluster (D_e <= 8), Jacobi
+ *   W = 8..64  LDS kernel, W lanes per cluster, 64/W clusters per wave (8 <= D_e <= 64), Jacobi
+ *   W = 1024   one 1024-thread workgroup per cluster, matrix in a device slab (D_e = 128, 256),
+ *              Jacobi; ground projector only once the exponential exists for the bucket
+ *   W = 0      Gibbs state exp(-beta theta)/Z by scaling and squaring on the FP64 matrix cores,
+ *              no eigenvectors (D_e >= 16; Gibbs passes only, the default there)
+ * Certification at D_e >= 16 always uses Householder tridiagonalisation + Sturm multisection
+ * (reported as W = 2 internally); the ground projector and the adjoint use the Jacobi shapes.
+ *
+ * Launch-shape autotuner (form 2): for every cluster bucket, time the Gibbs pass of the
  * candidate shapes -- threads per block {64, 128, 256} for the register kernels (D_e <= 4),
- * lanes per cluster for the LDS kernels (64/W clusters share a wave; W in {8, 16, 64} for
- * D_e = 8, {16, 32, 64} for 16, {32, 64} for 32, 64 for 64) -- in the precision of `flags`
- * (LRH_F32 or FP64) and keep the fastest.  cache_path (may be NULL) names a JSON file of
- * earlier choices keyed by (D_e, D_child, real/complex, precision, bucket size): cached
- * buckets are not re-measured, and the file is rewritten with every choice.  Synchronous.
- * Results are identical for every shape (the same arithmetic per cluster). */
+ * the compiled W above otherwise; the slab Jacobi is not timed where the exponential exists --
+ * on seeded random messages, in the precision of `flags` (LRH_F32 or FP64), and keep the
+ * fastest.  cache_path (may be NULL) names a JSON file of earlier choices keyed by (D_e,
+ * D_child, real/complex, precision, bucket size): cached buckets are not re-measured, and the
+ * file is rewritten with every choice.  Synchronous.  Every shape computes the same quantities;
+ * results agree to rounding. */
 lrh_status lrh_autotune(lrh_problem p, uint32_t flags, const char* cache_path, hipStream_t stream);
 
 /* Launch shapes in use, one entry per cluster bucket (at most `cap` written; *count = number
@@ -262,9 +272,9 @@ lrh_status lrh_get_shapes(lrh_problem p, int32_t cap, int32_t* De, int32_t* Dc, 
 
 /* Force the launch shape of every cluster bucket of dimension De for the precision of `flags`
  * (LRH_F32: FP32 iterations, else FP64): block = threads per block of the register kernel
- * (64, 128, 256), W = 1 for one lane per cluster (register kernel) or the lanes per cluster of
- * the LDS kernel.  Errors: LRH_E_INVALID (no such bucket, bad block), LRH_E_UNSUPPORTED (shape
- * not compiled for that bucket). */
+ * (64, 128, 256), W one of the shapes listed above for the Gibbs pass.  Errors:
+ * LRH_E_INVALID (no such bucket, bad block), LRH_E_UNSUPPORTED (shape not compiled for that
+ * bucket). */
 lrh_status lrh_set_shape(lrh_problem p, int32_t De, int32_t block, int32_t W, uint32_t flags);
 
 /* Per-bucket kernel timing for roofline accounting: runs reps + 1 launches of every cluster
