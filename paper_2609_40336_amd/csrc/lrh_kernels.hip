@@ -1253,8 +1253,11 @@ __global__ __launch_bounds__(1024) void k_cluster_big(ClusterArgs<T> A, T* scrat
 //     rho = Y_s / Tr Y_s,  log Z = 2^s log Tr E0 + sum_j 2^(s-j) log tau_j + log Tr Y_s
 // for any positive rescalings tau_j of the squarings (here exact powers of two).
 // The truncation error of T12 at norm 1/2 is below 2e-14 relative, i.e. a backward error of
-// about 7e-14 ||X|| in X that the squarings do not amplify; all of it runs in FP64 on
-// v_mfma_f64_16x16x4_f64 whatever the message precision.
+// about 7e-14 ||X|| in X, which exact squaring preserves.  Rounding in the squarings adds a
+// relative error of order D u (spectral spread / gap) to rho: the part along the dominant
+// eigenvector is removed by the final trace normalisation, the rest is damped once the
+// spectrum separates.  All of it runs in FP64 on v_mfma_f64_16x16x4_f64 whatever the message
+// precision.
 //
 // One wavefront per cluster.  A matrix is NB x NB blocks of 16 x 16 held in the MFMA result
 // layout: lane l, register r of block (I, J) is element (16 I + 4 r + l/16, 16 J + l%16).
