@@ -334,6 +334,23 @@ def tfim_plaquette_batch(Ls: Sequence[int], hs: Sequence[float], J: float = 1.0,
                                         hs=list(map(float, hs)), J=J))
 
 
+def tfim_rect_plaquettes(L: int, h: float, w: int = 2, hgt: int = 3, J: float = 1.0) -> ProblemDesc:
+    """Periodic L x L TFIM with w x hgt rectangular plaquettes as top clusters (2 x 3: six sites,
+    64-dimensional clusters; the interior bonds of a plaquette become its children)."""
+    n = L * L
+    b = _Builder(f"tfim_rect{w}x{hgt}_L{L}", n)
+    zz = -J * kron(Z, Z)
+    for (i, j) in square_edges(L, True, 0):
+        b.add_term((i, j), zz)
+    for s_ in range(n):
+        b.add_term((s_,), -h * X)
+    sid = lambda xx, yy: (xx % L) + L * (yy % L)
+    for y in range(L):
+        for x in range(L):
+            b.add_top(tuple(sid(x + dx, y + dy) for dy in range(hgt) for dx in range(w)))
+    return b.build(real=True, meta=dict(model="tfim_rect", L=L, h=h, w=w, hgt=hgt))
+
+
 def tfim_plaquette_sweep(n_inst: int = 512, seed: int = 4, Lmin: int = 8, Lmax: int = 64):
     """The batched sweep: L ~ U{Lmin..Lmax}, h ~ U[0.5, 4], drawn in that order."""
     rng = np.random.default_rng(seed)

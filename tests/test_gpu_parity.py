@@ -73,6 +73,7 @@ PROBLEMS = {
     "randchain_Y7_real": lambda: W.with_tops(W.heisenberg_chain(9, field_x=0.4),
                                              [tuple(range(i, i + 7)) for i in range(3)], subintervals=True),
     "k5_complete": lambda: k5_complete(),
+    "tfim_rect2x3": lambda: W.tfim_rect_plaquettes(4, 1.1),
 }
 
 
@@ -121,7 +122,7 @@ def test_dual_eval_fp32(name):
 
 
 @pytest.mark.parametrize("name", ["c1_tfim16_complex", "randchain_Y6", "plaq_batch_ragged", "xxz_tri3", "gue_Y7",
-                                  "gue_Y8", "randchain_Y7_real", "k5_complete"])
+                                  "gue_Y8", "randchain_Y7_real", "k5_complete", "tfim_rect2x3"])
 def test_certify_fp64_and_from_fp32(name):
     lrh = lrhmod()
     say(f"[certify] {name}")
@@ -448,6 +449,8 @@ EXPM_PROBLEMS = {
     # a 5-site cluster over the complete graph has ten pair children: the generic
     # (more than eight children) assembly and output path of the one-wave kernel
     "k5_complete_real": (lambda: k5_complete(), [32]),
+    # 2 x 3 plaquettes of a periodic 4 x 4 TFIM lattice: 64-dimensional real clusters
+    "tfim_rect2x3_real": (lambda: W.tfim_rect_plaquettes(4, 1.1), [64]),
 }
 
 
