@@ -1379,13 +1379,15 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
   __shared__ T stc_i[CPLX ? kExpmLut : 1][CPLX ? DE * DE / 4 : 1];
   XMat<NB, CPLX> X, P2, P3, M;
   // ---- a1/a2: assemble theta_e at eta ----
+  // D_c and D_e / D_c are powers of two: shifts and masks instead of integer division
+  const int ldc = Dc > 0 ? __builtin_ctz(Dc) : 0;
+  const int lnr = NBITS - ldc;
   if (lut) {
     for (int s = 0; s < nch; ++s) {
       const int mask = A.chmask[(int64_t)s * A.n + c];
       if (l < DE) {
         pextL[s][l] = (unsigned char)pext_rt(l, mask, NBITS);
-        const int NR = DE / (Dc > 0 ? Dc : 1);
-        depL[s][l] = (unsigned char)pdep_rt(l / NR, l % NR, mask, NBITS);
+        depL[s][l] = (unsigned char)pdep_rt(l >> lnr, l & ((1 << lnr) - 1), mask, NBITS);
       }
     }
     __syncthreads();
@@ -1407,16 +1409,17 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
           aci[I][J][r] = (T)vi;
         }
     // the (extrapolated) child messages, dense D_c x D_c in LDS, one pass over all children
-    for (int idx = l; idx < nch * Dc * Dc; idx += 64) {
-      const int s = idx / (Dc * Dc), ab = idx % (Dc * Dc);
+    for (int idx = l; idx < nch << (2 * ldc); idx += 64) {
+      const int s = idx >> (2 * ldc), ab = idx & ((1 << (2 * ldc)) - 1);
       const int m = A.ch[(int64_t)s * A.n + c];
       if (m < 0) continue;
+      const int a = ab >> ldc, b = ab & (Dc - 1);
       T er, ei;
       if (A.ze_c)
         herm_elem_bf<T, CPLX>([&](int k) { const int64_t o = (int64_t)k * A.Mc + m;
-                                           return extrap<T>(A.nu_c[o], A.ze_c[o], th); }, ab / Dc, ab % Dc, Dc, er, ei);
+                                           return extrap<T>(A.nu_c[o], A.ze_c[o], th); }, a, b, Dc, er, ei);
       else
-        herm_elem_bf<T, CPLX>([&](int k) { return A.nu_c[(int64_t)k * A.Mc + m]; }, ab / Dc, ab % Dc, Dc, er, ei);
+        herm_elem_bf<T, CPLX>([&](int k) { return A.nu_c[(int64_t)k * A.Mc + m]; }, a, b, Dc, er, ei);
       stc_r[s][ab] = er;
       if constexpr (CPLX) stc_i[s][ab] = ei;
     }
@@ -1433,7 +1436,7 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
           for (int r = 0; r < 4; ++r) {
             const int i = 16 * I + 4 * r + (l >> 4), j = 16 * J + (l & 15);
             const bool ok = ((i ^ j) & ~mask & (DE - 1)) == 0;
-            const int ab = pextL[s][i] * Dc + pextL[s][j];
+            const int ab = (pextL[s][i] << ldc) | pextL[s][j];
             acr[I][J][r] -= ok ? stc_r[s][ab] : T(0);
             if constexpr (CPLX) aci[I][J][r] -= ok ? stc_i[s][ab] : T(0);
           }
@@ -1646,10 +1649,14 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
   }
   // partial traces onto every child, all (child, component) pairs across the lanes
   if (A.Tout && Dc > 0) {
-    const int NR = DE / Dc;
+    const int NR = 1 << lnr;
     const int NCC = CPLX ? Dc * Dc : Dc * (Dc + 1) / 2;
     for (int idx = l; idx < nch * NCC; idx += 64) {
-      const int s = idx / NCC, k = idx % NCC;
+      int s = 0, k = idx;
+      while (k >= NCC) {   // (child, component) without an integer division; at most nch steps
+        k -= NCC;
+        ++s;
+      }
       const int m = A.ch[(int64_t)s * A.n + c];
       if (m < 0) continue;
       int a, b;
@@ -1657,7 +1664,7 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
       decode_comp(k, Dc, a, b, im);
       const T* y = im ? sai : sar;
       T sum = T(0);
-      for (int x = 0; x < NR; ++x) sum += y[depL[s][a * NR + x] * LD + depL[s][b * NR + x]];
+      for (int x = 0; x < NR; ++x) sum += y[depL[s][(a << lnr) + x] * LD + depL[s][(b << lnr) + x]];
       A.Tout[(int64_t)k * A.Mc + m] = sum;
     }
   }
