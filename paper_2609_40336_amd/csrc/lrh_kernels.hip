@@ -271,17 +271,24 @@ __device__ __forceinline__ void jacobi_sweep_reg(HMat<T, CPLX, D>& A, T (&ur)[D]
     }
 }
 
+// Squared off-diagonal Frobenius norm, accumulated in FP64 whatever T: the convergence test of
+// the FP32 iterations is taken in FP64, so near-degenerate clusters (large rotation angles on
+// tiny off-diagonals) are judged on the FP32 matrix without a second rounding of the test.
 template <typename T, bool CPLX, int D>
-__device__ __forceinline__ T offdiag2(const HMat<T, CPLX, D>& A) {
-  T s = T(0);
+__device__ __forceinline__ double offdiag2(const HMat<T, CPLX, D>& A) {
+  double s = 0.0;
 #pragma unroll
   for (int a = 0; a < D; ++a)
 #pragma unroll
     for (int b = a + 1; b < D; ++b) {
-      s = dfma<T>(A.r[tri_index(a, b, D)], A.r[tri_index(a, b, D)], s);
-      if constexpr (CPLX) s = dfma<T>(A.i[tri_index(a, b, D)], A.i[tri_index(a, b, D)], s);
+      const double x = (double)A.r[tri_index(a, b, D)];
+      s = fma(x, x, s);
+      if constexpr (CPLX) {
+        const double y = (double)A.i[tri_index(a, b, D)];
+        s = fma(y, y, s);
+      }
     }
-  return T(2) * s;
+  return 2.0 * s;
 }
 
 template <typename T>
@@ -367,11 +374,14 @@ __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
       unpack_add<T, CPLX, DE>([&](int k) { return A.nu_p[(int64_t)k * A.Mp + m]; }, H);
     }
   }
-  // ---- a3: cyclic Jacobi ----
-  T dg = T(0);
+  // ---- a3: cyclic Jacobi (norms and the convergence test in FP64) ----
+  double dg = 0.0;
 #pragma unroll
-  for (int k = 0; k < DE; ++k) dg = dfma<T>(H.r[tri_index(k, k, DE)], H.r[tri_index(k, k, DE)], dg);
-  const T nrm2 = dg + offdiag2<T, CPLX, DE>(H);
+  for (int k = 0; k < DE; ++k) {
+    const double x = (double)H.r[tri_index(k, k, DE)];
+    dg = fma(x, x, dg);
+  }
+  const double nrm2 = dg + offdiag2<T, CPLX, DE>(H);
   T ur[DE][DE], ui[DE][DE];  // eigenvectors (unused, and removed, without VEC / CPLX)
   if constexpr (VEC) {
 #pragma unroll
@@ -382,7 +392,7 @@ __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
         if constexpr (CPLX) ui[i][j] = T(0);
       }
   }
-  const T tol2 = (T)(A.tol * A.tol) * nrm2;
+  const double tol2 = A.tol * A.tol * nrm2;
   bool conv = false;
   for (int sweep = 0; sweep <= A.max_sweeps; ++sweep) {
     if (offdiag2<T, CPLX, DE>(H) <= tol2) { conv = true; break; }
@@ -632,19 +642,23 @@ struct JacobiScratch {
 // `done` clusters (converged, capped, or absent) skip the work but keep the wave together.
 // Returns true when the off-diagonal norm fell below tol2 within max_sweeps sweeps.
 template <typename T, bool CPLX, int DE, bool VEC, int W>
-__device__ bool lds_jacobi(T* sar, T* sai, T* sur, T* sui, JacobiScratch<T, DE / 2>& J, T tol2, int max_sweeps,
+__device__ bool lds_jacobi(T* sar, T* sai, T* sur, T* sui, JacobiScratch<T, DE / 2>& J, double tol2, int max_sweeps,
                            int lt, bool active) {
   constexpr int LD = DE + 1;
   constexpr int NP = DE / 2;
   bool done = !active, conv = false;
   for (int sweep = 0;; ++sweep) {
-    T off = T(0);
+    double off = 0.0;   // the convergence test in FP64 whatever T
     if (!done) {
       for (int idx = lt; idx < DE * DE; idx += W) {
         const int i = idx / DE, j = idx % DE;
         if (i != j) {
-          off = dfma<T>(sar[i * LD + j], sar[i * LD + j], off);
-          if constexpr (CPLX) off = dfma<T>(sai[i * LD + j], sai[i * LD + j], off);
+          const double x = (double)sar[i * LD + j];
+          off = fma(x, x, off);
+          if constexpr (CPLX) {
+            const double y = (double)sai[i * LD + j];
+            off = fma(y, y, off);
+          }
         }
       }
     }
@@ -878,7 +892,7 @@ __global__ __launch_bounds__(64) void k_cluster_lds(ClusterArgs<T> A) {
   }
   __syncthreads();
   // ---- a3: parallel cyclic Jacobi ----
-  const bool conv = lds_jacobi<T, CPLX, DE, VEC, W>(sar, sai, sur, sui, J_[g], (T)(A.tol * A.tol) * nrm2,
+  const bool conv = lds_jacobi<T, CPLX, DE, VEC, W>(sar, sai, sur, sui, J_[g], A.tol * A.tol * (double)nrm2,
                                                     A.max_sweeps, lt, active);
   if (active && !conv && lt == 0 && A.noconv) atomicAdd(A.noconv, 1ull);
   T lmin = T(INFINITY);
@@ -1099,6 +1113,7 @@ __global__ __launch_bounds__(1024) void k_cluster_big(ClusterArgs<T> A, T* scrat
   __shared__ T cs_c[128], cs_s[128], cs_er[128], cs_ei[128], cs_app[128], cs_aqq[128];
   __shared__ int cs_p[128], cs_q[128];
   __shared__ T red[16];
+  __shared__ double redd[16];
   __shared__ T sp[256];
   const int D = A.De;
   const int NB = log2i(D);
@@ -1119,17 +1134,21 @@ __global__ __launch_bounds__(1024) void k_cluster_big(ClusterArgs<T> A, T* scrat
     const T my_n2 = big_assemble<T, T, CPLX, VEC>(A, c, D, ar, ai, ur, ui, th, tid, nth);
     const T nrm2 = block_sum(my_n2, red);
     // ---- a3: parallel cyclic Jacobi over the slab ----
-    const T tol2 = (T)(A.tol * A.tol) * nrm2;
+    const double tol2 = A.tol * A.tol * (double)nrm2;
     bool conv = false;
     for (int sweep = 0; sweep <= A.max_sweeps; ++sweep) {
-      T off = T(0);
+      double off = 0.0;   // the convergence test in FP64 whatever T
       for (int64_t idx = tid; idx < DD; idx += nth) {
         if (idx / D != idx % D) {
-          off = dfma<T>(ar[idx], ar[idx], off);
-          if constexpr (CPLX) off = dfma<T>(ai[idx], ai[idx], off);
+          const double x = (double)ar[idx];
+          off = fma(x, x, off);
+          if constexpr (CPLX) {
+            const double y = (double)ai[idx];
+            off = fma(y, y, off);
+          }
         }
       }
-      off = block_sum(off, red);
+      off = block_sum(off, redd);
       if (off <= tol2) { conv = true; break; }
       if (sweep == A.max_sweeps) break;
       for (int r = 0; r < D - 1; ++r) {
@@ -2169,7 +2188,7 @@ __global__ __launch_bounds__(64) void k_cluster_vjp(ClusterArgs<T> A) {
     if constexpr (CPLX) sui[i * LD + j] = T(0);
   }
   __syncthreads();
-  const bool conv = lds_jacobi<T, CPLX, DE, true, 64>(sar, sai, sur, sui, J, (T)(A.tol * A.tol) * nrm2,
+  const bool conv = lds_jacobi<T, CPLX, DE, true, 64>(sar, sai, sur, sui, J, A.tol * A.tol * (double)nrm2,
                                                       A.max_sweeps, tid, true);
   if (!conv && tid == 0 && A.noconv) atomicAdd(A.noconv, 1ull);
   T lmin = T(INFINITY);
