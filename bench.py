@@ -262,16 +262,63 @@ def _line(metric_value, args, name, P, extra):
     return out
 
 
+def time_to_gap(P, desc, n_sites, torch, target=1e-4):
+    """Time to a certified gap of `target` per site in every instance, for the fused FP32 and
+    the plain FP64 forms: beta doubles every 250 iterations from 1 up to
+    beta_max = 2 Gamma / (n target) (the smoothing-error lemma with Gamma = sum_e log D_e), with a
+    certification after every stage and a stop at the first stage that reaches the target.  The
+    optimum is the best certified value of an untimed FP64 run three times as long, with two more
+    beta stages, and of both timed runs."""
+    from paper_2609_40336_amd import lrh
+    n_tot = float(desc.n_sites)
+    beta_max = 2.0 * P.Gamma / (n_tot * target)
+    S = int(math.ceil(math.log2(beta_max))) + 1
+    sched = [(2.0 ** s, 250) for s in range(S)]
+    Sr = Solver(P, False, True, [(2.0 ** s, 750) for s in range(S + 2)])
+    qref = np.full(P.n_inst, -np.inf)
+    for _ in range(S + 2):
+        Sr.run(750)
+        qr, mr, _ = P.certify(Sr.nu)
+        qref = np.maximum(qref, (qr - mr).cpu().numpy())
+    del Sr
+    out = {"target_gap_per_site": target, "beta_max": beta_max, "stages_of_250": S,
+           "reference": "best certified value of an FP64 run 3x as long with two more beta stages"}
+    for key, f32, fused in (("fused_fp32", True, True), ("plain_fp64", False, False)):
+        Sx = Solver(P, f32, fused, sched)
+        q = torch.zeros(P.n_inst, dtype=torch.float64, device="cuda")
+        mg = torch.zeros_like(q)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reached, gap = None, None
+        for k in range(S):
+            Sx.run(250)
+            lrh.lrh_certify(P.h, Sx.nu, lrh.LRH_F32 if f32 else 0, q, mg)
+            b = (q - mg).cpu().numpy()   # synchronises
+            qref = np.maximum(qref, b)
+            gap = float(np.max((qref - b) / n_sites))
+            if gap <= target:
+                reached = (time.perf_counter() - t0, 250 * (k + 1))
+                break
+        out[key] = {"seconds": reached[0] if reached else None, "iterations": reached[1] if reached else None,
+                    "max_gap_per_site_at_end": gap}
+        del Sx
+    print(f"[bench] time to {target:g} gap/site: {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def bench_rate(workload, args, torch):
     """Batched Algorithm 2 on a large workload: FP32 iterations replayed from captured graphs
     with autotuned launch shapes, beta doubling 1 -> 1024 over 11 stages of
     --iters-per-stage iterations, FP64 certification after every stage; then the same
-    schedule in the plain FP64 form (one launch per phase, no graph).  No closed-form
-    reference energy exists for these workloads, so no time-to-gap is reported."""
+    schedule in the plain FP64 form (one launch per phase, no graph).  There is no closed-form
+    optimum for these workloads: for the plaquette sweep and the intervals k <= 5 the time to a
+    1e-4 gap per site in every instance is measured as well (time_to_gap)."""
     import lrh_workloads as W
     from paper_2609_40336_amd import lrh
     t0 = time.perf_counter()
+    reference = False
     if workload == "c4":
+        reference = True
         desc = W.workload_c4()
         sample = W.workload_c4(n_inst=2)
         name = "tfim_plaquette_sweep_512_L8to64_h0.5to4_nesterov_fp32"
@@ -280,6 +327,7 @@ def bench_rate(workload, args, torch):
     elif workload.startswith("c3k"):
         k = int(workload[3:])
         desc = W.workload_c3(k)
+        reference = k <= 5
         sample = W.interval_chain_gue(24, k, 0.1, seed=3)
         name = f"interval_chain_gue_n4096_eps0.1_Y{k}_nesterov_fp32"
         sample_txt = f"the same interval hierarchy Y{k} on a 24-site chain"
@@ -315,23 +363,28 @@ def bench_rate(workload, args, torch):
         torch.cuda.synchronize()
         sec = ev[0].elapsed_time(ev[-1]) / 1e3
         stage_ms = [ev[k].elapsed_time(ev[k + 1]) / ips for k in range(len(sched))]
-        return S, sec, stage_ms, (q[-1] - mg[-1]).cpu().numpy()
+        t_at = [ev[0].elapsed_time(ev[k + 1]) / 1e3 for k in range(len(sched))]
+        return S, sec, stage_ms, (q - mg).cpu().numpy(), t_at
 
     iters = len(sched) * ips
-    S, sec, stage_ms, bound = timed_schedule(True, True)
+    S, sec, stage_ms, bounds, t_at = timed_schedule(True, True)
+    bound = bounds[-1]
     print(f"[bench] fused fp32: {sec:.3f} s for {iters} iterations", file=sys.stderr, flush=True)
     nchk, nnf = P.check()
     n_sites = np.bincount(desc.site_instance, minlength=desc.n_instances)
     roof = dominant_kernel_roofline(P, S.nu, 64.0, True, torch)
     del S
-    _, sec_plain, stage_plain, bound_plain = timed_schedule(False, False)
+    _, sec_plain, stage_plain, bounds_plain, t_at_plain = timed_schedule(False, False)
+    bound_plain = bounds_plain[-1]
     print(f"[bench] plain fp64: {sec_plain:.3f} s for {iters} iterations", file=sys.stderr, flush=True)
+    tte = time_to_gap(P, desc, n_sites, torch) if (reference and args.time_to_gap) else None
     extra = {
         "ms_per_step": sec / len(sched) * 1e3, "dtype": "f32 iterations, f64 certify",
         "us_per_iteration": sec / iters * 1e6,
         "schedule": f"beta = 2^s, s = 0..10, {ips} iterations per stage, FP64 certify after each stage",
         "ms_per_iteration_by_stage": [round(x, 4) for x in stage_ms],
         "mean_certified_bound_per_site": float(np.mean(bound / n_sites)),
+        "time_to_1e-4_gap_per_site_s": tte,
         "plain_fp64": {"value": P.n_clusters * iters / sec_plain, "unit": "cluster updates/s",
                        "ms_per_iteration_by_stage": [round(x, 4) for x in stage_plain],
                        "mean_certified_bound_per_site": float(np.mean(bound_plain / n_sites))},
@@ -645,6 +698,8 @@ def main():
                          "(interval hierarchy Y_k on the n = 4096 GUE chain), c4 (512 plaquette lattices), "
                          "c5 (64x64 XXZ value and coupling gradient), ex3 (iterations-to-eps experiment), "
                          "ex2 (optimal message norm vs chain length)")
+    ap.add_argument("--time-to-gap", action="store_true",
+                    help="c3k2..c3k5, c4: also measure the time to a 1e-4 certified gap per site")
     ap.add_argument("--ex3-max-iters", type=float, default=4e5,
                     help="ex3: iteration cap of Algorithm 1 (Algorithm 2: a quarter of it)")
     ap.add_argument("--iters-per-stage", type=int, default=0,
