@@ -206,7 +206,7 @@ def dominant_kernel_roofline(P, nu, beta, f32, torch, reps=3):
     F = (11 if P.is_real else 44) * D ** 3 * n
     t = us[b] * 1e-6
     W = sh["W"] if f32 else sh.get("W", 0)
-    if W == 0 and D >= 16 and beta > 0:
+    if W in (0, 4) and D >= 16 and beta > 0:
         bound, peak, kind = "mfma", FP64_MFMA_PEAK_TFLOPS, "scaling-and-squaring Gibbs kernel (FP64 MFMA)"
     else:
         bound = "alu"

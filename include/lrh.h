@@ -250,7 +250,10 @@ lrh_status lrh_check(lrh_problem p, hipStream_t stream, int64_t* noconv, int64_t
  *   W = 1024   one 1024-thread workgroup per cluster, matrix in a device slab (D_e = 128, 256),
  *              Jacobi; ground projector only once the exponential exists for the bucket
  *   W = 0      Gibbs state exp(-beta theta)/Z by scaling and squaring on the FP64 matrix cores,
- *              no eigenvectors (D_e >= 16; Gibbs passes only, the default there)
+ *              no eigenvectors, one wave per cluster, matrices in registers (D_e = 16, 32;
+ *              Gibbs passes only, the default there)
+ *   W = 4      the same on one 256-thread workgroup per cluster, matrices in a device slab
+ *              (D_e >= 32; the default for D_e >= 64)
  * Certification at D_e >= 16 always uses Householder tridiagonalisation + Sturm multisection
  * (reported as W = 2 internally); the ground projector and the adjoint use the Jacobi shapes.
  *

@@ -743,7 +743,7 @@ lrh_status ensure_work(lrh_problem_s* P, bool fused) {
     int64_t nx = 0;
     int Dmax = 0;
     for (const CBucket& B : P->cb)
-      if (B.De >= 64 || (B.De == 32 && P->cplx)) {
+      if (B.De >= 32) {
         nx = std::max<int64_t>(nx, B.n);
         Dmax = std::max(Dmax, B.De);
       }
@@ -819,7 +819,7 @@ ClusterArgs<T> base_args(lrh_problem_s* P, const CBucket& B) {
     a.big_slab = w.big_slab;
     a.big_blocks = w.big_blocks;
   }
-  if (B.De >= 64 || (B.De == 32 && P->cplx)) {
+  if (B.De >= 32) {
     Work<T>& w = P->work<T>();
     a.expm_scratch = w.xbig;
     a.expm_slab = w.xslab;
@@ -1377,9 +1377,10 @@ lrh_status autotune_t(lrh_problem_s* P, const char* cache, hipStream_t s) {
     {
       int shapes[8];
       const int ns = cluster_shapes(B.De, B.Dc, dbl, P->cplx, MODE_GIBBS, shapes);
-      const bool has_expm = std::find(shapes, shapes + ns, 0) != shapes + ns;
+      const bool has_expm = std::find(shapes, shapes + ns, 0) != shapes + ns ||
+                            std::find(shapes, shapes + ns, 4) != shapes + ns;
       for (int i = 0; i < ns; ++i) {
-        if (has_expm && B.De >= 128 && shapes[i] != 0) continue;  // slab Jacobi: orders of magnitude slower
+        if (has_expm && B.De >= 128 && shapes[i] != 0 && shapes[i] != 4) continue;  // slab Jacobi: far slower
         if (shapes[i] == 1 || B.De <= 4)
           for (int b : {64, 128, 256}) cands.push_back({b, shapes[i]});
         else

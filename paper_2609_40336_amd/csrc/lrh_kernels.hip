@@ -2530,7 +2530,10 @@ int cluster_shapes(int De, int Dc, bool dbl, bool cplx, int mode, int* out) {
     if (De == 8) reg = !(dbl && cplx && mode != MODE_CERTIFY);
   }
   if (reg) out[n++] = 1;
-  if (mode == MODE_GIBBS && expm_ok(De, cplx)) out[n++] = 0;
+  if (mode == MODE_GIBBS && expm_ok(De, cplx)) {
+    if (De <= 32) out[n++] = 0;   // one wave per cluster
+    if (De >= 32) out[n++] = 4;   // one workgroup per cluster
+  }
   if (mode == MODE_CERTIFY && De >= 16 && De <= 256) out[n++] = 2;
   int lds[8];
   const int nl = lds_shapes(De, lds);
@@ -2572,13 +2575,13 @@ static hipError_t launch_reg(const ClusterArgs<T>& a, int block, hipStream_t s) 
 template <typename T, bool CPLX, int MODE>
 static hipError_t launch_cluster_m(const ClusterArgs<T>& a, int block, int W, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
-  if (W == 0) {
+  if (W == 0 || W == 4) {   // 0: one wave per cluster up to D = 32, 4: one workgroup per cluster
     if constexpr (MODE == MODE_GIBBS) {
       if (a.fp != nullptr || a.n > 0x7fffffff) return hipErrorInvalidValue;
-      if (a.De == 16)
+      if (a.De == 16 && W == 0)
         hipLaunchKernelGGL((k_cluster_expm<T, CPLX, 16>), dim3((unsigned)a.n), dim3(64), 0, s, a);
-      else if (a.De == 32 && !CPLX)
-        hipLaunchKernelGGL((k_cluster_expm<T, false, 32>), dim3((unsigned)a.n), dim3(64), 0, s, a);
+      else if (a.De == 32 && W == 0)
+        hipLaunchKernelGGL((k_cluster_expm<T, CPLX, 32>), dim3((unsigned)a.n), dim3(64), 0, s, a);
       else if (a.De >= 32 && a.De <= 256 && a.expm_scratch != nullptr && a.expm_blocks > 0) {
         const unsigned grid = (unsigned)std::min<int64_t>(a.n, a.expm_blocks);
         if (a.De == 32)

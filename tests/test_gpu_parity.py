@@ -454,21 +454,25 @@ EXPM_PROBLEMS = {
 }
 
 
+@pytest.mark.parametrize("variant", ["wave", "workgroup"])
 @pytest.mark.parametrize("name", list(EXPM_PROBLEMS))
 @pytest.mark.parametrize("beta", [0.7, 6.0, 300.0, 5000.0])
-def test_gibbs_by_scaling_and_squaring_matches_oracle(name, beta):
+def test_gibbs_by_scaling_and_squaring_matches_oracle(name, beta, variant):
     """The matrix-core Gibbs kernel (shape W = 0: exp(-beta theta) by scaling and squaring, no
     eigenvectors) against the oracle's eigen-decomposition, FP64 and FP32 messages.  beta = 300
     takes about 12 squarings, beta = 5000 about 16.  Entry tolerance: the kernel's backward
     error (about 1e-13 ||theta||) times the Gibbs state's Lipschitz constant beta / 2."""
     lrh = lrhmod()
-    say(f"[expm] {name} beta={beta}")
+    say(f"[expm] {name} beta={beta} {variant}")
     make, dims = EXPM_PROBLEMS[name]
+    if variant == "workgroup" and not any(De >= 32 for De in dims):
+        pytest.skip("no cluster dimension with a workgroup variant")
     d = make()
     P = lrh.Problem(d, 0)
     R = O.Relaxation(d)
     for De in dims:
-        P.force_shape(De, 0)
+        # shape 0: one wave per cluster (D <= 32); shape 4: one workgroup per cluster (D >= 32)
+        P.force_shape(De, 0 if (De < 32 or (De == 32 and variant == "wave")) else 4)
     nu_o = R.draw(41, 0.5)
     q, g, m = P.dual_eval(P.from_dense(R.to_pairs(nu_o)), beta, grad=True, marg=True)
     torch.cuda.synchronize()
