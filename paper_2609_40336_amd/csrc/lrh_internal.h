@@ -89,7 +89,7 @@ struct ClusterArgs {
   void* big_scratch;             // big_blocks slabs of big_slab elements of T
   int64_t big_slab;
   int64_t big_blocks;
-  // ---- scaling-and-squaring Gibbs kernel, De >= 64: per-workgroup FP64 slab ----
+  // ---- workgroup scaling-and-squaring Gibbs kernel, De >= 32: per-workgroup FP64 slab ----
   double* expm_scratch;          // expm_blocks slabs of expm_slab doubles
   int64_t expm_slab;
   int64_t expm_blocks;

@@ -1725,33 +1725,57 @@ __device__ double gmm(const double* xr, const double* xi, const double* yr, cons
         accr[ii][jj] = mfma_f64x4{0.0, 0.0, 0.0, 0.0};
         acci[ii][jj] = mfma_f64x4{0.0, 0.0, 0.0, 0.0};
       }
-#pragma unroll 1
-    for (int K = 0; K < NB; ++K) {
+    // operand fragments of one K step (four k-sub-steps); with 16 x 16 tiles they are loaded one
+    // step ahead of the products that use them, so the L2 latency overlaps the matrix-core work
+    constexpr int NP = CPLX ? 2 : 1;
+    double fa[2][4][TB][NP], fb[2][4][TB][NP];
+    auto load_step = [&](int K, double (&ga)[4][TB][NP], double (&gb)[4][TB][NP]) {
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int64_t row = (int64_t)(16 * K + 4 * kk + lr) * DE;
-        double a_r[TB], a_i[TB], b_r[TB], b_i[TB];
 #pragma unroll
         for (int q = 0; q < TB; ++q) {
           const int ca = 16 * (TB * TI + q) + lc, cb = 16 * (TB * TJ + q) + lc;
-          a_r[q] = xr[row + ca];
-          b_r[q] = yr[row + cb];
+          ga[kk][q][0] = xr[row + ca];
+          gb[kk][q][0] = yr[row + cb];
           if constexpr (CPLX) {
-            a_i[q] = xi[row + ca];
-            b_i[q] = yi[row + cb];
+            ga[kk][q][1] = xi[row + ca];
+            gb[kk][q][1] = yi[row + cb];
           }
         }
+      }
+    };
+    auto mma_step = [&](const double (&ga)[4][TB][NP], const double (&gb)[4][TB][NP]) {
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
         for (int ii = 0; ii < TB; ++ii)
 #pragma unroll
           for (int jj = 0; jj < TB; ++jj) {
-            accr[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[ii], b_r[jj], accr[ii][jj], 0, 0, 0);
+            accr[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[kk][ii][0], gb[kk][jj][0], accr[ii][jj], 0, 0, 0);
             if constexpr (CPLX) {
-              accr[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[ii], b_i[jj], accr[ii][jj], 0, 0, 0);
-              acci[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[ii], b_i[jj], acci[ii][jj], 0, 0, 0);
-              acci[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_i[ii], b_r[jj], acci[ii][jj], 0, 0, 0);
+              accr[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[kk][ii][1], gb[kk][jj][1], accr[ii][jj], 0, 0, 0);
+              acci[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[kk][ii][0], gb[kk][jj][1], acci[ii][jj], 0, 0, 0);
+              acci[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[kk][ii][1], gb[kk][jj][0], acci[ii][jj], 0, 0, 0);
             }
           }
+    };
+    if constexpr (TB == 1) {   // 16 x 16 tiles: latency-bound, registers to spare
+      load_step(0, fa[0], fb[0]);
+#pragma unroll 1
+      for (int K = 0; K < NB; K += 2) {
+        if (K + 1 < NB) load_step(K + 1, fa[1], fb[1]);
+        mma_step(fa[0], fb[0]);
+        if (K + 1 < NB) {
+          if (K + 2 < NB) load_step(K + 2, fa[0], fb[0]);
+          mma_step(fa[1], fb[1]);
+        }
+      }
+    } else {   // 32 x 32 tiles: no second buffer (it costs occupancy and time at D >= 128)
+#pragma unroll 1
+      for (int K = 0; K < NB; ++K) {
+        load_step(K, fa[0], fb[0]);
+        mma_step(fa[0], fb[0]);
       }
     }
 #pragma unroll
