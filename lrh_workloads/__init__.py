@@ -45,6 +45,7 @@ class ProblemDesc:
     site_instance: np.ndarray       # int32 [n_sites]
     n_instances: int
     subintervals: bool = False      # add every contiguous run of each top cluster
+    two_level: bool = False         # family = top clusters + their maximal pairwise overlaps
     # Optional linear parametrisation of terms, h_t = sum_p c_p * B_{t,p}; used by
     # gradient workloads.  term_param[t] = index of the coupling the term is
     # proportional to (-1: constant term), dterm_* = d h_t / d c.
@@ -141,7 +142,8 @@ class _Builder:
             raise ValueError("cluster has repeated sites")
         self.tops.append(s)
 
-    def build(self, real: Optional[bool] = None, subintervals=False, params=None, meta=None):
+    def build(self, real: Optional[bool] = None, subintervals=False, params=None, meta=None,
+              two_level=False):
         n_t = len(self.terms)
         term_ptr = np.zeros(n_t + 1, dtype=np.int64)
         term_off = np.zeros(n_t + 1, dtype=np.int64)
@@ -175,7 +177,7 @@ class _Builder:
             term_ptr=term_ptr, term_sites=term_sites, term_off=term_off,
             term_re=term_re, term_im=term_im, top_ptr=top_ptr, top_sites=top_sites,
             site_instance=self.site_instance.copy(), n_instances=self.n_instances,
-            subintervals=subintervals, term_param=term_param,
+            subintervals=subintervals, two_level=bool(two_level), term_param=term_param,
             params=None if params is None else np.asarray(params, dtype=np.float64),
             dterm_re=dre, dterm_im=dim, meta=dict(meta or {}))
 
@@ -268,7 +270,7 @@ def anisotropic_heisenberg_chain(n: int, Jx: float = 2.0, Jy: float = -3.0, Jz: 
 
 
 def random_chain(n: int, seed: int, scale: float = 1.0, top_len: int = 2,
-                 subintervals: bool = False) -> ProblemDesc:
+                 subintervals: bool = False, two_level: bool = False) -> ProblemDesc:
     """Chain with independent GUE 2-site terms; top clusters are intervals of length top_len."""
     rng = np.random.default_rng(seed)
     b = _Builder(f"random_chain_n{n}_s{seed}", n)
@@ -276,18 +278,19 @@ def random_chain(n: int, seed: int, scale: float = 1.0, top_len: int = 2,
         b.add_term((i, i + 1), scale * gue(rng, 4))
     for i in range(n - top_len + 1):
         b.add_top(tuple(range(i, i + top_len)))
-    return b.build(real=False, subintervals=subintervals,
+    return b.build(real=False, subintervals=subintervals, two_level=two_level,
                    meta=dict(model="random", seed=seed, top_len=top_len))
 
 
-def interval_chain_gue(n: int, k: int, eps: float = 0.1, seed: int = 3) -> ProblemDesc:
+def interval_chain_gue(n: int, k: int, eps: float = 0.1, seed: int = 3, two_level: bool = False) -> ProblemDesc:
     """Weakly perturbed separable chain of Thm. 3: H = sum h_i + eps sum v_{i,i+1}.
 
     h_i = V_i diag(0, 1) V_i^H with V_i the eigenvectors of a seeded 2x2 GUE draw
     (unit norm, unique ground state of energy 0, gap 1); v_{i,i+1} is a 4x4 GUE draw
     scaled to spectral norm 1.  Draw order: every h_i first, then every v_i.
     Cluster family: the interval hierarchy Y_k (all intervals of length k and every
-    contiguous sub-interval).
+    contiguous sub-interval), or with two_level=True only the windows of length k and the
+    overlaps of consecutive windows (the same optimum on a chain).
     """
     rng = np.random.default_rng(seed)
     b = _Builder(f"interval_chain_n{n}_k{k}_s{seed}", n)
@@ -300,8 +303,8 @@ def interval_chain_gue(n: int, k: int, eps: float = 0.1, seed: int = 3) -> Probl
         b.add_term((i, i + 1), eps * v)
     for i in range(n - k + 1):
         b.add_top(tuple(range(i, i + k)))
-    return b.build(real=False, subintervals=True,
-                   meta=dict(model="interval_gue", eps=eps, seed=seed, k=k, n=n))
+    return b.build(real=False, subintervals=not two_level, two_level=two_level,
+                   meta=dict(model="interval_gue", eps=eps, seed=seed, k=k, n=n, two_level=two_level))
 
 
 def tfim_plaquette_batch(Ls: Sequence[int], hs: Sequence[float], J: float = 1.0,
@@ -441,7 +444,7 @@ def whole_system(desc: ProblemDesc) -> ProblemDesc:
 
 
 def with_tops(desc: ProblemDesc, tops: Sequence[Sequence[int]], subintervals=False,
-              name: Optional[str] = None) -> ProblemDesc:
+              name: Optional[str] = None, two_level: bool = False) -> ProblemDesc:
     """Same terms, another top-level cluster family."""
     b = _Builder(name or desc.name + "_tops", desc.n_sites)
     b.site_dim = desc.site_dim.copy()
@@ -451,7 +454,7 @@ def with_tops(desc: ProblemDesc, tops: Sequence[Sequence[int]], subintervals=Fal
         b.add_term(s, m)
     for t in tops:
         b.add_top(t)
-    return b.build(real=desc.is_real, subintervals=subintervals)
+    return b.build(real=desc.is_real, subintervals=subintervals, two_level=two_level)
 
 
 # --------------------------------------------------------------------------------------
@@ -468,9 +471,9 @@ def batch_scaled(descs: Sequence[ProblemDesc], scales: Sequence[float], name: st
     subint = None
     for i, (d, sc) in enumerate(zip(descs, scales)):
         if subint is None:
-            subint = d.subintervals
-        elif subint != d.subintervals:
-            raise ValueError("instances disagree on the interval closure")
+            subint = (d.subintervals, d.two_level)
+        elif subint != (d.subintervals, d.two_level):
+            raise ValueError("instances disagree on the cluster family")
         b.site_dim[off:off + d.n_sites] = d.site_dim
         b.site_instance[off:off + d.n_sites] = i
         for sites, m in d.terms():
@@ -480,7 +483,8 @@ def batch_scaled(descs: Sequence[ProblemDesc], scales: Sequence[float], name: st
         off += d.n_sites
     b.n_instances = len(descs)
     real = all(d.is_real for d in descs)
-    return b.build(real=real, subintervals=bool(subint), meta=dict(model="batch", scales=list(map(float, scales))))
+    return b.build(real=real, subintervals=bool(subint[0]), two_level=bool(subint[1]),
+                   meta=dict(model="batch", scales=list(map(float, scales))))
 
 
 def message_draw(seed: int, parent: Sequence[int], child: Sequence[int], D: int,
@@ -511,8 +515,8 @@ def workload_c2(L: int = 32) -> ProblemDesc:
     return heisenberg_square(L)
 
 
-def workload_c3(k: int, n: int = 4096, eps: float = 0.1, seed: int = 3) -> ProblemDesc:
-    return interval_chain_gue(n, k, eps, seed)
+def workload_c3(k: int, n: int = 4096, eps: float = 0.1, seed: int = 3, two_level: bool = False) -> ProblemDesc:
+    return interval_chain_gue(n, k, eps, seed, two_level=two_level)
 
 
 def workload_c4(n_inst: int = 512, seed: int = 4, Lmin: int = 8, Lmax: int = 64) -> ProblemDesc:

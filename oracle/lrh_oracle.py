@@ -99,6 +99,26 @@ def herm(A: np.ndarray) -> np.ndarray:
 # the relaxation: poset, augmented Hamiltonians, dual values and (sub)gradients
 # --------------------------------------------------------------------------------------
 
+def maximal_overlaps(tops: Sequence[Tuple[int, ...]]) -> List[Tuple[int, ...]]:
+    """Non-empty intersections of two top clusters that no other such intersection strictly
+    contains.  For the windows of length t on a chain these are the n - t overlaps of
+    consecutive windows (length t - 1)."""
+    holders: Dict[int, List[int]] = {}
+    for i, c in enumerate(tops):
+        for v in c:
+            holders.setdefault(v, []).append(i)
+    inter = set()
+    for hs in holders.values():          # only pairs that share a site intersect
+        for a, b in combinations(hs, 2):
+            inter.add(tuple(sorted(set(tops[a]) & set(tops[b]))))
+    # an intersection strictly inside another one shares a site with it
+    by_site: Dict[int, List[Tuple[int, ...]]] = {}
+    for c in inter:
+        for v in c:
+            by_site.setdefault(v, []).append(c)
+    return sorted(c for c in inter if not any(set(c) < set(o) for o in by_site[c[0]]))
+
+
 class Relaxation:
     """Cluster poset of one problem (all instances) and the dual's building blocks."""
 
@@ -107,19 +127,28 @@ class Relaxation:
         n = desc.n_sites
         sd = [int(x) for x in desc.site_dim]
         self.site_dim = sd
+        terms = list(desc.terms())
+        self.two_level = bool(getattr(desc, "two_level", False))
+        if self.two_level and desc.subintervals:
+            raise ValueError("the two-level family and the interval closure exclude each other")
         # ---- C_full (Sec. 3.2 cluster family; Y_t adds contiguous runs) -------------
         cset = set()
-        for top in desc.tops():
-            cset.add(top)
-            if desc.subintervals:
-                for a in range(len(top)):
-                    for b in range(a + 1, len(top) + 1):
-                        cset.add(top[a:b])
-        terms = list(desc.terms())
-        for s, _ in terms:
-            cset.add(s)
-        for v in range(n):
-            cset.add((v,))
+        if self.two_level:
+            # top clusters and the maximal pairwise overlaps of top clusters, nothing else
+            tops = sorted(set(desc.tops()))
+            cset.update(tops)
+            cset.update(maximal_overlaps(tops))
+        else:
+            for top in desc.tops():
+                cset.add(top)
+                if desc.subintervals:
+                    for a in range(len(top)):
+                        for b in range(a + 1, len(top) + 1):
+                            cset.add(top[a:b])
+            for s, _ in terms:
+                cset.add(s)
+            for v in range(n):
+                cset.add((v,))
         self.clusters: List[Tuple[int, ...]] = sorted(cset, key=lambda c: (len(c), c))
         self.index: Dict[Tuple[int, ...], int] = {c: i for i, c in enumerate(self.clusters)}
         nc = len(self.clusters)
@@ -150,13 +179,35 @@ class Relaxation:
         # ---- messages (one per covering pair e -> f) -------------------------------
         self.msgs: List[Tuple[int, int]] = [(e, f) for e in range(nc) for f in self.children[e]]
         self.msg_index = {m: i for i, m in enumerate(self.msgs)}
-        # ---- h_e: sum of the terms whose support is exactly e ----------------------
-        self.h: Dict[int, np.ndarray] = {}
+        # ---- h_e ---------------------------------------------------------------------
+        # closure family: the sum of the terms whose support is exactly e;
+        # two-level family: every term split evenly over the top clusters holding its
+        # support, lifted into each (same primal objective wherever the tops agree on
+        # the term's support)
+        self.term_homes: List[List[Tuple[int, Tuple[int, ...], float]]] = []
+        if self.two_level:
+            holders: Dict[int, List[int]] = {}
+            for c in tops:
+                for v in c:
+                    holders.setdefault(v, []).append(self.index[c])
         for s, m in terms:
             if not np.allclose(m, m.conj().T, atol=herm_tol * max(1.0, np.abs(m).max())):
                 raise ValueError(f"term on {s} is not Hermitian")
-            e = self.index[s]
-            self.h[e] = self.h.get(e, 0) + m
+            if self.two_level:
+                homes = [e for e in holders.get(s[0], []) if set(s) <= set(self.clusters[e])]
+                if not homes:
+                    raise ValueError(f"term on {s} lies in no top cluster")
+                w = 1.0 / len(homes)
+                self.term_homes.append([(e, tuple(self.clusters[e].index(v) for v in s), w)
+                                        for e in homes])
+            else:
+                e = self.index[s]
+                self.term_homes.append([(e, tuple(range(len(s))), 1.0)])
+        self.h: Dict[int, np.ndarray] = {}
+        for (s, m), homes in zip(terms, self.term_homes):
+            for e, pos, w in homes:
+                dims_e = [sd[v] for v in self.clusters[e]]
+                self.h[e] = self.h.get(e, 0) + w * lift(m, dims_e, pos)
         self.real = desc.is_real
         # ---- groups for batched evaluation ---------------------------------------
         self.cgroups: Dict[int, np.ndarray] = {}
@@ -494,8 +545,10 @@ def term_params(R: Relaxation):
     for t in range(d.n_terms):
         p = int(d.term_param[t])
         if p >= 0:
-            sites, _ = d.term(t)
-            out.append((R.index[sites], p, d.dterm(t)))
+            B = d.dterm(t)
+            for e, pos, w in R.term_homes[t]:
+                dims_e = [R.site_dim[v] for v in R.clusters[e]]
+                out.append((e, p, w * lift(B, dims_e, pos)))
     return out
 
 
