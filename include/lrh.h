@@ -53,6 +53,14 @@ typedef enum {
 /* flags for lrh_problem_desc.flags */
 #define LRH_SUBINTERVALS 0x1u  /* add every contiguous run of each top cluster (Y_t, eq.
                                   interval_set_defn: intervals "with their subsets")      */
+#define LRH_TWO_LEVEL    0x2u  /* two-level family: the top clusters and the intersections of
+                                  two top clusters that no other such intersection strictly
+                                  contains, nothing else (no term supports, no singletons).
+                                  Each term is split evenly over the top clusters holding its
+                                  support (LRH_E_INVALID if none does).  On a chain with the
+                                  windows of length t as tops this keeps Y_t's optimum with
+                                  only the windows and their overlaps (Sec. 3.2, Sec. 4.2).
+                                  Excludes LRH_SUBINTERVALS.                               */
 
 /* flags for the compute calls */
 #define LRH_F32    0x1u   /* state buffers (nu, zeta, grad, marginals) are float, and the
@@ -75,10 +83,10 @@ typedef struct lrh_problem_s* lrh_problem;   /* opaque; owned by the library */
  * term_im (term_im == NULL: every term is real, the problem is solved in real
  * arithmetic).  The cluster family (Sec. 3.2) is the list of top clusters
  * top_sites[top_ptr[c] .. top_ptr[c+1]) (ascending); the library adds every term
- * support and every singleton, plus contiguous runs when LRH_SUBINTERVALS is set,
- * and keeps the covering relations of the inclusion poset (Sec. 4.2: constraints
- * between consecutive poset levels suffice).  site_instance may be NULL (one
- * instance). */
+ * support and every singleton, plus contiguous runs when LRH_SUBINTERVALS is set
+ * (LRH_TWO_LEVEL: only the maximal pairwise overlaps of the tops), and keeps the
+ * covering relations of the inclusion poset (Sec. 4.2: constraints between consecutive
+ * poset levels suffice).  site_instance may be NULL (one instance). */
 typedef struct {
   int32_t n_sites;
   const int32_t* site_dim;        /* [n_sites], must be 2                                */
@@ -92,7 +100,7 @@ typedef struct {
   const int64_t* top_ptr;         /* [n_top+1]                                           */
   const int32_t* top_sites;
   const int32_t* site_instance;   /* [n_sites] or NULL                                   */
-  uint32_t flags;                 /* LRH_SUBINTERVALS                                    */
+  uint32_t flags;                 /* LRH_SUBINTERVALS or LRH_TWO_LEVEL                   */
   /* Optional linear parametrisation of terms (for gradients with respect to couplings):
    * term t with term_param[t] = p >= 0 is h_t(c) = h_t + (c_p - params[p]) * dterm_t, with
    * dterm_t = d h_t / d c_p stored like the terms (term_off, dterm_im NULL for a real

@@ -4,7 +4,9 @@
 // Poset (paper Sec. 3.2 and Sec. 4.2): C_full holds the top clusters, every term support,
 // every singleton and, for the interval hierarchy, every contiguous run of a top
 // cluster; only covering relations (maximal proper subsets present in C_full) carry
-// messages.  Terms are added to the cluster equal to their support.
+// messages.  Terms are added to the cluster equal to their support.  The two-level family
+// holds only the top clusters and their maximal pairwise overlaps; each term is then split
+// evenly over the top clusters that hold its support.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -258,12 +260,19 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
     keys.push_back(key);
     return id;
   };
+  const bool two_level = (d->flags & LRH_TWO_LEVEL) != 0;
+  if (two_level && (d->flags & LRH_SUBINTERVALS))
+    return fail(LRH_E_INVALID, "LRH_TWO_LEVEL and LRH_SUBINTERVALS exclude each other");
+  if (d->flags & ~(LRH_SUBINTERVALS | LRH_TWO_LEVEL)) return fail(LRH_E_INVALID, "unknown problem flag");
+  std::vector<int32_t> top_ids;   // C_full id of every distinct top cluster
   for (int c = 0; c < d->n_top; ++c) {
     Key key;
     const int64_t a = d->top_ptr[c], b = d->top_ptr[c + 1];
     lrh_status st = make_key(d->top_sites + a, (int)(b - a), key);
     if (st != LRH_OK) return st;
-    add(key);
+    const size_t before = keys.size();
+    const int32_t id = add(key);
+    if (keys.size() > before) top_ids.push_back(id);
     if (d->flags & LRH_SUBINTERVALS) {
       for (int x = 0; x < key.k; ++x)
         for (int y = x + 1; y <= key.k; ++y) {
@@ -274,7 +283,53 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
         }
     }
   }
-  std::vector<int32_t> term_cluster(d->n_terms);
+  // top clusters holding each site (two-level family)
+  std::vector<std::vector<int32_t>> tops_at(two_level ? n : 0);
+  if (two_level) {
+    for (int32_t id : top_ids)
+      for (int i = 0; i < keys[id].k; ++i) tops_at[keys[id].s[i]].push_back(id);
+    // maximal pairwise overlaps of top clusters: only tops sharing a site intersect
+    std::unordered_map<Key, int32_t, KeyHash> ov_index;
+    std::vector<Key> ov;
+    for (int v = 0; v < n; ++v) {
+      const auto& T = tops_at[v];
+      for (size_t x = 0; x < T.size(); ++x)
+        for (size_t y = x + 1; y < T.size(); ++y) {
+          const Key &A = keys[T[x]], &B = keys[T[y]];
+          Key I;
+          for (int i = 0, j = 0; i < A.k && j < B.k;) {
+            if (A.s[i] == B.s[j]) { I.s[I.k++] = A.s[i]; ++i; ++j; }
+            else if (A.s[i] < B.s[j]) ++i;
+            else ++j;
+          }
+          if (I.s[0] != v) continue;   // count each pair once: at its first shared site
+          if (ov_index.emplace(I, (int32_t)ov.size()).second) ov.push_back(I);
+        }
+    }
+    // an overlap strictly inside another one shares its first site with it
+    std::vector<std::vector<int32_t>> ov_at(n);
+    for (size_t o = 0; o < ov.size(); ++o)
+      for (int i = 0; i < ov[o].k; ++i) ov_at[ov[o].s[i]].push_back((int32_t)o);
+    auto subset = [](const Key& a, const Key& b) {   // a strictly inside b
+      if (a.k >= b.k) return false;
+      int j = 0;
+      for (int i = 0; i < a.k; ++i) {
+        while (j < b.k && b.s[j] < a.s[i]) ++j;
+        if (j == b.k || b.s[j] != a.s[i]) return false;
+      }
+      return true;
+    };
+    for (size_t o = 0; o < ov.size(); ++o) {
+      bool maximal = true;
+      for (int32_t q : ov_at[ov[o].s[0]])
+        if (subset(ov[o], ov[q])) { maximal = false; break; }
+      if (maximal) add(ov[o]);
+    }
+  }
+  // homes of every term: the cluster equal to its support, or (two-level family) every
+  // top cluster holding the support, each with weight 1 / (number of such tops)
+  struct Home { int32_t c; uint8_t pos[8]; double w; };
+  std::vector<std::vector<Home>> term_home(d->n_terms);
   for (int t = 0; t < d->n_terms; ++t) {
     Key key;
     const int64_t a = d->term_ptr[t], b = d->term_ptr[t + 1];
@@ -282,14 +337,29 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
     if (st != LRH_OK) return st;
     const int64_t D = (int64_t)1 << key.k;
     if (d->term_off[t + 1] - d->term_off[t] != D * D) return fail(LRH_E_INVALID, "term block size mismatch");
-    term_cluster[t] = add(key);
+    if (!two_level) {
+      Home h{add(key), {0, 1, 2, 3, 4, 5, 6, 7}, 1.0};
+      term_home[t].push_back(h);
+      continue;
+    }
+    for (int32_t id : tops_at[key.s[0]]) {
+      const Key& T = keys[id];
+      Home h{id, {}, 0.0};
+      int found = 0;
+      for (int i = 0, j = 0; i < key.k && j < T.k; ++j)
+        if (T.s[j] == key.s[i]) h.pos[i++] = (uint8_t)j, ++found;
+      if (found == key.k) term_home[t].push_back(h);
+    }
+    if (term_home[t].empty()) return fail(LRH_E_INVALID, "term support lies in no top cluster");
+    for (auto& h : term_home[t]) h.w = 1.0 / (double)term_home[t].size();
   }
-  for (int v = 0; v < n; ++v) {
-    Key key;
-    key.k = 1;
-    key.s[0] = v;
-    add(key);
-  }
+  if (!two_level)
+    for (int v = 0; v < n; ++v) {
+      Key key;
+      key.k = 1;
+      key.s[0] = v;
+      add(key);
+    }
   const int64_t nc = (int64_t)keys.size();
   if (nc > (int64_t)INT32_MAX / 2) return fail(LRH_E_UNSUPPORTED, "too many clusters");
   // instance of every cluster
@@ -497,11 +567,38 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
   }
   P->R_len = roff;
 
-  // ---- h_e: sum of the terms whose support is the cluster, packed ----
+  // ---- h_e: the terms at home in the cluster, lifted and weighted, packed ----
+  // H += w * (1 (x) B): B (Dt x Dt) acts on the cluster's sites at positions pos[0..kt),
+  // position p being bit (ke - 1 - p) of a cluster index
+  auto lift_add = [](std::vector<std::complex<double>>& H, int ke, const Home& h, int kt, const double* re,
+                     const double* im, double scale) {
+    const int De = 1 << ke, Dt = 1 << kt;
+    int bit[8];
+    uint32_t tmask = 0;
+    for (int j = 0; j < kt; ++j) {
+      bit[j] = ke - 1 - h.pos[j];
+      tmask |= 1u << bit[j];
+    }
+    auto spread = [&](int a) {   // term index -> cluster bits
+      uint32_t x = 0;
+      for (int j = 0; j < kt; ++j)
+        if (a >> (kt - 1 - j) & 1) x |= 1u << bit[j];
+      return x;
+    };
+    for (int i = 0; i < De; ++i) {
+      int a = 0;
+      for (int j = 0; j < kt; ++j) a = (a << 1) | (i >> bit[j] & 1);
+      const uint32_t rest = (uint32_t)i & ~tmask;
+      for (int b = 0; b < Dt; ++b) {
+        const uint32_t jj = rest | spread(b);
+        H[(size_t)i * De + jj] += scale * h.w * std::complex<double>(re[a * Dt + b], im ? im[a * Dt + b] : 0.0);
+      }
+    }
+  };
   std::vector<std::vector<std::complex<double>>> hdense(nc);
   for (int t = 0; t < d->n_terms; ++t) {
-    const int32_t g = gid_of[term_cluster[t]];
-    const int D = P->c_D[g];
+    const int kt = (int)(d->term_ptr[t + 1] - d->term_ptr[t]);
+    const int D = 1 << kt;
     const double* re = d->term_re + d->term_off[t];
     const double* im = d->term_im ? d->term_im + d->term_off[t] : nullptr;
     double mx = 0;
@@ -512,9 +609,13 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
         std::complex<double> b(re[j * D + i], im ? -im[j * D + i] : 0.0);
         if (std::abs(a - b) > 1e-12 * std::max(1.0, mx)) return fail(LRH_E_INVALID, "term is not Hermitian");
       }
-    auto& H = hdense[g];
-    if (H.empty()) H.assign((size_t)D * D, 0.0);
-    for (int i = 0; i < D * D; ++i) H[i] += std::complex<double>(re[i], im ? im[i] : 0.0);
+    for (const Home& h : term_home[t]) {
+      const int32_t g = gid_of[h.c];
+      const int De = P->c_D[g];
+      auto& H = hdense[g];
+      if (H.empty()) H.assign((size_t)De * De, 0.0);
+      lift_add(H, keys[h.c].k, h, kt, re, im, 1.0);
+    }
   }
   std::vector<double> hpack;
   std::vector<std::vector<int64_t>> h_hoff(nb);
@@ -547,27 +648,33 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
       const int32_t pidx = d->term_param[t];
       if (pidx < 0) continue;
       if (pidx >= d->n_params) return fail(LRH_E_INVALID, "term_param out of range");
-      const int32_t g = gid_of[term_cluster[t]];
-      const int D = P->c_D[g];
+      const int kt = (int)(d->term_ptr[t + 1] - d->term_ptr[t]);
+      const int Dt = 1 << kt;
       const double* re = d->dterm_re + d->term_off[t];
       const double* im = d->dterm_im ? d->dterm_im + d->term_off[t] : nullptr;
-      for (int i = 0; i < D; ++i)
-        for (int j = 0; j < D; ++j) {
-          std::complex<double> a(re[i * D + j], im ? im[i * D + j] : 0.0);
-          std::complex<double> b(re[j * D + i], im ? -im[j * D + i] : 0.0);
+      for (int i = 0; i < Dt; ++i)
+        for (int j = 0; j < Dt; ++j) {
+          std::complex<double> a(re[i * Dt + j], im ? im[i * Dt + j] : 0.0);
+          std::complex<double> b(re[j * Dt + i], im ? -im[j * Dt + i] : 0.0);
           if (std::abs(a - b) > 1e-12 * std::max(1.0, std::abs(a))) return fail(LRH_E_INVALID, "dterm is not Hermitian");
         }
-      const int64_t doff = (int64_t)dterm_pack.size();
-      for (int i = 0; i < D; ++i)
-        for (int j = i; j < D; ++j) dterm_pack.push_back(0.5 * (re[i * D + j] + re[j * D + i]));
-      if (P->cplx)
+      for (const Home& h : term_home[t]) {
+        const int32_t g = gid_of[h.c];
+        const int D = P->c_D[g];
+        std::vector<std::complex<double>> B((size_t)D * D, 0.0);
+        lift_add(B, keys[h.c].k, h, kt, re, im, 1.0);
+        const int64_t doff = (int64_t)dterm_pack.size();
         for (int i = 0; i < D; ++i)
-          for (int j = i + 1; j < D; ++j) dterm_pack.push_back(0.5 * (im[i * D + j] - im[j * D + i]));
-      // constant part of the cluster: subtract params[p] * dterm
-      const int64_t ho = h_hoff[cb_of[g]][pos_in_cb[g]];
-      const int nco = comps_of(D, P->cplx);
-      for (int k = 0; k < nco; ++k) hfix_pack[ho + k] -= d->params[pidx] * dterm_pack[doff + k];
-      pts.push_back({g, pidx, t, doff});
+          for (int j = i; j < D; ++j) dterm_pack.push_back(0.5 * (B[i * D + j].real() + B[j * D + i].real()));
+        if (P->cplx)
+          for (int i = 0; i < D; ++i)
+            for (int j = i + 1; j < D; ++j) dterm_pack.push_back(0.5 * (B[i * D + j].imag() - B[j * D + i].imag()));
+        // constant part of the cluster: subtract params[p] * dterm
+        const int64_t ho = h_hoff[cb_of[g]][pos_in_cb[g]];
+        const int nco = comps_of(D, P->cplx);
+        for (int k = 0; k < nco; ++k) hfix_pack[ho + k] -= d->params[pidx] * dterm_pack[doff + k];
+        pts.push_back({g, pidx, t, doff});
+      }
     }
     // clusters -> terms
     std::vector<PT> byc = pts;

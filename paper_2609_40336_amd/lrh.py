@@ -21,6 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblrh.so")
 
 LRH_SUBINTERVALS = 0x1
+LRH_TWO_LEVEL = 0x2
 LRH_F32 = 0x1
 LRH_FUSED = 0x2
 LRH_PACKED_COTANGENT = 0x4
@@ -172,7 +173,8 @@ def lrh_build_clusters(desc, hip_device: int = 0):
     d.top_ptr = _ptr(keep["top_ptr"], C.c_int64)
     d.top_sites = _ptr(keep["top_sites"], C.c_int32)
     d.site_instance = _ptr(keep["site_instance"], C.c_int32)
-    d.flags = LRH_SUBINTERVALS if desc.subintervals else 0
+    d.flags = ((LRH_SUBINTERVALS if desc.subintervals else 0)
+               | (LRH_TWO_LEVEL if getattr(desc, "two_level", False) else 0))
     d.n_params = npar
     if npar:
         d.term_param = _ptr(keep["term_param"], C.c_int32)

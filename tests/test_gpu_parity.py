@@ -57,6 +57,10 @@ def k5_complete():
     return W.with_tops(W.heisenberg_graph(5, pairs, 0.7, field_x=0.3), [tuple(range(5))])
 
 
+def two_level(d):
+    return W.with_tops(d, list(d.tops()), two_level=True)
+
+
 PROBLEMS = {
     "c1_tfim16_complex": lambda: W.workload_c1(),
     "heis_square4": lambda: W.heisenberg_square(4),
@@ -74,6 +78,12 @@ PROBLEMS = {
                                              [tuple(range(i, i + 7)) for i in range(3)], subintervals=True),
     "k5_complete": lambda: k5_complete(),
     "tfim_rect2x3": lambda: W.tfim_rect_plaquettes(4, 1.1),
+    # two-level family: windows and the overlaps of consecutive windows only, terms split
+    "randchain_T3_two_level": lambda: W.random_chain(8, seed=1, top_len=3, two_level=True),
+    "gue_T5_two_level": lambda: W.interval_chain_gue(10, 5, 0.1, seed=3, two_level=True),
+    "gue_T8_two_level": lambda: W.interval_chain_gue(10, 8, 0.1, seed=3, two_level=True),
+    "plaq_two_level": lambda: two_level(W.tfim_plaquette_batch([3, 4, 5], [0.7, 2.0, 3.5])),
+    "tree_two_level": lambda: two_level(W.classical_ising_tree(9, 4, rotate=True)),
 }
 
 
@@ -102,7 +112,8 @@ def test_dual_eval_fp64(name, beta):
     assert P.check() == (0, 0)
 
 
-@pytest.mark.parametrize("name", ["c1_tfim16_complex", "randchain_Y4", "plaq_batch_ragged", "gue_Y5", "gue_Y8"])
+@pytest.mark.parametrize("name", ["c1_tfim16_complex", "randchain_Y4", "plaq_batch_ragged", "gue_Y5", "gue_Y8",
+                                  "gue_T8_two_level", "plaq_two_level"])
 def test_dual_eval_fp32(name):
     """FP32 iteration arithmetic: values within 2e-5 per site, gradients within 5e-5."""
     lrh = lrhmod()
@@ -122,7 +133,8 @@ def test_dual_eval_fp32(name):
 
 
 @pytest.mark.parametrize("name", ["c1_tfim16_complex", "randchain_Y6", "plaq_batch_ragged", "xxz_tri3", "gue_Y7",
-                                  "gue_Y8", "randchain_Y7_real", "k5_complete", "tfim_rect2x3"])
+                                  "gue_Y8", "randchain_Y7_real", "k5_complete", "tfim_rect2x3", "gue_T5_two_level",
+                                  "gue_T8_two_level", "plaq_two_level"])
 def test_certify_fp64_and_from_fp32(name):
     lrh = lrhmod()
     say(f"[certify] {name}")
@@ -210,6 +222,8 @@ NEST = {
     "plaq_batch": (lambda: W.tfim_plaquette_batch([3, 4], [1.0, 2.5]), [(2.0, 40)]),
     "xxz_tri3": (lambda: W.xxz_triangular(3, 0.5, seed=2), [(4.0, 40)]),
     "gue_Y8": (lambda: W.interval_chain_gue(9, 8, 0.1, seed=3), [(2.0, 6), (8.0, 6)]),
+    "gue_T6_two_level": (lambda: W.interval_chain_gue(10, 6, 0.1, seed=3, two_level=True), [(2.0, 12), (8.0, 12)]),
+    "tree_two_level": (lambda: two_level(W.classical_ising_tree(9, 4, rotate=True)), [(4.0, 40)]),
 }
 
 
@@ -235,14 +249,16 @@ def test_nesterov_plain_fp64(name):
 
 
 @pytest.mark.parametrize("f32", [False, True])
-@pytest.mark.parametrize("name", ["heis_field", "tfim_complex"])
+@pytest.mark.parametrize("name", ["heis_field", "tfim_complex", "tfim_two_level"])
 def test_fused_equals_plain_bitwise(name, f32):
     """The fused single-launch iteration (graph-replayed) performs the same arithmetic as the
-    plain two-kernel iteration: identical bits, across graph chunks and a remainder."""
+    plain two-kernel iteration: identical bits, across graph chunks and a remainder.  The
+    two-level chain has no end-site clusters, so its end edges have one child only."""
     lrh = lrhmod()
     say(f"[fused==plain] {name} f32={f32}")
     d = (W.heisenberg_chain(12, field_x=0.5) if name == "heis_field"
-         else W.tfim_chain(10, 1.0, 0.9, complex_storage=True))
+         else W.tfim_chain(10, 1.0, 0.9, complex_storage=True) if name == "tfim_complex"
+         else two_level(W.tfim_chain(10, 1.0, 0.9, complex_storage=True)))
     P = lrh.Problem(d, 0)
     res = []
     for fused in (False, True):
@@ -451,6 +467,8 @@ EXPM_PROBLEMS = {
     "k5_complete_real": (lambda: k5_complete(), [32]),
     # 2 x 3 plaquettes of a periodic 4 x 4 TFIM lattice: 64-dimensional real clusters
     "tfim_rect2x3_real": (lambda: W.tfim_rect_plaquettes(4, 1.1), [64]),
+    # two-level windows of 6 sites: 64-dimensional windows over 32-dimensional overlaps
+    "gue_T6_two_level": (lambda: W.interval_chain_gue(10, 6, 0.1, seed=3, two_level=True), [32, 64]),
 }
 
 

@@ -27,6 +27,10 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(lrh.EXPORTS)
 
 
+def _two_level(d):
+    return W.with_tops(d, list(d.tops()), two_level=True)
+
+
 PROBLEMS = [
     lambda: W.workload_c1(),
     lambda: W.heisenberg_square(4),
@@ -36,6 +40,10 @@ PROBLEMS = [
     lambda: W.xxz_triangular(4, 0.5, seed=5),
     lambda: W.classical_ising_tree(9, 3),
     lambda: W.interval_chain_gue(12, 5, 0.1, seed=3),
+    lambda: W.interval_chain_gue(12, 5, 0.1, seed=3, two_level=True),
+    lambda: W.random_chain(9, seed=1, top_len=2, two_level=True),
+    lambda: _two_level(W.classical_ising_tree(9, 3)),
+    lambda: _two_level(W.tfim_plaquette_batch([3, 5, 4], [0.5, 1.0, 3.0])),
 ]
 
 
@@ -99,6 +107,15 @@ def test_validation_errors():
     uns.top_sites = uns.top_sites.copy()
     uns.top_sites[0], uns.top_sites[1] = uns.top_sites[1], uns.top_sites[0]
     _expect(1, lambda: lrh.Problem(uns, -1))
+    # two-level family: with the interval closure, and with a term outside every top
+    both = W.random_chain(6, seed=1, top_len=3, two_level=True)
+    both.subintervals = True
+    _expect(1, lambda: lrh.Problem(both, -1))
+    orphan = W.with_tops(W.tfim_chain(5, 1.0, 0.5), [(0, 1, 2), (1, 2, 3)], two_level=True)
+    _expect(1, lambda: lrh.Problem(orphan, -1))
+    # 2 x 3 plaquettes on the 4 x 4 torus overlap in 3 and in 4 sites: children of one cluster
+    # with different dimensions are not supported
+    _expect(2, lambda: lrh.Problem(_two_level(W.tfim_rect_plaquettes(4, 1.0)), -1))
     # compute on a host-only problem
     P = lrh.Problem(good, -1)
     _expect(1, lambda: lrh._check(lrh.load().lrh_certify(P.h, 8, 0, 8, 8, None, None)))
