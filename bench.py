@@ -332,6 +332,14 @@ def bench_rate(workload, args, torch):
         name = f"interval_chain_gue_n4096_eps0.1_Y{k}_nesterov_fp32"
         sample_txt = f"the same interval hierarchy Y{k} on a 24-site chain"
         ips = 10 if k >= 8 else 50
+    elif workload.startswith("c3t"):
+        k = int(workload[3:])
+        desc = W.workload_c3(k, two_level=True)
+        reference = k <= 5
+        sample = W.interval_chain_gue(24, k, 0.1, seed=3, two_level=True)
+        name = f"interval_chain_gue_n4096_eps0.1_two_level_windows{k}_nesterov_fp32"
+        sample_txt = f"the same two-level family (windows of {k} and their overlaps) on a 24-site chain"
+        ips = 10 if k >= 8 else 50
     else:
         raise SystemExit(f"unknown workload {workload}")
     if args.iters_per_stage:
@@ -378,9 +386,12 @@ def bench_rate(workload, args, torch):
     bound_plain = bounds_plain[-1]
     print(f"[bench] plain fp64: {sec_plain:.3f} s for {iters} iterations", file=sys.stderr, flush=True)
     tte = time_to_gap(P, desc, n_sites, torch) if (reference and args.time_to_gap) else None
+    children = {c for (_, c) in P.message_keys()}
+    n_top = sum(1 for c in P.clusters if c not in children)
     extra = {
         "ms_per_step": sec / len(sched) * 1e3, "dtype": "f32 iterations, f64 certify",
         "us_per_iteration": sec / iters * 1e6,
+        "top_cluster_updates_per_s": n_top * iters / sec,
         "schedule": f"beta = 2^s, s = 0..10, {ips} iterations per stage, FP64 certify after each stage",
         "ms_per_iteration_by_stage": [round(x, 4) for x in stage_ms],
         "mean_certified_bound_per_site": float(np.mean(bound / n_sites)),
@@ -695,15 +706,16 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--workload", default="c2",
                     help="c2 (default: the 32x32 Heisenberg solve), c1 (TFIM chain, Algorithm 1), c3k<k> "
-                         "(interval hierarchy Y_k on the n = 4096 GUE chain), c4 (512 plaquette lattices), "
+                         "(interval hierarchy Y_k on the n = 4096 GUE chain), c3t<k> (the same chain with the "
+                         "two-level family: windows of k sites and their overlaps), c4 (512 plaquette lattices), "
                          "c5 (64x64 XXZ value and coupling gradient), ex3 (iterations-to-eps experiment), "
                          "ex2 (optimal message norm vs chain length)")
     ap.add_argument("--time-to-gap", action="store_true",
-                    help="c3k2..c3k5, c4: also measure the time to a 1e-4 certified gap per site")
+                    help="c3k2..c3k5, c3t2..c3t5, c4: also measure the time to a 1e-4 certified gap per site")
     ap.add_argument("--ex3-max-iters", type=float, default=4e5,
                     help="ex3: iteration cap of Algorithm 1 (Algorithm 2: a quarter of it)")
     ap.add_argument("--iters-per-stage", type=int, default=0,
-                    help="c3k<k>, c4: iterations per beta stage (default 50; 10 for k = 8)")
+                    help="c3k<k>, c3t<k>, c4: iterations per beta stage (default 50; 10 for k = 8)")
     ap.add_argument("--profile-traffic", action="store_true",
                     help="short run for hardware counters: 4 fused graph chunks, then a 64 MiB "
                          "device copy (a plain copy kernel of known size, for calibration)")

@@ -946,6 +946,20 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
   return s;
 }
 template <typename T>
+__device__ __forceinline__ T block_max(T v, T* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  T s = red[0];
+  const int nw = blockDim.x / 64;
+  for (int i = 1; i < nw; ++i) s = fmax(s, red[i]);
+  __syncthreads();
+  return s;
+}
+template <typename T>
 __device__ __forceinline__ T block_min(T v, T* red) {
   v = wave_min(v);
   const int w = threadIdx.x / 64, l = threadIdx.x % 64;
@@ -1266,13 +1280,16 @@ __global__ __launch_bounds__(1024) void k_cluster_big(ClusterArgs<T> A, T* scrat
 //
 // The smoothed dual needs rho_e = exp(-beta theta_e) / Z and F_beta = -(1/beta) log Z only
 // (Sec. 4.1.2); the eigenvectors are not needed for that.  With mu = Tr(theta)/D and
-// X = beta (theta - mu), the scaling s is the least s >= 0 with ||X||_F / 2^s <= 1/2, and
+// X = beta (theta - mu), the scaling s is the least s >= 0 with ||X|| / 2^s <= 1/2, where
+// ||X|| = min(||X||_F, ||X||_1) (both norms are submultiplicative, so the Taylor remainder
+// bound holds in either; the induced 1-norm, the largest absolute row sum, is the tight one
+// for lifted local terms 1 (x) h, whose Frobenius norm carries a factor sqrt(D / D_h)), and
 //     E0 = T12(-X / 2^s)                (degree-12 Taylor polynomial, Paterson-Stockmeyer, p = 3)
 //     Y0 = E0 / Tr E0,  Y_j = Y_{j-1}^2 / tau_j    (j = 1..s)
 //     rho = Y_s / Tr Y_s,  log Z = 2^s log Tr E0 + sum_j 2^(s-j) log tau_j + log Tr Y_s
 // for any positive rescalings tau_j of the squarings (here exact powers of two).
-// The truncation error of T12 at norm 1/2 is below 2e-14 relative, i.e. a backward error of
-// about 7e-14 ||X|| in X, which exact squaring preserves.  Rounding in the squarings adds a
+// The truncation error of T12 at norm 1/2 is below 2e-14 relative (in the norm that set s),
+// i.e. a backward error of about 7e-14 ||X|| in X, which exact squaring preserves.  Rounding in the squarings adds a
 // relative error of order D u (spectral spread / gap) to rho: the part along the dominant
 // eigenvector is removed by the final trace normalisation, the rest is damped once the
 // spectrum separates.  All of it runs in FP64 on v_mfma_f64_16x16x4_f64 whatever the message
@@ -1518,7 +1535,26 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
         n2 = fma(v, v, n2);
         if constexpr (CPLX) n2 = fma(X.im[I][J][r], X.im[I][J][r], n2);
       }
-  const double nrm = beta * sqrt(wave_sum(n2));
+  // induced 1-norm: row (16 I + 4 r + l/16) is spread over the blocks J and the 16 lanes that
+  // share l/16; the butterfly leaves every lane of a group with the same sum
+  double rmax = 0.0;
+#pragma unroll
+  for (int I = 0; I < NB; ++I)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double a = 0.0;
+#pragma unroll
+      for (int J = 0; J < NB; ++J) {
+        if constexpr (CPLX) a += sqrt(fma(X.re[I][J][r], X.re[I][J][r], X.im[I][J][r] * X.im[I][J][r]));
+        else a += fabs(X.re[I][J][r]);
+      }
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) a += __shfl_xor(a, o, 64);
+      rmax = fmax(rmax, a);
+    }
+  rmax = fmax(rmax, __shfl_xor(rmax, 16, 64));
+  rmax = fmax(rmax, __shfl_xor(rmax, 32, 64));
+  const double nrm = beta * fmin(sqrt(wave_sum(n2)), rmax);
   int s = 0;
   while (s < 200 && nrm > ldexp(0.5, s)) ++s;
   s = __builtin_amdgcn_readfirstlane(s);   // every lane holds the same value; make it scalar
@@ -1844,7 +1880,18 @@ __global__ __launch_bounds__(256) void k_cluster_expm_wg(ClusterArgs<T> A, doubl
       n2 = fma(v, v, n2);
       if constexpr (CPLX) n2 = fma(Xi[idx], Xi[idx], n2);
     }
-    const double nrm = beta * sqrt(block_sum(n2, red));
+    double rmax = 0.0;   // induced 1-norm: one row per thread
+    for (int i = tid; i < DE; i += nth) {
+      const double* xr = Xr + (int64_t)i * DE;
+      double a = 0.0;
+      for (int j = 0; j < DE; ++j) {
+        const double v = xr[j] - (i == j ? mu : 0.0);
+        if constexpr (CPLX) a += sqrt(fma(v, v, Xi[(int64_t)i * DE + j] * Xi[(int64_t)i * DE + j]));
+        else a += fabs(v);
+      }
+      rmax = fmax(rmax, a);
+    }
+    const double nrm = beta * fmin(sqrt(block_sum(n2, red)), block_max(rmax, red));
     int s = 0;
     while (s < 200 && nrm > ldexp(0.5, s)) ++s;   // block-uniform
     const double sc = -ldexp(beta, -s);
