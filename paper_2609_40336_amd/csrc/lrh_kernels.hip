@@ -34,14 +34,28 @@ namespace lrh {
 // small helpers
 // ------------------------------------------------------------------------------------------
 
+// FP32 iterations use the single hardware instructions (v_sqrt_f32, v_rsq_f32, v_rcp_f32,
+// v_exp_f32, v_log_f32; about 1 ulp), far inside the FP32 tolerances and much shorter than the
+// correctly rounded sequences on the serial chain of a one-lane-per-cluster kernel.  FP64 keeps
+// IEEE division, square root and the libm exponential and logarithm.
 template <typename T> __device__ __forceinline__ T dsqrt(T x);
-template <> __device__ __forceinline__ float dsqrt<float>(float x) { return sqrtf(x); }
+template <> __device__ __forceinline__ float dsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 template <> __device__ __forceinline__ double dsqrt<double>(double x) { return sqrt(x); }
+template <typename T> __device__ __forceinline__ T drsq(T x);   // 1 / sqrt(x)
+template <> __device__ __forceinline__ float drsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <> __device__ __forceinline__ double drsq<double>(double x) { return 1.0 / sqrt(x); }
+template <typename T> __device__ __forceinline__ T ddiv(T a, T b);   // a / b
+template <> __device__ __forceinline__ float ddiv<float>(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+template <> __device__ __forceinline__ double ddiv<double>(double a, double b) { return a / b; }
 template <typename T> __device__ __forceinline__ T dexp(T x);
-template <> __device__ __forceinline__ float dexp<float>(float x) { return expf(x); }
+template <> __device__ __forceinline__ float dexp<float>(float x) {
+  return __builtin_amdgcn_exp2f(x * 1.44269504088896341f);
+}
 template <> __device__ __forceinline__ double dexp<double>(double x) { return exp(x); }
 template <typename T> __device__ __forceinline__ T dlog(T x);
-template <> __device__ __forceinline__ float dlog<float>(float x) { return logf(x); }
+template <> __device__ __forceinline__ float dlog<float>(float x) {
+  return __builtin_amdgcn_logf(x) * 0.693147180559945309f;
+}
 template <> __device__ __forceinline__ double dlog<double>(double x) { return log(x); }
 template <typename T> __device__ __forceinline__ T dfma(T a, T b, T c);
 template <> __device__ __forceinline__ float dfma<float>(float a, float b, float c) { return fmaf(a, b, c); }
@@ -58,10 +72,10 @@ __device__ __forceinline__ T extrap(T x, T y, T th) {
 // tau = (a_qq - a_pp) / (2 r), t = sign(tau) / (|tau| + sqrt(tau^2 + 1)), c = 1/sqrt(1+t^2).
 template <typename T>
 __device__ __forceinline__ void rot_params(T app, T aqq, T r, T& t, T& c, T& s) {
-  T tau = (aqq - app) / (T(2) * r);
+  T tau = ddiv<T>(aqq - app, T(2) * r);
   T at = fabs(tau);
-  t = (tau >= T(0) ? T(1) : T(-1)) / (at + dsqrt<T>(dfma<T>(tau, tau, T(1))));
-  c = T(1) / dsqrt<T>(dfma<T>(t, t, T(1)));
+  t = ddiv<T>(tau >= T(0) ? T(1) : T(-1), at + dsqrt<T>(dfma<T>(tau, tau, T(1))));
+  c = drsq<T>(dfma<T>(t, t, T(1)));
   s = t * c;
 }
 
@@ -232,7 +246,14 @@ __device__ __forceinline__ void jacobi_sweep_reg(HMat<T, CPLX, D>& A, T (&ur)[D]
       const bool nz = (r != T(0));
       const T rs = nz ? r : T(1);
       // e^{-i phi} with a_pq = r e^{i phi}; real case: sign(a_pq)
-      const T er = nz ? xr / rs : T(1), ei = (CPLX && nz) ? -xi / rs : T(0);
+      T er, ei;
+      if constexpr (CPLX) {
+        er = nz ? ddiv<T>(xr, rs) : T(1);
+        ei = nz ? ddiv<T>(-xi, rs) : T(0);
+      } else {
+        er = nz ? copysign(T(1), xr) : T(1);
+        ei = T(0);
+      }
       const T app = A.re(p, p), aqq = A.re(q, q);
       T t, c, s;
       rot_params<T>(app, aqq, rs, t, c, s);
@@ -423,16 +444,16 @@ __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
       T Z = T(0);
 #pragma unroll
       for (int k = 0; k < DE; ++k) { p[k] = dexp<T>(-b * (lam[k] - lmin)); Z += p[k]; }
-      const T iZ = T(1) / Z;
+      const T iZ = ddiv<T>(T(1), Z);
 #pragma unroll
       for (int k = 0; k < DE; ++k) p[k] *= iZ;
-      if (A.scal) A.scal[gid] = (double)(lmin - dlog<T>(Z) / b);
+      if (A.scal) A.scal[gid] = (double)(lmin - ddiv<T>(dlog<T>(Z), b));
     } else {
       const T tau = (T)A.tau_rel * fmax(T(1), dsqrt<T>(nrm2));
       T g = T(0);
 #pragma unroll
       for (int k = 0; k < DE; ++k) { p[k] = (lam[k] <= lmin + tau) ? T(1) : T(0); g += p[k]; }
-      const T ig = T(1) / g;
+      const T ig = ddiv<T>(T(1), g);
 #pragma unroll
       for (int k = 0; k < DE; ++k) p[k] *= ig;
       if (A.scal) A.scal[gid] = (double)lmin;
@@ -680,8 +701,8 @@ __device__ bool lds_jacobi(T* sar, T* sai, T* sur, T* sui, JacobiScratch<T, DE /
           const T app = sar[p * LD + p], aqq = sar[q * LD + q];
           if (rr != T(0)) {
             rot_params<T>(app, aqq, rr, t, cc, ss);
-            er = xr / rr;
-            ei = CPLX ? -xi / rr : T(0);
+            er = CPLX ? ddiv<T>(xr, rr) : copysign(T(1), xr);
+            ei = CPLX ? ddiv<T>(-xi, rr) : T(0);
           }
           J.p[k] = p; J.q[k] = q;
           J.c[k] = cc; J.s[k] = ss; J.er[k] = er; J.ei[k] = ei;
@@ -826,9 +847,9 @@ __device__ T lds_weights(const T* sar, T* sp, T lmin, T beta, T tau, int lt, boo
   const T Z = seg_sum<W>(w);
   __syncthreads();
   if (active)
-    for (int k = lt; k < DE; k += W) sp[k] /= Z;
+    for (int k = lt; k < DE; k += W) sp[k] = ddiv<T>(sp[k], Z);
   __syncthreads();
-  if constexpr (MODE == MODE_GIBBS) return lmin - dlog<T>(Z) / beta;
+  if constexpr (MODE == MODE_GIBBS) return lmin - ddiv<T>(dlog<T>(Z), beta);
   else return lmin;
 }
 
@@ -1176,8 +1197,8 @@ __global__ __launch_bounds__(1024) void k_cluster_big(ClusterArgs<T> A, T* scrat
           const T app = ar[(int64_t)p * D + p], aqq = ar[(int64_t)q * D + q];
           if (rr != T(0)) {
             rot_params<T>(app, aqq, rr, t, cc, ss);
-            er = xr / rr;
-            ei = CPLX ? -xi / rr : T(0);
+            er = CPLX ? ddiv<T>(xr, rr) : copysign(T(1), xr);
+            ei = CPLX ? ddiv<T>(-xi, rr) : T(0);
           }
           cs_p[tid] = p; cs_q[tid] = q;
           cs_c[tid] = cc; cs_s[tid] = ss; cs_er[tid] = er; cs_ei[tid] = ei;
@@ -1807,7 +1828,10 @@ __device__ double gmm(const double* xr, const double* xi, const double* yr, cons
           mma_step(fa[1], fb[1]);
         }
       }
-    } else {   // 32 x 32 tiles: no second buffer (it costs occupancy and time at D >= 128)
+    } else {
+      // 32 x 32 tiles: one K step at a time.  Its 32 loads in flight together hide the latency
+      // better than a ring of k-sub-step fragments loaded two or three k-sub-steps ahead (30 %
+      // slower at D = 128 and 256), and a second K-step buffer costs the second wave per SIMD.
 #pragma unroll 1
       for (int K = 0; K < NB; ++K) {
         load_step(K, fa[0], fb[0]);
