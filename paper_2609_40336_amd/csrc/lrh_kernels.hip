@@ -1323,6 +1323,31 @@ __global__ __launch_bounds__(1024) void k_cluster_big(ClusterArgs<T> A, T* scrat
 // block (K, I): both operands come straight from the registers, with no data movement.
 constexpr int kExpmLut = 8;   // children handled through the LDS index tables (more: generic path)
 
+// pext and pdep over the site bits of a one-wave cluster (at most 5 sites), for every site mask,
+// built at compile time: pext[mask][i] packs the bits of i at the mask positions;
+// pdepN[mask][(a << lnr) | x] places the bits of a at the mask positions and those of x at the
+// other N - popcount(mask) = lnr positions.
+struct SiteBitTables {
+  unsigned char pext[32][32];
+  unsigned char pdep4[16][16];
+  unsigned char pdep5[32][32];
+};
+constexpr SiteBitTables make_site_bit_tables() {
+  SiteBitTables t{};
+  for (int m = 0; m < 32; ++m)
+    for (int i = 0; i < 32; ++i) t.pext[m][i] = (unsigned char)pext_bits(i, m, 5);
+  for (int m = 0; m < 16; ++m) {
+    const int lnr = 4 - __builtin_popcount(m);
+    for (int p = 0; p < 16; ++p) t.pdep4[m][p] = (unsigned char)pdep_bits(p >> lnr, p & ((1 << lnr) - 1), m, 4);
+  }
+  for (int m = 0; m < 32; ++m) {
+    const int lnr = 5 - __builtin_popcount(m);
+    for (int p = 0; p < 32; ++p) t.pdep5[m][p] = (unsigned char)pdep_bits(p >> lnr, p & ((1 << lnr) - 1), m, 5);
+  }
+  return t;
+}
+__constant__ SiteBitTables kSiteBits = make_site_bit_tables();
+
 template <int NB, bool CPLX>
 struct XMat {
   double re[NB][NB][4];
@@ -1426,6 +1451,7 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
   const T th = A.tab ? (T)A.tab->theta_cur : (T)A.theta;
   const double beta = A.tab ? A.tab->beta : A.beta;
   constexpr int NBITS = log2i(DE);
+  static_assert(NBITS == 4 || NBITS == 5, "the one-wave kernel covers D = 16 and 32");
   const int Dc = A.Dc;
   const int nch = A.maxch;
   const bool lut = nch <= kExpmLut;   // cluster-uniform
@@ -1441,10 +1467,11 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
   const int lnr = NBITS - ldc;
   if (lut) {
     for (int s = 0; s < nch; ++s) {
-      const int mask = A.chmask[(int64_t)s * A.n + c];
+      const int mask = A.chmask[(int64_t)s * A.n + c] & (DE - 1);
       if (l < DE) {
-        pextL[s][l] = (unsigned char)pext_rt(l, mask, NBITS);
-        depL[s][l] = (unsigned char)pdep_rt(l >> lnr, l & ((1 << lnr) - 1), mask, NBITS);
+        pextL[s][l] = kSiteBits.pext[mask][l];
+        if constexpr (NBITS == 4) depL[s][l] = kSiteBits.pdep4[mask][l];
+        else depL[s][l] = kSiteBits.pdep5[mask][l];
       }
     }
     __syncthreads();
