@@ -376,10 +376,12 @@ def triangular_edges(L: int):
 
 
 def xxz_triangular(L: int = 64, Delta: float = 0.5, seed: int = 5, n_bonds: int = 32,
-                   Jlo: float = 0.8, Jhi: float = 1.2) -> ProblemDesc:
+                   Jlo: float = 0.8, Jhi: float = 1.2, two_level: bool = False) -> ProblemDesc:
     """XXZ model J_e (XX + YY + Delta ZZ) on the periodic triangular lattice with up and
     down triangles as clusters.  J_e ~ U[Jlo, Jhi] in canonical edge order; then
-    `n_bonds` distinct bonds are drawn for gradient checks (meta['bonds'])."""
+    `n_bonds` distinct bonds are drawn for gradient checks (meta['bonds']).  two_level=True:
+    the triangles and their overlaps (the bonds) only, each bond term split over its two
+    triangles."""
     if L < 3:
         raise ValueError("triangular lattice needs L >= 3")
     rng = np.random.default_rng(seed)
@@ -395,7 +397,7 @@ def xxz_triangular(L: int = 64, Delta: float = 0.5, seed: int = 5, n_bonds: int 
         for x in range(L):
             b.add_top((sid(x, y), sid(x + 1, y), sid(x + 1, y + 1)))
             b.add_top((sid(x, y), sid(x, y + 1), sid(x + 1, y + 1)))
-    return b.build(real=True, params=J,
+    return b.build(real=True, params=J, two_level=two_level,
                    meta=dict(model="xxz_triangular", L=L, Delta=Delta, seed=seed,
                              bonds=[int(x) for x in bonds]))
 

@@ -42,6 +42,10 @@ VJP_PROBLEMS = {
     "tfim16_complex": lambda: W.workload_c1(),
     "plaq_L3": lambda: W.tfim_plaquette_batch([3, 4], [0.8, 2.0]),
     "randchain_Y5_complex": lambda: W.random_chain(7, seed=4, top_len=5, subintervals=True),
+    # two-level family: triangles over their shared bonds, every bond term (and its coupling
+    # derivative) lifted into and split over its two triangles
+    "xxz_tri3_two_level": lambda: W.xxz_triangular(3, 0.5, seed=5, two_level=True),
+    "randchain_T4_complex": lambda: W.random_chain(8, seed=6, top_len=4, two_level=True),
 }
 
 
@@ -90,11 +94,11 @@ def test_set_params_moves_the_terms():
     assert q2.item() == pytest.approx(ref, abs=1e-9 * d.n_sites)
 
 
-@pytest.mark.parametrize("T", [0, 5, 16])
-def test_unrolled_bound_grad_matches_oracle(T):
+@pytest.mark.parametrize("T,two", [(0, False), (5, False), (16, False), (5, True)])
+def test_unrolled_bound_grad_matches_oracle(T, two):
     lrh = lrhmod()
-    say(f"[unrolled grad] xxz L=4 T={T}")
-    d = W.xxz_triangular(4, 0.5, seed=5)
+    say(f"[unrolled grad] xxz L=4 T={T} two_level={two}")
+    d = W.xxz_triangular(4, 0.5, seed=5, two_level=two)
     P = lrh.Problem(d, 0)
     R = O.Relaxation(d)
     beta = 4.0

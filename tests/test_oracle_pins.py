@@ -494,9 +494,9 @@ def test_unrolled_bound_gradient_zero_steps_is_hellmann_feynman():
     assert B[0] == pytest.approx(-2.5 * d.params.sum(), abs=1e-10)
 
 
-@pytest.mark.parametrize("T", [3, 8])
-def test_unrolled_bound_gradient_matches_central_differences(T):
-    d = W.xxz_triangular(3, 0.5, seed=5, n_bonds=5)
+@pytest.mark.parametrize("T,two", [(3, False), (8, False), (3, True)])
+def test_unrolled_bound_gradient_matches_central_differences(T, two):
+    d = W.xxz_triangular(3, 0.5, seed=5, n_bonds=5, two_level=two)
     R = O.Relaxation(d)
     _, cb, _ = O.unrolled_bound_grad(R, 4.0, T)
     c0 = d.params.copy()
@@ -674,3 +674,23 @@ def test_two_level_optimum_equals_the_interval_hierarchy():
     # both runs still sit 1e-4 .. 1e-3 below the common optimum (their difference falls
     # from 1.5e-3 at 3000 iterations to 5e-5 at 12000)
     assert vals[True] == pytest.approx(vals[False], abs=5e-4)
+
+
+def test_two_level_parametrised_terms_move_with_the_couplings():
+    """Coupling-parametrised terms in the two-level family: moving the couplings to c through
+    the lifted, split derivative blocks gives the split Hamiltonian whose bond terms are scaled
+    to c (checked on a random global state against a dense H built from the scaled terms)."""
+    d = W.xxz_triangular(3, 0.5, seed=5, two_level=True)
+    R = O.Relaxation(d)
+    c = d.params * np.linspace(0.6, 1.4, len(d.params))
+    b = W._Builder("xxz_scaled", d.n_sites)
+    for t in range(d.n_terms):
+        sites, m = d.term(t)
+        p = int(d.term_param[t])
+        b.add_term(sites, m * (c[p] / d.params[p]))
+    b.tops = list(d.tops())
+    H = E.dense_H(b.build(real=True, two_level=True))
+    hc = O.h_at_params(R, c)
+    rho = _random_state(9, 3)
+    tot = sum(np.trace(hc[e] @ bf_ptrace(rho, [2] * 9, R.clusters[e])).real for e in hc)
+    assert tot == pytest.approx(np.trace(H @ rho).real, abs=1e-10)
