@@ -324,6 +324,13 @@ def bench_rate(workload, args, torch):
         name = "tfim_plaquette_sweep_512_L8to64_h0.5to4_nesterov_fp32"
         sample_txt = "a 2-instance plaquette sweep drawn the same way"
         ips = 50
+    elif workload == "c4t":
+        reference = True
+        desc = W.workload_c4(two_level=True)
+        sample = W.workload_c4(n_inst=2, two_level=True)
+        name = "tfim_plaquette_sweep_512_L8to64_h0.5to4_two_level_nesterov_fp32"
+        sample_txt = "a 2-instance plaquette sweep drawn the same way, two-level family"
+        ips = 50
     elif workload.startswith("c3k"):
         k = int(workload[3:])
         desc = W.workload_c3(k)
@@ -707,7 +714,8 @@ def main():
     ap.add_argument("--workload", default="c2",
                     help="c2 (default: the 32x32 Heisenberg solve), c1 (TFIM chain, Algorithm 1), c3k<k> "
                          "(interval hierarchy Y_k on the n = 4096 GUE chain), c3t<k> (the same chain with the "
-                         "two-level family: windows of k sites and their overlaps), c4 (512 plaquette lattices), "
+                         "two-level family: windows of k sites and their overlaps), c4 (512 plaquette lattices; c4t: "
+                         "the two-level family of plaquettes and shared bonds), "
                          "c5 (64x64 XXZ value and coupling gradient), ex3 (iterations-to-eps experiment), "
                          "ex2 (optimal message norm vs chain length)")
     ap.add_argument("--time-to-gap", action="store_true",

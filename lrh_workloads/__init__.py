@@ -308,10 +308,11 @@ def interval_chain_gue(n: int, k: int, eps: float = 0.1, seed: int = 3, two_leve
 
 
 def tfim_plaquette_batch(Ls: Sequence[int], hs: Sequence[float], J: float = 1.0,
-                         name: str = "tfim_plaquette_batch") -> ProblemDesc:
+                         name: str = "tfim_plaquette_batch", two_level: bool = False) -> ProblemDesc:
     """Independent periodic L x L TFIM instances, H_b = -J sum ZZ - h_b sum X.
 
-    Cluster family per instance: every 2x2 plaquette {(x,y),(x+1,y),(x,y+1),(x+1,y+1)}.
+    Cluster family per instance: every 2x2 plaquette {(x,y),(x+1,y),(x,y+1),(x+1,y+1)} (with
+    two_level=True the plaquettes and the bonds they share only).
     Sites of instance b are numbered offset_b + x + L y.
     """
     n = int(sum(L * L for L in Ls))
@@ -333,8 +334,8 @@ def tfim_plaquette_batch(Ls: Sequence[int], hs: Sequence[float], J: float = 1.0,
                 b.add_top((sid(x, y), sid(x + 1, y), sid(x, y + 1), sid(x + 1, y + 1)))
         off += L * L
     b.n_instances = len(Ls)
-    return b.build(real=True, meta=dict(model="tfim_plaquette", Ls=list(map(int, Ls)),
-                                        hs=list(map(float, hs)), J=J))
+    return b.build(real=True, two_level=two_level,
+                   meta=dict(model="tfim_plaquette", Ls=list(map(int, Ls)), hs=list(map(float, hs)), J=J))
 
 
 def tfim_rect_plaquettes(L: int, h: float, w: int = 2, hgt: int = 3, J: float = 1.0) -> ProblemDesc:
@@ -354,12 +355,13 @@ def tfim_rect_plaquettes(L: int, h: float, w: int = 2, hgt: int = 3, J: float = 
     return b.build(real=True, meta=dict(model="tfim_rect", L=L, h=h, w=w, hgt=hgt))
 
 
-def tfim_plaquette_sweep(n_inst: int = 512, seed: int = 4, Lmin: int = 8, Lmax: int = 64):
+def tfim_plaquette_sweep(n_inst: int = 512, seed: int = 4, Lmin: int = 8, Lmax: int = 64,
+                         two_level: bool = False):
     """The batched sweep: L ~ U{Lmin..Lmax}, h ~ U[0.5, 4], drawn in that order."""
     rng = np.random.default_rng(seed)
     Ls = rng.integers(Lmin, Lmax + 1, n_inst)
     hs = rng.uniform(0.5, 4.0, n_inst)
-    return tfim_plaquette_batch(Ls, hs, name=f"tfim_plaquette_sweep_{n_inst}_s{seed}")
+    return tfim_plaquette_batch(Ls, hs, name=f"tfim_plaquette_sweep_{n_inst}_s{seed}", two_level=two_level)
 
 
 def triangular_edges(L: int):
@@ -521,8 +523,9 @@ def workload_c3(k: int, n: int = 4096, eps: float = 0.1, seed: int = 3, two_leve
     return interval_chain_gue(n, k, eps, seed, two_level=two_level)
 
 
-def workload_c4(n_inst: int = 512, seed: int = 4, Lmin: int = 8, Lmax: int = 64) -> ProblemDesc:
-    return tfim_plaquette_sweep(n_inst, seed, Lmin, Lmax)
+def workload_c4(n_inst: int = 512, seed: int = 4, Lmin: int = 8, Lmax: int = 64,
+                two_level: bool = False) -> ProblemDesc:
+    return tfim_plaquette_sweep(n_inst, seed, Lmin, Lmax, two_level=two_level)
 
 
 def workload_c5(L: int = 64, seed: int = 5) -> ProblemDesc:

@@ -2641,8 +2641,9 @@ constexpr bool reg_ok() {
 // Scaling-and-squaring Gibbs kernel (shape code W = 0): dimensions and fields compiled.
 static bool expm_ok(int De, bool cplx) { return De == 16 || De == 32 || De == 64 || De == 128 || De == 256; }
 
+// (childless 4 x 4 and 8 x 8 clusters are the overlaps of the two-level family)
 static bool reg_pair(int De, int Dc) {
-  return (De == 2 && Dc == 0) || (De == 4 && Dc == 2) || (De == 8 && (Dc == 4 || Dc == 2));
+  return (De == 2 && Dc == 0) || (De == 4 && (Dc == 2 || Dc == 0)) || (De == 8 && (Dc == 4 || Dc == 2 || Dc == 0));
 }
 
 int cluster_shapes(int De, int Dc, bool dbl, bool cplx, int mode, int* out) {
@@ -2749,12 +2750,15 @@ static hipError_t launch_cluster_m(const ClusterArgs<T>& a, int block, int W, hi
   if (W == 1 && a.De >= 8) {
     if (a.De == 8 && a.Dc == 4) return launch_reg<T, CPLX, MODE, 8, 4>(a, block, s);
     if (a.De == 8 && a.Dc == 2) return launch_reg<T, CPLX, MODE, 8, 2>(a, block, s);
+    if (a.De == 8 && a.Dc == 0) return launch_reg<T, CPLX, MODE, 8, 0>(a, block, s);
     return hipErrorInvalidValue;
   }
   if (a.De == 2 && a.Dc == 0) {
     hipLaunchKernelGGL((k_cluster_reg<T, CPLX, 2, 0, MODE>), dim3(grid_for(a.n, block)), dim3(block), 0, s, a);
   } else if (a.De == 4 && a.Dc == 2) {
     hipLaunchKernelGGL((k_cluster_reg<T, CPLX, 4, 2, MODE>), dim3(grid_for(a.n, block)), dim3(block), 0, s, a);
+  } else if (a.De == 4 && a.Dc == 0 && W == 1) {
+    hipLaunchKernelGGL((k_cluster_reg<T, CPLX, 4, 0, MODE>), dim3(grid_for(a.n, block)), dim3(block), 0, s, a);
   } else if (a.fp != nullptr) {
     return hipErrorInvalidValue;  // fused update only in the register kernel
   } else if (a.De == 4 && W == 64) {

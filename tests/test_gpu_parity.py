@@ -84,6 +84,10 @@ PROBLEMS = {
     "gue_T8_two_level": lambda: W.interval_chain_gue(10, 8, 0.1, seed=3, two_level=True),
     "plaq_two_level": lambda: two_level(W.tfim_plaquette_batch([3, 4, 5], [0.7, 2.0, 3.5])),
     "tree_two_level": lambda: two_level(W.classical_ising_tree(9, 4, rotate=True)),
+    # windows of 4: childless 8 x 8 overlaps (real and complex)
+    "heis_T4_two_level": lambda: W.with_tops(W.heisenberg_chain(10, field_x=0.4),
+                                             [tuple(range(i, i + 4)) for i in range(7)], two_level=True),
+    "randchain_T4_two_level": lambda: W.random_chain(8, seed=2, top_len=4, two_level=True),
 }
 
 
@@ -449,6 +453,39 @@ def test_triangle_clusters_every_shape(shape):
     q_o, g_o = R.grad_beta(R.from_pairs(P.to_dense(nu32)), 2.0)
     assert abs(q32.item() - q_o[0]) <= 2e-5 * d.n_sites
     assert max_pair_err(P.to_dense(g32), R.to_pairs(g_o)) < 5e-5
+
+
+@pytest.mark.parametrize("case", ["D4_register", "D8_register", "D8_lds16", "D8_lds8", "D8_lds64"])
+def test_childless_overlaps_every_shape(case):
+    """Childless clusters (the overlaps of the two-level family: 4 x 4 for windows of 3 sites,
+    8 x 8 for windows of 4) through every launch shape, real, against the oracle."""
+    lrh = lrhmod()
+    say(f"[shapes] childless {case}")
+    De = 4 if case.startswith("D4") else 8
+    k = 3 if De == 4 else 4
+    d = W.with_tops(W.heisenberg_chain(10, field_x=0.4), [tuple(range(i, i + k)) for i in range(11 - k)],
+                    two_level=True)
+    P = lrh.Problem(d, 0)
+    R = O.Relaxation(d)
+    Wsel = {"register": 1, "lds16": 16, "lds8": 8, "lds64": 64}[case.split("_")[1]]
+    P.force_shape(De, Wsel)
+    nu_o = R.draw(33, 0.4)
+    for beta in (0.0, 2.0):
+        q, g, m = P.dual_eval(P.from_dense(R.to_pairs(nu_o)), beta, grad=True, marg=True)
+        torch.cuda.synchronize()
+        q_o, g_o = (R.grad_beta(nu_o, beta) if beta > 0 else R.subgrad(nu_o))
+        assert abs(q.item() - q_o[0]) <= 1e-9 * d.n_sites
+        assert max_pair_err(P.to_dense(g), R.to_pairs(g_o)) < 1e-10
+    nu32 = P.from_dense(R.to_pairs(nu_o), f32=True)
+    q32, g32, _ = P.dual_eval(nu32, 2.0, grad=True)
+    torch.cuda.synchronize()
+    q_o, g_o = R.grad_beta(R.from_pairs(P.to_dense(nu32)), 2.0)
+    assert abs(q32.item() - q_o[0]) <= 2e-5 * d.n_sites
+    assert max_pair_err(P.to_dense(g32), R.to_pairs(g_o)) < 5e-5
+    q, mg, lm = P.certify(P.from_dense(R.to_pairs(nu_o)), lmin=True)
+    torch.cuda.synchronize()
+    q_o, _ = R.certify(nu_o)
+    assert abs(q.item() - q_o[0]) <= 1e-9 * d.n_sites
 
 
 EXPM_PROBLEMS = {
