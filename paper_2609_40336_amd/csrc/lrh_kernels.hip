@@ -2010,6 +2010,7 @@ template <bool CPLX, int DE>
 __global__ __launch_bounds__(256) void k_cluster_tridiag(ClusterArgs<double> A, double* scratch, int64_t slab) {
   constexpr int64_t DD = (int64_t)DE * DE;
   __shared__ double vr[DE], vi[DE], pr[DE], pi[DE];
+  __shared__ double qvr[DE], qvi[DE], qwr[DE], qwi[DE];
   __shared__ double dg[DE], e2[DE];
   __shared__ double red[8];
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -2019,48 +2020,85 @@ __global__ __launch_bounds__(256) void k_cluster_tridiag(ClusterArgs<double> A, 
     const double my_n2 = big_assemble<double, double, CPLX, false>(A, c, DE, ar, ai, (double*)nullptr,
                                                                     (double*)nullptr, 0.0, tid, nth);
     const double nrm2 = block_sum(my_n2, red);
+    // The rank-2 update of each reflection is applied during the next reflection's sweep over
+    // the trailing matrix (pending vectors qv, qw): every trailing element is read and written
+    // once per reflection instead of read twice and written once.  Row k and the final 2 x 2
+    // block are corrected on the fly.
+    for (int i = tid; i < DE; i += nth) {
+      qvr[i] = 0.0;
+      qvi[i] = 0.0;
+      qwr[i] = 0.0;
+      qwi[i] = 0.0;
+    }
+    __syncthreads();
+    // pending correction of element (r, cc): v_r conj(w_cc) + w_r conj(v_cc)
+    auto pend = [&](int r, int cc, double& ur, double& ui) {
+      ur = fma(qvr[r], qwr[cc], fma(qvi[r], qwi[cc], fma(qwr[r], qvr[cc], qwi[r] * qvi[cc])));
+      ui = fma(qvi[r], qwr[cc], fma(-qvr[r], qwi[cc], fma(qwi[r], qvr[cc], -qwr[r] * qvi[cc])));
+    };
     for (int k = 0; k < DE - 2; ++k) {
       const int m = DE - k - 1;
       const int64_t rk = (int64_t)k * DE + k + 1;   // x_i = A[k+1+i][k] = conj(A[k][k+1+i])
       double xs = 0.0;
       for (int i = tid; i < m; i += nth) {
-        const double xr = ar[rk + i];
+        double ur, ui;
+        pend(k, k + 1 + i, ur, ui);
+        const double xr = ar[rk + i] - ur;
+        const double xim = CPLX ? ai[rk + i] - ui : 0.0;
+        vr[i] = xr;     // x, turned into v below
+        vi[i] = -xim;
         xs = fma(xr, xr, xs);
-        if constexpr (CPLX) xs = fma(ai[rk + i], ai[rk + i], xs);
+        if constexpr (CPLX) xs = fma(xim, xim, xs);
       }
       const double xn2 = block_sum(xs, red);
       const double xn = sqrt(xn2);
-      const double x0r = ar[rk], x0i = CPLX ? -ai[rk] : 0.0;
+      const double x0r = vr[0], x0i = vi[0];
       const double a0 = sqrt(fma(x0r, x0r, x0i * x0i));
       if (tid == 0) {
-        dg[k] = ar[(int64_t)k * DE + k];
+        double ur, ui;
+        pend(k, k, ur, ui);
+        dg[k] = ar[(int64_t)k * DE + k] - ur;
         e2[k] = xn2;
       }
       const double vn2 = 2.0 * (xn2 + a0 * xn);
-      if (!(vn2 > 0.0)) continue;   // column already reduced (block-uniform)
-      const double ur = a0 > 0.0 ? x0r / a0 : 1.0, ui = a0 > 0.0 ? x0i / a0 : 0.0;
-      const double tau = 2.0 / vn2;
-      for (int i = tid; i < m; i += nth) {
-        double r = ar[rk + i], im = CPLX ? -ai[rk + i] : 0.0;
-        if (i == 0) {
-          r += ur * xn;    // v = x - alpha e1, alpha = -(x0/|x0|) ||x||
-          im += ui * xn;
+      // an already reduced column (block-uniform) reflects nothing (v = 0) but still flushes the
+      // pending update into the trailing matrix
+      const bool act = vn2 > 0.0;
+      const double ur0 = a0 > 0.0 ? x0r / a0 : 1.0, ui0 = a0 > 0.0 ? x0i / a0 : 0.0;
+      const double tau = act ? 2.0 / vn2 : 0.0;
+      __syncthreads();
+      if (act) {
+        if (tid == 0) {   // v = x - alpha e1, alpha = -(x0/|x0|) ||x||
+          vr[0] = fma(ur0, xn, x0r);
+          vi[0] = fma(ui0, xn, x0i);
         }
-        vr[i] = r;
-        vi[i] = im;
+      } else {
+        for (int i = tid; i < m; i += nth) {
+          vr[i] = 0.0;
+          vi[i] = 0.0;
+        }
       }
       __syncthreads();
-      // p = tau A22 v; A22 is Hermitian, so row i of A22 v reads column i (coalesced across i)
+      // p = tau A22 v on the updated A22, written back as it is read; A22 is Hermitian, so row i
+      // of A22 v reads column i (coalesced across i)
       for (int i = tid; i < m; i += nth) {
+        const int cc = k + 1 + i;
+        const double wcr = qwr[cc], wci = qwi[cc], vcr = qvr[cc], vci = qvi[cc];
+        double* col_r = ar + (int64_t)(k + 1) * DE + cc;
+        double* col_i = CPLX ? ai + (int64_t)(k + 1) * DE + cc : nullptr;
         double sr = 0.0, si = 0.0;
-        const double* col_r = ar + (int64_t)(k + 1) * DE + (k + 1 + i);
-        const double* col_i = CPLX ? ai + (int64_t)(k + 1) * DE + (k + 1 + i) : nullptr;
 #pragma unroll 4
         for (int j = 0; j < m; ++j) {
-          const double a_r = col_r[(int64_t)j * DE];
+          const int r = k + 1 + j;
+          const double a_r = col_r[(int64_t)j * DE] -
+                             fma(qvr[r], wcr, fma(qvi[r], wci, fma(qwr[r], vcr, qwi[r] * vci)));
+          col_r[(int64_t)j * DE] = a_r;
           sr = fma(a_r, vr[j], sr);
           if constexpr (CPLX) {
-            const double a_i = -col_i[(int64_t)j * DE];
+            const double b_i = col_i[(int64_t)j * DE] -
+                               fma(qvi[r], wcr, fma(-qvr[r], wci, fma(qwi[r], vcr, -qwr[r] * vci)));
+            col_i[(int64_t)j * DE] = b_i;
+            const double a_i = -b_i;   // Im A[cc][r]
             sr = fma(-a_i, vi[j], sr);
             si = fma(a_r, vi[j], fma(a_i, vr[j], si));
           }
@@ -2072,28 +2110,24 @@ __global__ __launch_bounds__(256) void k_cluster_tridiag(ClusterArgs<double> A, 
       double ks = 0.0;
       for (int i = tid; i < m; i += nth) ks = fma(vr[i], pr[i], fma(vi[i], pi[i], ks));
       const double K = 0.5 * tau * block_sum(ks, red);
+      // the update of this reflection, A22 -= v w^H + w v^H with w = p - K v, becomes pending
       for (int i = tid; i < m; i += nth) {
-        pr[i] = fma(-K, vr[i], pr[i]);
-        pi[i] = fma(-K, vi[i], pi[i]);
-      }
-      __syncthreads();
-      // A22 -= v w^H + w v^H
-      for (int idx = tid; idx < m * m; idx += nth) {
-        const int i = idx / m, j = idx % m;
-        const int64_t o = (int64_t)(k + 1 + i) * DE + (k + 1 + j);
-        double re = fma(vr[i], pr[j], fma(vi[i], pi[j], fma(pr[i], vr[j], pi[i] * vi[j])));
-        ar[o] -= re;
-        if constexpr (CPLX) {
-          const double im = fma(vi[i], pr[j], fma(-vr[i], pi[j], fma(pi[i], vr[j], -pr[i] * vi[j])));
-          ai[o] -= im;
-        }
+        qvr[k + 1 + i] = vr[i];
+        qvi[k + 1 + i] = vi[i];
+        qwr[k + 1 + i] = fma(-K, vr[i], pr[i]);
+        qwi[k + 1 + i] = fma(-K, vi[i], pi[i]);
       }
       __syncthreads();
     }
     if (tid == 0) {
-      dg[DE - 2] = ar[(int64_t)(DE - 2) * DE + DE - 2];
-      dg[DE - 1] = ar[(int64_t)(DE - 1) * DE + DE - 1];
-      const double xr = ar[(int64_t)(DE - 2) * DE + DE - 1], xi = CPLX ? ai[(int64_t)(DE - 2) * DE + DE - 1] : 0.0;
+      double ur, ui;
+      pend(DE - 2, DE - 2, ur, ui);
+      dg[DE - 2] = ar[(int64_t)(DE - 2) * DE + DE - 2] - ur;
+      pend(DE - 1, DE - 1, ur, ui);
+      dg[DE - 1] = ar[(int64_t)(DE - 1) * DE + DE - 1] - ur;
+      pend(DE - 2, DE - 1, ur, ui);
+      const double xr = ar[(int64_t)(DE - 2) * DE + DE - 1] - ur;
+      const double xi = CPLX ? ai[(int64_t)(DE - 2) * DE + DE - 1] - ui : 0.0;
       e2[DE - 2] = fma(xr, xr, xi * xi);
       e2[DE - 1] = 0.0;
     }
