@@ -519,6 +519,45 @@ __device__ __forceinline__ T wave_sum(T v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
+// Reductions over the 64 lanes of a wave built from DPP row operations (xor 1, xor 2, mirror
+// within 8 lanes, mirror within 16 lanes: every lane of a row of 16 ends with the same sum) and
+// four readlanes, instead of six LDS-crossbar shuffles.  Every lane of the wave must be active;
+// the result is wave-uniform.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double row_sum16(double v) {
+  v += dpp_mov<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp_mov<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_mov<0x141>(v);   // row_half_mirror
+  v += dpp_mov<0x140>(v);   // row_mirror
+  return v;
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v = row_sum16(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+__device__ __forceinline__ double wave_min_dpp(double v) {
+  v = fmin(v, dpp_mov<0xB1>(v));
+  v = fmin(v, dpp_mov<0x4E>(v));
+  v = fmin(v, dpp_mov<0x141>(v));
+  v = fmin(v, dpp_mov<0x140>(v));
+  return fmin(fmin(readlane_d(v, 0), readlane_d(v, 16)), fmin(readlane_d(v, 32), readlane_d(v, 48)));
+}
+__device__ __forceinline__ double wave_max_rows(double v) {   // v already uniform within each row
+  return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_min(T v) {
 #pragma unroll
@@ -1414,7 +1453,7 @@ __device__ __forceinline__ double xtrace(const XMat<NB, CPLX>& M, int l) {
 #pragma unroll
     for (int r = 0; r < 4; ++r)
       if (xdiag(r, l)) t += M.re[I][I][r];
-  return wave_sum(t);
+  return wave_sum_dpp(t);
 }
 
 // D = a I + b A + c A2 (+ d A3)
@@ -1584,7 +1623,7 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
         if constexpr (CPLX) n2 = fma(X.im[I][J][r], X.im[I][J][r], n2);
       }
   // induced 1-norm: row (16 I + 4 r + l/16) is spread over the blocks J and the 16 lanes that
-  // share l/16; the butterfly leaves every lane of a group with the same sum
+  // share l/16 (one DPP row), whose reduction leaves every lane of the row with the same sum
   double rmax = 0.0;
 #pragma unroll
   for (int I = 0; I < NB; ++I)
@@ -1596,13 +1635,10 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
         if constexpr (CPLX) a += sqrt(fma(X.re[I][J][r], X.re[I][J][r], X.im[I][J][r] * X.im[I][J][r]));
         else a += fabs(X.re[I][J][r]);
       }
-#pragma unroll
-      for (int o = 1; o < 16; o <<= 1) a += __shfl_xor(a, o, 64);
-      rmax = fmax(rmax, a);
+      rmax = fmax(rmax, row_sum16(a));
     }
-  rmax = fmax(rmax, __shfl_xor(rmax, 16, 64));
-  rmax = fmax(rmax, __shfl_xor(rmax, 32, 64));
-  const double nrm = beta * fmin(sqrt(wave_sum(n2)), rmax);
+  rmax = wave_max_rows(rmax);
+  const double nrm = beta * fmin(sqrt(wave_sum_dpp(n2)), rmax);
   int s = 0;
   while (s < 200 && nrm > ldexp(0.5, s)) ++s;
   s = __builtin_amdgcn_readfirstlane(s);   // every lane holds the same value; make it scalar
@@ -2187,8 +2223,8 @@ __global__ __launch_bounds__(64) void k_cluster_tridiag_w(ClusterArgs<double> A)
   const int64_t c = blockIdx.x;
   const int l = threadIdx.x;
   const int li = l % DE, lg = l / DE;
-  const double nrm2 =
-      wave_sum(lds_assemble<double, CPLX, DE, 64>(A, c, l, A.nu_c, nullptr, A.nu_p, nullptr, 0.0, true, 1.0, ar, ai));
+  const double nrm2 = wave_sum_dpp(
+      lds_assemble<double, CPLX, DE, 64>(A, c, l, A.nu_c, nullptr, A.nu_p, nullptr, 0.0, true, 1.0, ar, ai));
   __syncthreads();
   for (int k = 0; k < DE - 2; ++k) {
     const int m = DE - k - 1;
@@ -2198,7 +2234,7 @@ __global__ __launch_bounds__(64) void k_cluster_tridiag_w(ClusterArgs<double> A)
       xs = ar[rk + l] * ar[rk + l];
       if constexpr (CPLX) xs = fma(ai[rk + l], ai[rk + l], xs);
     }
-    const double xn2 = wave_sum(xs);
+    const double xn2 = wave_sum_dpp(xs);
     const double xn = sqrt(xn2);
     const double x0r = ar[rk], x0i = CPLX ? -ai[rk] : 0.0;
     const double a0 = sqrt(fma(x0r, x0r, x0i * x0i));
@@ -2242,17 +2278,20 @@ __global__ __launch_bounds__(64) void k_cluster_tridiag_w(ClusterArgs<double> A)
     sr *= tau;
     si *= tau;
     const double ks = (l < m) ? fma(vr[l], sr, vi[l] * si) : 0.0;
-    const double K = 0.5 * tau * wave_sum(ks);
+    const double K = 0.5 * tau * wave_sum_dpp(ks);
     if (l < m) {
       pr[l] = fma(-K, vr[l], sr);
       pi[l] = fma(-K, vi[l], si);
     }
     __syncthreads();
-    for (int idx = l; idx < m * m; idx += 64) {
-      const int i = idx / m, j = idx % m;
-      const int o = (k + 1 + i) * LD + (k + 1 + j);
-      ar[o] -= fma(vr[i], pr[j], fma(vi[i], pi[j], fma(pr[i], vr[j], pi[i] * vi[j])));
-      if constexpr (CPLX) ai[o] -= fma(vi[i], pr[j], fma(-vr[i], pi[j], fma(pi[i], vr[j], -pr[i] * vi[j])));
+    // A22 -= v w^H + w v^H: lane (li, lg) updates column li of rows lg, lg + G, ... (no division)
+    if (li < m) {
+#pragma unroll 4
+      for (int i = lg; i < m; i += G) {
+        const int o = (k + 1 + i) * LD + (k + 1 + li);
+        ar[o] -= fma(vr[i], pr[li], fma(vi[i], pi[li], fma(pr[i], vr[li], pi[i] * vi[li])));
+        if constexpr (CPLX) ai[o] -= fma(vi[i], pr[li], fma(-vr[i], pi[li], fma(pi[i], vr[li], -pr[i] * vi[li])));
+      }
     }
     __syncthreads();
   }
@@ -2287,7 +2326,7 @@ __global__ __launch_bounds__(64) void k_cluster_tridiag_w(ClusterArgs<double> A)
       if (fabs(q) < pivmin) q = -pivmin;
       cnt += q < 0.0;
     }
-    const int t = (int)wave_min(cnt > 0 ? (double)l : 64.0);
+    const int t = (int)wave_min_dpp(cnt > 0 ? (double)l : 64.0);
     const double nlo = t == 0 ? lo : lo + (hi - lo) * (double)t / 65.0;
     const double nhi = t == 64 ? hi : lo + (hi - lo) * (double)(t + 1) / 65.0;
     if (!(nhi - nlo < hi - lo)) break;
