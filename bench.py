@@ -119,7 +119,7 @@ def kernel_timing(P, torch, f32=True, reps=20):
 
 
 def algorithmic_work(P):
-    """Per iteration (Sec. 8(d) of the design notes): bytes B = w (6 sum_msg s_f + 2 sum_{f
+    """Algorithmic work per iteration, fixed before measuring: bytes B = w (6 sum_msg s_f + 2 sum_{f
     with parents} s_f) with s the packed size, w = 4 (FP32); flops F = 11 D^3 per real
     cluster (symmetric eigen-decomposition with vectors plus the U diag U^T rebuild)."""
     w = 4
@@ -192,10 +192,27 @@ def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
+def message_kernel_roofline(P, nu, ze, beta, torch, reps=3):
+    """HBM roofline of the accelerated message update (a6): every message component costs six
+    accesses of the state precision (read nu, zeta, T and R; write nu and zeta); the launches
+    of every message bucket are timed live with HIP events, on scratch copies of the state."""
+    nu2, ze2 = nu.clone(), ze.clone()
+    us = P.time_messages(nu2, ze2, beta, reps)
+    del nu2, ze2
+    w = 4 if nu.dtype == torch.float32 else 8
+    nbytes = sum(b["M"] * b["comps"] * 6 * w for b in P.buckets)
+    sec = sum(us) / 1e6
+    gbs = nbytes / sec / 1e9
+    return dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=gbs / HBM_PEAK_GBS,
+                kernel="k_msg (accelerated message update, one launch per message bucket)",
+                per_iteration=dict(bytes=nbytes, seconds=sec), buckets_us=[round(u, 3) for u in us])
+
+
 def dominant_kernel_roofline(P, nu, beta, f32, torch, reps=3):
     """Roofline of the slowest cluster-kernel launch of one pass at messages nu: the bucket's
-    algorithmic flops (11 D^3 real / 44 D^3 complex per cluster, Sec. 8(d) of the design
-    notes) over its launch duration timed live with HIP events on the launch stream.  The
+    algorithmic flops (11 D^3 real / 44 D^3 complex per cluster: symmetric QR with vectors plus
+    the reconstruction) over its launch duration timed live with HIP events on the launch
+    stream.  The
     scaling-and-squaring kernel (shape 0) runs in FP64 on the matrix cores, the others on the
     vector ALUs in the iteration precision."""
     us = P.time_buckets(nu, beta, reps)
@@ -388,6 +405,7 @@ def bench_rate(workload, args, torch):
     nchk, nnf = P.check()
     n_sites = np.bincount(desc.site_instance, minlength=desc.n_instances)
     roof = dominant_kernel_roofline(P, S.nu, 64.0, True, torch)
+    msg_roof = message_kernel_roofline(P, S.nu, S.ze, 64.0, torch)
     del S
     _, sec_plain, stage_plain, bounds_plain, t_at_plain = timed_schedule(False, False)
     bound_plain = bounds_plain[-1]
@@ -407,6 +425,7 @@ def bench_rate(workload, args, torch):
                        "ms_per_iteration_by_stage": [round(x, 4) for x in stage_plain],
                        "mean_certified_bound_per_site": float(np.mean(bound_plain / n_sites))},
         "shapes": shapes, "jacobi_noconv": nchk, "nonfinite": nnf, "roofline": roof,
+        "roofline_message_kernel": msg_roof,
     }
     if not args.no_cpu:
         v, n, dt = oracle_rate(sample, args.cpu_budget)

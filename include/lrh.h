@@ -297,6 +297,16 @@ lrh_status lrh_set_shape(lrh_problem p, int32_t De, int32_t block, int32_t W, ui
 lrh_status lrh_time_buckets(lrh_problem p, const void* nu, uint32_t flags, double beta, int32_t reps, double* us,
                             hipStream_t stream);
 
+/* Per-bucket timing of the accelerated message update (a6: zeta += g / (theta L), nu averaged;
+ * Algorithm 2) for roofline accounting: one Gibbs pass at beta > 0 on nu fills the workspace,
+ * then reps + 1 launches of every message bucket's update run on nu and zeta in place (device,
+ * nu_len elements each, precision of `flags`; both are overwritten, pass scratch copies), and
+ * the average duration of one launch in microseconds goes to us[b] (host array, one entry per
+ * message bucket in lrh_query order).  Overwrites the library's workspace; synchronises the
+ * stream.  Errors: LRH_E_INVALID (null pointer, reps < 1, beta <= 0), LRH_E_DEVICE. */
+lrh_status lrh_time_messages(lrh_problem p, void* nu, void* zeta, uint32_t flags, double beta, int32_t reps,
+                             double* us, hipStream_t stream);
+
 /* Jacobi sweep cap (default 30) and relative off-diagonal tolerance (0 = default:
  * 4 eps of the iteration precision). */
 lrh_status lrh_set_jacobi(lrh_problem p, int32_t max_sweeps, double rel_tol);

@@ -23,7 +23,7 @@ What is computed (paper, Sec. 4 "Distributed algorithm"):
   * Algorithm 1 (constant/variable-step subgradient ascent with best-iterate tracking)
     and Algorithm 2 (accelerated ascent on the smoothed dual).
 
-Readings where the paper is silent or inconsistent (each listed in the design notes):
+Readings where the paper is silent or inconsistent:
   * sign convention: the expanded Lagrangian of Sec. 4.1 (edge Hamiltonian gets
     -nu (x) 1, node Hamiltonian +nu, ascent nu += alpha (mu_i - Tr_j mu_ij));
   * "a sampled zero-energy eigenvector" is read as the normalised ground-space

@@ -1014,6 +1014,36 @@ MsgArgs<T> msg_args(lrh_problem_s* P, const MBucket& M) {
 }
 
 template <typename T>
+lrh_status time_messages_t(lrh_problem_s* P, T* nu, T* ze, double beta, int reps, double* us, hipStream_t s) {
+  lrh_status st = ensure_work<T>(P, false);
+  if (st != LRH_OK) return st;
+  // one Gibbs pass at the given messages fills the partial traces and marginals the update reads
+  if ((st = cluster_pass<T>(P, nu, nullptr, 0.0, MODE_GIBBS, beta, nullptr, s)) != LRH_OK) return st;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  for (size_t b = 0; b < P->mb.size(); ++b) {
+    const MBucket& M = P->mb[b];
+    MsgArgs<T> a = msg_args<T>(P, M);
+    a.nu = nu + M.offset;
+    a.ze = ze + M.offset;
+    a.theta = 1.0;
+    a.inv_thL = 1e-3;
+    HIP_TRY(launch_msg<T>(a, MSG_NESTEROV, 256, s));
+    HIP_TRY(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) HIP_TRY(launch_msg<T>(a, MSG_NESTEROV, 256, s));
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    us[b] = 1e3 * ms / reps;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return LRH_OK;
+}
+
+template <typename T>
 lrh_status dual_eval_t(lrh_problem_s* P, const T* nu, double beta, double* q, T* grad, T* marg,
                        hipStream_t s) {
   lrh_status st = ensure_work<T>(P, false);
@@ -1801,6 +1831,16 @@ lrh_status lrh_time_buckets(lrh_problem p, const void* nu, uint32_t flags, doubl
   DeviceGuard guard(p->device);
   if (flags & LRH_F32) return time_buckets_t<float>(p, (const float*)nu, beta, reps, us, stream);
   return time_buckets_t<double>(p, (const double*)nu, beta, reps, us, stream);
+}
+
+lrh_status lrh_time_messages(lrh_problem p, void* nu, void* zeta, uint32_t flags, double beta, int32_t reps,
+                             double* us, hipStream_t stream) {
+  if (!p || !nu || !zeta || !us || reps < 1) return fail(LRH_E_INVALID, "null argument or reps < 1");
+  if (p->host_only) return fail(LRH_E_INVALID, "problem was built without a device");
+  if (!(beta > 0.0) || !std::isfinite(beta)) return fail(LRH_E_INVALID, "beta must be finite and > 0");
+  DeviceGuard guard(p->device);
+  if (flags & LRH_F32) return time_messages_t<float>(p, (float*)nu, (float*)zeta, beta, reps, us, stream);
+  return time_messages_t<double>(p, (double*)nu, (double*)zeta, beta, reps, us, stream);
 }
 
 lrh_status lrh_set_jacobi(lrh_problem p, int32_t max_sweeps, double rel_tol) {

@@ -2509,10 +2509,16 @@ __global__ __launch_bounds__(64) void k_cluster_vjp(ClusterArgs<T> A) {
 // message kernel (a6), reductions, small helpers
 // ------------------------------------------------------------------------------------------
 
+constexpr int64_t kMsgChunk = 16;   // message components per thread of the update kernel
+
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_msg(MsgArgs<T> A) {
+  // x: one thread per message; y: chunks of kMsgChunk components, so that buckets of large
+  // messages (few messages, up to 65536 components each) still fill the GPU
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= A.M) return;
+  const int64_t k0 = (int64_t)blockIdx.y * kMsgChunk;
+  const int64_t k1 = k0 + kMsgChunk < A.comps ? k0 + kMsgChunk : A.comps;
   const int64_t rs = A.rslot[m];
   T th, ith;
   if (A.fp && A.fp_cur) { th = (T)A.fp->theta_cur; ith = (T)A.fp->inv_thL_cur; }
@@ -2522,7 +2528,7 @@ __global__ __launch_bounds__(256) void k_msg(MsgArgs<T> A) {
   const T alpha = (T)A.alpha;
   const T* nsrc = A.nu_src ? A.nu_src : A.nu;
   const T* zsrc = A.ze_src ? A.ze_src : A.ze;
-  for (int64_t k = 0; k < A.comps; ++k) {
+  for (int64_t k = k0; k < k1; ++k) {
     const int64_t o = k * A.M + m;
     const T g = A.R[k * A.S + rs] - A.Tm[o];
     if constexpr (MODE == MSG_GRAD) {
@@ -2883,8 +2889,10 @@ hipError_t launch_cluster(const ClusterArgs<T>& a, bool cplx, int mode, int bloc
 
 template <typename T>
 hipError_t launch_msg(const MsgArgs<T>& a, int mode, int block, hipStream_t s) {
-  if (a.M == 0) return hipSuccess;
-  const dim3 g(grid_for(a.M, block)), b(block);
+  if (a.M == 0 || a.comps == 0) return hipSuccess;
+  const int64_t chunks = (a.comps + kMsgChunk - 1) / kMsgChunk;
+  if (chunks > 65535) return hipErrorInvalidValue;
+  const dim3 g(grid_for(a.M, block), (unsigned)chunks), b(block);
   if (mode == MSG_GRAD) hipLaunchKernelGGL((k_msg<T, MSG_GRAD>), g, b, 0, s, a);
   else if (mode == MSG_SUBGRAD) hipLaunchKernelGGL((k_msg<T, MSG_SUBGRAD>), g, b, 0, s, a);
   else hipLaunchKernelGGL((k_msg<T, MSG_NESTEROV>), g, b, 0, s, a);

@@ -70,7 +70,7 @@ _lib = None
 EXPORTS = ["lrh_build_clusters", "lrh_query", "lrh_export_clusters", "lrh_export_messages",
            "lrh_dual_eval", "lrh_step_subgrad", "lrh_step_nesterov", "lrh_certify", "lrh_check",
            "lrh_set_jacobi", "lrh_destroy", "lrh_last_error", "lrh_set_params", "lrh_dual_vjp",
-           "lrh_unrolled_bound_grad", "lrh_autotune", "lrh_get_shapes", "lrh_set_shape", "lrh_time_buckets"]
+           "lrh_unrolled_bound_grad", "lrh_autotune", "lrh_get_shapes", "lrh_set_shape", "lrh_time_buckets", "lrh_time_messages"]
 
 
 def load(path: str = LIB_PATH):
@@ -97,6 +97,7 @@ def load(path: str = LIB_PATH):
         "lrh_autotune": (i32, [vp, u32, C.c_char_p, vp]),
         "lrh_set_shape": (i32, [vp, i32, i32, i32, u32]),
         "lrh_time_buckets": (i32, [vp, vp, u32, C.c_double, i32, vp, vp]),
+        "lrh_time_messages": (i32, [vp, vp, vp, u32, C.c_double, i32, vp, vp]),
         "lrh_get_shapes": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, C.POINTER(i32)]),
         "lrh_dual_vjp": (i32, [vp, vp, u32, dbl, vp, vp, vp, vp, vp]),
         "lrh_unrolled_bound_grad": (i32, [vp, vp, dbl, dbl, i32, vp, vp, vp, vp, u32, vp]),
@@ -256,6 +257,15 @@ def lrh_time_buckets(h, nu, beta: float, reps: int = 3, stream=None):
     _check(load().lrh_time_buckets(h, _dptr(nu), LRH_F32 if f32 else 0, float(beta), int(reps), us.ctypes.data,
                                    _stream(stream)))
     return [float(u) for u in us[:cnt.value]]
+
+
+def lrh_time_messages(h, nu, zeta, beta: float, n_buckets: int, reps: int = 3, stream=None):
+    import torch
+    us = np.zeros(max(n_buckets, 1), np.float64)
+    f32 = nu.dtype == torch.float32
+    _check(load().lrh_time_messages(h, _dptr(nu), _dptr(zeta), LRH_F32 if f32 else 0, float(beta), int(reps),
+                                    us.ctypes.data, _stream(stream)))
+    return [float(u) for u in us[:n_buckets]]
 
 
 def lrh_get_shapes(h):
@@ -482,6 +492,11 @@ class Problem:
     def time_buckets(self, nu, beta: float, reps: int = 3, stream=None):
         """Per-bucket cluster-kernel launch durations (us), in shapes() order."""
         return lrh_time_buckets(self.h, nu, beta, reps, stream)
+
+    def time_messages(self, nu, zeta, beta: float, reps: int = 3, stream=None):
+        """Per-message-bucket durations (us) of the accelerated message update, run in place on
+        nu and zeta (pass copies), in buckets order."""
+        return lrh_time_messages(self.h, nu, zeta, beta, len(self.buckets), reps, stream)
 
     def force_shape(self, De: int, W: int, block: int = 64, f32=None):
         for flag in ([LRH_F32, 0] if f32 is None else [LRH_F32 if f32 else 0]):

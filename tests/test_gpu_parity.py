@@ -600,3 +600,19 @@ def test_scaled_instances_reproduce_step_and_beta_choices():
         nu_o = O.nesterov(R, [(beta, 40)])
         q_o, _ = R.certify(nu_o)
         assert abs(b.cpu().numpy()[i] / beta - q_o[0]) <= 1e-9 * d.n_sites
+
+
+def test_time_messages_runs_every_bucket():
+    """The per-bucket timing of the accelerated message update runs every message bucket, in
+    both precisions, leaves the caller's state alone when given copies and raises no flag."""
+    lrh = lrhmod()
+    say("[time_messages] plaquette batch")
+    d = W.tfim_plaquette_batch([3, 4], [1.0, 2.0])
+    P = lrh.Problem(d, 0)
+    for f32 in (True, False):
+        nu, ze = P.zeros(f32), P.zeros(f32)
+        us = P.time_messages(nu.clone(), ze.clone(), 2.0, reps=2)
+        torch.cuda.synchronize()
+        assert len(us) == len(P.buckets) and all(u > 0 for u in us)
+        assert float(nu.abs().max()) == 0.0
+    assert P.check() == (0, 0)
