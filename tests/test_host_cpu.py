@@ -119,6 +119,9 @@ def test_validation_errors():
     # compute on a host-only problem
     P = lrh.Problem(good, -1)
     _expect(1, lambda: lrh._check(lrh.load().lrh_certify(P.h, 8, 0, 8, 8, None, None)))
+    _expect(1, lambda: lrh._check(lrh.load().lrh_time_messages(P.h, 8, 8, 0, 1.0, 1, 8, None)))
+    _expect(1, lambda: lrh._check(lrh.load().lrh_time_messages(P.h, 8, 8, 0, 1.0, 0, 8, None)))
+    _expect(1, lambda: lrh._check(lrh.load().lrh_time_messages(P.h, None, 8, 0, 1.0, 1, 8, None)))
 
 
 def test_batch_scaled_instances_are_scaled_copies():
