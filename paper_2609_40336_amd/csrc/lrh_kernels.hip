@@ -315,28 +315,144 @@ __device__ __forceinline__ double offdiag2(const HMat<T, CPLX, D>& A) {
 template <typename T>
 struct FusedCoef { T thp, ithp, thc; };
 
+// Read in place of an absent coefficient row or term block, so that those loads need no branch.
+// 64 doubles hold a packed complex 8 x 8 block, the largest a register kernel takes.
+static __device__ FusedParams kZeroRow;
+static __device__ double kZeroTerms[64];
+
 template <typename T, bool CPLX, int DE, int DC, int MODE>
 __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
   constexpr bool VEC = (MODE != MODE_CERTIFY);
   HMat<T, CPLX, DE> H;
-  // ---- a2: h_e ----
-  const int64_t ho = A.hoff[c];
-  if (ho >= 0) {
-    const double* h = A.h + ho;
-    unpack<T, CPLX, DE>([&](int k) { return (T)h[k]; }, H);
-  } else {
-    H.zero();
-  }
   const bool fused = (A.fp != nullptr);
-  FusedCoef<T> fc{};
-  if (fused) {
-    fc.thp = (T)A.fp->theta_prev;
-    fc.ithp = (T)A.fp->inv_thL_prev;
-    fc.thc = (T)A.fp->theta_cur;
+  // iteration coefficients: the fused row, else the stage table row, else the launch's own
+  // theta and beta (fused launches are replayed from a graph across stages)
+  const bool from_row = fused || A.tab != nullptr;
+  const FusedParams* fq = fused ? A.fp : (A.tab ? A.tab : &kZeroRow);
+  const FusedCoef<T> fc{(T)fq->theta_prev, (T)fq->inv_thL_prev, (T)fq->theta_cur};
+  const T th = from_row ? fc.thc : (T)A.theta;
+  const T beta = from_row ? (T)fq->beta : (T)A.beta;
+  // Loads are issued in two waves before any arithmetic or store: first every index (h offset,
+  // child and parent message ids, masks, marginal slots), then every value, branch-free with a
+  // valid index for an empty slot.  One cluster per lane and a cold L2 make each dependent round
+  // trip a full memory latency.  This applies to single-site children (at most log2(D_e) of
+  // them) and to the first kHoistPar parents of a 2 x 2 cluster; larger cases keep the plain
+  // per-slot loops.  The arithmetic and its order are unchanged.
+  constexpr bool HOIST_CH = (DC == 2);
+  constexpr bool HOIST_PAR = (DE == 2);
+  constexpr int MAXCH = HOIST_CH ? log2i(DE) : 1;
+  constexpr int NCC = HOIST_CH ? (CPLX ? 4 : 3) : 1;
+  constexpr int NCP = HOIST_PAR ? (CPLX ? 4 : 3) : 1;
+  constexpr int kHoistPar = 4;
+  // Source pointers are chosen per launch so that every hoisted load below is unconditional: an
+  // absent array is replaced by one that is present and the value read from it is never used,
+  // and an empty slot reads message 0 (a child or parent bucket that exists holds at least one).
+  const bool need_g = fused && !A.fused_first;  // the fused form's gradient step
+  // ---- index loads ----
+  const int64_t ho = A.hoff[c];
+  const int32_t gid = A.gid[c];
+  const int32_t rs_read = (A.rslot ? A.rslot : A.gid)[c];  // gid: a stand-in of n entries
+  const int64_t rs_self = A.rslot ? rs_read : -1;
+  int cm[MAXCH], cmask[MAXCH], crs[MAXCH];
+  if constexpr (HOIST_CH) {
+    const int32_t* rsp = fused ? A.ch_rslot : A.ch;  // the launcher requires ch_rslot when fused
+#pragma unroll
+    for (int s = 0; s < MAXCH; ++s) {
+      const int64_t so = (int64_t)(s < A.maxch ? s : 0) * A.n + c;
+      const int m = A.ch[so];
+      cm[s] = s < A.maxch ? m : -1;
+      cmask[s] = A.chmask[so];
+      crs[s] = rsp[so];
+    }
   }
-  const T th = fused ? fc.thc : (A.tab ? (T)A.tab->theta_cur : (T)A.theta);
+  int pm[kHoistPar];
+  if constexpr (HOIST_PAR) {
+    if (A.maxpar > 0) {
+#pragma unroll
+      for (int s = 0; s < kHoistPar; ++s) {
+        const int m = A.par[(int64_t)(s < A.maxpar ? s : 0) * A.n + c];
+        pm[s] = s < A.maxpar ? m : -1;
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < kHoistPar; ++s) pm[s] = -1;
+    }
+  }
+  // ---- value loads ----
+  static_assert((CPLX ? DE * DE : DE * (DE + 1) / 2) <= 64, "term block beyond kZeroTerms");
+  const double* hb = ho >= 0 ? A.h + ho : kZeroTerms;
+  unpack<T, CPLX, DE>([&](int k) { return (T)hb[k]; }, H);
+  T cn[MAXCH][NCC], cz[MAXCH][NCC], cg[MAXCH][NCC];
+  if constexpr (HOIST_CH) {
+    const T* sN = fused ? A.nu_c_prev : A.nu_c;
+    const T* sZ = fused ? A.ze_c_prev : (A.ze_c ? A.ze_c : A.nu_c);
+    const T* sR = need_g ? A.Rprev_c : sN;
+    const T* sT = need_g ? A.Tprev_c : sN;
+#pragma unroll
+    for (int s = 0; s < MAXCH; ++s) {
+      const int64_t m = cm[s] >= 0 ? cm[s] : 0;
+      const int64_t rs = crs[s] >= 0 ? crs[s] : 0;
+#pragma unroll
+      for (int k = 0; k < NCC; ++k) {
+        const int64_t o = (int64_t)k * A.Mc + m;
+        cn[s][k] = sN[o];
+        cz[s][k] = sZ[o];
+        cg[s][k] = sR[need_g ? (int64_t)k * A.Sc + rs : o] - sT[o];
+      }
+    }
+  }
+  T pn[kHoistPar][NCP], pz[kHoistPar][NCP], pg[kHoistPar][NCP];
+  if constexpr (HOIST_PAR) {
+    if (A.maxpar > 0) {
+      const T* sN = fused ? A.nu_p_prev : A.nu_p;
+      const T* sZ = fused ? A.ze_p_prev : (A.ze_p ? A.ze_p : A.nu_p);
+      const T* sR = need_g ? A.Rprev_p : sN;
+      const T* sT = need_g ? A.Tprev_p : sN;
+      const int64_t rs = rs_self >= 0 ? rs_self : 0;
+      T r[NCP];
+#pragma unroll
+      for (int k = 0; k < NCP; ++k) r[k] = sR[need_g ? (int64_t)k * A.S + rs : (int64_t)k * A.Mp];
+#pragma unroll
+      for (int s = 0; s < kHoistPar; ++s) {
+        const int64_t m = pm[s] >= 0 ? pm[s] : 0;
+#pragma unroll
+        for (int k = 0; k < NCP; ++k) {
+          const int64_t o = (int64_t)k * A.Mp + m;
+          pn[s][k] = sN[o];
+          pz[s][k] = sZ[o];
+          pg[s][k] = r[k] - sT[o];
+        }
+      }
+    }
+  }
   // ---- children: subtract lifted messages ----
-  if constexpr (DC > 0) {
+  if constexpr (HOIST_CH) {
+#pragma unroll
+    for (int s = 0; s < MAXCH; ++s) {
+      if (cm[s] < 0) continue;
+      HMat<T, CPLX, DC> X;
+      if (fused) {
+        unpack<T, CPLX, DC>([&](int k) {
+          T nu0 = cn[s][k], ze0 = cz[s][k];
+          if (!A.fused_first) {
+            ze0 = dfma<T>(cg[s][k], fc.ithp, ze0);
+            nu0 = extrap<T>(nu0, ze0, fc.thp);
+            const int64_t o = (int64_t)k * A.Mc + cm[s];
+            A.nu_c_new[o] = nu0;
+            A.ze_c_new[o] = ze0;
+          }
+          return extrap<T>(nu0, ze0, th);
+        }, X);
+      } else if (A.ze_c) {
+        unpack<T, CPLX, DC>([&](int k) { return extrap<T>(cn[s][k], cz[s][k], th); }, X);
+      } else {
+        unpack<T, CPLX, DC>([&](int k) { return cn[s][k]; }, X);
+      }
+      mask_dispatch<DE, DC>(cmask[s], [&](auto mc) __attribute__((always_inline)) {
+        lift_sub<T, CPLX, DE, DC, decltype(mc)::value>(H, X);
+      });
+    }
+  } else if constexpr (DC > 0) {
     for (int s = 0; s < A.maxch; ++s) {
       const int m = A.ch[(int64_t)s * A.n + c];
       if (m < 0) continue;
@@ -371,8 +487,29 @@ __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
     }
   }
   // ---- parents: add messages received ----
-  const int64_t rs_self = A.rslot ? A.rslot[c] : -1;
-  for (int s = 0; s < A.maxpar; ++s) {
+  int s_par0 = 0;
+  if constexpr (HOIST_PAR) {
+#pragma unroll
+    for (int s = 0; s < kHoistPar; ++s) {
+      if (pm[s] < 0) continue;
+      if (fused) {
+        unpack_add<T, CPLX, DE>([&](int k) {
+          T nu0 = pn[s][k], ze0 = pz[s][k];
+          if (!A.fused_first) {
+            ze0 = dfma<T>(pg[s][k], fc.ithp, ze0);
+            nu0 = extrap<T>(nu0, ze0, fc.thp);
+          }
+          return extrap<T>(nu0, ze0, th);
+        }, H);
+      } else if (A.ze_p) {
+        unpack_add<T, CPLX, DE>([&](int k) { return extrap<T>(pn[s][k], pz[s][k], th); }, H);
+      } else {
+        unpack_add<T, CPLX, DE>([&](int k) { return pn[s][k]; }, H);
+      }
+    }
+    s_par0 = kHoistPar;
+  }
+  for (int s = s_par0; s < A.maxpar; ++s) {
     const int m = A.par[(int64_t)s * A.n + c];
     if (m < 0) continue;
     if (fused) {
@@ -430,7 +567,6 @@ __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
 #pragma unroll
   for (int k = 0; k < DE; ++k) { lam[k] = H.r[tri_index(k, k, DE)]; lmin = fmin(lmin, lam[k]); }
   if (!isfinite((double)lmin) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
-  const int32_t gid = A.gid[c];
   if constexpr (MODE == MODE_CERTIFY) {
     A.scal[gid] = (double)lmin;
     A.scal2[gid] = 8.0 * DE * DBL_EPSILON * sqrt((double)nrm2);
@@ -439,8 +575,7 @@ __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
     // ---- a4: marginal weights ----
     T p[DE];
     if constexpr (MODE == MODE_GIBBS) {
-      // fused launches are replayed from a graph across stages: beta comes from the table
-      const T b = fused ? (T)A.fp->beta : (A.tab ? (T)A.tab->beta : (T)A.beta);
+      const T b = beta;
       T Z = T(0);
 #pragma unroll
       for (int k = 0; k < DE; ++k) { p[k] = dexp<T>(-b * (lam[k] - lmin)); Z += p[k]; }
@@ -488,10 +623,16 @@ __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
     // ---- a5: partial traces onto the children ----
     if constexpr (DC > 0) {
       if (A.Tout) {
-        for (int s = 0; s < A.maxch; ++s) {
-          const int m = A.ch[(int64_t)s * A.n + c];
+        for (int s = 0; s < (HOIST_CH ? MAXCH : A.maxch); ++s) {
+          int m, mask;
+          if constexpr (HOIST_CH) {
+            m = cm[s];
+            mask = cmask[s];
+          } else {
+            m = A.ch[(int64_t)s * A.n + c];
+            mask = m >= 0 ? A.chmask[(int64_t)s * A.n + c] : 0;
+          }
           if (m < 0) continue;
-          const int mask = A.chmask[(int64_t)s * A.n + c];
           HMat<T, CPLX, DC> Tm;
           mask_dispatch<DE, DC>(mask, [&](auto mc) __attribute__((always_inline)) {
             ptrace_reg<T, CPLX, DE, DC, decltype(mc)::value>(H, Tm);
@@ -2777,6 +2918,9 @@ static hipError_t launch_reg(const ClusterArgs<T>& a, int block, hipStream_t s) 
 template <typename T, bool CPLX, int MODE>
 static hipError_t launch_cluster_m(const ClusterArgs<T>& a, int block, int W, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
+  // the register kernels hold one slot per site for single-site children
+  if (a.Dc == 2 && (a.maxch < 1 || a.maxch > log2i(a.De))) return hipErrorInvalidValue;
+  if (a.Dc == 2 && a.fp != nullptr && a.ch_rslot == nullptr) return hipErrorInvalidValue;
   if (W == 0 || W == 4) {   // 0: one wave per cluster up to D = 32, 4: one workgroup per cluster
     if constexpr (MODE == MODE_GIBBS) {
       if (a.fp != nullptr || a.n > 0x7fffffff) return hipErrorInvalidValue;
@@ -2924,6 +3068,9 @@ hipError_t launch_cluster_pair(const ClusterArgs<T>& e, const ClusterArgs<T>& st
                                int block, hipStream_t s) {
   const int nbe = (int)grid_for(e.n, block), nbs = (int)grid_for(st.n, block);
   if (nbe + nbs == 0) return hipSuccess;
+  // an edge has one or two sites as children, found by (slot, cluster) in the fused form
+  if (e.n > 0 && (e.maxch < 1 || e.maxch > 2 || (e.fp != nullptr && e.ch_rslot == nullptr)))
+    return hipErrorInvalidValue;
   const dim3 g(nbe + nbs), b(block);
   if (mode == MODE_GIBBS) {
     if (cplx) hipLaunchKernelGGL((k_cluster_pair<T, true, MODE_GIBBS>), g, b, 0, s, e, st, nbe);
