@@ -253,21 +253,38 @@ def test_nesterov_plain_fp64(name):
 
 
 @pytest.mark.parametrize("f32", [False, True])
-@pytest.mark.parametrize("name", ["heis_field", "tfim_complex", "tfim_two_level"])
+@pytest.mark.parametrize("name", ["heis_field", "tfim_complex", "tfim_two_level", "heis_ring_field",
+                                  "heis_torus4_field", "heis_torus6"])
 def test_fused_equals_plain_bitwise(name, f32):
     """The fused single-launch iteration (graph-replayed) performs the same arithmetic as the
     plain two-kernel iteration: identical bits, across graph chunks and a remainder.  The
-    two-level chain has no end-site clusters, so its end edges have one child only."""
+    two-level chain has no end-site clusters, so its end edges have one child only.  On the ring
+    and the tori every site has two or four parents (the fused kernel reads up to four parent
+    slots ahead of any branch); the field-free torus starts from random messages, since zero
+    messages are optimal there and would stay zero."""
     lrh = lrhmod()
     say(f"[fused==plain] {name} f32={f32}")
-    d = (W.heisenberg_chain(12, field_x=0.5) if name == "heis_field"
-         else W.tfim_chain(10, 1.0, 0.9, complex_storage=True) if name == "tfim_complex"
-         else two_level(W.tfim_chain(10, 1.0, 0.9, complex_storage=True)))
+    if name == "heis_field":
+        d = W.heisenberg_chain(12, field_x=0.5)
+    elif name == "tfim_complex":
+        d = W.tfim_chain(10, 1.0, 0.9, complex_storage=True)
+    elif name == "tfim_two_level":
+        d = two_level(W.tfim_chain(10, 1.0, 0.9, complex_storage=True))
+    elif name == "heis_ring_field":
+        d = W.heisenberg_graph(12, [(i, (i + 1) % 12) for i in range(12)], field_x=0.5, name="ring12")
+    elif name == "heis_torus4_field":
+        d = W.heisenberg_graph(16, W.square_edges(4), field_x=0.3, name="torus4")
+    else:
+        d = W.heisenberg_square(6)
     P = lrh.Problem(d, 0)
     res = []
     for fused in (False, True):
         nu = P.zeros(f32)
         ze = P.zeros(f32)
+        if name == "heis_torus6":
+            g = torch.Generator().manual_seed(11)
+            nu.copy_(0.3 * torch.randn(nu.shape, generator=g, dtype=torch.float64).to(nu.dtype))
+            ze.copy_(nu)
         for beta, K in [(1.0, 70), (2.0, 64), (4.0, 3)]:
             st = P.new_nesterov_state(beta)
             P.step_nesterov(nu, ze, st, K, fused=fused)
