@@ -2650,16 +2650,18 @@ __global__ __launch_bounds__(64) void k_cluster_vjp(ClusterArgs<T> A) {
 // message kernel (a6), reductions, small helpers
 // ------------------------------------------------------------------------------------------
 
-constexpr int64_t kMsgChunk = 16;   // message components per thread of the update kernel
+// message components per thread of the update kernel: the whole message for one- and two-site
+// messages with 3, 4 or 10 components, else chunks of 16
+constexpr int kMsgChunk = 16;
 
-template <typename T, int MODE>
+template <typename T, int MODE, int CH>
 __global__ __launch_bounds__(256) void k_msg(MsgArgs<T> A) {
-  // x: one thread per message; y: chunks of kMsgChunk components, so that buckets of large
-  // messages (few messages, up to 65536 components each) still fill the GPU
+  // x: one thread per message; y: chunks of CH components, so that buckets of large messages
+  // (few messages, up to 65536 components each) still fill the GPU
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= A.M) return;
-  const int64_t k0 = (int64_t)blockIdx.y * kMsgChunk;
-  const int64_t k1 = k0 + kMsgChunk < A.comps ? k0 + kMsgChunk : A.comps;
+  const int64_t k0 = (int64_t)blockIdx.y * CH;
+  const int64_t k1 = k0 + CH < A.comps ? k0 + CH : A.comps;
   const int64_t rs = A.rslot[m];
   T th, ith;
   if (A.fp && A.fp_cur) { th = (T)A.fp->theta_cur; ith = (T)A.fp->inv_thL_cur; }
@@ -2669,19 +2671,42 @@ __global__ __launch_bounds__(256) void k_msg(MsgArgs<T> A) {
   const T alpha = (T)A.alpha;
   const T* nsrc = A.nu_src ? A.nu_src : A.nu;
   const T* zsrc = A.ze_src ? A.ze_src : A.ze;
-  for (int64_t k = k0; k < k1; ++k) {
+  // Every load of the chunk is issued before the first store, so that a thread keeps up to
+  // 4 x CH reads in flight; the message's own entries come first, since they do not wait for
+  // the marginal slot.  Loads past the chunk's end (k1 - k0 is the same across a workgroup)
+  // repeat its last component, so that none of them sits behind a branch.
+  const int64_t nk = k1 - k0;  // 1 .. CH
+  T rv[CH], tv[CH], nv[CH], zv[CH];
+#pragma unroll
+  for (int kk = 0; kk < CH; ++kk) {
+    const int64_t k = k0 + (kk < nk ? kk : nk - 1);
     const int64_t o = k * A.M + m;
-    const T g = A.R[k * A.S + rs] - A.Tm[o];
-    if constexpr (MODE == MSG_GRAD) {
-      A.grad[o] = g;
-    } else if constexpr (MODE == MSG_SUBGRAD) {
-      const T v = nsrc[o];
-      if (copy_best) A.nu_best[o] = v;
-      A.nu[o] = dfma<T>(alpha, g, v);
-    } else {
-      const T z = dfma<T>(g, ith, zsrc[o]);
-      A.ze[o] = z;
-      A.nu[o] = extrap<T>(nsrc[o], z, th);
+    tv[kk] = A.Tm[o];
+    if constexpr (MODE != MSG_GRAD) nv[kk] = nsrc[o];
+    if constexpr (MODE == MSG_NESTEROV) zv[kk] = zsrc[o];
+  }
+#pragma unroll
+  for (int kk = 0; kk < CH; ++kk) {
+    const int64_t k = k0 + (kk < nk ? kk : nk - 1);
+    rv[kk] = A.R[k * A.S + rs];
+  }
+#pragma unroll
+  for (int kk = 0; kk < CH; ++kk) {
+    const int64_t k = k0 + kk;
+    if (kk < nk) {
+      const int64_t o = k * A.M + m;
+      const T g = rv[kk] - tv[kk];
+      if constexpr (MODE == MSG_GRAD) {
+        A.grad[o] = g;
+      } else if constexpr (MODE == MSG_SUBGRAD) {
+        const T v = nv[kk];
+        if (copy_best) A.nu_best[o] = v;
+        A.nu[o] = dfma<T>(alpha, g, v);
+      } else {
+        const T z = dfma<T>(g, ith, zv[kk]);
+        A.ze[o] = z;
+        A.nu[o] = extrap<T>(nv[kk], z, th);
+      }
     }
   }
 }
@@ -3034,12 +3059,20 @@ hipError_t launch_cluster(const ClusterArgs<T>& a, bool cplx, int mode, int bloc
 template <typename T>
 hipError_t launch_msg(const MsgArgs<T>& a, int mode, int block, hipStream_t s) {
   if (a.M == 0 || a.comps == 0) return hipSuccess;
-  const int64_t chunks = (a.comps + kMsgChunk - 1) / kMsgChunk;
+  const int ch = (a.comps == 3 || a.comps == 4 || a.comps == 10) ? (int)a.comps : kMsgChunk;
+  const int64_t chunks = (a.comps + ch - 1) / ch;
   if (chunks > 65535) return hipErrorInvalidValue;
   const dim3 g(grid_for(a.M, block), (unsigned)chunks), b(block);
-  if (mode == MSG_GRAD) hipLaunchKernelGGL((k_msg<T, MSG_GRAD>), g, b, 0, s, a);
-  else if (mode == MSG_SUBGRAD) hipLaunchKernelGGL((k_msg<T, MSG_SUBGRAD>), g, b, 0, s, a);
-  else hipLaunchKernelGGL((k_msg<T, MSG_NESTEROV>), g, b, 0, s, a);
+  auto go = [&](auto chc) {
+    constexpr int CH = decltype(chc)::value;
+    if (mode == MSG_GRAD) hipLaunchKernelGGL((k_msg<T, MSG_GRAD, CH>), g, b, 0, s, a);
+    else if (mode == MSG_SUBGRAD) hipLaunchKernelGGL((k_msg<T, MSG_SUBGRAD, CH>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_msg<T, MSG_NESTEROV, CH>), g, b, 0, s, a);
+  };
+  if (ch == 3) go(std::integral_constant<int, 3>{});
+  else if (ch == 4) go(std::integral_constant<int, 4>{});
+  else if (ch == 10) go(std::integral_constant<int, 10>{});
+  else go(std::integral_constant<int, kMsgChunk>{});
   return hipGetLastError();
 }
 
