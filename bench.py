@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM-side bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by
 # a 64 MiB copy (profiles/k_cluster_pair_heisenberg32x32_traffic.md), keyed by the hash of the kernel
 # sources they were taken with; reported as null once the sources change.
-TRAFFIC_BYTES = {"dc6679ffe7ca7846": 1046296}
+TRAFFIC_BYTES = {"827efd5cb85fcb4b": 1050237}
 FP32_VALU_PEAK_TFLOPS = 157.3
 
 
