@@ -80,6 +80,11 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"liblrh.so not built ({path}); run __graft_entry__.build()")
+    # torch ships its own HIP runtime under the same soname as the system one.  Whichever is
+    # loaded first serves the whole process, so torch is imported before the library: both then
+    # share torch's runtime.  Loaded the other way round, torch's own kernel launches run on a
+    # runtime they were not built against and crash in the launch.
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     vp, i32, i64, u32, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_double
     sig = {
