@@ -1,2650 +1,9 @@
-// Device kernels of the local-relaxation message-passing step for gfx950 (CDNA4).
-//
-// One pass over a bucket of clusters of dimension De computes, per cluster e
-// (paper Sec. 4.2: theta_e, Q_C, Q_{C,beta} and their (sub)gradients):
-//   a1  eta = (1 - theta) nu + theta zeta           (Algorithm 2 extrapolation, fused in the loads)
-//   a2  theta_e = h_e - sum_children 1 (x) eta_{e->f} + sum_parents eta_{g->e}
-//   a3  cyclic Jacobi eigen-decomposition theta_e = U diag(l) U^H
-//   a4  Gibbs state rho = U softmax(-beta l) U^H and F_beta (stable shifted form), or the
-//       normalised ground projector P0/g and lambda_min
-//   a5  partial traces T_{e->f} = Tr_{e\f} rho for every child f, and rho itself when e
-//       has parents (consumed by the message update)
-//   a8  in certify mode: FP64 lambda_min and the backward-error margin 8 De eps ||theta||_F
-// The message kernel applies a6 (gradient and update) per message.
-//
-// Two cluster kernels:
-//   * k_cluster_reg: one lane per cluster, the whole De x De problem in registers with
-//     compile-time indexing (De <= 4: sites and edges of 2-local problems).  No LDS, no
-//     cross-lane traffic; a wave advances 64 independent clusters.
-//   * k_cluster_lds: one wavefront per cluster for 8 <= De <= 64; the matrix lives in LDS and
-//     the De/2 disjoint rotations of each round-robin step are applied in parallel.
-#include "lrh_internal.h"
-
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <cfloat>
-#include <cmath>
-#include <type_traits>
-#include <utility>
+// Launchers of the cluster kernels (dispatch by precision, field and mode), the message,
+// reduction and element-wise kernels.  The cluster kernel families themselves are instantiated
+// in lrh_k_*.hip (one translation unit per precision and mode).
+#include "lrh_device.h"
 
 namespace lrh {
-
-// ------------------------------------------------------------------------------------------
-// small helpers
-// ------------------------------------------------------------------------------------------
-
-// FP32 iterations use the single hardware instructions (v_sqrt_f32, v_rsq_f32, v_rcp_f32,
-// v_exp_f32, v_log_f32; about 1 ulp), far inside the FP32 tolerances and much shorter than the
-// correctly rounded sequences on the serial chain of a one-lane-per-cluster kernel.  FP64 keeps
-// IEEE division, square root and the libm exponential and logarithm.
-template <typename T> __device__ __forceinline__ T dsqrt(T x);
-template <> __device__ __forceinline__ float dsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
-template <> __device__ __forceinline__ double dsqrt<double>(double x) { return sqrt(x); }
-template <typename T> __device__ __forceinline__ T drsq(T x);   // 1 / sqrt(x)
-template <> __device__ __forceinline__ float drsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
-template <> __device__ __forceinline__ double drsq<double>(double x) { return 1.0 / sqrt(x); }
-template <typename T> __device__ __forceinline__ T ddiv(T a, T b);   // a / b
-template <> __device__ __forceinline__ float ddiv<float>(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-template <> __device__ __forceinline__ double ddiv<double>(double a, double b) { return a / b; }
-template <typename T> __device__ __forceinline__ T dexp(T x);
-template <> __device__ __forceinline__ float dexp<float>(float x) {
-  return __builtin_amdgcn_exp2f(x * 1.44269504088896341f);
-}
-template <> __device__ __forceinline__ double dexp<double>(double x) { return exp(x); }
-template <typename T> __device__ __forceinline__ T dlog(T x);
-template <> __device__ __forceinline__ float dlog<float>(float x) {
-  return __builtin_amdgcn_logf(x) * 0.693147180559945309f;
-}
-template <> __device__ __forceinline__ double dlog<double>(double x) { return log(x); }
-template <typename T> __device__ __forceinline__ T dfma(T a, T b, T c);
-template <> __device__ __forceinline__ float dfma<float>(float a, float b, float c) { return fmaf(a, b, c); }
-template <> __device__ __forceinline__ double dfma<double>(double a, double b, double c) { return fma(a, b, c); }
-
-// Algorithm 2 extrapolation / averaging (1 - th) x + th y, with one explicit rounding
-// pattern so that every kernel computing it from the same inputs gets the same bits.
-template <typename T>
-__device__ __forceinline__ T extrap(T x, T y, T th) {
-  return dfma<T>(T(1) - th, x, th * y);
-}
-
-// Jacobi rotation parameters for a pair with (real-ified) off-diagonal magnitude r > 0:
-// tau = (a_qq - a_pp) / (2 r), t = sign(tau) / (|tau| + sqrt(tau^2 + 1)), c = 1/sqrt(1+t^2).
-template <typename T>
-__device__ __forceinline__ void rot_params(T app, T aqq, T r, T& t, T& c, T& s) {
-  T tau = ddiv<T>(aqq - app, T(2) * r);
-  T at = fabs(tau);
-  t = ddiv<T>(tau >= T(0) ? T(1) : T(-1), at + dsqrt<T>(dfma<T>(tau, tau, T(1))));
-  c = drsq<T>(dfma<T>(t, t, T(1)));
-  s = t * c;
-}
-
-__host__ __device__ constexpr int pdep_bits(int a, int x, int mask, int nbits) {
-  int out = 0, ia = 0, ix = 0;
-  for (int b = 0; b < nbits; ++b) {
-    if ((mask >> b) & 1) { out |= ((a >> ia) & 1) << b; ++ia; }
-    else { out |= ((x >> ix) & 1) << b; ++ix; }
-  }
-  return out;
-}
-__host__ __device__ constexpr int pext_bits(int i, int mask, int nbits) {
-  int out = 0, k = 0;
-  for (int b = 0; b < nbits; ++b)
-    if ((mask >> b) & 1) { out |= ((i >> b) & 1) << k; ++k; }
-  return out;
-}
-__host__ __device__ constexpr int log2i(int D) { return D <= 1 ? 0 : 1 + log2i(D / 2); }
-
-// ------------------------------------------------------------------------------------------
-// register-resident cluster kernel (one lane per cluster, D_e <= 8)
-// ------------------------------------------------------------------------------------------
-
-// Hermitian D x D matrix kept as its packed upper triangle (real parts and imaginary parts);
-// every index is a compile-time constant after unrolling, so the storage lives in registers
-// and each independent entry is carried once across the sweep loop.
-template <typename T, bool CPLX, int D>
-struct HMat {
-  static constexpr int NT = D * (D + 1) / 2;
-  T r[NT];
-  T i[CPLX ? NT : 1];
-  __device__ __forceinline__ T re(int a, int b) const {
-    return a <= b ? r[tri_index(a, b, D)] : r[tri_index(b, a, D)];
-  }
-  __device__ __forceinline__ T im(int a, int b) const {
-    if constexpr (!CPLX) return T(0);
-    else return a < b ? i[tri_index(a, b, D)] : (a > b ? -i[tri_index(b, a, D)] : T(0));
-  }
-  __device__ __forceinline__ void set(int a, int b, T vr, T vi) {
-    if (a <= b) {
-      r[tri_index(a, b, D)] = vr;
-      if constexpr (CPLX) i[tri_index(a, b, D)] = (a == b) ? T(0) : vi;
-    } else {
-      r[tri_index(b, a, D)] = vr;
-      if constexpr (CPLX) i[tri_index(b, a, D)] = -vi;
-    }
-  }
-  __device__ __forceinline__ void zero() {
-#pragma unroll
-    for (int k = 0; k < NT; ++k) {
-      r[k] = T(0);
-      if constexpr (CPLX) i[k] = T(0);
-    }
-  }
-};
-
-// packed message / term components <-> HMat (layout: real upper triangle row-major, then the
-// imaginary strict upper triangle)
-template <typename T, bool CPLX, int D, typename Get>
-__device__ __forceinline__ void unpack(Get get, HMat<T, CPLX, D>& M) {
-#pragma unroll
-  for (int a = 0; a < D; ++a)
-#pragma unroll
-    for (int b = a; b < D; ++b) M.r[tri_index(a, b, D)] = get(tri_index(a, b, D));
-  if constexpr (CPLX) {
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      M.i[tri_index(a, a, D)] = T(0);
-#pragma unroll
-      for (int b = a + 1; b < D; ++b) M.i[tri_index(a, b, D)] = get(D * (D + 1) / 2 + stri_index(a, b, D));
-    }
-  }
-}
-
-template <typename T, bool CPLX, int D, typename Get>
-__device__ __forceinline__ void unpack_add(Get get, HMat<T, CPLX, D>& M) {
-#pragma unroll
-  for (int a = 0; a < D; ++a)
-#pragma unroll
-    for (int b = a; b < D; ++b) M.r[tri_index(a, b, D)] += get(tri_index(a, b, D));
-  if constexpr (CPLX) {
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-      for (int b = a + 1; b < D; ++b) M.i[tri_index(a, b, D)] += get(D * (D + 1) / 2 + stri_index(a, b, D));
-  }
-}
-
-template <typename T, bool CPLX, int D, typename Put>
-__device__ __forceinline__ void pack(Put put, const HMat<T, CPLX, D>& M) {
-#pragma unroll
-  for (int a = 0; a < D; ++a)
-#pragma unroll
-    for (int b = a; b < D; ++b) put(tri_index(a, b, D), M.r[tri_index(a, b, D)]);
-  if constexpr (CPLX) {
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-      for (int b = a + 1; b < D; ++b) put(D * (D + 1) / 2 + stri_index(a, b, D), M.i[tri_index(a, b, D)]);
-  }
-}
-
-// Calls f(integral_constant<int, M>) for the compile-time mask M == mask among the masks that
-// select log2(DC) of the log2(DE) site bits (the positions a child can occupy in its parent).
-// A flat fold over the candidate masks (no recursion), so everything inlines into the caller.
-template <int DE, int DC, int M, typename F>
-__device__ __forceinline__ void mask_case(int mask, F& f) {
-  if constexpr (__builtin_popcount(M) == log2i(DC)) {
-    if (mask == M) f(std::integral_constant<int, M>{});
-  }
-}
-template <int DE, int DC, typename F, int... I>
-__device__ __forceinline__ void mask_dispatch_seq(int mask, F& f, std::integer_sequence<int, I...>) {
-  (mask_case<DE, DC, I + 1>(mask, f), ...);
-}
-template <int DE, int DC, typename F>
-__device__ __forceinline__ void mask_dispatch(int mask, F&& f) {
-  mask_dispatch_seq<DE, DC>(mask, f, std::make_integer_sequence<int, DE - 1>{});
-}
-
-// theta_e -= 1_{e\f} (x) X for a child whose sites occupy bit mask MASK of e's index.
-template <typename T, bool CPLX, int DE, int DC, int MASK>
-__device__ __forceinline__ void lift_sub(HMat<T, CPLX, DE>& A, const HMat<T, CPLX, DC>& X) {
-  constexpr int NB = log2i(DE);
-#pragma unroll
-  for (int a = 0; a < DE; ++a)
-#pragma unroll
-    for (int b = a; b < DE; ++b) {
-      if (((a ^ b) & ~MASK & (DE - 1)) == 0) {
-        const int x = pext_bits(a, MASK, NB), y = pext_bits(b, MASK, NB);
-        A.r[tri_index(a, b, DE)] -= X.re(x, y);
-        if constexpr (CPLX) A.i[tri_index(a, b, DE)] -= X.im(x, y);
-      }
-    }
-}
-
-// T = Tr_{e\f} rho for a child at mask MASK.
-template <typename T, bool CPLX, int DE, int DC, int MASK>
-__device__ __forceinline__ void ptrace_reg(const HMat<T, CPLX, DE>& Rh, HMat<T, CPLX, DC>& Tm) {
-  constexpr int NB = log2i(DE);
-  constexpr int NR = DE / DC;
-#pragma unroll
-  for (int a = 0; a < DC; ++a)
-#pragma unroll
-    for (int b = a; b < DC; ++b) {
-      T sr = T(0), si = T(0);
-#pragma unroll
-      for (int x = 0; x < NR; ++x) {
-        sr += Rh.re(pdep_bits(a, x, MASK, NB), pdep_bits(b, x, MASK, NB));
-        if constexpr (CPLX) si += Rh.im(pdep_bits(a, x, MASK, NB), pdep_bits(b, x, MASK, NB));
-      }
-      Tm.set(a, b, sr, si);
-    }
-}
-
-// One cyclic sweep of two-sided Jacobi rotations over all pairs (p < q), row-cyclic order.
-// Branch-free: a pair with a_pq == 0 gets the identity rotation (t = 0, c = 1, s = 0), so the
-// unrolled sweep is straight-line code.
-template <typename T, bool CPLX, int D, bool VEC>
-__device__ __forceinline__ void jacobi_sweep_reg(HMat<T, CPLX, D>& A, T (&ur)[D][D], T (&ui)[D][D]) {
-#pragma unroll
-  for (int p = 0; p < D - 1; ++p)
-#pragma unroll
-    for (int q = p + 1; q < D; ++q) {
-      const T xr = A.re(p, q);
-      const T xi = A.im(p, q);
-      const T r = CPLX ? dsqrt<T>(dfma<T>(xr, xr, xi * xi)) : fabs(xr);
-      const bool nz = (r != T(0));
-      const T rs = nz ? r : T(1);
-      // e^{-i phi} with a_pq = r e^{i phi}; real case: sign(a_pq)
-      T er, ei;
-      if constexpr (CPLX) {
-        er = nz ? ddiv<T>(xr, rs) : T(1);
-        ei = nz ? ddiv<T>(-xi, rs) : T(0);
-      } else {
-        er = nz ? copysign(T(1), xr) : T(1);
-        ei = T(0);
-      }
-      const T app = A.re(p, p), aqq = A.re(q, q);
-      T t, c, s;
-      rot_params<T>(app, aqq, rs, t, c, s);
-      t = nz ? t : T(0);
-      c = nz ? c : T(1);
-      s = nz ? s : T(0);
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        if (k == p || k == q) continue;
-        // column update (A G): w = a_kq e^{-i phi}; rows follow by Hermitian symmetry
-        const T pr = A.re(k, p), pi = A.im(k, p);
-        const T qr = A.re(k, q), qi = A.im(k, q);
-        const T wr = CPLX ? (qr * er - qi * ei) : qr * er;
-        const T wi = CPLX ? (qr * ei + qi * er) : T(0);
-        A.set(k, p, c * pr - s * wr, c * pi - s * wi);
-        A.set(k, q, s * pr + c * wr, s * pi + c * wi);
-      }
-      A.set(p, p, app - t * r, T(0));
-      A.set(q, q, aqq + t * r, T(0));
-      A.set(p, q, nz ? T(0) : xr, nz ? T(0) : xi);
-      if constexpr (VEC) {
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-          const T pr = ur[k][p], pi = CPLX ? ui[k][p] : T(0);
-          const T qr = ur[k][q], qi = CPLX ? ui[k][q] : T(0);
-          const T wr = CPLX ? (qr * er - qi * ei) : qr * er;
-          const T wi = CPLX ? (qr * ei + qi * er) : T(0);
-          ur[k][p] = c * pr - s * wr;
-          ur[k][q] = s * pr + c * wr;
-          if constexpr (CPLX) {
-            ui[k][p] = c * pi - s * wi;
-            ui[k][q] = s * pi + c * wi;
-          }
-        }
-      }
-    }
-}
-
-// Squared off-diagonal Frobenius norm, accumulated in FP64 whatever T: the convergence test of
-// the FP32 iterations is taken in FP64, so near-degenerate clusters (large rotation angles on
-// tiny off-diagonals) are judged on the FP32 matrix without a second rounding of the test.
-template <typename T, bool CPLX, int D>
-__device__ __forceinline__ double offdiag2(const HMat<T, CPLX, D>& A) {
-  double s = 0.0;
-#pragma unroll
-  for (int a = 0; a < D; ++a)
-#pragma unroll
-    for (int b = a + 1; b < D; ++b) {
-      const double x = (double)A.r[tri_index(a, b, D)];
-      s = fma(x, x, s);
-      if constexpr (CPLX) {
-        const double y = (double)A.i[tri_index(a, b, D)];
-        s = fma(y, y, s);
-      }
-    }
-  return 2.0 * s;
-}
-
-template <typename T>
-struct FusedCoef { T thp, ithp, thc; };
-
-// Read in place of an absent coefficient row or term block, so that those loads need no branch.
-// 64 doubles hold a packed complex 8 x 8 block, the largest a register kernel takes.
-static __device__ FusedParams kZeroRow;
-static __device__ double kZeroTerms[64];
-
-template <typename T, bool CPLX, int DE, int DC, int MODE>
-__device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
-  constexpr bool VEC = (MODE != MODE_CERTIFY);
-  HMat<T, CPLX, DE> H;
-  const bool fused = (A.fp != nullptr);
-  // iteration coefficients: the fused row, else the stage table row, else the launch's own
-  // theta and beta (fused launches are replayed from a graph across stages)
-  const bool from_row = fused || A.tab != nullptr;
-  const FusedParams* fq = fused ? A.fp : (A.tab ? A.tab : &kZeroRow);
-  const FusedCoef<T> fc{(T)fq->theta_prev, (T)fq->inv_thL_prev, (T)fq->theta_cur};
-  const T th = from_row ? fc.thc : (T)A.theta;
-  const T beta = from_row ? (T)fq->beta : (T)A.beta;
-  // Loads are issued in two waves before any arithmetic or store: first every index (h offset,
-  // child and parent message ids, masks, marginal slots), then every value, branch-free with a
-  // valid index for an empty slot.  One cluster per lane and a cold L2 make each dependent round
-  // trip a full memory latency.  This applies to single-site children (at most log2(D_e) of
-  // them) and to the first kHoistPar parents of a 2 x 2 cluster; larger cases keep the plain
-  // per-slot loops.  The arithmetic and its order are unchanged.
-  constexpr bool HOIST_CH = (DC == 2);
-  constexpr bool HOIST_PAR = (DE == 2);
-  constexpr int MAXCH = HOIST_CH ? log2i(DE) : 1;
-  constexpr int NCC = HOIST_CH ? (CPLX ? 4 : 3) : 1;
-  constexpr int NCP = HOIST_PAR ? (CPLX ? 4 : 3) : 1;
-  constexpr int kHoistPar = 4;
-  // Source pointers are chosen per launch so that every hoisted load below is unconditional: an
-  // absent array is replaced by one that is present and the value read from it is never used,
-  // and an empty slot reads message 0 (a child or parent bucket that exists holds at least one).
-  const bool need_g = fused && !A.fused_first;  // the fused form's gradient step
-  // ---- index loads ----
-  const int64_t ho = A.hoff[c];
-  const int32_t gid = A.gid[c];
-  const int32_t rs_read = (A.rslot ? A.rslot : A.gid)[c];  // gid: a stand-in of n entries
-  const int64_t rs_self = A.rslot ? rs_read : -1;
-  int cm[MAXCH], cmask[MAXCH], crs[MAXCH];
-  if constexpr (HOIST_CH) {
-    const int32_t* rsp = fused ? A.ch_rslot : A.ch;  // the launcher requires ch_rslot when fused
-#pragma unroll
-    for (int s = 0; s < MAXCH; ++s) {
-      const int64_t so = (int64_t)(s < A.maxch ? s : 0) * A.n + c;
-      const int m = A.ch[so];
-      cm[s] = s < A.maxch ? m : -1;
-      cmask[s] = A.chmask[so];
-      crs[s] = rsp[so];
-    }
-  }
-  int pm[kHoistPar];
-  if constexpr (HOIST_PAR) {
-    if (A.maxpar > 0) {
-#pragma unroll
-      for (int s = 0; s < kHoistPar; ++s) {
-        const int m = A.par[(int64_t)(s < A.maxpar ? s : 0) * A.n + c];
-        pm[s] = s < A.maxpar ? m : -1;
-      }
-    } else {
-#pragma unroll
-      for (int s = 0; s < kHoistPar; ++s) pm[s] = -1;
-    }
-  }
-  // ---- value loads ----
-  static_assert((CPLX ? DE * DE : DE * (DE + 1) / 2) <= 64, "term block beyond kZeroTerms");
-  const double* hb = ho >= 0 ? A.h + ho : kZeroTerms;
-  unpack<T, CPLX, DE>([&](int k) { return (T)hb[k]; }, H);
-  T cn[MAXCH][NCC], cz[MAXCH][NCC], cg[MAXCH][NCC];
-  if constexpr (HOIST_CH) {
-    const T* sN = fused ? A.nu_c_prev : A.nu_c;
-    const T* sZ = fused ? A.ze_c_prev : (A.ze_c ? A.ze_c : A.nu_c);
-    const T* sR = need_g ? A.Rprev_c : sN;
-    const T* sT = need_g ? A.Tprev_c : sN;
-#pragma unroll
-    for (int s = 0; s < MAXCH; ++s) {
-      const int64_t m = cm[s] >= 0 ? cm[s] : 0;
-      const int64_t rs = crs[s] >= 0 ? crs[s] : 0;
-#pragma unroll
-      for (int k = 0; k < NCC; ++k) {
-        const int64_t o = (int64_t)k * A.Mc + m;
-        cn[s][k] = sN[o];
-        cz[s][k] = sZ[o];
-        cg[s][k] = sR[need_g ? (int64_t)k * A.Sc + rs : o] - sT[o];
-      }
-    }
-  }
-  T pn[kHoistPar][NCP], pz[kHoistPar][NCP], pg[kHoistPar][NCP];
-  if constexpr (HOIST_PAR) {
-    if (A.maxpar > 0) {
-      const T* sN = fused ? A.nu_p_prev : A.nu_p;
-      const T* sZ = fused ? A.ze_p_prev : (A.ze_p ? A.ze_p : A.nu_p);
-      const T* sR = need_g ? A.Rprev_p : sN;
-      const T* sT = need_g ? A.Tprev_p : sN;
-      const int64_t rs = rs_self >= 0 ? rs_self : 0;
-      T r[NCP];
-#pragma unroll
-      for (int k = 0; k < NCP; ++k) r[k] = sR[need_g ? (int64_t)k * A.S + rs : (int64_t)k * A.Mp];
-#pragma unroll
-      for (int s = 0; s < kHoistPar; ++s) {
-        const int64_t m = pm[s] >= 0 ? pm[s] : 0;
-#pragma unroll
-        for (int k = 0; k < NCP; ++k) {
-          const int64_t o = (int64_t)k * A.Mp + m;
-          pn[s][k] = sN[o];
-          pz[s][k] = sZ[o];
-          pg[s][k] = r[k] - sT[o];
-        }
-      }
-    }
-  }
-  // ---- children: subtract lifted messages ----
-  if constexpr (HOIST_CH) {
-#pragma unroll
-    for (int s = 0; s < MAXCH; ++s) {
-      if (cm[s] < 0) continue;
-      HMat<T, CPLX, DC> X;
-      if (fused) {
-        unpack<T, CPLX, DC>([&](int k) {
-          T nu0 = cn[s][k], ze0 = cz[s][k];
-          if (!A.fused_first) {
-            ze0 = dfma<T>(cg[s][k], fc.ithp, ze0);
-            nu0 = extrap<T>(nu0, ze0, fc.thp);
-            const int64_t o = (int64_t)k * A.Mc + cm[s];
-            A.nu_c_new[o] = nu0;
-            A.ze_c_new[o] = ze0;
-          }
-          return extrap<T>(nu0, ze0, th);
-        }, X);
-      } else if (A.ze_c) {
-        unpack<T, CPLX, DC>([&](int k) { return extrap<T>(cn[s][k], cz[s][k], th); }, X);
-      } else {
-        unpack<T, CPLX, DC>([&](int k) { return cn[s][k]; }, X);
-      }
-      mask_dispatch<DE, DC>(cmask[s], [&](auto mc) __attribute__((always_inline)) {
-        lift_sub<T, CPLX, DE, DC, decltype(mc)::value>(H, X);
-      });
-    }
-  } else if constexpr (DC > 0) {
-    for (int s = 0; s < A.maxch; ++s) {
-      const int m = A.ch[(int64_t)s * A.n + c];
-      if (m < 0) continue;
-      const int mask = A.chmask[(int64_t)s * A.n + c];
-      HMat<T, CPLX, DC> X;
-      if (fused) {
-        // by (slot, cluster) when available: the same level of dependent loads as ch itself
-        const int64_t rs = A.ch_rslot ? A.ch_rslot[(int64_t)s * A.n + c] : A.rslot_of_msg_c[m];
-        unpack<T, CPLX, DC>([&](int k) {
-          const int64_t o = (int64_t)k * A.Mc + m;
-          T nu0 = A.nu_c_prev[o], ze0 = A.ze_c_prev[o];
-          if (!A.fused_first) {
-            T g = A.Rprev_c[(int64_t)k * A.Sc + rs] - A.Tprev_c[o];
-            ze0 = dfma<T>(g, fc.ithp, ze0);
-            nu0 = extrap<T>(nu0, ze0, fc.thp);
-            A.nu_c_new[o] = nu0;
-            A.ze_c_new[o] = ze0;
-          }
-          return extrap<T>(nu0, ze0, th);
-        }, X);
-      } else if (A.ze_c) {
-        unpack<T, CPLX, DC>([&](int k) {
-          const int64_t o = (int64_t)k * A.Mc + m;
-          return extrap<T>(A.nu_c[o], A.ze_c[o], th);
-        }, X);
-      } else {
-        unpack<T, CPLX, DC>([&](int k) { return A.nu_c[(int64_t)k * A.Mc + m]; }, X);
-      }
-      mask_dispatch<DE, DC>(mask, [&](auto mc) __attribute__((always_inline)) {
-        lift_sub<T, CPLX, DE, DC, decltype(mc)::value>(H, X);
-      });
-    }
-  }
-  // ---- parents: add messages received ----
-  int s_par0 = 0;
-  if constexpr (HOIST_PAR) {
-#pragma unroll
-    for (int s = 0; s < kHoistPar; ++s) {
-      if (pm[s] < 0) continue;
-      if (fused) {
-        unpack_add<T, CPLX, DE>([&](int k) {
-          T nu0 = pn[s][k], ze0 = pz[s][k];
-          if (!A.fused_first) {
-            ze0 = dfma<T>(pg[s][k], fc.ithp, ze0);
-            nu0 = extrap<T>(nu0, ze0, fc.thp);
-          }
-          return extrap<T>(nu0, ze0, th);
-        }, H);
-      } else if (A.ze_p) {
-        unpack_add<T, CPLX, DE>([&](int k) { return extrap<T>(pn[s][k], pz[s][k], th); }, H);
-      } else {
-        unpack_add<T, CPLX, DE>([&](int k) { return pn[s][k]; }, H);
-      }
-    }
-    s_par0 = kHoistPar;
-  }
-  for (int s = s_par0; s < A.maxpar; ++s) {
-    const int m = A.par[(int64_t)s * A.n + c];
-    if (m < 0) continue;
-    if (fused) {
-      unpack_add<T, CPLX, DE>([&](int k) {
-        const int64_t o = (int64_t)k * A.Mp + m;
-        T nu0 = A.nu_p_prev[o], ze0 = A.ze_p_prev[o];
-        if (!A.fused_first) {
-          T g = A.Rprev_p[(int64_t)k * A.S + rs_self] - A.Tprev_p[o];
-          ze0 = dfma<T>(g, fc.ithp, ze0);
-          nu0 = extrap<T>(nu0, ze0, fc.thp);
-        }
-        return extrap<T>(nu0, ze0, th);
-      }, H);
-    } else if (A.ze_p) {
-      unpack_add<T, CPLX, DE>([&](int k) {
-        const int64_t o = (int64_t)k * A.Mp + m;
-        return extrap<T>(A.nu_p[o], A.ze_p[o], th);
-      }, H);
-    } else {
-      unpack_add<T, CPLX, DE>([&](int k) { return A.nu_p[(int64_t)k * A.Mp + m]; }, H);
-    }
-  }
-  // ---- a3: cyclic Jacobi (norms and the convergence test in FP64) ----
-  double dg = 0.0;
-#pragma unroll
-  for (int k = 0; k < DE; ++k) {
-    const double x = (double)H.r[tri_index(k, k, DE)];
-    dg = fma(x, x, dg);
-  }
-  const double nrm2 = dg + offdiag2<T, CPLX, DE>(H);
-  T ur[DE][DE], ui[DE][DE];  // eigenvectors (unused, and removed, without VEC / CPLX)
-  if constexpr (VEC) {
-#pragma unroll
-    for (int i = 0; i < DE; ++i)
-#pragma unroll
-      for (int j = 0; j < DE; ++j) {
-        ur[i][j] = (i == j) ? T(1) : T(0);
-        if constexpr (CPLX) ui[i][j] = T(0);
-      }
-  }
-  const double tol2 = A.tol * A.tol * nrm2;
-  bool conv = false;
-  for (int sweep = 0; sweep <= A.max_sweeps; ++sweep) {
-    if (offdiag2<T, CPLX, DE>(H) <= tol2) { conv = true; break; }
-    if (sweep == A.max_sweeps) break;
-    if constexpr (VEC) jacobi_sweep_reg<T, CPLX, DE, true>(H, ur, ui);
-    else {
-      T dr[DE][DE], di[DE][DE];
-      jacobi_sweep_reg<T, CPLX, DE, false>(H, dr, di);
-    }
-  }
-  if (!conv && A.noconv) atomicAdd(A.noconv, 1ull);
-  T lam[DE];
-  T lmin = H.r[0];
-#pragma unroll
-  for (int k = 0; k < DE; ++k) { lam[k] = H.r[tri_index(k, k, DE)]; lmin = fmin(lmin, lam[k]); }
-  if (!isfinite((double)lmin) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
-  if constexpr (MODE == MODE_CERTIFY) {
-    A.scal[gid] = (double)lmin;
-    A.scal2[gid] = 8.0 * DE * DBL_EPSILON * sqrt((double)nrm2);
-    return;
-  } else {
-    // ---- a4: marginal weights ----
-    T p[DE];
-    if constexpr (MODE == MODE_GIBBS) {
-      const T b = beta;
-      T Z = T(0);
-#pragma unroll
-      for (int k = 0; k < DE; ++k) { p[k] = dexp<T>(-b * (lam[k] - lmin)); Z += p[k]; }
-      const T iZ = ddiv<T>(T(1), Z);
-#pragma unroll
-      for (int k = 0; k < DE; ++k) p[k] *= iZ;
-      if (A.scal) A.scal[gid] = (double)(lmin - ddiv<T>(dlog<T>(Z), b));
-    } else {
-      const T tau = (T)A.tau_rel * fmax(T(1), dsqrt<T>(nrm2));
-      T g = T(0);
-#pragma unroll
-      for (int k = 0; k < DE; ++k) { p[k] = (lam[k] <= lmin + tau) ? T(1) : T(0); g += p[k]; }
-      const T ig = ddiv<T>(T(1), g);
-#pragma unroll
-      for (int k = 0; k < DE; ++k) p[k] *= ig;
-      if (A.scal) A.scal[gid] = (double)lmin;
-    }
-    // rho = U diag(p) U^H  (reuse H)
-#pragma unroll
-    for (int i = 0; i < DE; ++i)
-#pragma unroll
-      for (int j = i; j < DE; ++j) {
-        T sr = T(0), si = T(0);
-#pragma unroll
-        for (int k = 0; k < DE; ++k) {
-          const T a_r = ur[i][k] * p[k], a_i = CPLX ? ui[i][k] * p[k] : T(0);
-          // (a_r + i a_i) * conj(u_jk)
-          sr = dfma<T>(a_r, ur[j][k], sr);
-          if constexpr (CPLX) {
-            sr = dfma<T>(a_i, ui[j][k], sr);
-            si = dfma<T>(a_i, ur[j][k], si);
-            si = dfma<T>(-a_r, ui[j][k], si);
-          }
-        }
-        H.set(i, j, sr, si);
-      }
-    // ---- outputs: own marginal ----
-    if (rs_self >= 0 && A.R) {
-      pack<T, CPLX, DE>([&](int k, T v) { A.R[(int64_t)k * A.S + rs_self] = v; }, H);
-    }
-    if (A.marg) {
-      T* mo = A.marg + A.marg_off[gid];
-      pack<T, CPLX, DE>([&](int k, T v) { mo[k] = v; }, H);
-    }
-    // ---- a5: partial traces onto the children ----
-    if constexpr (DC > 0) {
-      if (A.Tout) {
-        for (int s = 0; s < (HOIST_CH ? MAXCH : A.maxch); ++s) {
-          int m, mask;
-          if constexpr (HOIST_CH) {
-            m = cm[s];
-            mask = cmask[s];
-          } else {
-            m = A.ch[(int64_t)s * A.n + c];
-            mask = m >= 0 ? A.chmask[(int64_t)s * A.n + c] : 0;
-          }
-          if (m < 0) continue;
-          HMat<T, CPLX, DC> Tm;
-          mask_dispatch<DE, DC>(mask, [&](auto mc) __attribute__((always_inline)) {
-            ptrace_reg<T, CPLX, DE, DC, decltype(mc)::value>(H, Tm);
-          });
-          pack<T, CPLX, DC>([&](int k, T v) { A.Tout[(int64_t)k * A.Mc + m] = v; }, Tm);
-        }
-      }
-    }
-  }
-}
-
-template <typename T, bool CPLX, int DE, int DC, int MODE>
-__global__ __launch_bounds__(256) void k_cluster_reg(ClusterArgs<T> A) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < A.n) cluster_reg_body<T, CPLX, DE, DC, MODE>(A, c);
-}
-
-// ------------------------------------------------------------------------------------------
-// wave-per-cluster LDS kernel (8 <= De <= 64)
-// ------------------------------------------------------------------------------------------
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-// Reductions over the 64 lanes of a wave built from DPP row operations (xor 1, xor 2, mirror
-// within 8 lanes, mirror within 16 lanes: every lane of a row of 16 ends with the same sum) and
-// four readlanes, instead of six LDS-crossbar shuffles.  Every lane of the wave must be active;
-// the result is wave-uniform.
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double v) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ double readlane_d(double v, int lane) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_readlane((int)b, lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ double row_sum16(double v) {
-  v += dpp_mov<0xB1>(v);    // quad_perm [1, 0, 3, 2]
-  v += dpp_mov<0x4E>(v);    // quad_perm [2, 3, 0, 1]
-  v += dpp_mov<0x141>(v);   // row_half_mirror
-  v += dpp_mov<0x140>(v);   // row_mirror
-  return v;
-}
-__device__ __forceinline__ double wave_sum_dpp(double v) {
-  v = row_sum16(v);
-  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
-}
-__device__ __forceinline__ double wave_min_dpp(double v) {
-  v = fmin(v, dpp_mov<0xB1>(v));
-  v = fmin(v, dpp_mov<0x4E>(v));
-  v = fmin(v, dpp_mov<0x141>(v));
-  v = fmin(v, dpp_mov<0x140>(v));
-  return fmin(fmin(readlane_d(v, 0), readlane_d(v, 16)), fmin(readlane_d(v, 32), readlane_d(v, 48)));
-}
-__device__ __forceinline__ double wave_max_rows(double v) {   // v already uniform within each row
-  return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_min(T v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-__device__ __forceinline__ int pdep_rt(int a, int x, int mask, int nbits) {
-  int out = 0, ia = 0, ix = 0;
-  for (int b = 0; b < nbits; ++b) {
-    if ((mask >> b) & 1) { out |= ((a >> ia) & 1) << b; ++ia; }
-    else { out |= ((x >> ix) & 1) << b; ++ix; }
-  }
-  return out;
-}
-__device__ __forceinline__ int pext_rt(int i, int mask, int nbits) {
-  int out = 0, k = 0;
-  for (int b = 0; b < nbits; ++b)
-    if ((mask >> b) & 1) { out |= ((i >> b) & 1) << k; ++k; }
-  return out;
-}
-
-// round-robin tournament: round r (0..D-2), pair k (0..D/2-1) -> (p < q); every pair once.
-__device__ __forceinline__ void rr_pair(int r, int k, int D, int& p, int& q) {
-  if (k == 0) { p = r; q = D - 1; }
-  else { p = (r + k) % (D - 1); q = (r - k + (D - 1)) % (D - 1); }
-  if (p > q) { int t = p; p = q; q = t; }
-}
-
-// element (a, b) of a packed Hermitian stored at stride `st` (component k at base[k*st])
-template <typename T, typename Get>
-__device__ __forceinline__ void herm_elem(Get get, int a, int b, int D, bool cplx, T& vr, T& vi) {
-  if (a <= b) {
-    vr = get(tri_index(a, b, D));
-    vi = (cplx && a < b) ? get(D * (D + 1) / 2 + stri_index(a, b, D)) : T(0);
-  } else {
-    vr = get(tri_index(b, a, D));
-    vi = cplx ? -get(D * (D + 1) / 2 + stri_index(b, a, D)) : T(0);
-  }
-}
-
-// Element (a, b) of a packed Hermitian without branches: both addresses are always valid, the
-// imaginary part is selected (conjugated below the diagonal, zero on it).
-template <typename T, bool CPLX, typename Get>
-__device__ __forceinline__ void herm_elem_bf(Get get, int a, int b, int D, T& vr, T& vi) {
-  const int lo = min(a, b), hi = max(a, b);
-  vr = get(tri_index(lo, hi, D));
-  if constexpr (CPLX) {
-    const T v = get(D * (D + 1) / 2 + (lo < hi ? stri_index(lo, hi, D) : 0));
-    vi = a < b ? v : (a > b ? -v : T(0));
-  } else {
-    vi = T(0);
-  }
-}
-
-// ---- shared pieces of the LDS kernels ----
-//
-// A 64-lane wave holds G = 64/W clusters, W lanes each (W is a power of two, 8..64); lane `lt`
-// of a cluster strides over that cluster's entries by W.  Every loop whose trip count depends
-// on the data is made wave-uniform (per-cluster `done` flags, exit on __all), so barriers and
-// cross-lane shuffles always see the whole wave.
-
-template <int W, typename T>
-__device__ __forceinline__ T seg_sum(T v) {
-#pragma unroll
-  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-template <int W, typename T>
-__device__ __forceinline__ T seg_min(T v) {
-#pragma unroll
-  for (int o = W / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-// theta_e = [h_e] - sum_children 1 (x) x_{e->f} + sum_parents x_{g->e}, written to (dr, di) with
-// leading dimension DE+1; x = extrap(nu, zeta, th) when zeta is given.  Off-diagonal message
-// elements are scaled by `offs` (packed-coordinate cotangents use 1/2).  Returns this lane's
-// share of the squared Frobenius norm.
-template <typename T, bool CPLX, int DE, int W>
-__device__ T lds_assemble(const ClusterArgs<T>& A, int64_t c, int lt, const T* xc, const T* zc, const T* xp,
-                          const T* zp, T th, bool with_h, T offs, T* dr, T* di) {
-  constexpr int LD = DE + 1;
-  constexpr int NB = log2i(DE);
-  const int64_t ho = with_h ? A.hoff[c] : -1;
-  const int Dc = A.Dc;
-  T my_n2 = T(0);
-  for (int idx = lt; idx < DE * DE; idx += W) {
-    const int i = idx / DE, j = idx % DE;
-    T vr = T(0), vi = T(0);
-    if (ho >= 0) {
-      const double* h = A.h + ho;
-      herm_elem<T>([&](int k) { return (T)h[k]; }, i, j, DE, CPLX, vr, vi);
-    }
-    for (int s = 0; s < A.maxch; ++s) {
-      const int m = A.ch[(int64_t)s * A.n + c];
-      if (m < 0) continue;
-      const int mask = A.chmask[(int64_t)s * A.n + c];
-      if (((i ^ j) & ~mask & (DE - 1)) != 0) continue;
-      const int a = pext_rt(i, mask, NB), b = pext_rt(j, mask, NB);
-      T er, ei;
-      if (zc)
-        herm_elem<T>([&](int k) { const int64_t o = (int64_t)k * A.Mc + m;
-                                  return extrap<T>(xc[o], zc[o], th); }, a, b, Dc, CPLX, er, ei);
-      else
-        herm_elem<T>([&](int k) { return xc[(int64_t)k * A.Mc + m]; }, a, b, Dc, CPLX, er, ei);
-      const T sc = (a == b) ? T(1) : offs;
-      vr -= sc * er;
-      vi -= sc * ei;
-    }
-    for (int s = 0; s < A.maxpar; ++s) {
-      const int m = A.par[(int64_t)s * A.n + c];
-      if (m < 0) continue;
-      T er, ei;
-      if (zp)
-        herm_elem<T>([&](int k) { const int64_t o = (int64_t)k * A.Mp + m;
-                                  return extrap<T>(xp[o], zp[o], th); }, i, j, DE, CPLX, er, ei);
-      else
-        herm_elem<T>([&](int k) { return xp[(int64_t)k * A.Mp + m]; }, i, j, DE, CPLX, er, ei);
-      const T sc = (i == j) ? T(1) : offs;
-      vr += sc * er;
-      vi += sc * ei;
-    }
-    dr[i * LD + j] = vr;
-    if constexpr (CPLX) di[i * LD + j] = vi;
-    my_n2 = dfma<T>(vr, vr, my_n2);
-    if constexpr (CPLX) my_n2 = dfma<T>(vi, vi, my_n2);
-  }
-  return my_n2;
-}
-
-// Rotation scratch of the round-robin parallel Jacobi (one per cluster).
-template <typename T, int NP>
-struct JacobiScratch {
-  T c[NP], s[NP], er[NP], ei[NP], app[NP], aqq[NP];
-  int p[NP], q[NP];
-};
-
-// Cyclic two-sided Jacobi on the LDS matrix (sar, sai) with eigenvectors accumulated in
-// (sur, sui) when VEC.  Each round applies the DE/2 disjoint rotations of a round-robin
-// tournament in parallel: columns (A G, U G), then rows (G^H A), then the exact 2x2 blocks.
-// `done` clusters (converged, capped, or absent) skip the work but keep the wave together.
-// Returns true when the off-diagonal norm fell below tol2 within max_sweeps sweeps.
-template <typename T, bool CPLX, int DE, bool VEC, int W>
-__device__ bool lds_jacobi(T* sar, T* sai, T* sur, T* sui, JacobiScratch<T, DE / 2>& J, double tol2, int max_sweeps,
-                           int lt, bool active) {
-  constexpr int LD = DE + 1;
-  constexpr int NP = DE / 2;
-  bool done = !active, conv = false;
-  for (int sweep = 0;; ++sweep) {
-    double off = 0.0;   // the convergence test in FP64 whatever T
-    if (!done) {
-      for (int idx = lt; idx < DE * DE; idx += W) {
-        const int i = idx / DE, j = idx % DE;
-        if (i != j) {
-          const double x = (double)sar[i * LD + j];
-          off = fma(x, x, off);
-          if constexpr (CPLX) {
-            const double y = (double)sai[i * LD + j];
-            off = fma(y, y, off);
-          }
-        }
-      }
-    }
-    off = seg_sum<W>(off);
-    if (!done) {
-      if (off <= tol2) { done = true; conv = true; }
-      else if (sweep >= max_sweeps) { done = true; }
-    }
-    if (__all(done ? 1 : 0)) break;
-    for (int r = 0; r < DE - 1; ++r) {
-      if (!done) {
-        for (int k = lt; k < NP; k += W) {
-          int p, q;
-          rr_pair(r, k, DE, p, q);
-          const T xr = sar[p * LD + q];
-          const T xi = CPLX ? sai[p * LD + q] : T(0);
-          const T rr = CPLX ? dsqrt<T>(dfma<T>(xr, xr, xi * xi)) : fabs(xr);
-          T t = T(0), cc = T(1), ss = T(0), er = T(1), ei = T(0);
-          const T app = sar[p * LD + p], aqq = sar[q * LD + q];
-          if (rr != T(0)) {
-            rot_params<T>(app, aqq, rr, t, cc, ss);
-            er = CPLX ? ddiv<T>(xr, rr) : copysign(T(1), xr);
-            ei = CPLX ? ddiv<T>(-xi, rr) : T(0);
-          }
-          J.p[k] = p; J.q[k] = q;
-          J.c[k] = cc; J.s[k] = ss; J.er[k] = er; J.ei[k] = ei;
-          J.app[k] = app - t * rr;
-          J.aqq[k] = aqq + t * rr;
-        }
-      }
-      __syncthreads();
-      if (!done) {
-        // columns: A <- A G, U <- U G  (w = x_q e^{-i phi})
-        for (int idx = lt; idx < DE * NP; idx += W) {
-          const int i = idx % DE, k = idx / DE;
-          const int p = J.p[k], q = J.q[k];
-          const T cc = J.c[k], ss = J.s[k], er = J.er[k], ei = J.ei[k];
-          {
-            T pr = sar[i * LD + p], qr = sar[i * LD + q];
-            T pi = CPLX ? sai[i * LD + p] : T(0), qi = CPLX ? sai[i * LD + q] : T(0);
-            T wr = CPLX ? qr * er - qi * ei : qr * er;
-            T wi = CPLX ? qr * ei + qi * er : T(0);
-            sar[i * LD + p] = cc * pr - ss * wr;
-            sar[i * LD + q] = ss * pr + cc * wr;
-            if constexpr (CPLX) {
-              sai[i * LD + p] = cc * pi - ss * wi;
-              sai[i * LD + q] = ss * pi + cc * wi;
-            }
-          }
-          if constexpr (VEC) {
-            T pr = sur[i * LD + p], qr = sur[i * LD + q];
-            T pi = CPLX ? sui[i * LD + p] : T(0), qi = CPLX ? sui[i * LD + q] : T(0);
-            T wr = CPLX ? qr * er - qi * ei : qr * er;
-            T wi = CPLX ? qr * ei + qi * er : T(0);
-            sur[i * LD + p] = cc * pr - ss * wr;
-            sur[i * LD + q] = ss * pr + cc * wr;
-            if constexpr (CPLX) {
-              sui[i * LD + p] = cc * pi - ss * wi;
-              sui[i * LD + q] = ss * pi + cc * wi;
-            }
-          }
-        }
-      }
-      __syncthreads();
-      if (!done) {
-        // rows: A <- G^H A  (w = x_q e^{+i phi})
-        for (int idx = lt; idx < DE * NP; idx += W) {
-          const int j = idx % DE, k = idx / DE;
-          const int p = J.p[k], q = J.q[k];
-          const T cc = J.c[k], ss = J.s[k], er = J.er[k], ei = -J.ei[k];
-          T pr = sar[p * LD + j], qr = sar[q * LD + j];
-          T pi = CPLX ? sai[p * LD + j] : T(0), qi = CPLX ? sai[q * LD + j] : T(0);
-          T wr = CPLX ? qr * er - qi * ei : qr * er;
-          T wi = CPLX ? qr * ei + qi * er : T(0);
-          sar[p * LD + j] = cc * pr - ss * wr;
-          sar[q * LD + j] = ss * pr + cc * wr;
-          if constexpr (CPLX) {
-            sai[p * LD + j] = cc * pi - ss * wi;
-            sai[q * LD + j] = ss * pi + cc * wi;
-          }
-        }
-      }
-      __syncthreads();
-      if (!done) {
-        for (int k = lt; k < NP; k += W) {
-          const int p = J.p[k], q = J.q[k];
-          sar[p * LD + p] = J.app[k];
-          sar[q * LD + q] = J.aqq[k];
-          sar[p * LD + q] = T(0);
-          sar[q * LD + p] = T(0);
-          if constexpr (CPLX) {
-            sai[p * LD + p] = T(0); sai[q * LD + q] = T(0);
-            sai[p * LD + q] = T(0); sai[q * LD + p] = T(0);
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-  return conv;
-}
-
-// component k of a packed D x D Hermitian -> (i, j, imaginary?)
-__device__ __forceinline__ void decode_comp(int k, int D, int& i, int& j, bool& im) {
-  im = false;
-  i = 0;
-  if (k >= D * (D + 1) / 2) { im = true; k -= D * (D + 1) / 2; }
-  const int rowlen0 = im ? D - 1 : D;
-  while (k >= rowlen0 - i) { k -= rowlen0 - i; ++i; }
-  j = i + k + (im ? 1 : 0);
-}
-
-// Write a cluster matrix Y (LDS) to its consumers: own marginal slot (if it has parents),
-// the per-cluster output buffer, and the partial traces onto every child.
-template <typename T, bool CPLX, int DE, int W>
-__device__ void lds_outputs(const ClusterArgs<T>& A, int64_t c, int lt, int32_t gid, const T* yr, const T* yi) {
-  constexpr int LD = DE + 1;
-  constexpr int NB = log2i(DE);
-  const int64_t rs_self = A.rslot ? A.rslot[c] : -1;
-  constexpr int NCE = n_comps(DE, CPLX);
-  for (int k = lt; k < NCE; k += W) {
-    int i, j;
-    bool im;
-    decode_comp(k, DE, i, j, im);
-    const T v = im ? yi[i * LD + j] : yr[i * LD + j];
-    if (rs_self >= 0 && A.R) A.R[(int64_t)k * A.S + rs_self] = v;
-    if (A.marg) A.marg[A.marg_off[gid] + k] = v;
-  }
-  const int Dc = A.Dc;
-  if (A.Tout && Dc > 0) {
-    const int NR = DE / Dc;
-    const int NCC = CPLX ? Dc * Dc : Dc * (Dc + 1) / 2;
-    for (int s = 0; s < A.maxch; ++s) {
-      const int m = A.ch[(int64_t)s * A.n + c];
-      if (m < 0) continue;
-      const int mask = A.chmask[(int64_t)s * A.n + c];
-      for (int k = lt; k < NCC; k += W) {
-        int a, b;
-        bool im;
-        decode_comp(k, Dc, a, b, im);
-        T sum = T(0);
-        for (int x = 0; x < NR; ++x) {
-          const int i = pdep_rt(a, x, mask, NB), j = pdep_rt(b, x, mask, NB);
-          sum += im ? yi[i * LD + j] : yr[i * LD + j];
-        }
-        A.Tout[(int64_t)k * A.Mc + m] = sum;
-      }
-    }
-  }
-}
-
-// Marginal weights from the eigenvalues on the diagonal of sar: Gibbs p (returns F_beta) or the
-// normalised ground-space indicator (returns lambda_min).  Weights go to sp[].
-template <typename T, int DE, int MODE, int W>
-__device__ T lds_weights(const T* sar, T* sp, T lmin, T beta, T tau, int lt, bool active) {
-  constexpr int LD = DE + 1;
-  T w = T(0);
-  if (active) {
-    if constexpr (MODE == MODE_GIBBS) {
-      for (int k = lt; k < DE; k += W) { T v = dexp<T>(-beta * (sar[k * LD + k] - lmin)); sp[k] = v; w += v; }
-    } else {
-      for (int k = lt; k < DE; k += W) { T v = (sar[k * LD + k] <= lmin + tau) ? T(1) : T(0); sp[k] = v; w += v; }
-    }
-  }
-  const T Z = seg_sum<W>(w);
-  __syncthreads();
-  if (active)
-    for (int k = lt; k < DE; k += W) sp[k] = ddiv<T>(sp[k], Z);
-  __syncthreads();
-  if constexpr (MODE == MODE_GIBBS) return lmin - ddiv<T>(dlog<T>(Z), beta);
-  else return lmin;
-}
-
-// (yr, yi) = U diag(sp) U^H
-template <typename T, bool CPLX, int DE, int W>
-__device__ void lds_rebuild(const T* sur, const T* sui, const T* sp, T* yr, T* yi, int lt) {
-  constexpr int LD = DE + 1;
-  for (int idx = lt; idx < DE * DE; idx += W) {
-    const int i = idx / DE, j = idx % DE;
-    T sr = T(0), si = T(0);
-    for (int k = 0; k < DE; ++k) {
-      const T a_r = sur[i * LD + k] * sp[k];
-      const T a_i = CPLX ? sui[i * LD + k] * sp[k] : T(0);
-      sr = dfma<T>(a_r, sur[j * LD + k], sr);
-      if constexpr (CPLX) {
-        sr = dfma<T>(a_i, sui[j * LD + k], sr);
-        si = dfma<T>(a_i, sur[j * LD + k], si);
-        si = dfma<T>(-a_r, sui[j * LD + k], si);
-      }
-    }
-    yr[i * LD + j] = sr;
-    if constexpr (CPLX) yi[i * LD + j] = (i == j) ? T(0) : si;
-  }
-}
-
-// W lanes per cluster, 64/W clusters per single-wave block.
-template <typename T, bool CPLX, int DE, int MODE, int W>
-__global__ __launch_bounds__(64) void k_cluster_lds(ClusterArgs<T> A) {
-  constexpr int LD = DE + 1;
-  constexpr int G = 64 / W;
-  constexpr int SZ = DE * LD;
-  constexpr bool VEC = (MODE != MODE_CERTIFY);
-  __shared__ T sar_[G * SZ];
-  __shared__ T sai_[CPLX ? G * SZ : 1];
-  __shared__ T sur_[VEC ? G * SZ : 1];
-  __shared__ T sui_[(VEC && CPLX) ? G * SZ : 1];
-  __shared__ JacobiScratch<T, DE / 2> J_[G];
-  __shared__ T sp_[G * DE];
-  const int g = threadIdx.x / W, lt = threadIdx.x % W;
-  const int64_t c = (int64_t)blockIdx.x * G + g;
-  const bool active = c < A.n;
-  T* sar = sar_ + g * SZ;
-  T* sai = CPLX ? sai_ + g * SZ : sai_;
-  T* sur = VEC ? sur_ + g * SZ : sur_;
-  T* sui = (VEC && CPLX) ? sui_ + g * SZ : sui_;
-  T* sp = sp_ + g * DE;
-  const T th = A.tab ? (T)A.tab->theta_cur : (T)A.theta;
-  const T beta = A.tab ? (T)A.tab->beta : (T)A.beta;
-  // ---- a1/a2: assemble theta_e at eta ----
-  T n2 = T(0);
-  if (active) n2 = lds_assemble<T, CPLX, DE, W>(A, c, lt, A.nu_c, A.ze_c, A.nu_p, A.ze_p, th, true, T(1), sar, sai);
-  const T nrm2 = seg_sum<W>(n2);
-  if constexpr (VEC) {
-    if (active) {
-      for (int idx = lt; idx < DE * DE; idx += W) {
-        const int i = idx / DE, j = idx % DE;
-        sur[i * LD + j] = (i == j) ? T(1) : T(0);
-        if constexpr (CPLX) sui[i * LD + j] = T(0);
-      }
-    }
-  }
-  __syncthreads();
-  // ---- a3: parallel cyclic Jacobi ----
-  const bool conv = lds_jacobi<T, CPLX, DE, VEC, W>(sar, sai, sur, sui, J_[g], A.tol * A.tol * (double)nrm2,
-                                                    A.max_sweeps, lt, active);
-  if (active && !conv && lt == 0 && A.noconv) atomicAdd(A.noconv, 1ull);
-  T lmin = T(INFINITY);
-  if (active)
-    for (int k = lt; k < DE; k += W) lmin = fmin(lmin, sar[k * LD + k]);
-  lmin = seg_min<W>(lmin);
-  if (active && lt == 0 && !isfinite((double)lmin) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
-  const int32_t gid = active ? A.gid[c] : 0;
-  if constexpr (MODE == MODE_CERTIFY) {
-    if (active && lt == 0) {
-      A.scal[gid] = (double)lmin;
-      A.scal2[gid] = 8.0 * DE * DBL_EPSILON * sqrt((double)nrm2);
-    }
-  } else {
-    // ---- a4: weights and the marginal U diag(p) U^H (over A) ----
-    const T val = lds_weights<T, DE, MODE, W>(sar, sp, lmin, beta, (T)A.tau_rel * fmax(T(1), dsqrt<T>(nrm2)), lt,
-                                              active);
-    if (active && lt == 0 && A.scal) A.scal[gid] = (double)val;
-    if (active) lds_rebuild<T, CPLX, DE, W>(sur, sui, sp, sar, sai, lt);
-    __syncthreads();
-    // ---- a5: outputs ----
-    if (active) lds_outputs<T, CPLX, DE, W>(A, c, lt, gid, sar, sai);
-  }
-}
-
-// ------------------------------------------------------------------------------------------
-// large clusters (De = 128, 256): one 1024-thread workgroup per cluster
-// ------------------------------------------------------------------------------------------
-//
-// A De x De complex matrix and its eigenvectors do not fit one CU's LDS, so theta_e, U and
-// rho live in a per-workgroup scratch slab in HBM (the workgroup walks clusters with a grid
-// stride); the round-robin parallel Jacobi applies De/2 disjoint rotations per round with all
-// 1024 threads.  The reconstruction rho = W W^H with W = U diag(sqrt p) is a dense contraction
-// and runs on the matrix cores: v_mfma_f32_32x32x2_f32 (FP32) / v_mfma_f64_16x16x4_f64 (FP64),
-// four real products per complex tile.
-
-typedef float mfma_f32x16 __attribute__((ext_vector_type(16)));
-typedef double mfma_f64x4 __attribute__((ext_vector_type(4)));
-
-template <typename T>
-__device__ __forceinline__ T block_sum(T v, T* red) {
-  v = wave_sum(v);
-  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
-  __syncthreads();
-  if (l == 0) red[w] = v;
-  __syncthreads();
-  T s = T(0);
-  const int nw = blockDim.x / 64;
-  for (int i = 0; i < nw; ++i) s += red[i];
-  __syncthreads();
-  return s;
-}
-template <typename T>
-__device__ __forceinline__ T block_max(T v, T* red) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
-  __syncthreads();
-  if (l == 0) red[w] = v;
-  __syncthreads();
-  T s = red[0];
-  const int nw = blockDim.x / 64;
-  for (int i = 1; i < nw; ++i) s = fmax(s, red[i]);
-  __syncthreads();
-  return s;
-}
-template <typename T>
-__device__ __forceinline__ T block_min(T v, T* red) {
-  v = wave_min(v);
-  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
-  __syncthreads();
-  if (l == 0) red[w] = v;
-  __syncthreads();
-  T s = red[0];
-  const int nw = blockDim.x / 64;
-  for (int i = 1; i < nw; ++i) s = fmin(s, red[i]);
-  __syncthreads();
-  return s;
-}
-
-// rho tile accumulation on the matrix cores; (wr, wi) = W rows, rho written to (orr, ori)
-template <typename T, bool CPLX>
-__device__ void mfma_rebuild(const T* ur, const T* ui, const T* sq, T* orr, T* ori, int D) {
-  const int wave = threadIdx.x / 64, l = threadIdx.x % 64, nw = blockDim.x / 64;
-  if constexpr (std::is_same<T, float>::value) {
-    const int nt = D / 32;
-    for (int tile = wave; tile < nt * nt; tile += nw) {
-      const int I = tile / nt, J = tile % nt;
-      mfma_f32x16 cr = {0}, ci = {0};
-      const int i = I * 32 + (l % 32), j = J * 32 + (l % 32);
-      for (int k0 = 0; k0 < D; k0 += 2) {
-        const int k = k0 + l / 32;
-        const float s = sq[k];
-        const float ar = ur[(int64_t)i * D + k] * s, br = ur[(int64_t)j * D + k] * s;
-        cr = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, cr, 0, 0, 0);
-        if constexpr (CPLX) {
-          const float ai = ui[(int64_t)i * D + k] * s, bi = ui[(int64_t)j * D + k] * s;
-          cr = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bi, cr, 0, 0, 0);
-          ci = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, ci, 0, 0, 0);
-          ci = __builtin_amdgcn_mfma_f32_32x32x2f32(-ar, bi, ci, 0, 0, 0);
-        }
-      }
-      for (int r = 0; r < 16; ++r) {
-        const int row = I * 32 + 8 * (r / 4) + 4 * (l / 32) + (r % 4), col = J * 32 + (l % 32);
-        orr[(int64_t)row * D + col] = cr[r];
-        if constexpr (CPLX) ori[(int64_t)row * D + col] = (row == col) ? 0.f : ci[r];
-      }
-    }
-  } else {
-    const int nt = D / 16;
-    for (int tile = wave; tile < nt * nt; tile += nw) {
-      const int I = tile / nt, J = tile % nt;
-      mfma_f64x4 cr = {0}, ci = {0};
-      const int i = I * 16 + (l % 16), j = J * 16 + (l % 16);
-      for (int k0 = 0; k0 < D; k0 += 4) {
-        const int k = k0 + l / 16;
-        const double s = sq[k];
-        const double ar = ur[(int64_t)i * D + k] * s, br = ur[(int64_t)j * D + k] * s;
-        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, cr, 0, 0, 0);
-        if constexpr (CPLX) {
-          const double ai = ui[(int64_t)i * D + k] * s, bi = ui[(int64_t)j * D + k] * s;
-          cr = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, cr, 0, 0, 0);
-          ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, ci, 0, 0, 0);
-          ci = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar, bi, ci, 0, 0, 0);
-        }
-      }
-      for (int r = 0; r < 4; ++r) {
-        const int row = I * 16 + 4 * r + (l / 16), col = J * 16 + (l % 16);
-        orr[(int64_t)row * D + col] = cr[r];
-        if constexpr (CPLX) ori[(int64_t)row * D + col] = (row == col) ? 0.0 : ci[r];
-      }
-    }
-  }
-}
-
-// theta_e of cluster c assembled element by element into a row-major D x D slab (ar, ai) of
-// element type S; with VEC the slab (ur, ui) is set to the identity.  Returns this thread's
-// share of ||theta||_F^2.
-template <typename T, typename S, bool CPLX, bool VEC>
-__device__ T big_assemble(const ClusterArgs<T>& A, int64_t c, int D, S* ar, S* ai, S* ur, S* ui, T th, int tid,
-                          int nth) {
-  const int NB = log2i(D);
-  const int64_t DD = (int64_t)D * D;
-  const int64_t ho = A.hoff[c];
-  const int Dc = A.Dc;
-  T my_n2 = T(0);
-  for (int64_t idx = tid; idx < DD; idx += nth) {
-    const int i = (int)(idx / D), j = (int)(idx % D);
-    T vr = T(0), vi = T(0);
-    if (ho >= 0) herm_elem<T>([&](int k) { return (T)A.h[ho + k]; }, i, j, D, CPLX, vr, vi);
-    for (int s = 0; s < A.maxch; ++s) {
-      const int m = A.ch[(int64_t)s * A.n + c];
-      if (m < 0) continue;
-      const int mask = A.chmask[(int64_t)s * A.n + c];
-      if (((i ^ j) & ~mask & (D - 1)) != 0) continue;
-      const int a = pext_rt(i, mask, NB), b = pext_rt(j, mask, NB);
-      T er, ei;
-      if (A.ze_c)
-        herm_elem<T>([&](int k) { const int64_t o = (int64_t)k * A.Mc + m;
-                                  return extrap<T>(A.nu_c[o], A.ze_c[o], th); }, a, b, Dc, CPLX, er, ei);
-      else
-        herm_elem<T>([&](int k) { return A.nu_c[(int64_t)k * A.Mc + m]; }, a, b, Dc, CPLX, er, ei);
-      vr -= er;
-      vi -= ei;
-    }
-    for (int s = 0; s < A.maxpar; ++s) {
-      const int m = A.par[(int64_t)s * A.n + c];
-      if (m < 0) continue;
-      T er, ei;
-      if (A.ze_p)
-        herm_elem<T>([&](int k) { const int64_t o = (int64_t)k * A.Mp + m;
-                                  return extrap<T>(A.nu_p[o], A.ze_p[o], th); }, i, j, D, CPLX, er, ei);
-      else
-        herm_elem<T>([&](int k) { return A.nu_p[(int64_t)k * A.Mp + m]; }, i, j, D, CPLX, er, ei);
-      vr += er;
-      vi += ei;
-    }
-    ar[idx] = (S)vr;
-    if constexpr (CPLX) ai[idx] = (S)vi;
-    if constexpr (VEC) {
-      ur[idx] = (i == j) ? S(1) : S(0);
-      if constexpr (CPLX) ui[idx] = S(0);
-    }
-    my_n2 = dfma<T>(vr, vr, my_n2);
-    if constexpr (CPLX) my_n2 = dfma<T>(vi, vi, my_n2);
-  }
-  return my_n2;
-}
-
-// Outputs of a cluster whose marginal scale * (rr, ri) sits in a row-major slab: own marginal
-// slot, per-cluster marginal, partial traces onto every child.
-template <typename T, typename S, bool CPLX>
-__device__ void big_outputs(const ClusterArgs<T>& A, int64_t c, int D, int32_t gid, const S* rr_, const S* ri_,
-                            S scale, int tid, int nth) {
-  const int NB = log2i(D);
-  const int Dc = A.Dc;
-  const int64_t rs_self = A.rslot ? A.rslot[c] : -1;
-  const int NCE = CPLX ? D * D : D * (D + 1) / 2;
-  for (int k = tid; k < NCE; k += nth) {
-    int i, j;
-    bool im;
-    decode_comp(k, D, i, j, im);
-    const T v = (T)(scale * (im ? ri_[(int64_t)i * D + j] : rr_[(int64_t)i * D + j]));
-    if (rs_self >= 0 && A.R) A.R[(int64_t)k * A.S + rs_self] = v;
-    if (A.marg) A.marg[A.marg_off[gid] + k] = v;
-  }
-  if (A.Tout && Dc > 0) {
-    const int NR = D / Dc;
-    const int NCC = CPLX ? Dc * Dc : Dc * (Dc + 1) / 2;
-    for (int s = 0; s < A.maxch; ++s) {
-      const int m = A.ch[(int64_t)s * A.n + c];
-      if (m < 0) continue;
-      const int mask = A.chmask[(int64_t)s * A.n + c];
-      for (int k = tid; k < NCC; k += nth) {
-        int a, b;
-        bool im;
-        decode_comp(k, Dc, a, b, im);
-        S sum = S(0);
-        for (int x = 0; x < NR; ++x) {
-          const int i = pdep_rt(a, x, mask, NB), j = pdep_rt(b, x, mask, NB);
-          sum += im ? ri_[(int64_t)i * D + j] : rr_[(int64_t)i * D + j];
-        }
-        A.Tout[(int64_t)k * A.Mc + m] = (T)(scale * sum);
-      }
-    }
-  }
-}
-
-template <typename T, bool CPLX, int MODE>
-__global__ __launch_bounds__(1024) void k_cluster_big(ClusterArgs<T> A, T* scratch, int64_t slab) {
-  constexpr bool VEC = (MODE != MODE_CERTIFY);
-  __shared__ T cs_c[128], cs_s[128], cs_er[128], cs_ei[128], cs_app[128], cs_aqq[128];
-  __shared__ int cs_p[128], cs_q[128];
-  __shared__ T red[16];
-  __shared__ double redd[16];
-  __shared__ T sp[256];
-  const int D = A.De;
-  const int NB = log2i(D);
-  const int NP = D / 2;
-  const int64_t DD = (int64_t)D * D;
-  T* ar = scratch + (int64_t)blockIdx.x * slab;
-  T* ai = ar + DD;   // unused for real problems
-  T* ur = ar + (CPLX ? 2 : 1) * DD;
-  T* ui = ur + DD;
-  T* rr_ = ar + (CPLX ? 4 : 2) * DD;
-  T* ri_ = rr_ + DD;
-  const int tid = threadIdx.x, nth = blockDim.x;
-  const T th = A.tab ? (T)A.tab->theta_cur : (T)A.theta;
-  const T beta = A.tab ? (T)A.tab->beta : (T)A.beta;
-  for (int64_t c = blockIdx.x; c < A.n; c += gridDim.x) {
-    // ---- a2: assemble theta_e ----
-    const int Dc = A.Dc;
-    const T my_n2 = big_assemble<T, T, CPLX, VEC>(A, c, D, ar, ai, ur, ui, th, tid, nth);
-    const T nrm2 = block_sum(my_n2, red);
-    // ---- a3: parallel cyclic Jacobi over the slab ----
-    const double tol2 = A.tol * A.tol * (double)nrm2;
-    bool conv = false;
-    for (int sweep = 0; sweep <= A.max_sweeps; ++sweep) {
-      double off = 0.0;   // the convergence test in FP64 whatever T
-      for (int64_t idx = tid; idx < DD; idx += nth) {
-        if (idx / D != idx % D) {
-          const double x = (double)ar[idx];
-          off = fma(x, x, off);
-          if constexpr (CPLX) {
-            const double y = (double)ai[idx];
-            off = fma(y, y, off);
-          }
-        }
-      }
-      off = block_sum(off, redd);
-      if (off <= tol2) { conv = true; break; }
-      if (sweep == A.max_sweeps) break;
-      for (int r = 0; r < D - 1; ++r) {
-        if (tid < NP) {
-          int p, q;
-          rr_pair(r, tid, D, p, q);
-          const T xr = ar[(int64_t)p * D + q];
-          const T xi = CPLX ? ai[(int64_t)p * D + q] : T(0);
-          const T rr = CPLX ? dsqrt<T>(dfma<T>(xr, xr, xi * xi)) : fabs(xr);
-          T t = T(0), cc = T(1), ss = T(0), er = T(1), ei = T(0);
-          const T app = ar[(int64_t)p * D + p], aqq = ar[(int64_t)q * D + q];
-          if (rr != T(0)) {
-            rot_params<T>(app, aqq, rr, t, cc, ss);
-            er = CPLX ? ddiv<T>(xr, rr) : copysign(T(1), xr);
-            ei = CPLX ? ddiv<T>(-xi, rr) : T(0);
-          }
-          cs_p[tid] = p; cs_q[tid] = q;
-          cs_c[tid] = cc; cs_s[tid] = ss; cs_er[tid] = er; cs_ei[tid] = ei;
-          cs_app[tid] = app - t * rr;
-          cs_aqq[tid] = aqq + t * rr;
-        }
-        __syncthreads();
-        for (int idx = tid; idx < D * NP; idx += nth) {
-          const int i = idx % D, k = idx / D;
-          const int p = cs_p[k], q = cs_q[k];
-          const T cc = cs_c[k], ss = cs_s[k], er = cs_er[k], ei = cs_ei[k];
-          {
-            const int64_t op = (int64_t)i * D + p, oq = (int64_t)i * D + q;
-            T pr = ar[op], qr = ar[oq];
-            T pi = CPLX ? ai[op] : T(0), qi = CPLX ? ai[oq] : T(0);
-            T wr = CPLX ? qr * er - qi * ei : qr * er;
-            T wi = CPLX ? qr * ei + qi * er : T(0);
-            ar[op] = cc * pr - ss * wr;
-            ar[oq] = ss * pr + cc * wr;
-            if constexpr (CPLX) { ai[op] = cc * pi - ss * wi; ai[oq] = ss * pi + cc * wi; }
-          }
-          if constexpr (VEC) {
-            const int64_t op = (int64_t)i * D + p, oq = (int64_t)i * D + q;
-            T pr = ur[op], qr = ur[oq];
-            T pi = CPLX ? ui[op] : T(0), qi = CPLX ? ui[oq] : T(0);
-            T wr = CPLX ? qr * er - qi * ei : qr * er;
-            T wi = CPLX ? qr * ei + qi * er : T(0);
-            ur[op] = cc * pr - ss * wr;
-            ur[oq] = ss * pr + cc * wr;
-            if constexpr (CPLX) { ui[op] = cc * pi - ss * wi; ui[oq] = ss * pi + cc * wi; }
-          }
-        }
-        __syncthreads();
-        for (int idx = tid; idx < D * NP; idx += nth) {
-          const int j = idx % D, k = idx / D;
-          const int p = cs_p[k], q = cs_q[k];
-          const T cc = cs_c[k], ss = cs_s[k], er = cs_er[k], ei = -cs_ei[k];
-          const int64_t op = (int64_t)p * D + j, oq = (int64_t)q * D + j;
-          T pr = ar[op], qr = ar[oq];
-          T pi = CPLX ? ai[op] : T(0), qi = CPLX ? ai[oq] : T(0);
-          T wr = CPLX ? qr * er - qi * ei : qr * er;
-          T wi = CPLX ? qr * ei + qi * er : T(0);
-          ar[op] = cc * pr - ss * wr;
-          ar[oq] = ss * pr + cc * wr;
-          if constexpr (CPLX) { ai[op] = cc * pi - ss * wi; ai[oq] = ss * pi + cc * wi; }
-        }
-        __syncthreads();
-        if (tid < NP) {
-          const int p = cs_p[tid], q = cs_q[tid];
-          ar[(int64_t)p * D + p] = cs_app[tid];
-          ar[(int64_t)q * D + q] = cs_aqq[tid];
-          ar[(int64_t)p * D + q] = T(0);
-          ar[(int64_t)q * D + p] = T(0);
-          if constexpr (CPLX) {
-            ai[(int64_t)p * D + p] = T(0); ai[(int64_t)q * D + q] = T(0);
-            ai[(int64_t)p * D + q] = T(0); ai[(int64_t)q * D + p] = T(0);
-          }
-        }
-        __syncthreads();
-      }
-    }
-    if (!conv && tid == 0 && A.noconv) atomicAdd(A.noconv, 1ull);
-    T lmin = T(INFINITY);
-    for (int k = tid; k < D; k += nth) lmin = fmin(lmin, ar[(int64_t)k * D + k]);
-    lmin = block_min(lmin, red);
-    if (tid == 0 && !isfinite((double)lmin) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
-    const int32_t gid = A.gid[c];
-    if constexpr (MODE == MODE_CERTIFY) {
-      if (tid == 0) {
-        A.scal[gid] = (double)lmin;
-        A.scal2[gid] = 8.0 * D * DBL_EPSILON * sqrt((double)nrm2);
-      }
-    } else {
-      // ---- a4: weights (sqrt stored for the W W^H product) ----
-      T w = T(0);
-      for (int k = tid; k < D; k += nth) {
-        const T lk = ar[(int64_t)k * D + k];
-        T v;
-        if constexpr (MODE == MODE_GIBBS) v = dexp<T>(-beta * (lk - lmin));
-        else v = (lk <= lmin + (T)A.tau_rel * fmax(T(1), dsqrt<T>(nrm2))) ? T(1) : T(0);
-        sp[k] = v;
-        w += v;
-      }
-      const T Z = block_sum(w, red);
-      for (int k = tid; k < D; k += nth) sp[k] = dsqrt<T>(sp[k] / Z);
-      if (tid == 0 && A.scal) A.scal[gid] = (MODE == MODE_GIBBS) ? (double)(lmin - dlog<T>(Z) / beta) : (double)lmin;
-      __syncthreads();
-      mfma_rebuild<T, CPLX>(ur, ui, sp, rr_, ri_, D);
-      __syncthreads();
-      // ---- a5: outputs ----
-      big_outputs<T, T, CPLX>(A, c, D, gid, rr_, ri_, T(1), tid, nth);
-    }
-    __syncthreads();
-  }
-}
-
-// ------------------------------------------------------------------------------------------
-// Gibbs state by scaling and squaring on the matrix cores (accelerated iteration, De = 16, 32)
-// ------------------------------------------------------------------------------------------
-//
-// The smoothed dual needs rho_e = exp(-beta theta_e) / Z and F_beta = -(1/beta) log Z only
-// (Sec. 4.1.2); the eigenvectors are not needed for that.  With mu = Tr(theta)/D and
-// X = beta (theta - mu), the scaling s is the least s >= 0 with ||X|| / 2^s <= 1/2, where
-// ||X|| = min(||X||_F, ||X||_1) (both norms are submultiplicative, so the Taylor remainder
-// bound holds in either; the induced 1-norm, the largest absolute row sum, is the tight one
-// for lifted local terms 1 (x) h, whose Frobenius norm carries a factor sqrt(D / D_h)), and
-//     E0 = T12(-X / 2^s)                (degree-12 Taylor polynomial, Paterson-Stockmeyer, p = 3)
-//     Y0 = E0 / Tr E0,  Y_j = Y_{j-1}^2 / tau_j    (j = 1..s)
-//     rho = Y_s / Tr Y_s,  log Z = 2^s log Tr E0 + sum_j 2^(s-j) log tau_j + log Tr Y_s
-// for any positive rescalings tau_j of the squarings (here exact powers of two).
-// The truncation error of T12 at norm 1/2 is below 2e-14 relative (in the norm that set s),
-// i.e. a backward error of about 7e-14 ||X|| in X, which exact squaring preserves.  Rounding in the squarings adds a
-// relative error of order D u (spectral spread / gap) to rho: the part along the dominant
-// eigenvector is removed by the final trace normalisation, the rest is damped once the
-// spectrum separates.  All of it runs in FP64 on v_mfma_f64_16x16x4_f64 whatever the message
-// precision.
-//
-// One wavefront per cluster.  A matrix is NB x NB blocks of 16 x 16 held in the MFMA result
-// layout: lane l, register r of block (I, J) is element (16 I + 4 r + l/16, 16 J + l%16).
-// Every matrix here is Hermitian (a polynomial in X), so the A operand of block (I, K) at
-// k-step kk, element (16 I + l%16, 16 K + 4 kk + l/16), is the conjugate of register kk of
-// block (K, I): both operands come straight from the registers, with no data movement.
-constexpr int kExpmLut = 8;   // children handled through the LDS index tables (more: generic path)
-
-// pext and pdep over the site bits of a one-wave cluster (at most 5 sites), for every site mask,
-// built at compile time: pext[mask][i] packs the bits of i at the mask positions;
-// pdepN[mask][(a << lnr) | x] places the bits of a at the mask positions and those of x at the
-// other N - popcount(mask) = lnr positions.
-struct SiteBitTables {
-  unsigned char pext[32][32];
-  unsigned char pdep4[16][16];
-  unsigned char pdep5[32][32];
-};
-constexpr SiteBitTables make_site_bit_tables() {
-  SiteBitTables t{};
-  for (int m = 0; m < 32; ++m)
-    for (int i = 0; i < 32; ++i) t.pext[m][i] = (unsigned char)pext_bits(i, m, 5);
-  for (int m = 0; m < 16; ++m) {
-    const int lnr = 4 - __builtin_popcount(m);
-    for (int p = 0; p < 16; ++p) t.pdep4[m][p] = (unsigned char)pdep_bits(p >> lnr, p & ((1 << lnr) - 1), m, 4);
-  }
-  for (int m = 0; m < 32; ++m) {
-    const int lnr = 5 - __builtin_popcount(m);
-    for (int p = 0; p < 32; ++p) t.pdep5[m][p] = (unsigned char)pdep_bits(p >> lnr, p & ((1 << lnr) - 1), m, 5);
-  }
-  return t;
-}
-__constant__ SiteBitTables kSiteBits = make_site_bit_tables();
-
-template <int NB, bool CPLX>
-struct XMat {
-  double re[NB][NB][4];
-  double im[CPLX ? NB : 1][CPLX ? NB : 1][4];
-};
-
-// C (+)= X Y for Hermitian X; C accumulates onto its contents, column block by column block,
-// so C may alias Y (never X).
-template <int NB, bool CPLX>
-__device__ __forceinline__ void xmm(const XMat<NB, CPLX>& X, const XMat<NB, CPLX>& Y, XMat<NB, CPLX>& C) {
-#pragma unroll
-  for (int J = 0; J < NB; ++J) {
-    mfma_f64x4 cr[NB], ci[NB];
-#pragma unroll
-    for (int I = 0; I < NB; ++I) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        cr[I][r] = C.re[I][J][r];
-        if constexpr (CPLX) ci[I][r] = C.im[I][J][r];
-      }
-#pragma unroll
-      for (int K = 0; K < NB; ++K)
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          cr[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(X.re[K][I][kk], Y.re[K][J][kk], cr[I], 0, 0, 0);
-          if constexpr (CPLX) {
-            cr[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(X.im[K][I][kk], Y.im[K][J][kk], cr[I], 0, 0, 0);
-            ci[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(X.re[K][I][kk], Y.im[K][J][kk], ci[I], 0, 0, 0);
-            ci[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(-X.im[K][I][kk], Y.re[K][J][kk], ci[I], 0, 0, 0);
-          }
-        }
-    }
-#pragma unroll
-    for (int I = 0; I < NB; ++I)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        C.re[I][J][r] = cr[I][r];
-        if constexpr (CPLX) C.im[I][J][r] = ci[I][r];
-      }
-  }
-}
-
-// lane-local diagonal test for register r of a diagonal block
-__device__ __forceinline__ bool xdiag(int r, int l) { return 4 * r + (l >> 4) == (l & 15); }
-
-template <int NB, bool CPLX>
-__device__ __forceinline__ void xzero(XMat<NB, CPLX>& M) {
-#pragma unroll
-  for (int I = 0; I < NB; ++I)
-#pragma unroll
-    for (int J = 0; J < NB; ++J)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        M.re[I][J][r] = 0.0;
-        if constexpr (CPLX) M.im[I][J][r] = 0.0;
-      }
-}
-
-template <int NB, bool CPLX>
-__device__ __forceinline__ double xtrace(const XMat<NB, CPLX>& M, int l) {
-  double t = 0.0;
-#pragma unroll
-  for (int I = 0; I < NB; ++I)
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (xdiag(r, l)) t += M.re[I][I][r];
-  return wave_sum_dpp(t);
-}
-
-// D = a I + b A + c A2 (+ d A3)
-template <int NB, bool CPLX, bool WITH3>
-__device__ __forceinline__ void xpoly(XMat<NB, CPLX>& D, double a, double b, double c, double d,
-                                      const XMat<NB, CPLX>& A1, const XMat<NB, CPLX>& A2,
-                                      const XMat<NB, CPLX>& A3, int l) {
-#pragma unroll
-  for (int I = 0; I < NB; ++I)
-#pragma unroll
-    for (int J = 0; J < NB; ++J)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        double v = fma(c, A2.re[I][J][r], b * A1.re[I][J][r]);
-        if constexpr (WITH3) v = fma(d, A3.re[I][J][r], v);
-        if (I == J && xdiag(r, l)) v += a;
-        D.re[I][J][r] = v;
-        if constexpr (CPLX) {
-          double w = fma(c, A2.im[I][J][r], b * A1.im[I][J][r]);
-          if constexpr (WITH3) w = fma(d, A3.im[I][J][r], w);
-          D.im[I][J][r] = w;
-        }
-      }
-}
-
-template <typename T, bool CPLX, int DE>
-__global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
-  constexpr int LD = DE + 1;
-  constexpr int NB = DE / 16;
-  __shared__ T sar[DE * LD];
-  __shared__ T sai[CPLX ? DE * LD : 1];
-  const int64_t c = blockIdx.x;
-  const int l = threadIdx.x;
-  const T th = A.tab ? (T)A.tab->theta_cur : (T)A.theta;
-  const double beta = A.tab ? A.tab->beta : A.beta;
-  constexpr int NBITS = log2i(DE);
-  static_assert(NBITS == 4 || NBITS == 5, "the one-wave kernel covers D = 16 and 32");
-  const int Dc = A.Dc;
-  const int nch = A.maxch;
-  const bool lut = nch <= kExpmLut;   // cluster-uniform
-  // per child: pext of every cluster index onto the child's sites, and pdep of (child index a,
-  // complement index x) back to the cluster index, as LDS tables
-  __shared__ unsigned char pextL[kExpmLut][DE], depL[kExpmLut][DE];
-  __shared__ T stc_r[kExpmLut][DE * DE / 4];
-  __shared__ T stc_i[CPLX ? kExpmLut : 1][CPLX ? DE * DE / 4 : 1];
-  XMat<NB, CPLX> X, P2, P3, M;
-  // ---- a1/a2: assemble theta_e at eta ----
-  // D_c and D_e / D_c are powers of two: shifts and masks instead of integer division
-  const int ldc = Dc > 0 ? __builtin_ctz(Dc) : 0;
-  const int lnr = NBITS - ldc;
-  if (lut) {
-    for (int s = 0; s < nch; ++s) {
-      const int mask = A.chmask[(int64_t)s * A.n + c] & (DE - 1);
-      if (l < DE) {
-        pextL[s][l] = kSiteBits.pext[mask][l];
-        if constexpr (NBITS == 4) depL[s][l] = kSiteBits.pdep4[mask][l];
-        else depL[s][l] = kSiteBits.pdep5[mask][l];
-      }
-    }
-    __syncthreads();
-    // branch-free element assembly: every candidate element is loaded from a valid address and
-    // then selected, so the lanes of the wave never diverge
-    // (h_e, then the children in slot order, then the parents: the order of the generic path)
-    const int64_t ho = A.hoff[c];
-    T acr[NB][NB][4], aci[NB][NB][4];
-#pragma unroll
-    for (int I = 0; I < NB; ++I)
-#pragma unroll
-      for (int J = 0; J < NB; ++J)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = 16 * I + 4 * r + (l >> 4), j = 16 * J + (l & 15);
-          double vr = 0.0, vi = 0.0;
-          if (ho >= 0) herm_elem_bf<double, CPLX>([&](int k) { return A.h[ho + k]; }, i, j, DE, vr, vi);
-          acr[I][J][r] = (T)vr;
-          aci[I][J][r] = (T)vi;
-        }
-    // the (extrapolated) child messages, dense D_c x D_c in LDS, one pass over all children
-    for (int idx = l; idx < nch << (2 * ldc); idx += 64) {
-      const int s = idx >> (2 * ldc), ab = idx & ((1 << (2 * ldc)) - 1);
-      const int m = A.ch[(int64_t)s * A.n + c];
-      if (m < 0) continue;
-      const int a = ab >> ldc, b = ab & (Dc - 1);
-      T er, ei;
-      if (A.ze_c)
-        herm_elem_bf<T, CPLX>([&](int k) { const int64_t o = (int64_t)k * A.Mc + m;
-                                           return extrap<T>(A.nu_c[o], A.ze_c[o], th); }, a, b, Dc, er, ei);
-      else
-        herm_elem_bf<T, CPLX>([&](int k) { return A.nu_c[(int64_t)k * A.Mc + m]; }, a, b, Dc, er, ei);
-      stc_r[s][ab] = er;
-      if constexpr (CPLX) stc_i[s][ab] = ei;
-    }
-    __syncthreads();
-    for (int s = 0; s < nch; ++s) {
-      const int m = A.ch[(int64_t)s * A.n + c];
-      if (m < 0) continue;   // cluster-uniform
-      const int mask = A.chmask[(int64_t)s * A.n + c];
-#pragma unroll
-      for (int I = 0; I < NB; ++I)
-#pragma unroll
-        for (int J = 0; J < NB; ++J)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int i = 16 * I + 4 * r + (l >> 4), j = 16 * J + (l & 15);
-            const bool ok = ((i ^ j) & ~mask & (DE - 1)) == 0;
-            const int ab = (pextL[s][i] << ldc) | pextL[s][j];
-            acr[I][J][r] -= ok ? stc_r[s][ab] : T(0);
-            if constexpr (CPLX) aci[I][J][r] -= ok ? stc_i[s][ab] : T(0);
-          }
-    }
-    for (int s = 0; s < A.maxpar; ++s) {
-      const int m = A.par[(int64_t)s * A.n + c];
-      if (m < 0) continue;   // cluster-uniform
-#pragma unroll
-      for (int I = 0; I < NB; ++I)
-#pragma unroll
-        for (int J = 0; J < NB; ++J)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int i = 16 * I + 4 * r + (l >> 4), j = 16 * J + (l & 15);
-            T er, ei;
-            if (A.ze_p)
-              herm_elem_bf<T, CPLX>([&](int k) { const int64_t o = (int64_t)k * A.Mp + m;
-                                                 return extrap<T>(A.nu_p[o], A.ze_p[o], th); }, i, j, DE, er, ei);
-            else
-              herm_elem_bf<T, CPLX>([&](int k) { return A.nu_p[(int64_t)k * A.Mp + m]; }, i, j, DE, er, ei);
-            acr[I][J][r] += er;
-            aci[I][J][r] += ei;
-          }
-    }
-#pragma unroll
-    for (int I = 0; I < NB; ++I)
-#pragma unroll
-      for (int J = 0; J < NB; ++J)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          X.re[I][J][r] = (double)acr[I][J][r];
-          if constexpr (CPLX) X.im[I][J][r] = (double)aci[I][J][r];
-        }
-  } else {
-    lds_assemble<T, CPLX, DE, 64>(A, c, l, A.nu_c, A.ze_c, A.nu_p, A.ze_p, th, true, T(1), sar, sai);
-    __syncthreads();
-#pragma unroll
-    for (int I = 0; I < NB; ++I)
-#pragma unroll
-      for (int J = 0; J < NB; ++J)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int o = (16 * I + 4 * r + (l >> 4)) * LD + 16 * J + (l & 15);
-          X.re[I][J][r] = (double)sar[o];
-          if constexpr (CPLX) X.im[I][J][r] = (double)sai[o];
-        }
-  }
-  // ---- shift, scale ----
-  const double mu = xtrace(X, l) / DE;
-  double n2 = 0.0;
-#pragma unroll
-  for (int I = 0; I < NB; ++I)
-#pragma unroll
-    for (int J = 0; J < NB; ++J)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        double v = X.re[I][J][r];
-        if (I == J && xdiag(r, l)) v -= mu;
-        X.re[I][J][r] = v;
-        n2 = fma(v, v, n2);
-        if constexpr (CPLX) n2 = fma(X.im[I][J][r], X.im[I][J][r], n2);
-      }
-  // induced 1-norm: row (16 I + 4 r + l/16) is spread over the blocks J and the 16 lanes that
-  // share l/16 (one DPP row), whose reduction leaves every lane of the row with the same sum
-  double rmax = 0.0;
-#pragma unroll
-  for (int I = 0; I < NB; ++I)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      double a = 0.0;
-#pragma unroll
-      for (int J = 0; J < NB; ++J) {
-        if constexpr (CPLX) a += sqrt(fma(X.re[I][J][r], X.re[I][J][r], X.im[I][J][r] * X.im[I][J][r]));
-        else a += fabs(X.re[I][J][r]);
-      }
-      rmax = fmax(rmax, row_sum16(a));
-    }
-  rmax = wave_max_rows(rmax);
-  const double nrm = beta * fmin(sqrt(wave_sum_dpp(n2)), rmax);
-  int s = 0;
-  while (s < 200 && nrm > ldexp(0.5, s)) ++s;
-  s = __builtin_amdgcn_readfirstlane(s);   // every lane holds the same value; make it scalar
-  const double sc = -ldexp(beta, -s);
-#pragma unroll
-  for (int I = 0; I < NB; ++I)
-#pragma unroll
-    for (int J = 0; J < NB; ++J)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        X.re[I][J][r] *= sc;
-        if constexpr (CPLX) X.im[I][J][r] *= sc;
-      }
-  // ---- E0 = T12(X): powers X^2, X^3 and a Horner recursion in X^3 ----
-  constexpr double c0 = 1.0, c1 = 1.0, c2 = 1.0 / 2, c3 = 1.0 / 6, c4 = 1.0 / 24, c5 = 1.0 / 120,
-                   c6 = 1.0 / 720, c7 = 1.0 / 5040, c8 = 1.0 / 40320, c9 = 1.0 / 362880, c10 = 1.0 / 3628800,
-                   c11 = 1.0 / 39916800, c12 = 1.0 / 479001600;
-  xzero(P2);
-  xmm(X, X, P2);
-  xzero(P3);
-  xmm(X, P2, P3);
-  xpoly<NB, CPLX, true>(M, c9, c10, c11, c12, X, P2, P3, l);    // B3
-  {
-    XMat<NB, CPLX> B;
-    xpoly<NB, CPLX, false>(B, c6, c7, c8, 0.0, X, P2, P3, l);   // B2 + X^3 B3
-    xmm(P3, M, B);
-    M = B;
-    xpoly<NB, CPLX, false>(B, c3, c4, c5, 0.0, X, P2, P3, l);   // B1 + X^3 (...)
-    xmm(P3, M, B);
-    M = B;
-    xpoly<NB, CPLX, false>(B, c0, c1, c2, 0.0, X, P2, P3, l);   // B0 + X^3 (...)
-    xmm(P3, M, B);
-    M = B;
-  }
-  // ---- normalise and square s times ----
-  double t = xtrace(M, l);
-  double L = log(t);
-  {
-    const double it = 1.0 / t;
-#pragma unroll
-    for (int I = 0; I < NB; ++I)
-#pragma unroll
-      for (int J = 0; J < NB; ++J)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          M.re[I][J][r] *= it;
-          if constexpr (CPLX) M.im[I][J][r] *= it;
-        }
-  }
-  // Squarings are rescaled by exact powers of two 2^-e_j, j = 3, 7, 11, ... and the last, chosen
-  // from the trace (for a PSD Y of trace 1, Tr(Y^(2^k)) >= D^(1 - 2^k), so four unscaled
-  // squarings stay far above the FP64 range limit); e_j = 0 elsewhere.  The exponents are
-  // accumulated as an integer, E <- 2E + e_j, so no logarithm or division sits in the loop:
-  //     log Z = 2^s log Tr E0 + E log 2 + log Tr Y_s,   rho = Y_s / Tr Y_s.
-  // X and M alternate as product buffers (the loop is unrolled by two).
-  double E = 0.0;
-  auto post = [&](XMat<NB, CPLX>& Y, int j) {
-    E *= 2.0;
-    if ((j & 3) == 3 || j == s - 1) {
-      const int e = __builtin_amdgcn_readfirstlane(ilogb(xtrace(Y, l)));
-      E += (double)e;
-      const double sc2 = ldexp(1.0, -e);
-#pragma unroll
-      for (int I = 0; I < NB; ++I)
-#pragma unroll
-        for (int J = 0; J < NB; ++J)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            Y.re[I][J][r] *= sc2;
-            if constexpr (CPLX) Y.im[I][J][r] *= sc2;
-          }
-    }
-  };
-  for (int j = 0; j < s; j += 2) {
-    xzero(X);
-    xmm(M, M, X);
-    post(X, j);
-    if (j + 1 < s) {
-      xzero(M);
-      xmm(X, X, M);
-      post(M, j + 1);
-    } else {
-      M = X;
-    }
-  }
-  {
-    const double tf = xtrace(M, l);
-    L = fma(ldexp(1.0, s), L, fma(E, 0.69314718055994530942, log(tf)));
-    const double it = 1.0 / tf;
-#pragma unroll
-    for (int I = 0; I < NB; ++I)
-#pragma unroll
-      for (int J = 0; J < NB; ++J)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          M.re[I][J][r] *= it;
-          if constexpr (CPLX) M.im[I][J][r] *= it;
-        }
-  }
-  const double F = mu - L / beta;
-  const int32_t gid = A.gid[c];
-  if (l == 0) {
-    if (A.scal) A.scal[gid] = F;
-    if (!isfinite(F) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
-  }
-  // ---- a5: rho back to LDS, then the outputs ----
-  __syncthreads();
-#pragma unroll
-  for (int I = 0; I < NB; ++I)
-#pragma unroll
-    for (int J = 0; J < NB; ++J)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int o = (16 * I + 4 * r + (l >> 4)) * LD + 16 * J + (l & 15);
-        sar[o] = (T)M.re[I][J][r];
-        if constexpr (CPLX) sai[o] = (T)M.im[I][J][r];
-      }
-  __syncthreads();
-  if (!lut) {
-    lds_outputs<T, CPLX, DE, 64>(A, c, l, gid, sar, sai);
-    return;
-  }
-  // own marginal slot and per-cluster marginal, straight from the registers (upper triangle)
-  const int64_t rs_self = A.rslot ? A.rslot[c] : -1;
-  if ((rs_self >= 0 && A.R) || A.marg) {
-#pragma unroll
-    for (int I = 0; I < NB; ++I)
-#pragma unroll
-      for (int J = 0; J < NB; ++J)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = 16 * I + 4 * r + (l >> 4), j = 16 * J + (l & 15);
-          if (i > j) continue;
-          const int kr = tri_index(i, j, DE);
-          const T vr = (T)M.re[I][J][r];
-          if (rs_self >= 0 && A.R) A.R[(int64_t)kr * A.S + rs_self] = vr;
-          if (A.marg) A.marg[A.marg_off[gid] + kr] = vr;
-          if constexpr (CPLX) {
-            if (i < j) {
-              const int ki = DE * (DE + 1) / 2 + stri_index(i, j, DE);
-              const T vi = (T)M.im[I][J][r];
-              if (rs_self >= 0 && A.R) A.R[(int64_t)ki * A.S + rs_self] = vi;
-              if (A.marg) A.marg[A.marg_off[gid] + ki] = vi;
-            }
-          }
-        }
-  }
-  // partial traces onto every child, all (child, component) pairs across the lanes
-  if (A.Tout && Dc > 0) {
-    const int NR = 1 << lnr;
-    const int NCC = CPLX ? Dc * Dc : Dc * (Dc + 1) / 2;
-    for (int idx = l; idx < nch * NCC; idx += 64) {
-      int s = 0, k = idx;
-      while (k >= NCC) {   // (child, component) without an integer division; at most nch steps
-        k -= NCC;
-        ++s;
-      }
-      const int m = A.ch[(int64_t)s * A.n + c];
-      if (m < 0) continue;
-      int a, b;
-      bool im;
-      decode_comp(k, Dc, a, b, im);
-      const T* y = im ? sai : sar;
-      T sum = T(0);
-      for (int x = 0; x < NR; ++x) sum += y[depL[s][(a << lnr) + x] * LD + depL[s][(b << lnr) + x]];
-      A.Tout[(int64_t)k * A.Mc + m] = sum;
-    }
-  }
-}
-
-// Workgroup variant for De = 32 (complex), 64, 128, 256: five matrices (X, X^2, X^3 and two Horner / squaring
-// buffers) in a per-workgroup FP64 slab, row-major, real plane then imaginary plane; four
-// waves, each computing 32 x 32 output tiles (2 x 2 blocks of the 16 x 16 MFMA; 16 x 16 below De = 128).  The A operand
-// of block (I, K) is read as the conjugate of block (K, I), which keeps both operand reads as
-// rows of 16 consecutive doubles.
-struct GInit {
-  double a, b, c;             // C = a I + b X + c P + scale * (A B)
-  const double* xr; const double* xi;
-  const double* pr; const double* pi;
-};
-
-template <bool CPLX, int DE>
-__device__ double gmm(const double* xr, const double* xi, const double* yr, const double* yi, double* cr_,
-                      double* ci_, double scale, const GInit& in, int tid) {
-  constexpr int TB = DE >= 128 ? 2 : 1;   // output tile of TB x TB blocks per wave
-  constexpr int NB = DE / 16, NT = NB / TB;
-  const int wave = tid / 64, l = tid % 64;
-  const int lr = l >> 4, lc = l & 15;
-  double tr = 0.0;
-  // C is Hermitian (every product here is a polynomial in one matrix): only the tiles on and
-  // above the diagonal are computed, an off-diagonal tile is also written conjugate-transposed
-  for (int t = wave; t < NT * (NT + 1) / 2; t += 4) {
-    int TI = 0, TJ = t;
-    while (TJ >= NT - TI) {
-      TJ -= NT - TI;
-      ++TI;
-    }
-    TJ += TI;
-    mfma_f64x4 accr[TB][TB], acci[TB][TB];
-#pragma unroll
-    for (int ii = 0; ii < TB; ++ii)
-#pragma unroll
-      for (int jj = 0; jj < TB; ++jj) {
-        accr[ii][jj] = mfma_f64x4{0.0, 0.0, 0.0, 0.0};
-        acci[ii][jj] = mfma_f64x4{0.0, 0.0, 0.0, 0.0};
-      }
-    // operand fragments of one K step (four k-sub-steps); with 16 x 16 tiles they are loaded one
-    // step ahead of the products that use them, so the L2 latency overlaps the matrix-core work
-    constexpr int NP = CPLX ? 2 : 1;
-    double fa[2][4][TB][NP], fb[2][4][TB][NP];
-    auto load_step = [&](int K, double (&ga)[4][TB][NP], double (&gb)[4][TB][NP]) {
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int64_t row = (int64_t)(16 * K + 4 * kk + lr) * DE;
-#pragma unroll
-        for (int q = 0; q < TB; ++q) {
-          const int ca = 16 * (TB * TI + q) + lc, cb = 16 * (TB * TJ + q) + lc;
-          ga[kk][q][0] = xr[row + ca];
-          gb[kk][q][0] = yr[row + cb];
-          if constexpr (CPLX) {
-            ga[kk][q][1] = xi[row + ca];
-            gb[kk][q][1] = yi[row + cb];
-          }
-        }
-      }
-    };
-    auto mma_step = [&](const double (&ga)[4][TB][NP], const double (&gb)[4][TB][NP]) {
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-        for (int ii = 0; ii < TB; ++ii)
-#pragma unroll
-          for (int jj = 0; jj < TB; ++jj) {
-            accr[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[kk][ii][0], gb[kk][jj][0], accr[ii][jj], 0, 0, 0);
-            if constexpr (CPLX) {
-              accr[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[kk][ii][1], gb[kk][jj][1], accr[ii][jj], 0, 0, 0);
-              acci[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[kk][ii][0], gb[kk][jj][1], acci[ii][jj], 0, 0, 0);
-              acci[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[kk][ii][1], gb[kk][jj][0], acci[ii][jj], 0, 0, 0);
-            }
-          }
-    };
-    if constexpr (TB == 1) {   // 16 x 16 tiles: latency-bound, registers to spare
-      load_step(0, fa[0], fb[0]);
-#pragma unroll 1
-      for (int K = 0; K < NB; K += 2) {
-        if (K + 1 < NB) load_step(K + 1, fa[1], fb[1]);
-        mma_step(fa[0], fb[0]);
-        if (K + 1 < NB) {
-          if (K + 2 < NB) load_step(K + 2, fa[0], fb[0]);
-          mma_step(fa[1], fb[1]);
-        }
-      }
-    } else {
-      // 32 x 32 tiles: one K step at a time.  Its 32 loads in flight together hide the latency
-      // better than a ring of k-sub-step fragments loaded two or three k-sub-steps ahead (30 %
-      // slower at D = 128 and 256), and a second K-step buffer costs the second wave per SIMD.
-#pragma unroll 1
-      for (int K = 0; K < NB; ++K) {
-        load_step(K, fa[0], fb[0]);
-        mma_step(fa[0], fb[0]);
-      }
-    }
-#pragma unroll
-    for (int ii = 0; ii < TB; ++ii)
-#pragma unroll
-      for (int jj = 0; jj < TB; ++jj)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = 16 * (TB * TI + ii) + 4 * r + lr, j = 16 * (TB * TJ + jj) + lc;
-          const int64_t o = (int64_t)i * DE + j;
-          double vr = scale * accr[ii][jj][r];
-          if (in.b != 0.0) vr = fma(in.b, in.xr[o], vr);
-          if (in.c != 0.0) vr = fma(in.c, in.pr[o], vr);
-          if (i == j) {
-            vr += in.a;
-            tr += vr;
-          }
-          cr_[o] = vr;
-          const int64_t ot = (int64_t)j * DE + i;
-          if (TI != TJ) cr_[ot] = vr;
-          if constexpr (CPLX) {
-            double vi = scale * acci[ii][jj][r];
-            if (in.b != 0.0) vi = fma(in.b, in.xi[o], vi);
-            if (in.c != 0.0) vi = fma(in.c, in.pi[o], vi);
-            ci_[o] = (i == j) ? 0.0 : vi;
-            if (TI != TJ) ci_[ot] = -vi;
-          }
-        }
-  }
-  return tr;
-}
-
-template <typename T, bool CPLX, int DE>
-__global__ __launch_bounds__(256) void k_cluster_expm_wg(ClusterArgs<T> A, double* scratch, int64_t slab) {
-  constexpr int64_t DD = (int64_t)DE * DE;
-  constexpr int NPL = CPLX ? 2 : 1;
-  __shared__ double red[8];
-  const int tid = threadIdx.x, nth = blockDim.x;
-  double* base = scratch + (int64_t)blockIdx.x * slab;
-  double* mr[5];
-  double* mi[5];
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    mr[k] = base + (int64_t)k * NPL * DD;
-    mi[k] = CPLX ? mr[k] + DD : nullptr;
-  }
-  double *Xr = mr[0], *Xi = mi[0], *P2r = mr[1], *P2i = mi[1], *P3r = mr[2], *P3i = mi[2];
-  const T th = A.tab ? (T)A.tab->theta_cur : (T)A.theta;
-  const double beta = A.tab ? A.tab->beta : A.beta;
-  constexpr double c0 = 1.0, c1 = 1.0, c2 = 1.0 / 2, c3 = 1.0 / 6, c4 = 1.0 / 24, c5 = 1.0 / 120,
-                   c6 = 1.0 / 720, c7 = 1.0 / 5040, c8 = 1.0 / 40320, c9 = 1.0 / 362880, c10 = 1.0 / 3628800,
-                   c11 = 1.0 / 39916800, c12 = 1.0 / 479001600;
-  const GInit zero{0.0, 0.0, 0.0, nullptr, nullptr, nullptr, nullptr};
-  for (int64_t c = blockIdx.x; c < A.n; c += gridDim.x) {
-    double *Mr = mr[3], *Mi = mi[3], *Br = mr[4], *Bi = mi[4];
-    // ---- a1/a2: assemble theta_e at eta ----
-    big_assemble<T, double, CPLX, false>(A, c, DE, Xr, Xi, (double*)nullptr, (double*)nullptr, th, tid, nth);
-    __syncthreads();
-    // ---- shift and scale: X = -(beta / 2^s) (theta - mu) ----
-    double tr = 0.0;
-    for (int k = tid; k < DE; k += nth) tr += Xr[(int64_t)k * DE + k];
-    const double mu = block_sum(tr, red) / DE;
-    double n2 = 0.0;
-    for (int64_t idx = tid; idx < DD; idx += nth) {
-      const double v = Xr[idx] - ((idx / DE == idx % DE) ? mu : 0.0);
-      n2 = fma(v, v, n2);
-      if constexpr (CPLX) n2 = fma(Xi[idx], Xi[idx], n2);
-    }
-    double rmax = 0.0;   // induced 1-norm: one row per thread
-    for (int i = tid; i < DE; i += nth) {
-      const double* xr = Xr + (int64_t)i * DE;
-      double a = 0.0;
-      for (int j = 0; j < DE; ++j) {
-        const double v = xr[j] - (i == j ? mu : 0.0);
-        if constexpr (CPLX) a += sqrt(fma(v, v, Xi[(int64_t)i * DE + j] * Xi[(int64_t)i * DE + j]));
-        else a += fabs(v);
-      }
-      rmax = fmax(rmax, a);
-    }
-    const double nrm = beta * fmin(sqrt(block_sum(n2, red)), block_max(rmax, red));
-    int s = 0;
-    while (s < 200 && nrm > ldexp(0.5, s)) ++s;   // block-uniform
-    const double sc = -ldexp(beta, -s);
-    for (int64_t idx = tid; idx < DD; idx += nth) {
-      Xr[idx] = sc * (Xr[idx] - ((idx / DE == idx % DE) ? mu : 0.0));
-      if constexpr (CPLX) Xi[idx] *= sc;
-    }
-    __syncthreads();
-    // ---- E0 = T12(X) ----
-    gmm<CPLX, DE>(Xr, Xi, Xr, Xi, P2r, P2i, 1.0, zero, tid);
-    __syncthreads();
-    gmm<CPLX, DE>(Xr, Xi, P2r, P2i, P3r, P3i, 1.0, zero, tid);
-    __syncthreads();
-    for (int64_t idx = tid; idx < DD; idx += nth) {
-      double v = fma(c12, P3r[idx], fma(c11, P2r[idx], c10 * Xr[idx]));
-      if (idx / DE == idx % DE) v += c9;
-      Mr[idx] = v;
-      if constexpr (CPLX) Mi[idx] = fma(c12, P3i[idx], fma(c11, P2i[idx], c10 * Xi[idx]));
-    }
-    __syncthreads();
-    const double hc[3][3] = {{c6, c7, c8}, {c3, c4, c5}, {c0, c1, c2}};
-    double trp = 0.0;
-    for (int h = 0; h < 3; ++h) {
-      const GInit in{hc[h][0], hc[h][1], hc[h][2], Xr, Xi, P2r, P2i};
-      trp = gmm<CPLX, DE>(P3r, P3i, Mr, Mi, Br, Bi, 1.0, in, tid);
-      __syncthreads();
-      double* tp = Mr; Mr = Br; Br = tp;
-      tp = Mi; Mi = Bi; Bi = tp;
-    }
-    // ---- normalise and square: Z_{j+1} = Z_j^2 / (Tr Z_j)^2 ----
-    double t = block_sum(trp, red);
-    double L = log(t);
-    for (int j = 0; j < s; ++j) {
-      trp = gmm<CPLX, DE>(Mr, Mi, Mr, Mi, Br, Bi, 1.0 / (t * t), zero, tid);
-      __syncthreads();
-      double* tp = Mr; Mr = Br; Br = tp;
-      tp = Mi; Mi = Bi; Bi = tp;
-      t = block_sum(trp, red);
-      L = fma(2.0, L, log(t));
-    }
-    const double F = mu - L / beta;
-    const int32_t gid = A.gid[c];
-    if (tid == 0) {
-      if (A.scal) A.scal[gid] = F;
-      if (!isfinite(F) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
-    }
-    // ---- a5: outputs of rho = Z_s / Tr Z_s ----
-    big_outputs<T, double, CPLX>(A, c, DE, gid, Mr, Mi, 1.0 / t, tid, nth);
-    __syncthreads();
-  }
-}
-
-// ------------------------------------------------------------------------------------------
-// certified lambda_min for De >= 64 without eigenvectors (a8)
-// ------------------------------------------------------------------------------------------
-//
-// theta_e (FP64, in a per-workgroup slab) is reduced to a Hermitian tridiagonal matrix by De - 2
-// Householder reflections H = I - tau v v^H acting on the trailing block (A <- H A H with the
-// rank-2 form A - v w^H - w v^H, w = p - (tau/2)(v^H p) v, p = tau A v).  A diagonal unitary
-// makes the off-diagonal real and non-negative, so the eigenvalues are those of the real
-// symmetric tridiagonal (d, |e|).  lambda_min is then bracketed by multisection on Sturm counts
-// (number of eigenvalues below x from the signs of the LDL^T pivots), 256 points per round;
-// the lower end of the final bracket, below which no eigenvalue lies, is returned.
-template <bool CPLX, int DE>
-__global__ __launch_bounds__(256) void k_cluster_tridiag(ClusterArgs<double> A, double* scratch, int64_t slab) {
-  constexpr int64_t DD = (int64_t)DE * DE;
-  __shared__ double vr[DE], vi[DE], pr[DE], pi[DE];
-  __shared__ double qvr[DE], qvi[DE], qwr[DE], qwi[DE];
-  __shared__ double dg[DE], e2[DE];
-  __shared__ double red[8];
-  const int tid = threadIdx.x, nth = blockDim.x;
-  double* ar = scratch + (int64_t)blockIdx.x * slab;
-  double* ai = CPLX ? ar + DD : nullptr;
-  for (int64_t c = blockIdx.x; c < A.n; c += gridDim.x) {
-    const double my_n2 = big_assemble<double, double, CPLX, false>(A, c, DE, ar, ai, (double*)nullptr,
-                                                                    (double*)nullptr, 0.0, tid, nth);
-    const double nrm2 = block_sum(my_n2, red);
-    // The rank-2 update of each reflection is applied during the next reflection's sweep over
-    // the trailing matrix (pending vectors qv, qw): every trailing element is read and written
-    // once per reflection instead of read twice and written once.  Row k and the final 2 x 2
-    // block are corrected on the fly.
-    for (int i = tid; i < DE; i += nth) {
-      qvr[i] = 0.0;
-      qvi[i] = 0.0;
-      qwr[i] = 0.0;
-      qwi[i] = 0.0;
-    }
-    __syncthreads();
-    // pending correction of element (r, cc): v_r conj(w_cc) + w_r conj(v_cc)
-    auto pend = [&](int r, int cc, double& ur, double& ui) {
-      ur = fma(qvr[r], qwr[cc], fma(qvi[r], qwi[cc], fma(qwr[r], qvr[cc], qwi[r] * qvi[cc])));
-      ui = fma(qvi[r], qwr[cc], fma(-qvr[r], qwi[cc], fma(qwi[r], qvr[cc], -qwr[r] * qvi[cc])));
-    };
-    for (int k = 0; k < DE - 2; ++k) {
-      const int m = DE - k - 1;
-      const int64_t rk = (int64_t)k * DE + k + 1;   // x_i = A[k+1+i][k] = conj(A[k][k+1+i])
-      double xs = 0.0;
-      for (int i = tid; i < m; i += nth) {
-        double ur, ui;
-        pend(k, k + 1 + i, ur, ui);
-        const double xr = ar[rk + i] - ur;
-        const double xim = CPLX ? ai[rk + i] - ui : 0.0;
-        vr[i] = xr;     // x, turned into v below
-        vi[i] = -xim;
-        xs = fma(xr, xr, xs);
-        if constexpr (CPLX) xs = fma(xim, xim, xs);
-      }
-      const double xn2 = block_sum(xs, red);
-      const double xn = sqrt(xn2);
-      const double x0r = vr[0], x0i = vi[0];
-      const double a0 = sqrt(fma(x0r, x0r, x0i * x0i));
-      if (tid == 0) {
-        double ur, ui;
-        pend(k, k, ur, ui);
-        dg[k] = ar[(int64_t)k * DE + k] - ur;
-        e2[k] = xn2;
-      }
-      const double vn2 = 2.0 * (xn2 + a0 * xn);
-      // an already reduced column (block-uniform) reflects nothing (v = 0) but still flushes the
-      // pending update into the trailing matrix
-      const bool act = vn2 > 0.0;
-      const double ur0 = a0 > 0.0 ? x0r / a0 : 1.0, ui0 = a0 > 0.0 ? x0i / a0 : 0.0;
-      const double tau = act ? 2.0 / vn2 : 0.0;
-      __syncthreads();
-      if (act) {
-        if (tid == 0) {   // v = x - alpha e1, alpha = -(x0/|x0|) ||x||
-          vr[0] = fma(ur0, xn, x0r);
-          vi[0] = fma(ui0, xn, x0i);
-        }
-      } else {
-        for (int i = tid; i < m; i += nth) {
-          vr[i] = 0.0;
-          vi[i] = 0.0;
-        }
-      }
-      __syncthreads();
-      // p = tau A22 v on the updated A22, written back as it is read; A22 is Hermitian, so row i
-      // of A22 v reads column i (coalesced across i)
-      for (int i = tid; i < m; i += nth) {
-        const int cc = k + 1 + i;
-        const double wcr = qwr[cc], wci = qwi[cc], vcr = qvr[cc], vci = qvi[cc];
-        double* col_r = ar + (int64_t)(k + 1) * DE + cc;
-        double* col_i = CPLX ? ai + (int64_t)(k + 1) * DE + cc : nullptr;
-        double sr = 0.0, si = 0.0;
-#pragma unroll 4
-        for (int j = 0; j < m; ++j) {
-          const int r = k + 1 + j;
-          const double a_r = col_r[(int64_t)j * DE] -
-                             fma(qvr[r], wcr, fma(qvi[r], wci, fma(qwr[r], vcr, qwi[r] * vci)));
-          col_r[(int64_t)j * DE] = a_r;
-          sr = fma(a_r, vr[j], sr);
-          if constexpr (CPLX) {
-            const double b_i = col_i[(int64_t)j * DE] -
-                               fma(qvi[r], wcr, fma(-qvr[r], wci, fma(qwi[r], vcr, -qwr[r] * vci)));
-            col_i[(int64_t)j * DE] = b_i;
-            const double a_i = -b_i;   // Im A[cc][r]
-            sr = fma(-a_i, vi[j], sr);
-            si = fma(a_r, vi[j], fma(a_i, vr[j], si));
-          }
-        }
-        pr[i] = tau * sr;
-        pi[i] = tau * si;
-      }
-      __syncthreads();
-      double ks = 0.0;
-      for (int i = tid; i < m; i += nth) ks = fma(vr[i], pr[i], fma(vi[i], pi[i], ks));
-      const double K = 0.5 * tau * block_sum(ks, red);
-      // the update of this reflection, A22 -= v w^H + w v^H with w = p - K v, becomes pending
-      for (int i = tid; i < m; i += nth) {
-        qvr[k + 1 + i] = vr[i];
-        qvi[k + 1 + i] = vi[i];
-        qwr[k + 1 + i] = fma(-K, vr[i], pr[i]);
-        qwi[k + 1 + i] = fma(-K, vi[i], pi[i]);
-      }
-      __syncthreads();
-    }
-    if (tid == 0) {
-      double ur, ui;
-      pend(DE - 2, DE - 2, ur, ui);
-      dg[DE - 2] = ar[(int64_t)(DE - 2) * DE + DE - 2] - ur;
-      pend(DE - 1, DE - 1, ur, ui);
-      dg[DE - 1] = ar[(int64_t)(DE - 1) * DE + DE - 1] - ur;
-      pend(DE - 2, DE - 1, ur, ui);
-      const double xr = ar[(int64_t)(DE - 2) * DE + DE - 1] - ur;
-      const double xi = CPLX ? ai[(int64_t)(DE - 2) * DE + DE - 1] - ui : 0.0;
-      e2[DE - 2] = fma(xr, xr, xi * xi);
-      e2[DE - 1] = 0.0;
-    }
-    __syncthreads();
-    // Gershgorin bracket (every thread, same order: identical values)
-    double lo = INFINITY, hi = -INFINITY, emax = 0.0;
-    for (int i = 0; i < DE; ++i) {
-      const double r = (i > 0 ? sqrt(e2[i - 1]) : 0.0) + sqrt(e2[i]);
-      lo = fmin(lo, dg[i] - r);
-      hi = fmax(hi, dg[i] + r);
-      emax = fmax(emax, e2[i]);
-    }
-    const double pivmin = DBL_MIN * fmax(1.0, emax);
-    const double span0 = fmax(hi - lo, DBL_MIN);
-    lo -= 2.0 * DBL_EPSILON * fabs(lo) + span0 * DBL_EPSILON;
-    hi += 2.0 * DBL_EPSILON * fabs(hi) + span0 * DBL_EPSILON;
-    for (int round = 0; round < 12; ++round) {
-      if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi))) break;   // a few ulps of lambda_min
-      const double x = lo + (hi - lo) * (double)(tid + 1) / (double)(nth + 1);
-      int cnt = 0;
-      double q = dg[0] - x;
-      if (fabs(q) < pivmin) q = -pivmin;
-      cnt += q < 0.0;
-      for (int i = 1; i < DE; ++i) {
-        q = (dg[i] - x) - e2[i - 1] / q;
-        if (fabs(q) < pivmin) q = -pivmin;
-        cnt += q < 0.0;
-      }
-      const double first = block_min(cnt > 0 ? (double)tid : (double)nth, red);
-      const int t = (int)first;
-      const double nlo = t == 0 ? lo : lo + (hi - lo) * (double)t / (double)(nth + 1);
-      const double nhi = t == nth ? hi : lo + (hi - lo) * (double)(t + 1) / (double)(nth + 1);
-      if (!(nhi - nlo < hi - lo)) break;
-      lo = nlo;
-      hi = nhi;
-    }
-    const int32_t gid = A.gid[c];
-    if (tid == 0) {
-      A.scal[gid] = lo;
-      A.scal2[gid] = 8.0 * DE * DBL_EPSILON * sqrt(nrm2);
-      if (!isfinite(lo) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
-    }
-    __syncthreads();
-  }
-}
-
-// One-wave variant for De = 16, 32: the matrix in LDS, the De rows of A22 v split over
-// 64/De lane groups (partial sums over j = g, g + G, ... combined by shuffles), 64 Sturm
-// points per multisection round.
-template <bool CPLX, int DE>
-__global__ __launch_bounds__(64) void k_cluster_tridiag_w(ClusterArgs<double> A) {
-  constexpr int LD = DE + 1;
-  constexpr int G = 64 / DE;
-  __shared__ double ar[DE * LD];
-  __shared__ double ai[CPLX ? DE * LD : 1];
-  __shared__ double vr[DE], vi[DE], pr[DE], pi[DE], dg[DE], e2[DE];
-  const int64_t c = blockIdx.x;
-  const int l = threadIdx.x;
-  const int li = l % DE, lg = l / DE;
-  const double nrm2 = wave_sum_dpp(
-      lds_assemble<double, CPLX, DE, 64>(A, c, l, A.nu_c, nullptr, A.nu_p, nullptr, 0.0, true, 1.0, ar, ai));
-  __syncthreads();
-  for (int k = 0; k < DE - 2; ++k) {
-    const int m = DE - k - 1;
-    const int rk = k * LD + k + 1;   // x_i = A[k+1+i][k] = conj(A[k][k+1+i])
-    double xs = 0.0;
-    if (l < m) {
-      xs = ar[rk + l] * ar[rk + l];
-      if constexpr (CPLX) xs = fma(ai[rk + l], ai[rk + l], xs);
-    }
-    const double xn2 = wave_sum_dpp(xs);
-    const double xn = sqrt(xn2);
-    const double x0r = ar[rk], x0i = CPLX ? -ai[rk] : 0.0;
-    const double a0 = sqrt(fma(x0r, x0r, x0i * x0i));
-    if (l == 0) {
-      dg[k] = ar[k * LD + k];
-      e2[k] = xn2;
-    }
-    const double vn2 = 2.0 * (xn2 + a0 * xn);
-    if (!(vn2 > 0.0)) continue;   // wave-uniform
-    const double ur = a0 > 0.0 ? x0r / a0 : 1.0, ui = a0 > 0.0 ? x0i / a0 : 0.0;
-    const double tau = 2.0 / vn2;
-    if (l < m) {
-      double r = ar[rk + l], im = CPLX ? -ai[rk + l] : 0.0;
-      if (l == 0) {
-        r += ur * xn;
-        im += ui * xn;
-      }
-      vr[l] = r;
-      vi[l] = im;
-    }
-    __syncthreads();
-    // p = tau A22 v: lane (li, lg) sums j = lg, lg + G, ... of row li (read as column li)
-    double sr = 0.0, si = 0.0;
-    if (li < m) {
-      for (int j = lg; j < m; j += G) {
-        const int o = (k + 1 + j) * LD + (k + 1 + li);
-        const double a_r = ar[o];
-        sr = fma(a_r, vr[j], sr);
-        if constexpr (CPLX) {
-          const double a_i = -ai[o];
-          sr = fma(-a_i, vi[j], sr);
-          si = fma(a_r, vi[j], fma(a_i, vr[j], si));
-        }
-      }
-    }
-#pragma unroll
-    for (int o = DE; o < 64; o <<= 1) {
-      sr += __shfl_xor(sr, o, 64);
-      if constexpr (CPLX) si += __shfl_xor(si, o, 64);
-    }
-    sr *= tau;
-    si *= tau;
-    const double ks = (l < m) ? fma(vr[l], sr, vi[l] * si) : 0.0;
-    const double K = 0.5 * tau * wave_sum_dpp(ks);
-    if (l < m) {
-      pr[l] = fma(-K, vr[l], sr);
-      pi[l] = fma(-K, vi[l], si);
-    }
-    __syncthreads();
-    // A22 -= v w^H + w v^H: lane (li, lg) updates column li of rows lg, lg + G, ... (no division)
-    if (li < m) {
-#pragma unroll 4
-      for (int i = lg; i < m; i += G) {
-        const int o = (k + 1 + i) * LD + (k + 1 + li);
-        ar[o] -= fma(vr[i], pr[li], fma(vi[i], pi[li], fma(pr[i], vr[li], pi[i] * vi[li])));
-        if constexpr (CPLX) ai[o] -= fma(vi[i], pr[li], fma(-vr[i], pi[li], fma(pi[i], vr[li], -pr[i] * vi[li])));
-      }
-    }
-    __syncthreads();
-  }
-  if (l == 0) {
-    dg[DE - 2] = ar[(DE - 2) * LD + DE - 2];
-    dg[DE - 1] = ar[(DE - 1) * LD + DE - 1];
-    const double xr = ar[(DE - 2) * LD + DE - 1], xi = CPLX ? ai[(DE - 2) * LD + DE - 1] : 0.0;
-    e2[DE - 2] = fma(xr, xr, xi * xi);
-    e2[DE - 1] = 0.0;
-  }
-  __syncthreads();
-  double lo = INFINITY, hi = -INFINITY, emax = 0.0;
-  for (int i = 0; i < DE; ++i) {
-    const double r = (i > 0 ? sqrt(e2[i - 1]) : 0.0) + sqrt(e2[i]);
-    lo = fmin(lo, dg[i] - r);
-    hi = fmax(hi, dg[i] + r);
-    emax = fmax(emax, e2[i]);
-  }
-  const double pivmin = DBL_MIN * fmax(1.0, emax);
-  const double span0 = fmax(hi - lo, DBL_MIN);
-  lo -= 2.0 * DBL_EPSILON * fabs(lo) + span0 * DBL_EPSILON;
-  hi += 2.0 * DBL_EPSILON * fabs(hi) + span0 * DBL_EPSILON;
-  for (int round = 0; round < 14; ++round) {
-    if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi))) break;   // a few ulps of lambda_min
-    const double x = lo + (hi - lo) * (double)(l + 1) / 65.0;
-    int cnt = 0;
-    double q = dg[0] - x;
-    if (fabs(q) < pivmin) q = -pivmin;
-    cnt += q < 0.0;
-    for (int i = 1; i < DE; ++i) {
-      q = (dg[i] - x) - e2[i - 1] / q;
-      if (fabs(q) < pivmin) q = -pivmin;
-      cnt += q < 0.0;
-    }
-    const int t = (int)wave_min_dpp(cnt > 0 ? (double)l : 64.0);
-    const double nlo = t == 0 ? lo : lo + (hi - lo) * (double)t / 65.0;
-    const double nhi = t == 64 ? hi : lo + (hi - lo) * (double)(t + 1) / 65.0;
-    if (!(nhi - nlo < hi - lo)) break;
-    lo = nlo;
-    hi = nhi;
-  }
-  const int32_t gid = A.gid[c];
-  if (l == 0) {
-    A.scal[gid] = lo;
-    A.scal2[gid] = 8.0 * DE * DBL_EPSILON * sqrt(nrm2);
-    if (!isfinite(lo) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
-  }
-}
-
-// ------------------------------------------------------------------------------------------
-// adjoint (a9): VJP of (Q_beta, grad Q_beta) through one cluster
-// ------------------------------------------------------------------------------------------
-//
-// grad Q_beta = B^* rho_beta(B nu + h) with B the linear map from messages to augmented
-// Hamiltonians (chain rule of the Lipschitz lemma, Sec. 4.1.2).  For cotangents qbar (per
-// instance) and gbar (per message) the cluster's cotangent is
-//     Y_e = qbar rho_e + D rho_e[(B gbar)_e],
-// with the Daleckii-Krein derivative of the normalised matrix exponential
-//     D rho[X] = U [Gamma o (U^H X U)] U^H + beta <rho, X> rho,
-//     Gamma_ab = (p_a - p_b)/(l_a - l_b) = p_lo expm1(-beta (l_hi - l_lo)) / (l_hi - l_lo),
-//     Gamma_aa = -beta p_a.
-// nu_bar = B^* Y is then the message kernel's gradient stage (Y_f - Tr_{e\f} Y_e).  At beta = 0
-// the cotangent of Q is Y_e = qbar mu_e (the ground projector; gbar must be absent).
-template <typename T, bool CPLX, int DE, int MODE>
-__global__ __launch_bounds__(64) void k_cluster_vjp(ClusterArgs<T> A) {
-  constexpr int LD = DE + 1;
-  __shared__ T sar[DE * LD];
-  __shared__ T sai[CPLX ? DE * LD : 1];
-  __shared__ T sur[DE * LD];
-  __shared__ T sui[CPLX ? DE * LD : 1];
-  __shared__ T sxr[DE * LD];
-  __shared__ T sxi[CPLX ? DE * LD : 1];
-  __shared__ T str[DE * LD];
-  __shared__ T sti[CPLX ? DE * LD : 1];
-  __shared__ JacobiScratch<T, DE / 2> J;
-  __shared__ T sp[DE];
-  __shared__ T slam[DE];
-  const int64_t c = blockIdx.x;
-  if (c >= A.n) return;
-  const int tid = threadIdx.x;
-  const bool has_g = (A.gb_c != nullptr || A.gb_p != nullptr);
-  const T nrm2 = wave_sum(lds_assemble<T, CPLX, DE, 64>(A, c, tid, A.nu_c, nullptr, A.nu_p, nullptr, T(0), true,
-                                                        T(1), sar, sai));
-  if (has_g) lds_assemble<T, CPLX, DE, 64>(A, c, tid, A.gb_c, nullptr, A.gb_p, nullptr, T(0), false,
-                                           (T)A.gb_offscale, sxr, sxi);
-  for (int idx = tid; idx < DE * DE; idx += 64) {
-    const int i = idx / DE, j = idx % DE;
-    sur[i * LD + j] = (i == j) ? T(1) : T(0);
-    if constexpr (CPLX) sui[i * LD + j] = T(0);
-  }
-  __syncthreads();
-  const bool conv = lds_jacobi<T, CPLX, DE, true, 64>(sar, sai, sur, sui, J, A.tol * A.tol * (double)nrm2,
-                                                      A.max_sweeps, tid, true);
-  if (!conv && tid == 0 && A.noconv) atomicAdd(A.noconv, 1ull);
-  T lmin = T(INFINITY);
-  for (int k = tid; k < DE; k += 64) {
-    slam[k] = sar[k * LD + k];
-    lmin = fmin(lmin, sar[k * LD + k]);
-  }
-  lmin = wave_min(lmin);
-  const T beta = (T)A.beta;
-  lds_weights<T, DE, MODE, 64>(sar, sp, lmin, beta, (T)A.tau_rel * fmax(T(1), dsqrt<T>(nrm2)), tid, true);
-  // rho (or mu) over A
-  lds_rebuild<T, CPLX, DE, 64>(sur, sui, sp, sar, sai, tid);
-  __syncthreads();
-  const int32_t gid = A.gid[c];
-  const T qb = A.qbar ? (T)A.qbar[A.cinst[gid]] : T(0);
-  if (MODE == MODE_GIBBS && has_g) {
-    // <rho, X>
-    T rx = T(0);
-    for (int idx = tid; idx < DE * DE; idx += 64) {
-      rx = dfma<T>(sar[idx / DE * LD + idx % DE], sxr[idx / DE * LD + idx % DE], rx);
-      if constexpr (CPLX) rx = dfma<T>(sai[idx / DE * LD + idx % DE], sxi[idx / DE * LD + idx % DE], rx);
-    }
-    rx = wave_sum(rx);
-    // Tm = U^H X
-    for (int idx = tid; idx < DE * DE; idx += 64) {
-      const int a = idx / DE, j = idx % DE;
-      T sr = T(0), si = T(0);
-      for (int k = 0; k < DE; ++k) {
-        const T ur = sur[k * LD + a], ui = CPLX ? -sui[k * LD + a] : T(0);  // conj(U_ka)
-        const T xr = sxr[k * LD + j], xi = CPLX ? sxi[k * LD + j] : T(0);
-        sr = dfma<T>(ur, xr, sr);
-        if constexpr (CPLX) {
-          sr = dfma<T>(-ui, xi, sr);
-          si = dfma<T>(ur, xi, si);
-          si = dfma<T>(ui, xr, si);
-        }
-      }
-      str[a * LD + j] = sr;
-      if constexpr (CPLX) sti[a * LD + j] = si;
-    }
-    __syncthreads();
-    // M = (U^H X) U, then Gamma o M (into X)
-    for (int idx = tid; idx < DE * DE; idx += 64) {
-      const int a = idx / DE, b = idx % DE;
-      T sr = T(0), si = T(0);
-      for (int k = 0; k < DE; ++k) {
-        const T tr = str[a * LD + k], ti = CPLX ? sti[a * LD + k] : T(0);
-        const T ur = sur[k * LD + b], ui = CPLX ? sui[k * LD + b] : T(0);
-        sr = dfma<T>(tr, ur, sr);
-        if constexpr (CPLX) {
-          sr = dfma<T>(-ti, ui, sr);
-          si = dfma<T>(tr, ui, si);
-          si = dfma<T>(ti, ur, si);
-        }
-      }
-      const int hi = slam[a] >= slam[b] ? a : b, lo = slam[a] >= slam[b] ? b : a;
-      const T dl = slam[hi] - slam[lo];
-      const T g = (dl == T(0)) ? -beta * sp[lo] : sp[lo] * (T)expm1((double)(-beta * dl)) / dl;
-      sxr[a * LD + b] = g * sr;
-      if constexpr (CPLX) sxi[a * LD + b] = g * si;
-    }
-    __syncthreads();
-    // Tm = U (Gamma o M)
-    for (int idx = tid; idx < DE * DE; idx += 64) {
-      const int i = idx / DE, b = idx % DE;
-      T sr = T(0), si = T(0);
-      for (int k = 0; k < DE; ++k) {
-        const T ur = sur[i * LD + k], ui = CPLX ? sui[i * LD + k] : T(0);
-        const T mr = sxr[k * LD + b], mi = CPLX ? sxi[k * LD + b] : T(0);
-        sr = dfma<T>(ur, mr, sr);
-        if constexpr (CPLX) {
-          sr = dfma<T>(-ui, mi, sr);
-          si = dfma<T>(ur, mi, si);
-          si = dfma<T>(ui, mr, si);
-        }
-      }
-      str[i * LD + b] = sr;
-      if constexpr (CPLX) sti[i * LD + b] = si;
-    }
-    __syncthreads();
-    // Y = Tm U^H + (beta <rho,X> + qbar) rho  (into X)
-    const T w = beta * rx + qb;
-    for (int idx = tid; idx < DE * DE; idx += 64) {
-      const int i = idx / DE, j = idx % DE;
-      T sr = T(0), si = T(0);
-      for (int k = 0; k < DE; ++k) {
-        const T tr = str[i * LD + k], ti = CPLX ? sti[i * LD + k] : T(0);
-        const T ur = sur[j * LD + k], ui = CPLX ? -sui[j * LD + k] : T(0);  // conj(U_jk)
-        sr = dfma<T>(tr, ur, sr);
-        if constexpr (CPLX) {
-          sr = dfma<T>(-ti, ui, sr);
-          si = dfma<T>(tr, ui, si);
-          si = dfma<T>(ti, ur, si);
-        }
-      }
-      sxr[i * LD + j] = dfma<T>(w, sar[i * LD + j], sr);
-      if constexpr (CPLX) sxi[i * LD + j] = dfma<T>(w, sai[i * LD + j], si);
-    }
-    __syncthreads();
-    // symmetrise (Y is Hermitian up to rounding): keep the upper triangle mirrored
-    for (int idx = tid; idx < DE * DE; idx += 64) {
-      const int i = idx / DE, j = idx % DE;
-      if (i < j) {
-        sxr[j * LD + i] = sxr[i * LD + j];
-        if constexpr (CPLX) sxi[j * LD + i] = -sxi[i * LD + j];
-      }
-      if constexpr (CPLX) { if (i == j) sxi[i * LD + i] = T(0); }
-    }
-    __syncthreads();
-    lds_outputs<T, CPLX, DE, 64>(A, c, tid, gid, sxr, sxi);
-  } else {
-    for (int idx = tid; idx < DE * DE; idx += 64) {
-      const int i = idx / DE, j = idx % DE;
-      sxr[i * LD + j] = qb * sar[i * LD + j];
-      if constexpr (CPLX) sxi[i * LD + j] = qb * sai[i * LD + j];
-    }
-    __syncthreads();
-    lds_outputs<T, CPLX, DE, 64>(A, c, tid, gid, sxr, sxi);
-  }
-}
 
 // ------------------------------------------------------------------------------------------
 // message kernel (a6), reductions, small helpers
@@ -2867,29 +226,6 @@ __global__ __launch_bounds__(256) void k_scale_offdiag(double* x, int64_t M, int
   }
 }
 
-// ------------------------------------------------------------------------------------------
-// launchers
-// ------------------------------------------------------------------------------------------
-
-static inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
-
-// Register (one lane per cluster) instantiations: which (De, precision, field, mode) fit the
-// register file (the whole De x De matrix and, with vectors, U live in one lane's VGPRs).
-template <typename T, bool CPLX, int DE, int MODE>
-constexpr bool reg_ok() {
-  constexpr bool dbl = std::is_same<T, double>::value;
-  if constexpr (DE <= 4) return true;
-  if constexpr (DE == 8) return !(dbl && CPLX && MODE != MODE_CERTIFY);
-  return false;  // D_e = 16: H + U exceed the arch VGPR file of one lane; the LDS kernel takes it
-}
-
-// Scaling-and-squaring Gibbs kernel (shape code W = 0): dimensions and fields compiled.
-static bool expm_ok(int De, bool cplx) { return De == 16 || De == 32 || De == 64 || De == 128 || De == 256; }
-
-// (childless 4 x 4 and 8 x 8 clusters are the overlaps of the two-level family)
-static bool reg_pair(int De, int Dc) {
-  return (De == 2 && Dc == 0) || (De == 4 && (Dc == 2 || Dc == 0)) || (De == 8 && (Dc == 4 || Dc == 2 || Dc == 0));
-}
 
 int cluster_shapes(int De, int Dc, bool dbl, bool cplx, int mode, int* out) {
   int n = 0;
@@ -2924,136 +260,32 @@ int lds_shapes(int De, int* out) {
   }
 }
 
-template <typename T, bool CPLX, int MODE, int DE, int W>
-static void launch_lds_w(const ClusterArgs<T>& a, hipStream_t s) {
-  constexpr int G = 64 / W;
-  hipLaunchKernelGGL((k_cluster_lds<T, CPLX, DE, MODE, W>), dim3((unsigned)((a.n + G - 1) / G)), dim3(64), 0, s, a);
-}
-
-template <typename T, bool CPLX, int MODE, int DE, int DC>
-static hipError_t launch_reg(const ClusterArgs<T>& a, int block, hipStream_t s) {
-  if constexpr (reg_ok<T, CPLX, DE, MODE>()) {
-    hipLaunchKernelGGL((k_cluster_reg<T, CPLX, DE, DC, MODE>), dim3(grid_for(a.n, block)), dim3(block), 0, s, a);
-    return hipGetLastError();
-  } else {
-    return hipErrorInvalidValue;
-  }
-}
-
-template <typename T, bool CPLX, int MODE>
-static hipError_t launch_cluster_m(const ClusterArgs<T>& a, int block, int W, hipStream_t s) {
-  if (a.n == 0) return hipSuccess;
-  // the register kernels hold one slot per site for single-site children
-  if (a.Dc == 2 && (a.maxch < 1 || a.maxch > log2i(a.De))) return hipErrorInvalidValue;
-  if (a.Dc == 2 && a.fp != nullptr && a.ch_rslot == nullptr) return hipErrorInvalidValue;
-  if (W == 0 || W == 4) {   // 0: one wave per cluster up to D = 32, 4: one workgroup per cluster
-    if constexpr (MODE == MODE_GIBBS) {
-      if (a.fp != nullptr || a.n > 0x7fffffff) return hipErrorInvalidValue;
-      if (a.De == 16 && W == 0)
-        hipLaunchKernelGGL((k_cluster_expm<T, CPLX, 16>), dim3((unsigned)a.n), dim3(64), 0, s, a);
-      else if (a.De == 32 && W == 0)
-        hipLaunchKernelGGL((k_cluster_expm<T, CPLX, 32>), dim3((unsigned)a.n), dim3(64), 0, s, a);
-      else if (a.De >= 32 && a.De <= 256 && a.expm_scratch != nullptr && a.expm_blocks > 0) {
-        const unsigned grid = (unsigned)std::min<int64_t>(a.n, a.expm_blocks);
-        if (a.De == 32)
-          hipLaunchKernelGGL((k_cluster_expm_wg<T, CPLX, 32>), dim3(grid), dim3(256), 0, s, a, a.expm_scratch, a.expm_slab);
-        else if (a.De == 64)
-          hipLaunchKernelGGL((k_cluster_expm_wg<T, CPLX, 64>), dim3(grid), dim3(256), 0, s, a, a.expm_scratch, a.expm_slab);
-        else if (a.De == 128)
-          hipLaunchKernelGGL((k_cluster_expm_wg<T, CPLX, 128>), dim3(grid), dim3(256), 0, s, a, a.expm_scratch, a.expm_slab);
-        else if (a.De == 256)
-          hipLaunchKernelGGL((k_cluster_expm_wg<T, CPLX, 256>), dim3(grid), dim3(256), 0, s, a, a.expm_scratch, a.expm_slab);
-        else
-          return hipErrorInvalidValue;
-      } else
-        return hipErrorInvalidValue;
-      return hipGetLastError();
-    }
-    return hipErrorInvalidValue;
-  }
-  if (W == 2) {
-    if constexpr (MODE == MODE_CERTIFY && std::is_same<T, double>::value) {
-      if (a.De == 16 || a.De == 32) {
-        if (a.n > 0x7fffffff) return hipErrorInvalidValue;
-        if (a.De == 16)
-          hipLaunchKernelGGL((k_cluster_tridiag_w<CPLX, 16>), dim3((unsigned)a.n), dim3(64), 0, s, a);
-        else
-          hipLaunchKernelGGL((k_cluster_tridiag_w<CPLX, 32>), dim3((unsigned)a.n), dim3(64), 0, s, a);
-        return hipGetLastError();
-      }
-      if (a.expm_scratch == nullptr || a.expm_blocks <= 0) return hipErrorInvalidValue;
-      const unsigned grid = (unsigned)std::min<int64_t>(a.n, a.expm_blocks);
-      if (a.De == 64)
-        hipLaunchKernelGGL((k_cluster_tridiag<CPLX, 64>), dim3(grid), dim3(256), 0, s, a, a.expm_scratch, a.expm_slab);
-      else if (a.De == 128)
-        hipLaunchKernelGGL((k_cluster_tridiag<CPLX, 128>), dim3(grid), dim3(256), 0, s, a, a.expm_scratch, a.expm_slab);
-      else if (a.De == 256)
-        hipLaunchKernelGGL((k_cluster_tridiag<CPLX, 256>), dim3(grid), dim3(256), 0, s, a, a.expm_scratch, a.expm_slab);
-      else
-        return hipErrorInvalidValue;
-      return hipGetLastError();
-    }
-    return hipErrorInvalidValue;
-  }
-  if (W == 1 && a.De >= 8) {
-    if (a.De == 8 && a.Dc == 4) return launch_reg<T, CPLX, MODE, 8, 4>(a, block, s);
-    if (a.De == 8 && a.Dc == 2) return launch_reg<T, CPLX, MODE, 8, 2>(a, block, s);
-    if (a.De == 8 && a.Dc == 0) return launch_reg<T, CPLX, MODE, 8, 0>(a, block, s);
-    return hipErrorInvalidValue;
-  }
-  if (a.De == 2 && a.Dc == 0) {
-    hipLaunchKernelGGL((k_cluster_reg<T, CPLX, 2, 0, MODE>), dim3(grid_for(a.n, block)), dim3(block), 0, s, a);
-  } else if (a.De == 4 && a.Dc == 2) {
-    hipLaunchKernelGGL((k_cluster_reg<T, CPLX, 4, 2, MODE>), dim3(grid_for(a.n, block)), dim3(block), 0, s, a);
-  } else if (a.De == 4 && a.Dc == 0 && W == 1) {
-    hipLaunchKernelGGL((k_cluster_reg<T, CPLX, 4, 0, MODE>), dim3(grid_for(a.n, block)), dim3(block), 0, s, a);
-  } else if (a.fp != nullptr) {
-    return hipErrorInvalidValue;  // fused update only in the register kernel
-  } else if (a.De == 4 && W == 64) {
-    launch_lds_w<T, CPLX, MODE, 4, 64>(a, s);
-  } else if (a.De == 8 && W == 16) {
-    launch_lds_w<T, CPLX, MODE, 8, 16>(a, s);
-  } else if (a.De == 8 && W == 8) {
-    launch_lds_w<T, CPLX, MODE, 8, 8>(a, s);
-  } else if (a.De == 8 && W == 64) {
-    launch_lds_w<T, CPLX, MODE, 8, 64>(a, s);
-  } else if (a.De == 16 && W == 16) {
-    launch_lds_w<T, CPLX, MODE, 16, 16>(a, s);
-  } else if (a.De == 16 && W == 32) {
-    launch_lds_w<T, CPLX, MODE, 16, 32>(a, s);
-  } else if (a.De == 16 && W == 64) {
-    launch_lds_w<T, CPLX, MODE, 16, 64>(a, s);
-  } else if (a.De == 32 && W == 32) {
-    launch_lds_w<T, CPLX, MODE, 32, 32>(a, s);
-  } else if (a.De == 32 && W == 64) {
-    launch_lds_w<T, CPLX, MODE, 32, 64>(a, s);
-  } else if (a.De == 64 && W == 64) {
-    launch_lds_w<T, CPLX, MODE, 64, 64>(a, s);
-  } else if ((a.De == 128 || a.De == 256) && a.big_scratch != nullptr) {
-    const unsigned grid = (unsigned)std::min<int64_t>(a.n, a.big_blocks);
-    hipLaunchKernelGGL((k_cluster_big<T, CPLX, MODE>), dim3(grid), dim3(1024), 0, s, a, (T*)a.big_scratch,
-                       a.big_slab);
-  } else {
-    return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
+extern template hipError_t launch_cluster_mode<float, false, MODE_GIBBS>(const ClusterArgs<float>&, int, int, hipStream_t);
+extern template hipError_t launch_cluster_mode<float, true, MODE_GIBBS>(const ClusterArgs<float>&, int, int, hipStream_t);
+extern template hipError_t launch_cluster_mode<float, false, MODE_GROUND>(const ClusterArgs<float>&, int, int, hipStream_t);
+extern template hipError_t launch_cluster_mode<float, true, MODE_GROUND>(const ClusterArgs<float>&, int, int, hipStream_t);
+extern template hipError_t launch_cluster_mode<double, false, MODE_GIBBS>(const ClusterArgs<double>&, int, int, hipStream_t);
+extern template hipError_t launch_cluster_mode<double, true, MODE_GIBBS>(const ClusterArgs<double>&, int, int, hipStream_t);
+extern template hipError_t launch_cluster_mode<double, false, MODE_GROUND>(const ClusterArgs<double>&, int, int, hipStream_t);
+extern template hipError_t launch_cluster_mode<double, true, MODE_GROUND>(const ClusterArgs<double>&, int, int, hipStream_t);
+extern template hipError_t launch_cluster_mode<double, false, MODE_CERTIFY>(const ClusterArgs<double>&, int, int, hipStream_t);
+extern template hipError_t launch_cluster_mode<double, true, MODE_CERTIFY>(const ClusterArgs<double>&, int, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_cluster(const ClusterArgs<T>& a, bool cplx, int mode, int block, int W, hipStream_t s) {
   if (mode == MODE_CERTIFY) {
     if constexpr (std::is_same<T, double>::value) {
-      return cplx ? launch_cluster_m<T, true, MODE_CERTIFY>(a, block, W, s)
-                  : launch_cluster_m<T, false, MODE_CERTIFY>(a, block, W, s);
+      return cplx ? launch_cluster_mode<T, true, MODE_CERTIFY>(a, block, W, s)
+                  : launch_cluster_mode<T, false, MODE_CERTIFY>(a, block, W, s);
     } else {
       return hipErrorInvalidValue;
     }
   }
   if (mode == MODE_GIBBS)
-    return cplx ? launch_cluster_m<T, true, MODE_GIBBS>(a, block, W, s)
-                : launch_cluster_m<T, false, MODE_GIBBS>(a, block, W, s);
-  return cplx ? launch_cluster_m<T, true, MODE_GROUND>(a, block, W, s)
-              : launch_cluster_m<T, false, MODE_GROUND>(a, block, W, s);
+    return cplx ? launch_cluster_mode<T, true, MODE_GIBBS>(a, block, W, s)
+                : launch_cluster_mode<T, false, MODE_GIBBS>(a, block, W, s);
+  return cplx ? launch_cluster_mode<T, true, MODE_GROUND>(a, block, W, s)
+              : launch_cluster_mode<T, false, MODE_GROUND>(a, block, W, s);
 }
 
 template <typename T>
@@ -3122,34 +354,6 @@ hipError_t launch_copy(T* dst, const T* src, int64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL((k_copy<T>), dim3(grid_for(n, 256)), dim3(256), 0, s, dst, src, n);
   return hipGetLastError();
-}
-
-hipError_t launch_cluster_vjp(const ClusterArgs<double>& a, bool cplx, int mode, hipStream_t s) {
-  if (a.n == 0) return hipSuccess;
-  const dim3 g((unsigned)a.n), b(64);
-#define VJP_CASE(DE)                                                                                   \
-  if (a.De == DE) {                                                                                    \
-    if (mode == MODE_GIBBS) {                                                                          \
-      if (cplx) hipLaunchKernelGGL((k_cluster_vjp<double, true, DE, MODE_GIBBS>), g, b, 0, s, a);      \
-      else hipLaunchKernelGGL((k_cluster_vjp<double, false, DE, MODE_GIBBS>), g, b, 0, s, a);          \
-    } else {                                                                                           \
-      if (cplx) hipLaunchKernelGGL((k_cluster_vjp<double, true, DE, MODE_GROUND>), g, b, 0, s, a);     \
-      else hipLaunchKernelGGL((k_cluster_vjp<double, false, DE, MODE_GROUND>), g, b, 0, s, a);         \
-    }                                                                                                  \
-    return hipGetLastError();                                                                          \
-  }
-  VJP_CASE(2)
-  VJP_CASE(4)
-  VJP_CASE(8)
-  VJP_CASE(16)
-  VJP_CASE(32)
-  if (a.De == 64 && !cplx) {
-    if (mode == MODE_GIBBS) hipLaunchKernelGGL((k_cluster_vjp<double, false, 64, MODE_GIBBS>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_cluster_vjp<double, false, 64, MODE_GROUND>), g, b, 0, s, a);
-    return hipGetLastError();
-  }
-#undef VJP_CASE
-  return hipErrorInvalidValue;
 }
 
 hipError_t launch_set_params(double* h, const double* hfix, const int64_t* pc_hoff, const int64_t* pc_ptr,
