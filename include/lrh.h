@@ -188,7 +188,8 @@ typedef struct {
                        theta <- 1 (for nu = 0 this is Algorithm 2's initialisation)      */
   double theta;     /* theta_k (updated by the call)                                     */
   double beta;      /* inverse temperature of the stage (> 0)                            */
-  double L;         /* Lipschitz bound L_beta (> 0); beta * Lambda_G / 2 is the paper's  */
+  double L;         /* Lipschitz bound L_beta (> 0); 0 selects the paper's beta Lambda_G / 2
+                       (Sec. 4.2.2; Delta_G + d for 2-local families, Sec. 4.1.2), written back */
 } lrh_nesterov_state;
 
 /* Algorithm 2 (accelerated ascent on the smoothed dual): n_iter iterations of
@@ -198,16 +199,19 @@ typedef struct {
  * nu, zeta: device, nu_len elements (LRH_F32: float).  st: host, updated on return.
  * With LRH_FUSED the iterations run as one launch each from a captured graph; the
  * result is the same arithmetic in a different launch structure.
- * Errors: LRH_E_INVALID (null pointers, beta <= 0, L <= 0, n_iter < 0). */
+ * Errors: LRH_E_INVALID (null pointers, beta <= 0 or not finite, L < 0, n_iter < 0). */
 lrh_status lrh_step_nesterov(lrh_problem p, void* nu, void* zeta, lrh_nesterov_state* st,
                              int32_t n_iter, uint32_t flags, hipStream_t stream);
 
 /* Certified lower bound (weak duality, Sec. 4.1): FP64 lambda_min of every cluster at
  * nu, summed per instance in a fixed order.  q_dev[i] = Q_C(nu), margin_dev[i] =
- * sum_e 8 D_e eps_64 ||theta_e||_F (backward-error margin of the FP64 eigen-solve);
- * the certified bound is q - margin <= f*_C <= E0.  nu may be float (LRH_F32); it is
- * widened to double before theta_e is formed.  lmin_dev: device double[n_clusters]
- * (library cluster order) or NULL.
+ * sum_e [8 D_e eps_64 ||theta_e||_F + r_e] (backward-error margin of the FP64 eigen-solve;
+ * r_e = Frobenius norm of the off-diagonal part left by the Jacobi sweeps at D_e <= 8, so the
+ * bound holds even when a solve stops at its sweep cap, 0 at D_e >= 16 where the value is the
+ * lower end of a Sturm bracket); the certified bound is q - margin <= f*_C <= E0.
+ * Certification always uses the FP64 default Jacobi tolerance (lrh_set_jacobi's tolerance
+ * does not apply; its sweep cap does).  nu may be float (LRH_F32); it is widened to double
+ * before theta_e is formed.  lmin_dev: device double[n_clusters] (library cluster order) or NULL.
  * Errors: LRH_E_INVALID (null nu/q/margin). */
 lrh_status lrh_certify(lrh_problem p, const void* nu, uint32_t flags, double* q_dev,
                        double* margin_dev, double* lmin_dev, hipStream_t stream);
@@ -234,13 +238,13 @@ lrh_status lrh_dual_vjp(lrh_problem p, const void* nu, uint32_t flags, double be
 
 /* Certified value after T accelerated steps and its gradient (FP64):
  *   B_T = Q(nu^T) per instance, nu^T = T steps of Algorithm 2 at fixed beta and Lipschitz L
- *   from nu0 (zeta0 = nu0, theta0 = 1; nu0 == NULL: zero messages),
+ *   (L = 0: beta Lambda_G / 2) from nu0 (zeta0 = nu0, theta0 = 1; nu0 == NULL: zero messages),
  * and the reverse-mode derivative of sum_i qbar_i B_T,i (qbar NULL: all ones) with respect to
  * the parameters (param_bar_dev, double[n_params]) and to nu0 (nu0_bar_dev, nu_len doubles,
  * LRH_PACKED_COTANGENT applies).  The forward pass keeps every extrapolated point (T * nu_len
  * doubles of workspace); each reverse step is one lrh_dual_vjp at that point.  The rounding
  * margin of lrh_certify is not included in B_T.
- * Errors: LRH_E_INVALID (beta <= 0, L <= 0, T < 0, null bound_dev), LRH_E_UNSUPPORTED as for
+ * Errors: LRH_E_INVALID (beta <= 0, L < 0, T < 0, null bound_dev), LRH_E_UNSUPPORTED as for
  * lrh_dual_vjp. */
 lrh_status lrh_unrolled_bound_grad(lrh_problem p, const double* nu0_dev, double beta, double L, int32_t T,
                                    const double* qbar_dev, double* bound_dev, double* param_bar_dev,
@@ -308,11 +312,25 @@ lrh_status lrh_time_messages(lrh_problem p, void* nu, void* zeta, uint32_t flags
                              double* us, hipStream_t stream);
 
 /* Jacobi sweep cap (default 30) and relative off-diagonal tolerance (0 = default:
- * 4 eps of the iteration precision). */
+ * 4 eps of the iteration precision).  Like lrh_set_shape, lrh_autotune and lrh_set_slab_limit,
+ * this drops the graphs captured for LRH_FUSED (they hold the old settings); it waits for the
+ * device to finish with them first. */
 lrh_status lrh_set_jacobi(lrh_problem p, int32_t max_sweeps, double rel_tol);
+
+/* Cap the number of per-workgroup FP64 scratch slabs of the large-cluster kernels (workgroup
+ * Gibbs kernel and tridiagonal certification at D_e >= 32, slab Jacobi at D_e >= 128): a slab
+ * holds up to five D_e x D_e matrices (complex D_e = 256: 5.2 MB), and by default up to 1024
+ * (512 at D_e = 256) are allocated.  With fewer slabs than clusters each workgroup processes
+ * several clusters in turn in its slab; results do not depend on the cap.  max_slabs = 0
+ * restores the default.  Memory already allocated is kept, only its first max_slabs slabs are
+ * used.  Errors: LRH_E_INVALID (null problem, max_slabs < 0). */
+lrh_status lrh_set_slab_limit(lrh_problem p, int64_t max_slabs);
 
 void lrh_destroy(lrh_problem p);
 const char* lrh_last_error(void);
+/* Static text naming the HIP headers the library was compiled against and its device
+ * architecture (the runtime serving the process may be another release of the same major). */
+const char* lrh_build_info(void);
 
 #ifdef __cplusplus
 }

@@ -20,6 +20,8 @@ from __future__ import annotations
 from dataclasses import dataclass, field
 from typing import Dict, Iterable, List, Optional, Sequence, Tuple
 
+import math
+
 import numpy as np
 
 X = np.array([[0, 1], [1, 0]], dtype=np.complex128)
@@ -530,3 +532,31 @@ def workload_c4(n_inst: int = 512, seed: int = 4, Lmin: int = 8, Lmax: int = 64,
 
 def workload_c5(L: int = 64, seed: int = 5) -> ProblemDesc:
     return xxz_triangular(L, 0.5, seed)
+
+
+def exact_spectrum_matrix(lam, cplx: bool = False) -> np.ndarray:
+    """(H/sqrt(D)) diag(lam) (H/sqrt(D)) with H the Sylvester Hadamard matrix and lam integers:
+    every entry is a multiple of 1/D (exact in FP64) and the spectrum is exactly lam.  cplx:
+    conjugated by diag(i^k), which multiplies entries by powers of i (exact as well)."""
+    D = len(lam)
+    H = np.array([[1.0]])
+    while H.shape[0] < D:
+        H = np.block([[H, H], [H, -H]])
+    if H.shape[0] != D:
+        raise ValueError("D must be a power of two")
+    A = (H @ np.diag(np.asarray(lam, np.float64)) @ H) / D
+    if not np.array_equal(A * D, np.round(A * D)):
+        raise ValueError("entries not exact: integers too large")
+    if cplx:
+        s = np.array([1j ** k for k in range(D)])
+        A = (s[:, None] * A) * np.conj(s)[None, :]
+    return A
+
+
+def exact_spectrum_problem(lam, cplx: bool = False) -> ProblemDesc:
+    """One term on log2(D) qubits whose matrix has exactly the spectrum lam (integers)."""
+    D = len(lam)
+    k = int(round(math.log2(D)))
+    b = _Builder(f"exact_spectrum_{D}", k)
+    b.add_term(tuple(range(k)), exact_spectrum_matrix(lam, cplx))
+    return b.build(real=not cplx)

@@ -570,8 +570,11 @@ __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
   for (int k = 0; k < DE; ++k) { lam[k] = H.r[tri_index(k, k, DE)]; lmin = fmin(lmin, lam[k]); }
   if (!isfinite((double)lmin) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
   if constexpr (MODE == MODE_CERTIFY) {
+    // The rotated matrix differs from a diagonal one by its remaining off-diagonal part, so
+    // lambda_min >= min diag - ||off||_2 >= min diag - ||off||_F (Weyl): the bound holds whether or
+    // not the sweeps reached the tolerance.  The first term is the backward error of the rotations.
     A.scal[gid] = (double)lmin;
-    A.scal2[gid] = 8.0 * DE * DBL_EPSILON * sqrt((double)nrm2);
+    A.scal2[gid] = 8.0 * DE * DBL_EPSILON * sqrt((double)nrm2) + sqrt(offdiag2<T, CPLX, DE>(H));
     return;
   } else {
     // ---- a4: marginal weights ----
@@ -1105,9 +1108,23 @@ __global__ __launch_bounds__(64) void k_cluster_lds(ClusterArgs<T> A) {
   if (active && lt == 0 && !isfinite((double)lmin) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
   const int32_t gid = active ? A.gid[c] : 0;
   if constexpr (MODE == MODE_CERTIFY) {
+    // remaining off-diagonal mass (Weyl, as in the register kernel)
+    double off2 = 0.0;
+    if (active)
+      for (int idx = lt; idx < DE * DE; idx += W) {
+        const int i = idx / DE, j = idx % DE;
+        if (i == j) continue;
+        const double xr = (double)sar[i * LD + j];
+        off2 = fma(xr, xr, off2);
+        if constexpr (CPLX) {
+          const double xi = (double)sai[i * LD + j];
+          off2 = fma(xi, xi, off2);
+        }
+      }
+    off2 = seg_sum<W>(off2);
     if (active && lt == 0) {
       A.scal[gid] = (double)lmin;
-      A.scal2[gid] = 8.0 * DE * DBL_EPSILON * sqrt((double)nrm2);
+      A.scal2[gid] = 8.0 * DE * DBL_EPSILON * sqrt((double)nrm2) + sqrt(off2);
     }
   } else {
     // ---- a4: weights and the marginal U diag(p) U^H (over A) ----

@@ -8,6 +8,7 @@
 // holds only the top clusters and their maximal pairwise overlaps; each term is then split
 // evenly over the top clusters that hold its support.
 #include <hip/hip_runtime.h>
+#include <hip/hip_version.h>
 
 #include <algorithm>
 #include <cmath>
@@ -103,16 +104,22 @@ struct Work {
   bool fused_ready = false;
 };
 
+// A captured chunk fixes every kernel argument at capture time (buffers, launch shapes, Jacobi
+// settings, slab counts), so the cache is keyed by the caller's buffers and the problem's settings
+// generation, which every settings call advances (dropping the graphs of older generations).
 struct GraphKey {
   int prec;
   const void* nu;
   const void* ze;
+  uint64_t gen;
   bool operator<(const GraphKey& o) const {
     if (prec != o.prec) return prec < o.prec;
     if (nu != o.nu) return nu < o.nu;
-    return ze < o.ze;
+    if (ze != o.ze) return ze < o.ze;
+    return gen < o.gen;
   }
 };
+constexpr size_t kMaxGraphs = 8;  // captured chunks kept per problem (least recently used evicted)
 
 }  // namespace
 
@@ -160,7 +167,9 @@ struct lrh_problem_s {
   Work<float> w32;
   Work<double> w64;
   hipStream_t cap_stream = nullptr;
-  std::map<GraphKey, hipGraphExec_t> graphs;
+  std::map<GraphKey, std::pair<hipGraphExec_t, uint64_t>> graphs;  // exec, last use
+  uint64_t settings_gen = 0, graph_clock = 0;
+  int64_t slab_limit = 0;                // cap on per-workgroup scratch slabs (0: default caps)
   std::vector<void*> allocs;
   std::vector<int32_t> pp_tmp_g;
 
@@ -169,7 +178,7 @@ struct lrh_problem_s {
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(device);
-    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second.first);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (void* p : allocs) (void)hipFree(p);
     (void)hipSetDevice(cur);
@@ -832,6 +841,10 @@ template <typename T>
 lrh_status ensure_work(lrh_problem_s* P, bool fused) {
   Work<T>& w = P->work<T>();
   lrh_status st;
+  if (P->slab_limit > 0) {   // slabs allocated before a limit was set: use only the first ones
+    w.big_blocks = std::min<int64_t>(w.big_blocks, P->slab_limit);
+    w.xblocks = std::min<int64_t>(w.xblocks, P->slab_limit);
+  }
   if (!w.big) {
     int64_t nbig = 0;
     int Dmax = 0;
@@ -842,7 +855,7 @@ lrh_status ensure_work(lrh_problem_s* P, bool fused) {
       }
     if (nbig > 0) {
       w.big_slab = (int64_t)(P->cplx ? 6 : 3) * Dmax * Dmax;
-      w.big_blocks = std::min<int64_t>(nbig, 512);
+      w.big_blocks = std::min<int64_t>(nbig, P->slab_limit > 0 ? std::min<int64_t>(P->slab_limit, 512) : 512);
       if ((st = P->dalloc(&w.big, w.big_slab * w.big_blocks)) != LRH_OK) return st;
     }
   }
@@ -856,7 +869,8 @@ lrh_status ensure_work(lrh_problem_s* P, bool fused) {
       }
     if (nx > 0) {
       w.xslab = (int64_t)5 * (P->cplx ? 2 : 1) * Dmax * Dmax;
-      w.xblocks = std::min<int64_t>(nx, Dmax >= 256 ? 512 : 1024);
+      const int64_t cap = Dmax >= 256 ? 512 : 1024;
+      w.xblocks = std::min<int64_t>(nx, P->slab_limit > 0 ? std::min<int64_t>(P->slab_limit, cap) : cap);
       if ((st = P->dalloc(&w.xbig, w.xslab * w.xblocks)) != LRH_OK) return st;
     }
   }
@@ -1108,6 +1122,58 @@ lrh_status nesterov_plain(lrh_problem_s* P, T* nu, T* ze, lrh_nesterov_state* st
   return LRH_OK;
 }
 
+// Destroy every captured chunk (after the device has finished with them).
+void drop_graphs(lrh_problem_s* P) {
+  if (P->graphs.empty()) return;
+  (void)hipDeviceSynchronize();
+  for (auto& g : P->graphs) (void)hipGraphExecDestroy(g.second.first);
+  P->graphs.clear();
+}
+
+// Settings that captured chunks bake into their kernel arguments changed: start a new generation.
+void settings_changed(lrh_problem_s* P) {
+  ++P->settings_gen;
+  if (!P->host_only) {
+    DeviceGuard guard(P->device);
+    drop_graphs(P);
+  }
+}
+
+// Launch the captured chunk for `key`, capturing it first (enqueue(stream) records the chunk's
+// launches).  At most kMaxGraphs chunks are kept; the least recently used one is evicted.
+template <typename F>
+lrh_status launch_cached_graph(lrh_problem_s* P, const GraphKey& key, hipStream_t s, F&& enqueue) {
+  auto it = P->graphs.find(key);
+  if (it == P->graphs.end()) {
+    if (P->graphs.size() >= kMaxGraphs) {
+      auto lru = P->graphs.begin();
+      for (auto jt = P->graphs.begin(); jt != P->graphs.end(); ++jt)
+        if (jt->second.second < lru->second.second) lru = jt;
+      HIP_TRY(hipDeviceSynchronize());
+      (void)hipGraphExecDestroy(lru->second.first);
+      P->graphs.erase(lru);
+    }
+    if (!P->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeRelaxed));
+    lrh_status est = enqueue(P->cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t ee = hipStreamEndCapture(P->cap_stream, &graph);
+    if (est != LRH_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return est;
+    }
+    if (ee != hipSuccess) return fail(LRH_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+    hipGraphExec_t exec = nullptr;
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail(LRH_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    it = P->graphs.emplace(key, std::make_pair(exec, uint64_t(0))).first;
+  }
+  it->second.second = ++P->graph_clock;
+  HIP_TRY(hipGraphLaunch(it->second.first, s));
+  return LRH_OK;
+}
+
 bool fusable(const lrh_problem_s* P) {
   if (P->mb.size() != 1 || P->mb[0].D != 2) return false;
   for (const CBucket& B : P->cb)
@@ -1201,26 +1267,10 @@ lrh_status nesterov_fused(lrh_problem_s* P, T* nu, T* ze, lrh_nesterov_state* st
     }
     HIP_TRY(launch_set_fused(P->fp, tab, n + 1, s));
     if (n == CH) {
-      GraphKey key{prec, nu, ze};
-      auto it = P->graphs.find(key);
-      if (it == P->graphs.end()) {
-        if (!P->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
-        HIP_TRY(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeRelaxed));
-        lrh_status est = fused_enqueue<T>(P, nu, ze, n, P->cap_stream);
-        hipGraph_t graph = nullptr;
-        hipError_t ee = hipStreamEndCapture(P->cap_stream, &graph);
-        if (est != LRH_OK) {
-          if (graph) (void)hipGraphDestroy(graph);
-          return est;
-        }
-        if (ee != hipSuccess) return fail(LRH_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
-        hipGraphExec_t exec = nullptr;
-        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (ie != hipSuccess) return fail(LRH_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
-        it = P->graphs.emplace(key, exec).first;
-      }
-      HIP_TRY(hipGraphLaunch(it->second, s));
+      lrh_status gst = launch_cached_graph(P, GraphKey{prec, nu, ze, P->settings_gen}, s, [&](hipStream_t cs) {
+        return fused_enqueue<T>(P, nu, ze, n, cs);
+      });
+      if (gst != LRH_OK) return gst;
     } else {
       if ((st = fused_enqueue<T>(P, nu, ze, n, s)) != LRH_OK) return st;
     }
@@ -1269,26 +1319,10 @@ lrh_status nesterov_graph(lrh_problem_s* P, T* nu, T* ze, lrh_nesterov_state* st
     }
     HIP_TRY(launch_set_fused(P->fp, tab, n, s));
     if (n == CH) {
-      GraphKey key{prec, nu, ze};
-      auto it = P->graphs.find(key);
-      if (it == P->graphs.end()) {
-        if (!P->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
-        HIP_TRY(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeRelaxed));
-        lrh_status est = table_enqueue<T>(P, nu, ze, n, P->cap_stream);
-        hipGraph_t graph = nullptr;
-        hipError_t ee = hipStreamEndCapture(P->cap_stream, &graph);
-        if (est != LRH_OK) {
-          if (graph) (void)hipGraphDestroy(graph);
-          return est;
-        }
-        if (ee != hipSuccess) return fail(LRH_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
-        hipGraphExec_t exec = nullptr;
-        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (ie != hipSuccess) return fail(LRH_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
-        it = P->graphs.emplace(key, exec).first;
-      }
-      HIP_TRY(hipGraphLaunch(it->second, s));
+      lrh_status gst = launch_cached_graph(P, GraphKey{prec, nu, ze, P->settings_gen}, s, [&](hipStream_t cs) {
+        return table_enqueue<T>(P, nu, ze, n, cs);
+      });
+      if (gst != LRH_OK) return gst;
     } else {
       if ((st = table_enqueue<T>(P, nu, ze, n, s)) != LRH_OK) return st;
     }
@@ -1579,6 +1613,13 @@ extern "C" {
 
 const char* lrh_last_error(void) { return g_err.c_str(); }
 
+const char* lrh_build_info(void) {
+  static const std::string info = "HIP headers " + std::to_string(HIP_VERSION_MAJOR) + "." +
+                                  std::to_string(HIP_VERSION_MINOR) + "." + std::to_string(HIP_VERSION_PATCH) +
+                                  ", device code gfx950";
+  return info.c_str();
+}
+
 lrh_status lrh_build_clusters(const lrh_problem_desc* desc, int hip_device, lrh_problem* out) {
   if (!out) return fail(LRH_E_INVALID, "null output handle");
   *out = nullptr;
@@ -1680,7 +1721,9 @@ lrh_status lrh_step_nesterov(lrh_problem p, void* nu, void* zeta, lrh_nesterov_s
                              uint32_t flags, hipStream_t stream) {
   if (!p || !nu || !zeta || !st) return fail(LRH_E_INVALID, "null argument");
   if (p->host_only) return fail(LRH_E_INVALID, "problem was built without a device");
-  if (!(st->beta > 0.0) || !(st->L > 0.0)) return fail(LRH_E_INVALID, "beta and L must be positive");
+  if (!(st->beta > 0.0) || !std::isfinite(st->beta)) return fail(LRH_E_INVALID, "beta must be positive and finite");
+  if (!(st->L >= 0.0) || !std::isfinite(st->L)) return fail(LRH_E_INVALID, "L must be >= 0 and finite");
+  if (st->L == 0.0) st->L = st->beta * p->Lambda / 2.0;   // the paper's L_beta = beta Lambda_G / 2
   if (n_iter < 0 || st->k < 0) return fail(LRH_E_INVALID, "negative iteration counts");
   if (st->k > 0 && !(st->theta > 0.0 && st->theta <= 1.0)) return fail(LRH_E_INVALID, "theta out of (0, 1]");
   DeviceGuard guard(p->device);
@@ -1709,7 +1752,7 @@ lrh_status lrh_certify(lrh_problem p, const void* nu, uint32_t flags, double* q_
   }
   for (const CBucket& B : p->cb) {
     ClusterArgs<double> a = base_args<double>(p, B);
-    a.tol = p->tol_override > 0 ? p->tol_override : default_tol<double>();
+    a.tol = default_tol<double>();   // certification ignores a loosened iteration tolerance
     if (B.mb_child >= 0) a.nu_c = nu64 + p->mb[B.mb_child].offset;
     if (B.mb_self >= 0) a.nu_p = nu64 + p->mb[B.mb_self].offset;
     a.R = nullptr;
@@ -1757,7 +1800,8 @@ lrh_status lrh_unrolled_bound_grad(lrh_problem p, const double* nu0_dev, double 
                                    double* nu0_bar_dev, uint32_t flags, hipStream_t stream) {
   if (!p || !bound_dev) return fail(LRH_E_INVALID, "null argument");
   if (p->host_only) return fail(LRH_E_INVALID, "problem was built without a device");
-  if (!(beta > 0.0) || !(L > 0.0) || T < 0) return fail(LRH_E_INVALID, "beta, L must be positive and T >= 0");
+  if (!(beta > 0.0) || !(L >= 0.0) || T < 0) return fail(LRH_E_INVALID, "beta > 0, L >= 0 and T >= 0 required");
+  if (L == 0.0) L = beta * p->Lambda / 2.0;
   if (flags & LRH_F32) return fail(LRH_E_UNSUPPORTED, "the adjoint runs in FP64 only");
   DeviceGuard guard(p->device);
   return unrolled_grad(p, nu0_dev, beta, L, T, qbar_dev, bound_dev, param_bar_dev, nu0_bar_dev,
@@ -1783,6 +1827,7 @@ lrh_status lrh_autotune(lrh_problem p, uint32_t flags, const char* cache_path, h
   if (!p) return fail(LRH_E_INVALID, "null problem");
   if (p->host_only) return fail(LRH_E_INVALID, "problem was built without a device");
   DeviceGuard guard(p->device);
+  settings_changed(p);
   if (flags & LRH_F32) return autotune_t<float>(p, cache_path, stream);
   return autotune_t<double>(p, cache_path, stream);
 }
@@ -1820,6 +1865,7 @@ lrh_status lrh_set_shape(lrh_problem p, int32_t De, int32_t block, int32_t W, ui
     any = true;
   }
   if (!any) return fail(LRH_E_INVALID, "no cluster bucket with that dimension");
+  settings_changed(p);
   return LRH_OK;
 }
 
@@ -1848,6 +1894,15 @@ lrh_status lrh_set_jacobi(lrh_problem p, int32_t max_sweeps, double rel_tol) {
   if (max_sweeps < 0 || !(rel_tol >= 0.0)) return fail(LRH_E_INVALID, "bad Jacobi settings");
   p->max_sweeps = max_sweeps;
   p->tol_override = rel_tol;
+  settings_changed(p);
+  return LRH_OK;
+}
+
+lrh_status lrh_set_slab_limit(lrh_problem p, int64_t max_slabs) {
+  if (!p) return fail(LRH_E_INVALID, "null problem");
+  if (max_slabs < 0) return fail(LRH_E_INVALID, "max_slabs must be >= 0");
+  p->slab_limit = max_slabs;
+  settings_changed(p);
   return LRH_OK;
 }
 

@@ -70,7 +70,8 @@ _lib = None
 EXPORTS = ["lrh_build_clusters", "lrh_query", "lrh_export_clusters", "lrh_export_messages",
            "lrh_dual_eval", "lrh_step_subgrad", "lrh_step_nesterov", "lrh_certify", "lrh_check",
            "lrh_set_jacobi", "lrh_destroy", "lrh_last_error", "lrh_set_params", "lrh_dual_vjp",
-           "lrh_unrolled_bound_grad", "lrh_autotune", "lrh_get_shapes", "lrh_set_shape", "lrh_time_buckets", "lrh_time_messages"]
+           "lrh_unrolled_bound_grad", "lrh_autotune", "lrh_get_shapes", "lrh_set_shape", "lrh_time_buckets", "lrh_time_messages",
+           "lrh_set_slab_limit", "lrh_build_info"]
 
 
 def load(path: str = LIB_PATH):
@@ -86,6 +87,9 @@ def load(path: str = LIB_PATH):
     # runtime they were not built against and crash in the launch.
     import torch  # noqa: F401
     lib = C.CDLL(path)
+    mapped = hip_runtimes_mapped()
+    if len(mapped) != 1:
+        raise RuntimeError(f"expected exactly one HIP runtime in the process, found {mapped}")
     vp, i32, i64, u32, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_double
     sig = {
         "lrh_build_clusters": (i32, [C.POINTER(ProblemDesc), C.c_int, C.POINTER(vp)]),
@@ -98,6 +102,7 @@ def load(path: str = LIB_PATH):
         "lrh_certify": (i32, [vp, vp, u32, vp, vp, vp, vp]),
         "lrh_check": (i32, [vp, vp, C.POINTER(i64), C.POINTER(i64)]),
         "lrh_set_jacobi": (i32, [vp, i32, dbl]),
+        "lrh_set_slab_limit": (i32, [vp, i64]),
         "lrh_set_params": (i32, [vp, vp, vp]),
         "lrh_autotune": (i32, [vp, u32, C.c_char_p, vp]),
         "lrh_set_shape": (i32, [vp, i32, i32, i32, u32]),
@@ -108,6 +113,7 @@ def load(path: str = LIB_PATH):
         "lrh_unrolled_bound_grad": (i32, [vp, vp, dbl, dbl, i32, vp, vp, vp, vp, u32, vp]),
         "lrh_destroy": (None, [vp]),
         "lrh_last_error": (C.c_char_p, []),
+        "lrh_build_info": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -115,6 +121,21 @@ def load(path: str = LIB_PATH):
         f.argtypes = args
     _lib = lib
     return lib
+
+
+def hip_runtimes_mapped():
+    """Distinct libamdhip64 files mapped into this process (Linux /proc/self/maps)."""
+    with open("/proc/self/maps") as f:
+        return sorted({ln.split()[-1] for ln in f if "libamdhip64" in ln and "/" in ln})
+
+
+def runtime_info() -> dict:
+    """The HIP release the library was compiled against, the one torch ships (and which serves
+    the process once torch is imported first), and the runtime files mapped."""
+    import torch
+    lib = load()
+    return dict(library=lib.lrh_build_info().decode(), torch_hip=torch.version.hip,
+                mapped=hip_runtimes_mapped())
 
 
 def _check(code: int):
@@ -227,6 +248,10 @@ def lrh_check(h, stream=None) -> Tuple[int, int]:
 
 def lrh_set_jacobi(h, max_sweeps: int, rel_tol: float = 0.0):
     _check(load().lrh_set_jacobi(h, int(max_sweeps), float(rel_tol)))
+
+
+def lrh_set_slab_limit(h, max_slabs: int):
+    _check(load().lrh_set_slab_limit(h, int(max_slabs)))
 
 
 def lrh_set_params(h, params, stream=None):
@@ -439,7 +464,7 @@ class Problem:
         st.k = 0
         st.theta = 1.0
         st.beta = float(beta)
-        st.L = float(L) if L is not None else float(beta) * self.Lambda / 2.0
+        st.L = 0.0 if L is None else float(L)   # 0: the library's beta Lambda_G / 2
         return st
 
     def step_nesterov(self, nu, zeta, state: NesterovState, n_iter: int, fused: bool = False, stream=None):
@@ -475,7 +500,7 @@ class Problem:
 
     def unrolled_bound_grad(self, beta: float, T: int, L: Optional[float] = None, nu0=None, qbar=None,
                             want_nu0_bar: bool = False, packed: bool = False, stream=None):
-        L = float(beta) * self.Lambda / 2.0 if L is None else float(L)
+        L = 0.0 if L is None else float(L)   # 0: the library's beta Lambda_G / 2
         bound = self.qbuf()
         pbar = (self.torch.empty(self.n_params, dtype=self.torch.float64, device=self.device)
                 if self.n_params else None)
@@ -486,6 +511,9 @@ class Problem:
 
     def set_jacobi(self, max_sweeps: int, rel_tol: float = 0.0):
         lrh_set_jacobi(self.h, max_sweeps, rel_tol)
+
+    def set_slab_limit(self, max_slabs: int):
+        lrh_set_slab_limit(self.h, max_slabs)
 
     def autotune(self, f32: bool = False, cache_path: Optional[str] = None, stream=None):
         lrh_autotune(self.h, LRH_F32 if f32 else 0, cache_path, stream)
@@ -537,21 +565,29 @@ def _autograd():
 
         @staticmethod
         def forward(ctx, nu, params, problem, beta):
-            if params is not None and problem.n_params:
+            with_params = params is not None and problem.n_params > 0
+            if with_params:
                 problem.set_params(params.detach())
             q, g, _ = problem.dual_eval(nu.detach(), beta, grad=True)
-            ctx.problem, ctx.beta = problem, beta
-            ctx.save_for_backward(nu.detach())
+            ctx.problem, ctx.beta, ctx.with_params = problem, beta, with_params
+            if with_params:
+                ctx.save_for_backward(nu.detach(), params.detach().clone())
+            else:
+                ctx.save_for_backward(nu.detach())
             return q, g
 
         @staticmethod
         def backward(ctx, qbar, gbar):
-            (nu,) = ctx.saved_tensors
             P = ctx.problem
+            if ctx.with_params:
+                nu, params = ctx.saved_tensors
+                P.set_params(params)   # the Hamiltonian of this forward, whatever was set since
+            else:
+                (nu,) = ctx.saved_tensors
             qb = None if qbar is None else qbar.contiguous().double()
             gb = None if gbar is None else gbar.contiguous().double()
             nu_bar, pbar = P.dual_vjp(nu, ctx.beta, qb, gb, packed=True)
-            return nu_bar, pbar, None, None
+            return nu_bar, (pbar if ctx.with_params else None), None, None
 
     class UnrolledBound(torch.autograd.Function):
         """params -> B_T per instance (T accelerated steps at fixed beta from zero messages,

@@ -138,3 +138,28 @@ def test_batch_scaled_instances_are_scaled_copies():
     for i, (d, s) in enumerate(zip(descs, scales)):
         R = O.Relaxation(d)
         assert abs(qb[i] - s * R.Q(R.zeros())[0]) <= 1e-12 * max(1.0, abs(qb[i]))
+
+
+def test_one_hip_runtime_and_versions_recorded():
+    """torch is imported before the library, so the process maps exactly one libamdhip64 (two
+    runtimes under one soname crash torch's own launches); the library names the HIP headers it
+    was compiled against, torch the release it ships."""
+    info = lrh.runtime_info()
+    assert len(info["mapped"]) == 1, info
+    assert info["library"].startswith("HIP headers ") and "gfx950" in info["library"]
+    assert info["torch_hip"]
+    print("HIP runtime:", info)
+
+
+def test_settings_calls_and_defaults_on_host_problem():
+    """Settings calls validate their arguments; the slab limit accepts 0 (default) and positive
+    caps.  Compute calls on a host-only problem are rejected before any default is applied."""
+    P = lrh.Problem(W.tfim_chain(4, 1.0, 0.5), -1)
+    P.set_slab_limit(2)
+    P.set_slab_limit(0)
+    _expect(1, lambda: P.set_slab_limit(-1))
+    P.set_jacobi(30, 0.0)
+    _expect(1, lambda: P.set_jacobi(-1, 0.0))
+    st = lrh.NesterovState()
+    st.k, st.theta, st.beta, st.L = 0, 1.0, 2.0, 0.0
+    _expect(1, lambda: lrh._check(lrh.load().lrh_step_nesterov(P.h, 8, 8, lrh.C.byref(st), 1, 0, None)))

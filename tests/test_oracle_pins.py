@@ -786,29 +786,6 @@ def test_smoothed_dual_gradient_lipschitz_higher_order(name, maker, lam):
 # the certified value's rounding margin (weak duality in floating point)
 # ------------------------------------------------------------------------------------------
 
-def exact_spectrum_matrix(lam, cplx=False):
-    """(H/sqrt(D)) diag(lam) (H/sqrt(D)) with H the Sylvester Hadamard matrix, lam integers:
-    every entry is a multiple of 1/D (exact in FP64), the spectrum is exactly lam.  cplx:
-    conjugated by diag(i^k), which multiplies entries by powers of i (exact as well)."""
-    from scipy.linalg import hadamard
-    D = len(lam)
-    H = hadamard(D).astype(np.float64)
-    A = (H @ np.diag(np.asarray(lam, np.float64)) @ H) / D
-    assert np.array_equal(A * D, np.round(A * D))
-    if cplx:
-        s = np.array([1j ** k for k in range(D)])
-        A = (s[:, None] * A) * np.conj(s)[None, :]
-    return A
-
-
-def exact_spectrum_problem(lam, cplx=False):
-    D = len(lam)
-    k = int(round(math.log2(D)))
-    b = W._Builder(f"exact_spectrum_{D}", k)
-    b.add_term(tuple(range(k)), exact_spectrum_matrix(lam, cplx))
-    return b.build(real=not cplx)
-
-
 @pytest.mark.parametrize("D,cplx", [(8, False), (16, False), (16, True), (64, True)])
 def test_certify_margin_covers_rounding_on_an_exact_spectrum(D, cplx):
     """Q(0) - margin <= lambda_min for matrices whose spectrum is known exactly and spans
@@ -818,7 +795,7 @@ def test_certify_margin_covers_rounding_on_an_exact_spectrum(D, cplx):
     above = 0
     for _ in range(40):
         lam = rng.integers(-10 ** 6, 10 ** 6, D)
-        R = O.Relaxation(exact_spectrum_problem(lam, cplx))
+        R = O.Relaxation(W.exact_spectrum_problem(lam, cplx))
         q, mg = R.certify(R.zeros())
         exact = float(lam.min())
         above += q[0] > exact
