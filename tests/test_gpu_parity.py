@@ -152,7 +152,12 @@ def test_certify_fp64_and_from_fp32(name):
     q_o, mg_o = R.certify(nu_o)
     n = sites_per_instance(d)
     assert np.all(np.abs(q.cpu().numpy() - q_o) <= 1e-9 * n)
-    np.testing.assert_allclose(mg.cpu().numpy(), mg_o, rtol=1e-9)
+    # the library's margin is the oracle's backward-error term plus, for clusters certified by
+    # Jacobi (D_e <= 8), the off-diagonal mass left after convergence (at most the 4 eps
+    # relative tolerance of the sweeps, i.e. below half the backward-error term)
+    mgg = mg.cpu().numpy()
+    assert np.all(mgg >= mg_o * (1 - 1e-9)) and np.all(mgg <= 1.5 * mg_o)
+    assert np.all(np.abs((q - mg).cpu().numpy() - (q_o - mg_o)) <= 1e-9 * n)
     # per-cluster lambda_min in library order
     lmo = {}
     for D, vals in R.lambda_min(nu_o).items():
