@@ -216,6 +216,22 @@ lrh_status lrh_step_nesterov(lrh_problem p, void* nu, void* zeta, lrh_nesterov_s
 lrh_status lrh_certify(lrh_problem p, const void* nu, uint32_t flags, double* q_dev,
                        double* margin_dev, double* lmin_dev, hipStream_t stream);
 
+/* lrh_certify for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same kernels and results, but the
+ * call allocates nothing.  Its workspace -- the FP64 copy of float messages (LRH_F32) and one
+ * matrix slab per workgroup of the tridiagonalisation kernel at D_e >= 64 -- is a fixed 64 MiB
+ * array in device memory that the library holds on every GPU it runs on until the process ends.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be serialised by the caller.  Nothing in the array needs to start
+ * at zero.  With fewer slabs than clusters each workgroup certifies several clusters in turn.
+ * The problem itself (its terms, index tables and per-cluster values) is the one allocated by
+ * lrh_build_clusters; outputs as in lrh_certify.
+ * Errors: LRH_E_INVALID (null nu/q/margin, host-only problem), LRH_E_UNSUPPORTED (LRH_F32 with
+ * nu_len * 8 bytes above 64 MiB), LRH_E_DEVICE (the array's device address could not be found
+ * when the first problem was built on this GPU, or a launch failed). */
+lrh_status lrh_certify_noalloc(lrh_problem p, const void* nu, uint32_t flags, double* q_dev,
+                               double* margin_dev, double* lmin_dev, hipStream_t stream);
+
 /* Move the parametrised terms to new parameter values (device double[n_params]):
  * h_e = sum of the constant terms + sum_t params[p_t] * dterm_t, recomputed on the device.
  * Errors: LRH_E_INVALID (no parameters, null pointer). */

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -121,6 +122,46 @@ struct GraphKey {
 };
 constexpr size_t kMaxGraphs = 8;  // captured chunks kept per problem (least recently used evicted)
 
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// workspace of lrh_certify_noalloc: a file-scope device array, one copy per GPU, held until the
+// process ends.  Host code never passes `scratch` itself to a kernel (on the host it is only a
+// stand-in for the symbol): its device address is looked up once per device, with that device
+// current, when the first problem is built there, and kept per device.
+// ------------------------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+std::string g_scratch_err[kMaxDevices];
+
+// With `device` current: look up this device's copy of the array (once per device).
+void bind_static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || ptr == nullptr) {
+    g_scratch_err[device] = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    return;
+  }
+  g_scratch_ptr[device] = ptr;
+}
+
+void* static_scratch(int device, std::string& why) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) {
+    why = "device index beyond the static workspace table";
+    return nullptr;
+  }
+  if (!g_scratch_ptr[device]) why = g_scratch_err[device].empty() ? "static workspace not bound" : g_scratch_err[device];
+  return g_scratch_ptr[device];
+}
 }  // namespace
 
 struct lrh_problem_s {
@@ -1642,6 +1683,7 @@ lrh_status lrh_build_clusters(const lrh_problem_desc* desc, int hip_device, lrh_
     } catch (const std::bad_alloc&) {
       return fail(LRH_E_NOMEM, "host allocation failed");
     }
+    if (st == LRH_OK) bind_static_scratch(hip_device);   // the device is current here
   }
   if (st != LRH_OK) return st;
   *out = P.release();
@@ -1753,6 +1795,62 @@ lrh_status lrh_certify(lrh_problem p, const void* nu, uint32_t flags, double* q_
   for (const CBucket& B : p->cb) {
     ClusterArgs<double> a = base_args<double>(p, B);
     a.tol = default_tol<double>();   // certification ignores a loosened iteration tolerance
+    if (B.mb_child >= 0) a.nu_c = nu64 + p->mb[B.mb_child].offset;
+    if (B.mb_self >= 0) a.nu_p = nu64 + p->mb[B.mb_self].offset;
+    a.R = nullptr;
+    HIP_TRY(launch_cluster<double>(a, p->cplx, MODE_CERTIFY, B.block, shape_for(p, B, true, MODE_CERTIFY), stream));
+  }
+  HIP_TRY(launch_reduce(p->scal, p->inst_ptr, p->n_inst, q_dev, p->scal2, margin_dev, nullptr, nullptr, nullptr,
+                        stream));
+  if (lmin_dev) HIP_TRY(launch_copy<double>(lmin_dev, p->scal, p->n_clusters, stream));
+  return LRH_OK;
+}
+
+lrh_status lrh_certify_noalloc(lrh_problem p, const void* nu, uint32_t flags, double* q_dev, double* margin_dev,
+                               double* lmin_dev, hipStream_t stream) {
+  if (!p || !nu || !q_dev || !margin_dev) return fail(LRH_E_INVALID, "null argument");
+  if (p->host_only) return fail(LRH_E_INVALID, "problem was built without a device");
+  DeviceGuard guard(p->device);
+  std::string why;
+  unsigned char* base = (unsigned char*)static_scratch(p->device, why);
+  if (!base) return fail(LRH_E_DEVICE, why);
+  // layout of the static array: [widened messages (LRH_F32 only)][tridiagonalisation slabs]
+  size_t off = 0;
+  const double* nu64 = (const double*)nu;
+  if (flags & LRH_F32) {
+    const size_t need = ((size_t)std::max<int64_t>(p->nu_len, 1) * sizeof(double) + 255) / 256 * 256;
+    if (need > kStaticScratchBytes)
+      return fail(LRH_E_UNSUPPORTED, "float messages need " + std::to_string(need) +
+                                         " bytes widened, beyond the static workspace of " +
+                                         std::to_string(kStaticScratchBytes));
+    HIP_TRY(launch_widen((double*)base, (const float*)nu, p->nu_len, stream));
+    nu64 = (const double*)base;
+    off = need;
+  }
+  // one slab (the matrix, real and imaginary planes) per workgroup of the tridiagonalisation
+  // kernel (D_e >= 64); fewer slabs than clusters: each workgroup takes several in turn
+  int Dmax = 0;
+  int64_t nwg = 0;
+  for (const CBucket& B : p->cb)
+    if (B.De >= 64 && shape_for(p, B, true, MODE_CERTIFY) == 2) {
+      Dmax = std::max(Dmax, B.De);
+      nwg = std::max<int64_t>(nwg, B.n);
+    }
+  const int64_t slab = (int64_t)(p->cplx ? 2 : 1) * Dmax * Dmax;
+  int64_t blocks = 0;
+  if (Dmax > 0) {
+    blocks = std::min<int64_t>({nwg, 1024, (int64_t)((kStaticScratchBytes - off) / (slab * sizeof(double)))});
+    if (blocks < 1)
+      return fail(LRH_E_UNSUPPORTED, "no room for one " + std::to_string(Dmax) + "-dimensional slab in the static workspace");
+  }
+  for (const CBucket& B : p->cb) {
+    ClusterArgs<double> a = base_args<double>(p, B);
+    a.tol = default_tol<double>();
+    a.big_scratch = nullptr;
+    a.big_blocks = 0;
+    a.expm_scratch = Dmax > 0 ? (double*)(base + off) : nullptr;
+    a.expm_slab = slab;
+    a.expm_blocks = blocks;
     if (B.mb_child >= 0) a.nu_c = nu64 + p->mb[B.mb_child].offset;
     if (B.mb_self >= 0) a.nu_p = nu64 + p->mb[B.mb_self].offset;
     a.R = nullptr;

@@ -71,7 +71,7 @@ EXPORTS = ["lrh_build_clusters", "lrh_query", "lrh_export_clusters", "lrh_export
            "lrh_dual_eval", "lrh_step_subgrad", "lrh_step_nesterov", "lrh_certify", "lrh_check",
            "lrh_set_jacobi", "lrh_destroy", "lrh_last_error", "lrh_set_params", "lrh_dual_vjp",
            "lrh_unrolled_bound_grad", "lrh_autotune", "lrh_get_shapes", "lrh_set_shape", "lrh_time_buckets", "lrh_time_messages",
-           "lrh_set_slab_limit", "lrh_build_info"]
+           "lrh_set_slab_limit", "lrh_build_info", "lrh_certify_noalloc"]
 
 
 def load(path: str = LIB_PATH):
@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH):
         "lrh_step_subgrad": (i32, [vp, vp, vp, vp, i64, i32, i32, dbl, vp, u32, vp]),
         "lrh_step_nesterov": (i32, [vp, vp, vp, C.POINTER(NesterovState), i32, u32, vp]),
         "lrh_certify": (i32, [vp, vp, u32, vp, vp, vp, vp]),
+        "lrh_certify_noalloc": (i32, [vp, vp, u32, vp, vp, vp, vp]),
         "lrh_check": (i32, [vp, vp, C.POINTER(i64), C.POINTER(i64)]),
         "lrh_set_jacobi": (i32, [vp, i32, dbl]),
         "lrh_set_slab_limit": (i32, [vp, i64]),
@@ -238,6 +239,11 @@ def lrh_step_nesterov(h, nu, zeta, state: NesterovState, n_iter, flags=0, stream
 
 def lrh_certify(h, nu, flags, q, margin, lmin=None, stream=None):
     _check(load().lrh_certify(h, _dptr(nu), flags, _dptr(q), _dptr(margin), _dptr(lmin), _stream(stream)))
+
+
+def lrh_certify_noalloc(h, nu, flags, q, margin, lmin=None, stream=None):
+    _check(load().lrh_certify_noalloc(h, _dptr(nu), flags, _dptr(q), _dptr(margin), _dptr(lmin),
+                                      _stream(stream)))
 
 
 def lrh_check(h, stream=None) -> Tuple[int, int]:
