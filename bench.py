@@ -1,16 +1,18 @@
 """Benchmark: cluster updates/s and time-to-1e-4 gap/site on one MI355X.
 
-Workload: level-1 relaxation of the Heisenberg antiferromagnet on the 32x32 periodic
-square lattice (2048 edge clusters 4x4 + 1024 site clusters 2x2, real symmetric),
-entropy-smoothed Algorithm 2 with beta doubling 1 -> 1024 (11 stages over 5000
-iterations), FP32 iterations in the fused single-launch form replayed from a captured
-HIP graph, FP64 certification (lambda_min of every cluster + rounding margin) every 50
-iterations.  A "step" is 50 iterations followed by one certification; the default 100
-steps are the whole 5000-iteration solve.  Inputs are synthetic and built on the host,
-then resident in HBM before timing starts.
+Default workload: the batched sweep of 512 periodic L x L transverse-field Ising lattices
+(L ~ U{8..64}, h ~ U[0.5, 4], seed 4; 2 x 2 plaquette clusters 16 x 16 over their bonds and
+sites: 3.33 M clusters, 6.66 M messages, real symmetric), entropy-smoothed Algorithm 2 with FP32
+iterations replayed from captured HIP graphs in autotuned launch shapes, FP64 certification
+(lambda_min of every cluster + rounding margin).  A "step" is 50 accelerated iterations
+followed by one certification (every hot-path step a1-a8 over the whole batch); `value` is the
+cluster-update rate over the timed steps.  The same steps in the plain FP64 form (one launch
+per phase, no graph) are reported beside it, then the time to a certified gap of 1e-4 per site
+in every instance for both forms, against per-instance references (see plaquette_reference),
+and the FP64 CPU oracle on one host core and on all of them over a bounded sample.  Inputs are
+synthetic, built on the host and resident in HBM before any timing starts.
 
-Also reported: the same solve in the plain FP64 form (two launches per iteration, no
-graph), and the FP64 CPU oracle on a bounded sample of iterations (cpu_baseline).
+Other workloads (--workload): c2 (32 x 32 Heisenberg), c1, c3k<k>, c3t<k>, c4t, c5, ex2, ex3.
 """
 import argparse
 import json
@@ -323,6 +325,248 @@ def time_to_gap(P, desc, n_sites, torch, target=1e-4):
     return out
 
 
+# ---- time to a certified gap (default workload) ----------------------------------------------
+GAP_TARGET = 1e-4          # certified gap per site, every instance
+GAP_STAGE_ITERS = 500      # iterations per beta stage while beta doubles (each stage restarts)
+GAP_BETA_FINAL = 12288.0   # final inverse temperature, held without restarts until the target
+GAP_CHECK = 250            # certification cadence (its cost is inside the measured time)
+GAP_MAX_ITERS = 60000
+
+
+def gap_stages(beta_final=GAP_BETA_FINAL, K=GAP_STAGE_ITERS):
+    """beta = 2^s for K iterations each while below beta_final, then beta_final (open-ended)."""
+    betas = []
+    b = 1.0
+    while b < beta_final:
+        betas.append(b)
+        b *= 2.0
+    return [(bb, K) for bb in betas] + [(beta_final, None)]
+
+
+def plaquette_reference(hs, torch, L=3, stages=21, per=3000):
+    """Relaxation optimum per site of a periodic TFIM plaquette lattice for every field h.
+
+    A periodic lattice is translation invariant; Q is concave, so averaging an optimal message
+    set over the translations gives a translation-invariant optimal one, and with invariant
+    messages every plaquette, bond and site repeats the same three augmented Hamiltonians: the
+    optimum per site is the same for every L >= 3 (the poset is locally the same).  It is taken
+    as the best certified value per site of a 3 x 3 lattice per field, solved in FP64 with
+    beta = 2^0 .. 2^20 and `per` accelerated iterations per stage.  Returns (values per site,
+    improvement of the last stage per site), the latter bounding how far the reference still
+    is from converged."""
+    import lrh_workloads as W
+    from paper_2609_40336_amd import lrh
+    d = W.tfim_plaquette_batch([L] * len(hs), hs, name="plaquette_reference")
+    P = lrh.Problem(d, 0)
+    nu, ze = P.zeros(), P.zeros()
+    best = np.full(len(hs), -np.inf)
+    last = 0.0
+    for st_ in range(stages):
+        st = P.new_nesterov_state(2.0 ** st_)
+        P.step_nesterov(nu, ze, st, per, fused=True)
+        q, mg, _ = P.certify(nu)
+        b = (q - mg).cpu().numpy() / (L * L)
+        last = float(np.max(b - best)) if st_ else float("inf")
+        best = np.maximum(best, b)
+    P.close()
+    return best, last
+
+
+def solve_to_gap(P, f32, fused, ref, n_sites, torch, max_iters=GAP_MAX_ITERS):
+    """Algorithm 2 on the gap schedule from nu = 0, certified every GAP_CHECK iterations, until
+    every instance is within GAP_TARGET per site of its reference (or max_iters).  Timed with
+    HIP events around the whole solve, certifications and their read-back included."""
+    from paper_2609_40336_amd import lrh
+    stages = gap_stages()
+    nu, ze = P.zeros(f32), P.zeros(f32)
+    q = torch.zeros(P.n_inst, dtype=torch.float64, device="cuda")
+    mg = torch.zeros_like(q)
+    e0, e1 = _events(torch)
+    torch.cuda.synchronize()
+    e0.record()
+    k, si = 0, 0
+    st = P.new_nesterov_state(stages[0][0])
+    left = stages[0][1]
+    reached, gap, trace = None, None, []
+    while k < max_iters:
+        n = GAP_CHECK if left is None else min(GAP_CHECK, left)
+        P.step_nesterov(nu, ze, st, n, fused=fused)
+        k += n
+        lrh.lrh_certify(P.h, nu, lrh.LRH_F32 if f32 else 0, q, mg)
+        gaps = ref - (q - mg).cpu().numpy() / n_sites    # synchronises
+        gap = float(np.max(gaps))
+        if k % 2500 == 0:
+            trace.append((k, gap))
+        if gap <= GAP_TARGET:
+            reached = k
+            break
+        if left is not None:
+            left -= n
+            if left == 0:
+                si += 1
+                st = P.new_nesterov_state(stages[si][0])
+                left = stages[si][1]
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    return dict(seconds=sec if reached else None, iterations=reached, iterations_run=k,
+                max_gap_per_site_at_end=gap, solve_seconds=sec,
+                cluster_updates_per_s_whole_solve=P.n_clusters * k / sec,
+                max_gap_every_2500_iterations=[(kk, float("%.3g" % g)) for kk, g in trace]), nu, ze
+
+
+def _oracle_worker(job):
+    """One CPU process: Algorithm 2 iterations (FP64 oracle, one BLAS thread) at fixed beta on the
+    plaquette lattices `job` = (Ls, hs, beta, budget); returns (cluster updates, seconds)."""
+    Ls, hs, beta, budget = job
+    from threadpoolctl import threadpool_limits
+    import lrh_workloads as W
+    from oracle import lrh_oracle as O
+    with threadpool_limits(1):
+        R = O.Relaxation(W.tfim_plaquette_batch(Ls, hs, name="cpu_sample"))
+        nu = R.zeros()
+        ze = R.copy(nu)
+        L = R.lipschitz(beta)
+        th, n = 1.0, 0
+        t0 = time.perf_counter()
+        while True:
+            eta = R.axpby(1.0 - th, nu, th, ze)
+            _, g = R.grad_beta(eta, beta)
+            ze = R.symmetrise({k: ze[k] + g[k] / (th * L) for k in ze})
+            nu = R.symmetrise(R.axpby(1.0 - th, nu, th, ze))
+            th = O.theta_next(th)
+            n += 1
+            if n >= 2 and time.perf_counter() - t0 > budget:
+                break
+        return R.n_clusters * n, time.perf_counter() - t0
+
+
+def cpu_oracle_legs(Ls, hs, beta, budget):
+    """The untuned FP64 oracle on the host: one process on one instance of the sweep, then one
+    process per host core (at most 16, the host share of one GPU), each on its own instance, all
+    for `budget` seconds.  Runs in fresh processes before this process touches the GPU."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    ncpu = os.cpu_count() or 1
+    ncores = max(1, min(ncpu, 16))
+    out = {}
+    with ctx.Pool(1) as pool:
+        u, dt = pool.map(_oracle_worker, [([Ls[0]], [hs[0]], beta, budget)])[0]
+    out["one_core"] = dict(value=u / dt, unit="cluster updates/s", cores=1, kind="oracle",
+                           sample=f"Algorithm 2 iterations at beta = {beta:g} on instance 0 of the sweep "
+                                  f"(L = {Ls[0]}, h = {hs[0]:.3f}; FP64 NumPy, one thread), {dt:.1f} s")
+    jobs = [([Ls[i % len(Ls)]], [hs[i % len(hs)]], beta, budget) for i in range(ncores)]
+    t0 = time.perf_counter()
+    with ctx.Pool(ncores) as pool:
+        res = pool.map(_oracle_worker, jobs)
+    wall = time.perf_counter() - t0
+    upd = sum(u for u, _ in res)
+    span = max(dt for _, dt in res)
+    out["all_cores"] = dict(value=upd / span, unit="cluster updates/s", cores=ncores, kind="oracle",
+                            os_cpu_count=ncpu,
+                            sample=f"{ncores} processes, one instance of the sweep each (instances 0..{ncores - 1}, "
+                                   f"L = {sorted(set(int(Ls[i % len(Ls)]) for i in range(ncores)))}), Algorithm 2 "
+                                   f"iterations at beta = {beta:g} (FP64 NumPy, one thread each), {span:.1f} s "
+                                   f"({wall:.1f} s wall with start-up)")
+    return out
+
+
+def bench_c4_default(args, torch, cpu):
+    """The default line: the 512-lattice plaquette sweep (see the module docstring)."""
+    import lrh_workloads as W
+    from paper_2609_40336_amd import lrh
+    t0 = time.perf_counter()
+    desc = W.workload_c4()
+    hs = np.asarray(desc.meta["hs"], dtype=np.float64)
+    n_sites = np.bincount(desc.site_instance, minlength=desc.n_instances).astype(np.float64)
+    P = lrh.Problem(desc, 0)
+    print(f"[bench] {desc.name}: {P.n_clusters} clusters, {P.n_msgs} messages, built in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    cache = os.path.join(os.environ.get("TMPDIR", "/tmp"), "lrh_shapes.json")
+    shapes = P.autotune(True, cache)
+    P.autotune(False, cache)
+    beta = GAP_BETA_FINAL
+    ips = ITERS_PER_STEP
+
+    def timed_steps(f32, fused, steps, warmup, nu, ze):
+        """`steps` steps (ips iterations + one FP64 certification) of Algorithm 2 at the solve's
+        final beta, continuing from the solved state (nu, ze) -- the regime where the solve spends
+        most of its iterations -- after `warmup` untimed steps on a copy of it."""
+        w_nu, w_ze = nu.clone(), ze.clone()
+        w_st = P.new_nesterov_state(beta)
+        for _ in range(warmup):
+            P.step_nesterov(w_nu, w_ze, w_st, ips, fused=fused)
+            P.certify(w_nu)
+        del w_nu, w_ze
+        st = P.new_nesterov_state(beta)
+        q = torch.zeros((steps, P.n_inst), dtype=torch.float64, device="cuda")
+        mg = torch.zeros_like(q)
+        e0, e1 = _events(torch)
+        torch.cuda.synchronize()
+        e0.record()
+        for k in range(steps):
+            P.step_nesterov(nu, ze, st, ips, fused=fused)
+            lrh.lrh_certify(P.h, nu, lrh.LRH_F32 if f32 else 0, q[k], mg[k])
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    t1 = time.perf_counter()
+    ref, ref_last = plaquette_reference(hs, torch)
+    print(f"[bench] per-field references in {time.perf_counter() - t1:.1f} s (last stage moved "
+          f"{ref_last:.1e} per site)", file=sys.stderr, flush=True)
+    tte, nu, ze = solve_to_gap(P, True, True, ref, n_sites, torch)
+    print(f"[bench] fused fp32 to {GAP_TARGET:g}: {tte}", file=sys.stderr, flush=True)
+    iters = args.steps * ips
+    sec = timed_steps(True, True, args.steps, args.warmup, nu, ze)
+    print(f"[bench] fused fp32: {sec:.3f} s for {iters} iterations at beta = {beta:g}", file=sys.stderr, flush=True)
+    roof = dominant_kernel_roofline(P, nu, beta, True, torch)
+    roof64 = dominant_kernel_roofline(P, nu, 64.0, True, torch)
+    msg_roof = message_kernel_roofline(P, nu, ze, beta, torch)
+    del nu, ze
+    tte_plain = None
+    if not args.no_plain_gap:
+        tte_plain, nu, ze = solve_to_gap(P, False, False, ref, n_sites, torch)
+        print(f"[bench] plain fp64 to {GAP_TARGET:g}: {tte_plain}", file=sys.stderr, flush=True)
+    else:
+        nu, ze = P.zeros(False), P.zeros(False)
+    sec_plain = timed_steps(False, False, args.steps, min(args.warmup, 1), nu, ze)
+    print(f"[bench] plain fp64: {sec_plain:.3f} s for {iters} iterations", file=sys.stderr, flush=True)
+    del nu, ze
+    nchk, nnf = P.check()
+    out = {
+        "metric": "cluster updates/s and time-to-1e-4 gap/site: fused vs plain FP64, 1 MI355X",
+        "value": P.n_clusters * iters / sec, "unit": "cluster updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 iterations, f64 certify", "data": "synthetic",
+        "config": {"workload": "tfim_plaquette_sweep_512_L8to64_h0.5to4_seed4_plaquettes_nesterov",
+                   "instances": P.n_inst, "clusters": P.n_clusters, "messages": P.n_msgs,
+                   "iters_per_step": ips, "beta_of_timed_steps": beta, "parallelism": "single_gpu"},
+        "us_per_iteration": sec / iters * 1e6,
+        "time_to_1e-4_gap_per_site_s": tte["seconds"],
+        "time_to_gap": {
+            "fused_fp32": tte, "plain_fp64": tte_plain,
+            "target_gap_per_site": GAP_TARGET,
+            "schedule": f"beta = 2^s for {GAP_STAGE_ITERS} iterations each (Algorithm 2 restarted per stage) "
+                        f"while below {GAP_BETA_FINAL:g}, then beta = {GAP_BETA_FINAL:g} without restarts; "
+                        f"FP64 certification every {GAP_CHECK} iterations, inside the timing",
+            "reference": "per field h: best certified value per site of the 3 x 3 periodic lattice "
+                         "(translation invariance), FP64, beta up to 2^20",
+            "reference_last_stage_improvement_per_site": ref_last,
+        },
+        "plain_fp64": {"value": P.n_clusters * iters / sec_plain, "unit": "cluster updates/s",
+                       "form": "FP64, one launch per phase and message bucket, no graph, the same batch",
+                       "time_to_1e-4_gap_per_site_s": tte_plain["seconds"] if tte_plain else None},
+        "shapes": shapes, "jacobi_noconv": nchk, "nonfinite": nnf,
+        "roofline": roof, "roofline_at_beta_64": roof64, "roofline_message_kernel": msg_roof,
+    }
+    if cpu:
+        out["cpu_baseline"] = cpu["all_cores"]
+        out["cpu_baseline_one_core"] = cpu["one_core"]
+    print(json.dumps(out))
+
+
 def bench_rate(workload, args, torch):
     """Batched Algorithm 2 on a large workload: FP32 iterations replayed from captured graphs
     with autotuned launch shapes, beta doubling 1 -> 1024 over 11 stages of
@@ -334,7 +578,7 @@ def bench_rate(workload, args, torch):
     from paper_2609_40336_amd import lrh
     t0 = time.perf_counter()
     reference = False
-    if workload == "c4":
+    if workload == "c4rate":
         reference = True
         desc = W.workload_c4()
         sample = W.workload_c4(n_inst=2)
@@ -725,16 +969,20 @@ def bench_ex2(args, torch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=TOTAL_ITERS // ITERS_PER_STEP)
+    ap.add_argument("--steps", type=int, default=0,
+                    help="timed steps (default 20 on c4, 100 = the whole 5000-iteration solve on c2)")
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--workload", default="c2",
-                    help="c2 (default: the 32x32 Heisenberg solve), c1 (TFIM chain, Algorithm 1), c3k<k> "
+    ap.add_argument("--no-plain-gap", action="store_true",
+                    help="default workload: skip the plain FP64 solve to the gap target")
+    ap.add_argument("--workload", default="c4",
+                    help="c4 (default: the 512-lattice plaquette sweep, rate and time to 1e-4), c2 (the "
+                         "32x32 Heisenberg solve), c1 (TFIM chain, Algorithm 1), c3k<k> "
                          "(interval hierarchy Y_k on the n = 4096 GUE chain), c3t<k> (the same chain with the "
-                         "two-level family: windows of k sites and their overlaps), c4 (512 plaquette lattices; c4t: "
-                         "the two-level family of plaquettes and shared bonds), "
+                         "two-level family: windows of k sites and their overlaps), c4rate (the sweep on the "
+                         "older beta 1 -> 1024 schedule; c4t: the two-level family of plaquettes and shared bonds), "
                          "c5 (64x64 XXZ value and coupling gradient), ex3 (iterations-to-eps experiment), "
                          "ex2 (optimal message norm vs chain length)")
     ap.add_argument("--time-to-gap", action="store_true",
@@ -751,6 +999,20 @@ def main():
         print(f"bench.py runs on one GPU only (the path is single-GPU; --gpus {args.gpus} "
               f"is not supported)", file=sys.stderr)
         sys.exit(2)
+    if args.steps <= 0:
+        args.steps = 20 if args.workload == "c4" else TOTAL_ITERS // ITERS_PER_STEP
+    if args.workload == "c4":
+        # CPU legs first, in fresh processes, before this process touches the GPU
+        cpu = None
+        if not args.no_cpu:
+            import lrh_workloads as W
+            sweep = W.workload_c4()
+            Ls, hs = list(sweep.meta["Ls"]), list(sweep.meta["hs"])
+            del sweep
+            cpu = cpu_oracle_legs(Ls, hs, GAP_BETA_FINAL, args.cpu_budget)
+            print(f"[bench] cpu oracle: {cpu}", file=sys.stderr, flush=True)
+        import torch
+        return bench_c4_default(args, torch, cpu)
     import torch
     import lrh_workloads as W
     from paper_2609_40336_amd import lrh
