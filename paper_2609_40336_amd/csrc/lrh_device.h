@@ -65,6 +65,17 @@ template <> __device__ __forceinline__ double dfma<double>(double a, double b, d
 
 // Algorithm 2 extrapolation / averaging (1 - th) x + th y, with one explicit rounding
 // pattern so that every kernel computing it from the same inputs gets the same bits.
+// Cluster handled by workgroup i of a launch with one workgroup per cluster (n of them).  The
+// dispatcher hands consecutive workgroups to the 8 XCDs in turn, and each XCD has its own L2;
+// consecutive clusters read neighbouring messages (one cache line holds the same component of
+// many consecutive messages), so every XCD takes one contiguous run of clusters instead.
+__device__ __forceinline__ int64_t xcd_cluster(int64_t i, int64_t n) {
+  constexpr int64_t kXcd = 8;
+  const int64_t q = n / kXcd, r = n % kXcd;
+  const int64_t x = i % kXcd, j = i / kXcd;
+  return x * q + (x < r ? x : r) + j;
+}
+
 template <typename T>
 __device__ __forceinline__ T extrap(T x, T y, T th) {
   return dfma<T>(T(1) - th, x, th * y);
@@ -1645,7 +1656,7 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
   constexpr int NB = DE / 16;
   __shared__ T sar[DE * LD];
   __shared__ T sai[CPLX ? DE * LD : 1];
-  const int64_t c = blockIdx.x;
+  const int64_t c = xcd_cluster(blockIdx.x, A.n);
   const int l = threadIdx.x;
   const T th = A.tab ? (T)A.tab->theta_cur : (T)A.theta;
   const double beta = A.tab ? A.tab->beta : A.beta;
@@ -2370,6 +2381,233 @@ __global__ __launch_bounds__(256) void k_cluster_tridiag(ClusterArgs<double> A, 
   }
 }
 
+// Bits of a placed, lowest first, at the set bits of mask (lowest first).
+__device__ __forceinline__ int spread_bits(int a, int mask) {
+  int r = 0;
+  for (int t = 0; mask != 0; ++t) {
+    const int lb = mask & -mask;
+    if ((a >> t) & 1) r |= lb;
+    mask ^= lb;
+  }
+  return r;
+}
+
+// theta_e at the messages (no extrapolation) into the group's LDS matrix, De lanes per cluster
+// (lane i): h_e and the parent messages row by row, then the child messages entry by entry, each
+// entry (a, b) of 1 (x) nu_{e->f} scattered to its De / Dc positions (pdep(a, x), pdep(b, x)) over
+// the complement bits x.  Children go one after another: two of them can reach one element.
+template <bool CPLX, int DE>
+__device__ void rows_assemble(const ClusterArgs<double>& A, int64_t c, int i, bool active, double* dr, double* di) {
+  constexpr int LD = DE + 1;
+  double rr[DE], ri[CPLX ? DE : 1];
+#pragma unroll
+  for (int j = 0; j < DE; ++j) {
+    rr[j] = 0.0;
+    if constexpr (CPLX) ri[j] = 0.0;
+  }
+  const int64_t ho = active ? A.hoff[c] : -1;
+  if (ho >= 0) {
+    const double* h = A.h + ho;
+#pragma unroll
+    for (int j = 0; j < DE; ++j) {
+      double vr, vi;
+      herm_elem<double>([&](int k) { return h[k]; }, i, j, DE, CPLX, vr, vi);
+      rr[j] = vr;
+      if constexpr (CPLX) ri[j] = vi;
+    }
+  }
+  for (int s = 0; s < A.maxpar; ++s) {
+    const int m = active ? A.par[(int64_t)s * A.n + c] : -1;
+    if (m < 0) continue;
+#pragma unroll
+    for (int j = 0; j < DE; ++j) {
+      double vr, vi;
+      herm_elem<double>([&](int k) { return A.nu_p[(int64_t)k * A.Mp + m]; }, i, j, DE, CPLX, vr, vi);
+      rr[j] += vr;
+      if constexpr (CPLX) ri[j] += vi;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < DE; ++j) {
+    dr[i * LD + j] = rr[j];
+    if constexpr (CPLX) di[i * LD + j] = ri[j];
+  }
+  __syncthreads();
+  if (A.Dc <= 0) return;
+  const int Dc = A.Dc, ldc = __builtin_ctz(Dc), NE = Dc * Dc;
+  for (int s = 0; s < A.maxch; ++s) {   // maxch is the bucket's: the barrier below is uniform
+    const int m = active ? A.ch[(int64_t)s * A.n + c] : -1;
+    if (m >= 0) {
+      const int mask = A.chmask[(int64_t)s * A.n + c] & (DE - 1);
+      const int cm = ~mask & (DE - 1);
+      for (int ab = i; ab < NE; ab += DE) {
+        const int a = ab >> ldc, b = ab & (Dc - 1);
+        double er, ei;
+        herm_elem<double>([&](int k) { return A.nu_c[(int64_t)k * A.Mc + m]; }, a, b, Dc, CPLX, er, ei);
+        const int ia = spread_bits(a, mask), jb = spread_bits(b, mask);
+        int x = 0;
+        do {   // every subset x of the complement bits
+          dr[(ia | x) * LD + (jb | x)] -= er;
+          if constexpr (CPLX) di[(ia | x) * LD + (jb | x)] -= ei;
+          x = (x - cm) & cm;
+        } while (x != 0);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Row-parallel variant for De = 16, 32 (the default there): De lanes per cluster, 64 / De
+// clusters per wave, lane i holding row i of theta_e in registers.  Column k below the diagonal
+// is then one register per lane, the vectors v and w of each reflection are exchanged through
+// LDS, and the reductions stay inside the lane group.  The tridiagonal (d, |e|^2) goes to a
+// workspace (structure of arrays: d_k of cluster c at ws[k n + c], |e_k|^2 at ws[(De + k) n + c])
+// for k_sturm_bisect, which brackets lambda_min with one lane per cluster.
+template <bool CPLX, int DE>
+__global__ __launch_bounds__(64) void k_certify_rows(ClusterArgs<double> A, double* ws) {
+  constexpr int LD = DE + 1;
+  constexpr int G = 64 / DE;
+  __shared__ double sar[G * DE * LD];
+  __shared__ double sai[CPLX ? G * DE * LD : 1];
+  __shared__ double vbr[G][DE], vbi[G][CPLX ? DE : 1], wbr[G][DE], wbi[G][CPLX ? DE : 1];
+  const int l = threadIdx.x, g = l / DE, i = l % DE;
+  const int64_t c = (int64_t)blockIdx.x * G + g;
+  const bool active = c < A.n;
+  double* dr = sar + g * DE * LD;
+  double* di = CPLX ? sai + g * DE * LD : sai;
+  rows_assemble<CPLX, DE>(A, c, i, active, dr, di);
+  double ar[DE], ai[CPLX ? DE : 1];
+  double n2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < DE; ++j) {
+    ar[j] = active ? dr[i * LD + j] : 0.0;
+    n2 = fma(ar[j], ar[j], n2);
+    if constexpr (CPLX) {
+      ai[j] = active ? di[i * LD + j] : 0.0;
+      n2 = fma(ai[j], ai[j], n2);
+    }
+  }
+  const double nrm2 = seg_sum<DE>(n2);
+  double e2mine = 0.0;
+#pragma unroll
+  for (int k = 0; k < DE - 2; ++k) {
+    // x = column k below the diagonal: element k of the rows i > k
+    const bool below = i > k;
+    const double xr = below ? ar[k] : 0.0;
+    const double xi = (CPLX && below) ? ai[k] : 0.0;
+    const double xn2 = seg_sum<DE>(fma(xr, xr, xi * xi));
+    if (i == k) e2mine = xn2;
+    // x0 = element k + 1, the first of x, broadcast from lane k + 1 of the group
+    const double x0r = __shfl(xr, g * DE + k + 1, 64), x0i = CPLX ? __shfl(xi, g * DE + k + 1, 64) : 0.0;
+    const double xn = sqrt(xn2), a0 = sqrt(fma(x0r, x0r, x0i * x0i));
+    const double vn2 = 2.0 * (xn2 + a0 * xn);
+    const bool act = vn2 > 0.0;      // uniform in the group: nothing to reflect when x = 0
+    const double tau = act ? 2.0 / vn2 : 0.0;
+    const double ur = a0 > 0.0 ? x0r / a0 : 1.0, ui = a0 > 0.0 ? x0i / a0 : 0.0;
+    // v = x - alpha e_{k+1}, alpha = -(x0 / |x0|) ||x||
+    double vr = xr, vi = xi;
+    if (i == k + 1) {
+      vr = fma(ur, xn, vr);
+      vi = fma(ui, xn, vi);
+    }
+    vbr[g][i] = vr;
+    if constexpr (CPLX) vbi[g][i] = vi;
+    __syncthreads();
+    // p_i = tau sum_{j > k} A_ij v_j
+    double pr = 0.0, pim = 0.0;
+#pragma unroll
+    for (int j = k + 1; j < DE; ++j) {
+      const double bjr = vbr[g][j];
+      pr = fma(ar[j], bjr, pr);
+      if constexpr (CPLX) {
+        const double bji = vbi[g][j];
+        pr = fma(-ai[j], bji, pr);
+        pim = fma(ar[j], bji, fma(ai[j], bjr, pim));
+      }
+    }
+    pr *= tau;
+    pim *= tau;
+    // K = (tau / 2) v^H p (real), w = p - K v
+    const double K = 0.5 * tau * seg_sum<DE>(fma(vr, pr, vi * pim));
+    const double wr = fma(-K, vr, pr), wi = fma(-K, vi, pim);
+    wbr[g][i] = wr;
+    if constexpr (CPLX) wbi[g][i] = wi;
+    __syncthreads();
+    // A22 -= v w^H + w v^H (lanes i <= k have v_i = w_i = 0: their rows do not change)
+#pragma unroll
+    for (int j = k + 1; j < DE; ++j) {
+      const double vjr = vbr[g][j], wjr = wbr[g][j];
+      if constexpr (CPLX) {
+        const double vji = vbi[g][j], wji = wbi[g][j];
+        ar[j] -= fma(vr, wjr, fma(vi, wji, fma(wr, vjr, wi * vji)));
+        ai[j] -= fma(vi, wjr, fma(-vr, wji, fma(wi, vjr, -wr * vji)));
+      } else {
+        ar[j] -= fma(vr, wjr, wr * vjr);
+      }
+    }
+    __syncthreads();   // before the next step overwrites the broadcast vectors
+  }
+  // last 2 x 2 block: |e_{De-2}|^2 = |A_{De-2, De-1}|^2, element De - 1 of row De - 2
+  if (i == DE - 2) e2mine = fma(ar[DE - 1], ar[DE - 1], CPLX ? ai[DE - 1] * ai[DE - 1] : 0.0);
+  double dmine = 0.0;
+#pragma unroll
+  for (int j = 0; j < DE; ++j)
+    if (j == i) dmine = ar[j];
+  if (active) {
+    ws[(int64_t)i * A.n + c] = dmine;
+    ws[(int64_t)(DE + i) * A.n + c] = (i < DE - 1) ? e2mine : 0.0;
+    if (i == 0) A.scal2[A.gid[c]] = 8.0 * DE * DBL_EPSILON * sqrt(nrm2);
+  }
+}
+
+// lambda_min of every cluster's tridiagonal (d, |e|^2) by bisection on Sturm counts, one lane per
+// cluster: from the Gershgorin interval (widened by a few ulps) down to a few ulps of lambda_min;
+// the lower end of the final bracket, below which the tridiagonal has no eigenvalue, is returned.
+template <int DE>
+__global__ __launch_bounds__(256) void k_sturm_bisect(ClusterArgs<double> A, const double* ws) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= A.n) return;
+  double d[DE], e2[DE];
+#pragma unroll
+  for (int k = 0; k < DE; ++k) {
+    d[k] = ws[(int64_t)k * A.n + c];
+    e2[k] = ws[(int64_t)(DE + k) * A.n + c];
+  }
+  double lo = INFINITY, hi = -INFINITY, emax = 0.0, re_prev = 0.0;
+#pragma unroll
+  for (int k = 0; k < DE; ++k) {
+    const double re = sqrt(e2[k]);
+    lo = fmin(lo, d[k] - (re_prev + re));
+    hi = fmax(hi, d[k] + (re_prev + re));
+    emax = fmax(emax, e2[k]);
+    re_prev = re;
+  }
+  const double pivmin = DBL_MIN * fmax(1.0, emax);
+  const double span0 = fmax(hi - lo, DBL_MIN);
+  lo -= 2.0 * DBL_EPSILON * fabs(lo) + span0 * DBL_EPSILON;
+  hi += 2.0 * DBL_EPSILON * fabs(hi) + span0 * DBL_EPSILON;
+  for (int it = 0; it < 64; ++it) {
+    if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi))) break;
+    const double x = 0.5 * (lo + hi);
+    if (!(x > lo && x < hi)) break;
+    bool neg = false;
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    neg = q < 0.0;
+#pragma unroll
+    for (int k = 1; k < DE; ++k) {
+      q = (d[k] - x) - e2[k - 1] / q;
+      if (fabs(q) < pivmin) q = -pivmin;
+      neg = neg || (q < 0.0);
+    }
+    if (neg) hi = x;   // an eigenvalue below x
+    else lo = x;
+  }
+  const int32_t gid = A.gid[c];
+  A.scal[gid] = lo;
+  if (!isfinite(lo) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
+}
+
 // One-wave variant for De = 16, 32: the matrix in LDS, the De rows of A22 v split over
 // 64/De lane groups (partial sums over j = g, g + G, ... combined by shuffles), 64 Sturm
 // points per multisection round.
@@ -2380,7 +2618,7 @@ __global__ __launch_bounds__(64) void k_cluster_tridiag_w(ClusterArgs<double> A)
   __shared__ double ar[DE * LD];
   __shared__ double ai[CPLX ? DE * LD : 1];
   __shared__ double vr[DE], vi[DE], pr[DE], pi[DE], dg[DE], e2[DE];
-  const int64_t c = blockIdx.x;
+  const int64_t c = xcd_cluster(blockIdx.x, A.n);
   const int l = threadIdx.x;
   const int li = l % DE, lg = l / DE;
   const double nrm2 = wave_sum_dpp(
@@ -2529,7 +2767,7 @@ __global__ __launch_bounds__(64) void k_cluster_vjp(ClusterArgs<T> A) {
   __shared__ JacobiScratch<T, DE / 2> J;
   __shared__ T sp[DE];
   __shared__ T slam[DE];
-  const int64_t c = blockIdx.x;
+  const int64_t c = xcd_cluster(blockIdx.x, A.n);
   if (c >= A.n) return;
   const int tid = threadIdx.x;
   const bool has_g = (A.gb_c != nullptr || A.gb_p != nullptr);
@@ -2738,6 +2976,19 @@ static hipError_t launch_cluster_m(const ClusterArgs<T>& a, int block, int W, hi
   }
   if (W == 2) {
     if constexpr (MODE == MODE_CERTIFY && std::is_same<T, double>::value) {
+      if ((a.De == 16 || a.De == 32) && a.cert_ws != nullptr) {
+        const int G = 64 / a.De;
+        if ((a.n + G - 1) / G > 0x7fffffff) return hipErrorInvalidValue;
+        const dim3 g1((unsigned)((a.n + G - 1) / G)), g2(grid_for(a.n, 256));
+        if (a.De == 16) {
+          hipLaunchKernelGGL((k_certify_rows<CPLX, 16>), g1, dim3(64), 0, s, a, a.cert_ws);
+          hipLaunchKernelGGL((k_sturm_bisect<16>), g2, dim3(256), 0, s, a, (const double*)a.cert_ws);
+        } else {
+          hipLaunchKernelGGL((k_certify_rows<CPLX, 32>), g1, dim3(64), 0, s, a, a.cert_ws);
+          hipLaunchKernelGGL((k_sturm_bisect<32>), g2, dim3(256), 0, s, a, (const double*)a.cert_ws);
+        }
+        return hipGetLastError();
+      }
       if (a.De == 16 || a.De == 32) {
         if (a.n > 0x7fffffff) return hipErrorInvalidValue;
         if (a.De == 16)

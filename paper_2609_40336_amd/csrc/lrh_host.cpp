@@ -190,6 +190,7 @@ struct lrh_problem_s {
   unsigned long long* health = nullptr;  // [0] noconv, [1] nonfinite
   int32_t* improved = nullptr;
   double* nu64_tmp = nullptr;            // widened copy of a float nu for certify
+  double* cert_ws = nullptr;             // tridiagonals of the 16- and 32-dimensional buckets (certify)
   FusedParams* fp = nullptr;             // [kFusedTableMax]
   // ---- parametrised terms (adjoint) ----
   int64_t n_params = 0;
@@ -927,6 +928,15 @@ lrh_status ensure_work(lrh_problem_s* P, bool fused) {
     w.fused_ready = true;
   }
   return LRH_OK;
+}
+
+// Doubles of the certification workspace: the tridiagonal (d, |e|^2) of every cluster of the largest
+// 16- or 32-dimensional bucket (buckets are certified one after another).
+int64_t cert_ws_len(const lrh_problem_s* P) {
+  int64_t len = 0;
+  for (const CBucket& B : P->cb)
+    if (B.De == 16 || B.De == 32) len = std::max<int64_t>(len, (int64_t)2 * B.De * B.n);
+  return len;
 }
 
 template <typename T>
@@ -1792,9 +1802,15 @@ lrh_status lrh_certify(lrh_problem p, const void* nu, uint32_t flags, double* q_
     HIP_TRY(launch_widen(p->nu64_tmp, (const float*)nu, p->nu_len, stream));
     nu64 = p->nu64_tmp;
   }
+  const int64_t wsl = cert_ws_len(p);
+  if (wsl > 0 && !p->cert_ws) {
+    lrh_status st = p->dalloc(&p->cert_ws, wsl);
+    if (st != LRH_OK) return st;
+  }
   for (const CBucket& B : p->cb) {
     ClusterArgs<double> a = base_args<double>(p, B);
     a.tol = default_tol<double>();   // certification ignores a loosened iteration tolerance
+    a.cert_ws = p->cert_ws;
     if (B.mb_child >= 0) a.nu_c = nu64 + p->mb[B.mb_child].offset;
     if (B.mb_self >= 0) a.nu_p = nu64 + p->mb[B.mb_self].offset;
     a.R = nullptr;
@@ -1843,11 +1859,18 @@ lrh_status lrh_certify_noalloc(lrh_problem p, const void* nu, uint32_t flags, do
     if (blocks < 1)
       return fail(LRH_E_UNSUPPORTED, "no room for one " + std::to_string(Dmax) + "-dimensional slab in the static workspace");
   }
+  // tridiagonals of the 16- and 32-dimensional buckets, after the slabs if they fit (else those
+  // buckets use the one-wave kernel, which needs no workspace)
+  const size_t slab_bytes = ((size_t)std::max<int64_t>(blocks, 0) * slab * sizeof(double) + 255) / 256 * 256;
+  const size_t ws_bytes = (size_t)cert_ws_len(p) * sizeof(double);
+  double* ws = (ws_bytes > 0 && off + slab_bytes + ws_bytes <= kStaticScratchBytes)
+                   ? (double*)(base + off + slab_bytes) : nullptr;
   for (const CBucket& B : p->cb) {
     ClusterArgs<double> a = base_args<double>(p, B);
     a.tol = default_tol<double>();
     a.big_scratch = nullptr;
     a.big_blocks = 0;
+    a.cert_ws = ws;
     a.expm_scratch = Dmax > 0 ? (double*)(base + off) : nullptr;
     a.expm_slab = slab;
     a.expm_blocks = blocks;

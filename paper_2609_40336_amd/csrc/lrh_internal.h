@@ -93,6 +93,9 @@ struct ClusterArgs {
   double* expm_scratch;          // expm_blocks slabs of expm_slab doubles
   int64_t expm_slab;
   int64_t expm_blocks;
+  // ---- certification at De = 16, 32: tridiagonals of the bucket (2 De n doubles); nullptr: the
+  // one-wave kernel with multisection instead ----
+  double* cert_ws;
 };
 
 template <typename T>
