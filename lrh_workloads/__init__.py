@@ -357,6 +357,29 @@ def tfim_rect_plaquettes(L: int, h: float, w: int = 2, hgt: int = 3, J: float = 
     return b.build(real=True, meta=dict(model="tfim_rect", L=L, h=h, w=w, hgt=hgt))
 
 
+def tfim_growing_clusters(L: int, h: float, level: int = 1, J: float = 1.0) -> ProblemDesc:
+    """Periodic L x L TFIM (H = -J sum ZZ - h sum X) on a growing-cluster hierarchy (Sec. 3.2):
+    level 0 is the 2 x 2 plaquette family C, level 1 is C plus every 2 x 3 and 3 x 2 rectangle
+    (C_{+1}: each rectangle covers two plaquettes, its children in the poset).  L >= 4, so that no
+    rectangle wraps onto itself."""
+    if L < 4:
+        raise ValueError("the rectangles need L >= 4")
+    n = L * L
+    b = _Builder(f"tfim_grow{level}_L{L}", n)
+    zz = -J * kron(Z, Z)
+    for (i, j) in square_edges(L, True, 0):
+        b.add_term((i, j), zz)
+    for s_ in range(n):
+        b.add_term((s_,), -h * X)
+    sid = lambda xx, yy: (xx % L) + L * (yy % L)
+    shapes = [(2, 2)] + ([(3, 2), (2, 3)] if level >= 1 else [])
+    for (w, hgt) in shapes:
+        for y in range(L):
+            for x in range(L):
+                b.add_top(tuple(sorted(sid(x + dx, y + dy) for dy in range(hgt) for dx in range(w))))
+    return b.build(real=True, meta=dict(model="tfim_growing", L=L, h=h, level=level))
+
+
 def tfim_plaquette_sweep(n_inst: int = 512, seed: int = 4, Lmin: int = 8, Lmax: int = 64,
                          two_level: bool = False):
     """The batched sweep: L ~ U{Lmin..Lmax}, h ~ U[0.5, 4], drawn in that order."""

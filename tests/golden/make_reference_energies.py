@@ -9,3 +9,4 @@ from oracle import exact  # noqa: E402
 if __name__ == "__main__":
     print("tfim_chain_n16_E0", repr(exact.tfim_open_chain_E0(16, 1.0, 0.5)))
     print("heisenberg_chain3_E0", repr(exact.ground_energy(W.heisenberg_chain(3))))
+    print("tfim_torus4x4_h2.5_E0", repr(exact.ground_energy(W.tfim_growing_clusters(4, 2.5, 0))))

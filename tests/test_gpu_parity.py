@@ -88,6 +88,9 @@ PROBLEMS = {
     "heis_T4_two_level": lambda: W.with_tops(W.heisenberg_chain(10, field_x=0.4),
                                              [tuple(range(i, i + 4)) for i in range(7)], two_level=True),
     "randchain_T4_two_level": lambda: W.random_chain(8, seed=2, top_len=4, two_level=True),
+    # growing-cluster hierarchy on a 4 x 4 torus: plaquettes plus 2 x 3 and 3 x 2 rectangles
+    # (64-dimensional clusters over two 16-dimensional plaquettes, which have rectangle parents)
+    "tfim_grow4_level1": lambda: W.tfim_growing_clusters(4, 2.5, 1),
 }
 
 
@@ -138,7 +141,7 @@ def test_dual_eval_fp32(name):
 
 @pytest.mark.parametrize("name", ["c1_tfim16_complex", "randchain_Y6", "plaq_batch_ragged", "xxz_tri3", "gue_Y7",
                                   "gue_Y8", "randchain_Y7_real", "k5_complete", "tfim_rect2x3", "gue_T5_two_level",
-                                  "gue_T8_two_level", "plaq_two_level"])
+                                  "gue_T8_two_level", "plaq_two_level", "tfim_grow4_level1"])
 def test_certify_fp64_and_from_fp32(name):
     lrh = lrhmod()
     say(f"[certify] {name}")
@@ -233,6 +236,7 @@ NEST = {
     "gue_Y8": (lambda: W.interval_chain_gue(9, 8, 0.1, seed=3), [(2.0, 6), (8.0, 6)]),
     "gue_T6_two_level": (lambda: W.interval_chain_gue(10, 6, 0.1, seed=3, two_level=True), [(2.0, 12), (8.0, 12)]),
     "tree_two_level": (lambda: two_level(W.classical_ising_tree(9, 4, rotate=True)), [(4.0, 40)]),
+    "tfim_grow4_level1": (lambda: W.tfim_growing_clusters(4, 2.5, 1), [(2.0, 12), (16.0, 12)]),
 }
 
 
@@ -528,6 +532,8 @@ EXPM_PROBLEMS = {
     "tfim_rect2x3_real": (lambda: W.tfim_rect_plaquettes(4, 1.1), [64]),
     # two-level windows of 6 sites: 64-dimensional windows over 32-dimensional overlaps
     "gue_T6_two_level": (lambda: W.interval_chain_gue(10, 6, 0.1, seed=3, two_level=True), [32, 64]),
+    # growing-cluster hierarchy: plaquettes (with rectangle parents) and 2 x 3 / 3 x 2 rectangles
+    "tfim_grow4_level1": (lambda: W.tfim_growing_clusters(4, 2.5, 1), [16, 64]),
 }
 
 

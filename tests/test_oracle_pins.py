@@ -861,3 +861,23 @@ def test_interval_hierarchy_converges_exponentially_on_a_perturbed_separable_cha
     assert gaps[2] <= gaps[1] / 5
     for t, g in zip((2, 3, 4), gaps):
         assert g <= 1e-2 / t
+
+
+def test_growing_cluster_hierarchy_tightens_the_bound_on_a_torus():
+    """Sec. 3.2: C subset C_{+1} gives f*_C <= f*_{C+1} <= E0.  On the periodic 4 x 4 TFIM
+    (h = 2.5), C = the 2 x 2 plaquettes, C_{+1} = C with every 2 x 3 and 3 x 2 rectangle (each
+    covering two plaquettes): the certified value of the larger family, even from a short solve,
+    lies above the converged value of the smaller one and below E0 (Lanczos fixture)."""
+    E0 = read_reference_energies()["tfim_torus4x4_h2.5_E0"]
+    R0 = O.Relaxation(W.tfim_growing_clusters(4, 2.5, 0))
+    R1 = O.Relaxation(W.tfim_growing_clusters(4, 2.5, 1))
+    assert all(len(R1.children[e]) == 2 and R1.D[R1.children[e][0]] == 16
+               for e in range(R1.n_clusters) if R1.D[e] == 64)
+    q0, m0 = R0.certify(_solve_smoothed(R0, [2.0 ** s for s in range(0, 13, 3)], 400))
+    q1, m1 = R1.certify(_solve_smoothed(R1, [8.0, 128.0], 120))
+    b0, b1 = (q0 - m0)[0], (q1 - m1)[0]
+    assert b0 <= E0 and b1 <= E0
+    assert b1 >= b0 + 0.03 * 16    # the rectangles tighten the bound by more than 0.03 per site
+    # the plaquette family is converged: more iterations move it by far less than that gain
+    q0b, m0b = R0.certify(_solve_smoothed(R0, [2.0 ** s for s in range(0, 16, 3)], 800))
+    assert abs((q0b - m0b)[0] - b0) <= 0.003 * 16
