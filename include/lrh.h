@@ -13,9 +13,10 @@
  *     "device" pointers are HIP device memory owned by the caller; the call
  *     enqueues work on `stream` and returns without waiting: results are valid once
  *     the stream is synchronised.
- *   - Sites are spin-1/2 (d = 2) in this release; clusters hold at most 8 sites
- *     (D_e <= 256).  A cluster's basis is the big-endian product basis of its sites in
- *     ascending order (first site most significant), so A_{s0} (x) B_{s1} = kron(A, B).
+ *   - Sites are spin-1/2 (d = 2) or spin-1 (d = 3).  Clusters of spin-1/2 sites hold at most 8
+ *     sites (D_e <= 256); a cluster holding a spin-1 site has D_e = prod d <= 64.  A cluster's
+ *     basis is the big-endian mixed-radix product basis of its sites in ascending order (first
+ *     site most significant), so A_{s0} (x) B_{s1} = kron(A, B).
  *   - Message layout (structure of arrays).  Messages nu_{e->f} (e a cluster, f one of
  *     its covering children) are grouped into buckets by D_f.  Bucket b holds M_b
  *     messages of C_b components each; component c of message m lives at element
@@ -43,7 +44,8 @@ typedef enum {
   LRH_OK = 0,
   LRH_E_INVALID = 1,      /* bad argument: non-Hermitian term, cluster spanning instances,
                              beta <= 0, Lipschitz <= 0, null required pointer, ...          */
-  LRH_E_UNSUPPORTED = 2,  /* D_e > 256, site dimension != 2, mixed child dimensions       */
+  LRH_E_UNSUPPORTED = 2,  /* D_e > 256 (> 64 with a spin-1 site), site dimension not 2 or 3,
+                             children of one cluster with different dimensions              */
   LRH_E_NOMEM = 3,        /* device or host allocation failed                             */
   LRH_E_DEVICE = 4,       /* a HIP runtime call failed                                    */
   LRH_E_NOCONV = 5,       /* a Jacobi eigen-solve hit its sweep cap (see lrh_check)       */
@@ -89,7 +91,7 @@ typedef struct lrh_problem_s* lrh_problem;   /* opaque; owned by the library */
  * poset levels suffice).  site_instance may be NULL (one instance). */
 typedef struct {
   int32_t n_sites;
-  const int32_t* site_dim;        /* [n_sites], must be 2                                */
+  const int32_t* site_dim;        /* [n_sites], 2 or 3                                   */
   int32_t n_terms;
   const int64_t* term_ptr;        /* [n_terms+1]                                         */
   const int32_t* term_sites;
@@ -139,8 +141,8 @@ typedef struct {
  * call returns LRH_E_INVALID).
  * Errors: LRH_E_INVALID (non-Hermitian term beyond 1e-12 * max|h|, site out of range,
  * unsorted or repeated sites, cluster spanning instances), LRH_E_UNSUPPORTED (site
- * dimension != 2, a cluster with more than 8 sites, a cluster whose children have
- * different dimensions), LRH_E_NOMEM, LRH_E_DEVICE.  On success *out owns device
+ * dimension not 2 or 3, a cluster with more than 8 sites or, holding a spin-1 site, with
+ * D_e > 64, a cluster whose children have different dimensions), LRH_E_NOMEM, LRH_E_DEVICE.  On success *out owns device
  * memory until lrh_destroy. */
 lrh_status lrh_build_clusters(const lrh_problem_desc* desc, int hip_device, lrh_problem* out);
 
@@ -282,8 +284,14 @@ lrh_status lrh_check(lrh_problem p, hipStream_t stream, int64_t* noconv, int64_t
  *              Gibbs passes only, the default there)
  *   W = 4      the same on one 256-thread workgroup per cluster, matrices in a device slab
  *              (D_e >= 32; the default for D_e >= 64)
- * Certification at D_e >= 16 always uses Householder tridiagonalisation + Sturm multisection
- * (reported as W = 2 internally); the ground projector and the adjoint use the Jacobi shapes.
+ *   W = 5      clusters holding a spin-1 site (D_e not a power of two): the LDS Jacobi kernel
+ *              driven by index tables (lift and partial-trace maps per cluster and child) on the
+ *              next power of two, with decoupled padding; every mode, the only shape there
+ * Certification at D_e >= 16 (spin-1/2) always uses Householder tridiagonalisation and Sturm
+ * counts (reported as W = 2 internally: at D_e = 16 and 32 one lane group per cluster holding the
+ * rows in registers, then bisection with one lane per cluster; one workgroup per cluster above);
+ * the ground projector and the adjoint use the Jacobi shapes.  The adjoint (lrh_dual_vjp,
+ * lrh_unrolled_bound_grad) covers spin-1/2 clusters only.
  *
  * Launch-shape autotuner (form 2): for every cluster bucket, time the Gibbs pass of the
  * candidate shapes -- threads per block {64, 128, 256} for the register kernels (D_e <= 4),

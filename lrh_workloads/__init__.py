@@ -309,6 +309,32 @@ def interval_chain_gue(n: int, k: int, eps: float = 0.1, seed: int = 3, two_leve
                    meta=dict(model="interval_gue", eps=eps, seed=seed, k=k, n=n, two_level=two_level))
 
 
+SQ2 = np.sqrt(0.5)
+SX1 = SQ2 * np.array([[0, 1, 0], [1, 0, 1], [0, 1, 0]], dtype=np.complex128)
+SY1 = SQ2 * np.array([[0, -1j, 0], [1j, 0, -1j], [0, 1j, 0]], dtype=np.complex128)
+SZ1 = np.diag([1.0, 0.0, -1.0]).astype(np.complex128)
+
+
+def spin1_chain(n: int, J: float = 1.0, Dz: float = 0.3, hx: float = 0.2, dm: float = 0.0,
+                top_len: int = 2, subintervals: bool = False, two_level: bool = False) -> ProblemDesc:
+    """Open spin-1 chain (site dimension 3): H = J sum S_i . S_{i+1} + Dz sum (S^z_i)^2
+    + hx sum S^x_i + dm sum (S^x_i S^y_{i+1} - S^y_i S^x_{i+1}).  The last (Dzyaloshinskii-Moriya)
+    term is imaginary in the S^z basis, so dm != 0 gives a complex problem.  Top clusters: the
+    windows of top_len consecutive sites (with subintervals: the interval hierarchy Y_top_len)."""
+    b = _Builder(f"spin1_chain_n{n}_t{top_len}", n, d=3)
+    bond = J * (kron(SX1, SX1) + kron(SY1, SY1) + kron(SZ1, SZ1))
+    if dm != 0.0:
+        bond = bond + dm * (kron(SX1, SY1) - kron(SY1, SX1))
+    for i in range(n - 1):
+        b.add_term((i, i + 1), bond)
+    for i in range(n):
+        b.add_term((i,), Dz * SZ1 @ SZ1 + hx * SX1)
+    for i in range(n - top_len + 1):
+        b.add_top(tuple(range(i, i + top_len)))
+    return b.build(real=(dm == 0.0), subintervals=subintervals, two_level=two_level,
+                   meta=dict(model="spin1_chain", n=n, J=J, Dz=Dz, hx=hx, dm=dm, top_len=top_len))
+
+
 def tfim_plaquette_batch(Ls: Sequence[int], hs: Sequence[float], J: float = 1.0,
                          name: str = "tfim_plaquette_batch", two_level: bool = False) -> ProblemDesc:
     """Independent periodic L x L TFIM instances, H_b = -J sum ZZ - h_b sum X.

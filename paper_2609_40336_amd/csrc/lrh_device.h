@@ -1150,6 +1150,199 @@ __global__ __launch_bounds__(64) void k_cluster_lds(ClusterArgs<T> A) {
 }
 
 // ------------------------------------------------------------------------------------------
+// clusters holding a spin-1 site (De = 3, 9, 27, 6, ... <= 64): the LDS Jacobi kernel driven by
+// index tables instead of site bit masks, the De x De problem embedded in DEP x DEP (DEP the next
+// power of two) with decoupled padding
+// ------------------------------------------------------------------------------------------
+//
+// The padding indices De..DEP-1 carry a diagonal above every eigenvalue of theta_e and zero
+// off-diagonal entries.  A Jacobi rotation of a pair with a zero off-diagonal is the identity
+// (c = 1, s = 0) and a rotation of two other indices keeps zeros zero, so the padding indices stay
+// eigenvectors e_k with their own diagonal: they are left out of lambda_min, the weights, the norms
+// and the outputs by index.
+
+template <typename T, bool CPLX, int DEP, int W>
+__device__ T gen_assemble(const ClusterArgs<T>& A, int64_t c, int lt, T th, T* dr, T* di) {
+  constexpr int LD = DEP + 1;
+  const int De = A.De, Dc = A.Dc;
+  const int64_t ho = A.hoff[c];
+  T my_n2 = T(0);
+  for (int idx = lt; idx < DEP * DEP; idx += W) {
+    const int i = idx / DEP, j = idx % DEP;
+    T vr = T(0), vi = T(0);
+    if (i < De && j < De) {
+      if (ho >= 0) herm_elem<T>([&](int k) { return (T)A.h[ho + k]; }, i, j, De, CPLX, vr, vi);
+      for (int s = 0; s < A.maxch; ++s) {
+        const int m = A.ch[(int64_t)s * A.n + c];
+        if (m < 0) continue;
+        const int32_t* g = A.gtab + ((int64_t)s * A.n + c) * De;
+        const int ei = g[i], ej = g[j];
+        if (((ei >> 8) & 0xff) != ((ej >> 8) & 0xff)) continue;   // different remaining index
+        const int a = ei & 0xff, b = ej & 0xff;
+        T er, eim;
+        if (A.ze_c)
+          herm_elem<T>([&](int k) { const int64_t o = (int64_t)k * A.Mc + m;
+                                    return extrap<T>(A.nu_c[o], A.ze_c[o], th); }, a, b, Dc, CPLX, er, eim);
+        else
+          herm_elem<T>([&](int k) { return A.nu_c[(int64_t)k * A.Mc + m]; }, a, b, Dc, CPLX, er, eim);
+        vr -= er;
+        vi -= eim;
+      }
+      for (int s = 0; s < A.maxpar; ++s) {
+        const int m = A.par[(int64_t)s * A.n + c];
+        if (m < 0) continue;
+        T er, eim;
+        if (A.ze_p)
+          herm_elem<T>([&](int k) { const int64_t o = (int64_t)k * A.Mp + m;
+                                    return extrap<T>(A.nu_p[o], A.ze_p[o], th); }, i, j, De, CPLX, er, eim);
+        else
+          herm_elem<T>([&](int k) { return A.nu_p[(int64_t)k * A.Mp + m]; }, i, j, De, CPLX, er, eim);
+        vr += er;
+        vi += eim;
+      }
+      my_n2 = dfma<T>(vr, vr, my_n2);
+      if constexpr (CPLX) my_n2 = dfma<T>(vi, vi, my_n2);
+    }
+    dr[i * LD + j] = vr;
+    if constexpr (CPLX) di[i * LD + j] = vi;
+  }
+  return my_n2;
+}
+
+template <typename T, bool CPLX, int DEP, int W>
+__device__ void gen_outputs(const ClusterArgs<T>& A, int64_t c, int lt, int32_t gid, const T* yr, const T* yi) {
+  constexpr int LD = DEP + 1;
+  const int De = A.De, Dc = A.Dc;
+  const int64_t rs_self = A.rslot ? A.rslot[c] : -1;
+  const int NCE = CPLX ? De * De : De * (De + 1) / 2;
+  for (int k = lt; k < NCE; k += W) {
+    int i, j;
+    bool im;
+    decode_comp(k, De, i, j, im);
+    const T v = im ? yi[i * LD + j] : yr[i * LD + j];
+    if (rs_self >= 0 && A.R) A.R[(int64_t)k * A.S + rs_self] = v;
+    if (A.marg) A.marg[A.marg_off[gid] + k] = v;
+  }
+  if (A.Tout && Dc > 0) {
+    const int NR = De / Dc;
+    const int NCC = CPLX ? Dc * Dc : Dc * (Dc + 1) / 2;
+    for (int s = 0; s < A.maxch; ++s) {
+      const int m = A.ch[(int64_t)s * A.n + c];
+      if (m < 0) continue;
+      const int32_t* g = A.gtab + ((int64_t)s * A.n + c) * De;
+      for (int k = lt; k < NCC; k += W) {
+        int a, b;
+        bool im;
+        decode_comp(k, Dc, a, b, im);
+        T sum = T(0);
+        for (int x = 0; x < NR; ++x) {
+          const int i = g[a * NR + x] >> 16, j = g[b * NR + x] >> 16;
+          sum += im ? yi[i * LD + j] : yr[i * LD + j];
+        }
+        A.Tout[(int64_t)k * A.Mc + m] = sum;
+      }
+    }
+  }
+}
+
+template <typename T, bool CPLX, int DEP, int MODE, int W>
+__global__ __launch_bounds__(64) void k_cluster_gen(ClusterArgs<T> A) {
+  constexpr int LD = DEP + 1;
+  constexpr int G = 64 / W;
+  constexpr int SZ = DEP * LD;
+  constexpr bool VEC = (MODE != MODE_CERTIFY);
+  __shared__ T sar_[G * SZ];
+  __shared__ T sai_[CPLX ? G * SZ : 1];
+  __shared__ T sur_[VEC ? G * SZ : 1];
+  __shared__ T sui_[(VEC && CPLX) ? G * SZ : 1];
+  __shared__ JacobiScratch<T, DEP / 2> J_[G];
+  __shared__ T sp_[G * DEP];
+  const int g = threadIdx.x / W, lt = threadIdx.x % W;
+  const int64_t c = (int64_t)blockIdx.x * G + g;
+  const bool active = c < A.n;
+  const int De = A.De;
+  T* sar = sar_ + g * SZ;
+  T* sai = CPLX ? sai_ + g * SZ : sai_;
+  T* sur = VEC ? sur_ + g * SZ : sur_;
+  T* sui = (VEC && CPLX) ? sui_ + g * SZ : sui_;
+  T* sp = sp_ + g * DEP;
+  const T th = A.tab ? (T)A.tab->theta_cur : (T)A.theta;
+  const T beta = A.tab ? (T)A.tab->beta : (T)A.beta;
+  // ---- a1/a2: assemble theta_e at eta, then the padding diagonal ----
+  T n2 = T(0);
+  if (active) n2 = gen_assemble<T, CPLX, DEP, W>(A, c, lt, th, sar, sai);
+  const T nrm2 = seg_sum<W>(n2);
+  __syncthreads();
+  if (active)
+    for (int k = De + lt; k < DEP; k += W) sar[k * LD + k] = T(2) * dsqrt<T>(nrm2) + T(1);   // > every eigenvalue
+  if constexpr (VEC) {
+    if (active) {
+      for (int idx = lt; idx < DEP * DEP; idx += W) {
+        const int i = idx / DEP, j = idx % DEP;
+        sur[i * LD + j] = (i == j) ? T(1) : T(0);
+        if constexpr (CPLX) sui[i * LD + j] = T(0);
+      }
+    }
+  }
+  __syncthreads();
+  // ---- a3: parallel cyclic Jacobi over DEP (the padding stays decoupled) ----
+  const bool conv = lds_jacobi<T, CPLX, DEP, VEC, W>(sar, sai, sur, sui, J_[g], A.tol * A.tol * (double)nrm2,
+                                                     A.max_sweeps, lt, active);
+  if (active && !conv && lt == 0 && A.noconv) atomicAdd(A.noconv, 1ull);
+  T lmin = T(INFINITY);
+  if (active)
+    for (int k = lt; k < De; k += W) lmin = fmin(lmin, sar[k * LD + k]);
+  lmin = seg_min<W>(lmin);
+  if (active && lt == 0 && !isfinite((double)lmin) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
+  const int32_t gid = active ? A.gid[c] : 0;
+  if constexpr (MODE == MODE_CERTIFY) {
+    double off2 = 0.0;   // off-diagonal mass left by the sweeps (Weyl)
+    if (active)
+      for (int idx = lt; idx < DEP * DEP; idx += W) {
+        const int i = idx / DEP, j = idx % DEP;
+        if (i == j) continue;
+        const double xr = (double)sar[i * LD + j];
+        off2 = fma(xr, xr, off2);
+        if constexpr (CPLX) {
+          const double xi = (double)sai[i * LD + j];
+          off2 = fma(xi, xi, off2);
+        }
+      }
+    off2 = seg_sum<W>(off2);
+    if (active && lt == 0) {
+      A.scal[gid] = (double)lmin;
+      A.scal2[gid] = 8.0 * De * DBL_EPSILON * sqrt((double)nrm2) + sqrt(off2);
+    }
+  } else {
+    // ---- a4: weights (padding indices excluded) and the marginal U diag(p) U^H ----
+    T w = T(0);
+    if (active) {
+      const T tau = (T)A.tau_rel * fmax(T(1), dsqrt<T>(nrm2));
+      for (int k = lt; k < DEP; k += W) {
+        T v = T(0);
+        if (k < De) {
+          if constexpr (MODE == MODE_GIBBS) v = dexp<T>(-beta * (sar[k * LD + k] - lmin));
+          else v = (sar[k * LD + k] <= lmin + tau) ? T(1) : T(0);
+        }
+        sp[k] = v;
+        w += v;
+      }
+    }
+    const T Z = seg_sum<W>(w);
+    __syncthreads();
+    if (active)
+      for (int k = lt; k < DEP; k += W) sp[k] = ddiv<T>(sp[k], Z);
+    __syncthreads();
+    const T val = (MODE == MODE_GIBBS) ? lmin - ddiv<T>(dlog<T>(Z), beta) : lmin;
+    if (active && lt == 0 && A.scal) A.scal[gid] = (double)val;
+    if (active) lds_rebuild<T, CPLX, DEP, W>(sur, sui, sp, sar, sai, lt);
+    __syncthreads();
+    // ---- a5: outputs ----
+    if (active) gen_outputs<T, CPLX, DEP, W>(A, c, lt, gid, sar, sai);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // large clusters (De = 128, 256): one 1024-thread workgroup per cluster
 // ------------------------------------------------------------------------------------------
 //
@@ -3010,6 +3203,17 @@ static hipError_t launch_cluster_m(const ClusterArgs<T>& a, int block, int W, hi
       return hipGetLastError();
     }
     return hipErrorInvalidValue;
+  }
+  if (W == 5) {   // clusters with a spin-1 site: table-driven Jacobi on the padded dimension
+    if (a.gtab == nullptr && a.Dc > 0) return hipErrorInvalidValue;
+    const int De = a.De;
+    if (De <= 4) hipLaunchKernelGGL((k_cluster_gen<T, CPLX, 4, MODE, 4>), dim3((unsigned)((a.n + 15) / 16)), dim3(64), 0, s, a);
+    else if (De <= 8) hipLaunchKernelGGL((k_cluster_gen<T, CPLX, 8, MODE, 8>), dim3((unsigned)((a.n + 7) / 8)), dim3(64), 0, s, a);
+    else if (De <= 16) hipLaunchKernelGGL((k_cluster_gen<T, CPLX, 16, MODE, 16>), dim3((unsigned)((a.n + 3) / 4)), dim3(64), 0, s, a);
+    else if (De <= 32) hipLaunchKernelGGL((k_cluster_gen<T, CPLX, 32, MODE, 32>), dim3((unsigned)((a.n + 1) / 2)), dim3(64), 0, s, a);
+    else if (De <= 64) hipLaunchKernelGGL((k_cluster_gen<T, CPLX, 64, MODE, 64>), dim3((unsigned)a.n), dim3(64), 0, s, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
   }
   if (W == 1 && a.De >= 8) {
     if (a.De == 8 && a.Dc == 4) return launch_reg<T, CPLX, MODE, 8, 4>(a, block, s);

@@ -44,6 +44,11 @@ lrh_status fail(lrh_status s, const std::string& msg) {
   } while (0)
 
 constexpr int kMaxSites = 8;  // D_e <= 256 for spin-1/2 sites
+constexpr int kMaxGenericD = 64;  // clusters holding a spin-1 site: D_e <= 64 (table-driven kernel)
+
+// Clusters whose dimension is not a power of two hold a spin-1 (d = 3) site; their buckets use the
+// table-driven kernels (index maps instead of site bit masks).
+inline bool generic_dim(int D) { return (D & (D - 1)) != 0; }
 
 struct Key {
   int k = 0;
@@ -83,6 +88,7 @@ struct CBucket {
   int32_t* par = nullptr;
   int32_t* rslot = nullptr;
   int32_t* chrs = nullptr;   // [maxch][n] marginal slot of each child (-1: none)
+  int32_t* gtab = nullptr;   // clusters with a spin-1 site: [maxch][n][De] index maps (see ClusterArgs)
 };
 
 struct MBucket {
@@ -272,8 +278,14 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
   const int n = d->n_sites;
   if (n <= 0) return fail(LRH_E_INVALID, "n_sites must be positive");
   if (!d->site_dim) return fail(LRH_E_INVALID, "null site_dim");
-  for (int i = 0; i < n; ++i)
-    if (d->site_dim[i] != 2) return fail(LRH_E_UNSUPPORTED, "only spin-1/2 sites (d = 2) are supported");
+  std::vector<int> sd(n);
+  for (int i = 0; i < n; ++i) {
+    if (d->site_dim[i] != 2 && d->site_dim[i] != 3)
+      return fail(LRH_E_UNSUPPORTED, "site dimension must be 2 (spin-1/2) or 3 (spin-1)");
+    sd[i] = d->site_dim[i];
+  }
+  int dmax = 2;
+  for (int i = 0; i < n; ++i) dmax = std::max(dmax, sd[i]);
   if (d->n_terms < 0 || d->n_top < 0) return fail(LRH_E_INVALID, "negative counts");
   if (d->n_terms > 0 && (!d->term_ptr || !d->term_sites || !d->term_off || !d->term_re))
     return fail(LRH_E_INVALID, "null term arrays");
@@ -296,11 +308,16 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
     if (k <= 0) return fail(LRH_E_INVALID, "empty cluster or term support");
     if (k > kMaxSites) return fail(LRH_E_UNSUPPORTED, "cluster with more than 8 sites (D_e > 256)");
     key.k = k;
+    int64_t D = 1;
+    bool q = true;
     for (int i = 0; i < k; ++i) {
       if (s[i] < 0 || s[i] >= n) return fail(LRH_E_INVALID, "site index out of range");
       if (i > 0 && s[i] <= s[i - 1]) return fail(LRH_E_INVALID, "sites must be ascending and distinct");
       key.s[i] = s[i];
+      D *= sd[s[i]];
+      q = q && sd[s[i]] == 2;
     }
+    if (!q && D > kMaxGenericD) return fail(LRH_E_UNSUPPORTED, "cluster with a spin-1 site and D_e > 64");
     return LRH_OK;
   };
   auto add = [&](const Key& key) {
@@ -386,7 +403,8 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
     const int64_t a = d->term_ptr[t], b = d->term_ptr[t + 1];
     lrh_status st = make_key(d->term_sites + a, (int)(b - a), key);
     if (st != LRH_OK) return st;
-    const int64_t D = (int64_t)1 << key.k;
+    int64_t D = 1;
+    for (int i = 0; i < key.k; ++i) D *= sd[key.s[i]];
     if (d->term_off[t + 1] - d->term_off[t] != D * D) return fail(LRH_E_INVALID, "term block size mismatch");
     if (!two_level) {
       Home h{add(key), {0, 1, 2, 3, 4, 5, 6, 7}, 1.0};
@@ -442,7 +460,9 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
     const Key& k = keys[order[g]];
     P->c_ptr[g + 1] = P->c_ptr[g] + k.k;
     P->c_inst[g] = cinst[order[g]];
-    P->c_D[g] = 1 << k.k;
+    int D = 1;
+    for (int i = 0; i < k.k; ++i) D *= sd[k.s[i]];
+    P->c_D[g] = D;
     P->max_D = std::max(P->max_D, P->c_D[g]);
   }
   P->c_sites.resize(P->c_ptr[nc]);
@@ -619,29 +639,33 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
   P->R_len = roff;
 
   // ---- h_e: the terms at home in the cluster, lifted and weighted, packed ----
-  // H += w * (1 (x) B): B (Dt x Dt) acts on the cluster's sites at positions pos[0..kt),
-  // position p being bit (ke - 1 - p) of a cluster index
-  auto lift_add = [](std::vector<std::complex<double>>& H, int ke, const Home& h, int kt, const double* re,
-                     const double* im, double scale) {
-    const int De = 1 << ke, Dt = 1 << kt;
-    int bit[8];
-    uint32_t tmask = 0;
-    for (int j = 0; j < kt; ++j) {
-      bit[j] = ke - 1 - h.pos[j];
-      tmask |= 1u << bit[j];
+  // H += w * (1 (x) B): B (Dt x Dt) acts on the cluster's sites at positions pos[0..kt); a cluster
+  // index is the big-endian mixed-radix number of its sites' states (first site most significant)
+  auto lift_add = [&](std::vector<std::complex<double>>& H, const Key& ck, const Home& h, int kt, const double* re,
+                      const double* im, double scale) {
+    const int ke = ck.k;
+    int de[8], stride[8], tst[8];
+    int De = 1;
+    for (int p = ke - 1; p >= 0; --p) {
+      de[p] = sd[ck.s[p]];
+      stride[p] = De;
+      De *= de[p];
     }
-    auto spread = [&](int a) {   // term index -> cluster bits
-      uint32_t x = 0;
-      for (int j = 0; j < kt; ++j)
-        if (a >> (kt - 1 - j) & 1) x |= 1u << bit[j];
-      return x;
-    };
+    int Dt = 1;
+    for (int j = kt - 1; j >= 0; --j) {
+      tst[j] = Dt;
+      Dt *= de[h.pos[j]];
+    }
     for (int i = 0; i < De; ++i) {
-      int a = 0;
-      for (int j = 0; j < kt; ++j) a = (a << 1) | (i >> bit[j] & 1);
-      const uint32_t rest = (uint32_t)i & ~tmask;
+      int a = 0, base = i;
+      for (int j = 0; j < kt; ++j) {
+        const int dg = (i / stride[h.pos[j]]) % de[h.pos[j]];
+        a += dg * tst[j];
+        base -= dg * stride[h.pos[j]];
+      }
       for (int b = 0; b < Dt; ++b) {
-        const uint32_t jj = rest | spread(b);
+        int jj = base;
+        for (int j = 0; j < kt; ++j) jj += ((b / tst[j]) % de[h.pos[j]]) * stride[h.pos[j]];
         H[(size_t)i * De + jj] += scale * h.w * std::complex<double>(re[a * Dt + b], im ? im[a * Dt + b] : 0.0);
       }
     }
@@ -649,7 +673,8 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
   std::vector<std::vector<std::complex<double>>> hdense(nc);
   for (int t = 0; t < d->n_terms; ++t) {
     const int kt = (int)(d->term_ptr[t + 1] - d->term_ptr[t]);
-    const int D = 1 << kt;
+    int D = 1;
+    for (int64_t q = d->term_ptr[t]; q < d->term_ptr[t + 1]; ++q) D *= sd[d->term_sites[q]];
     const double* re = d->term_re + d->term_off[t];
     const double* im = d->term_im ? d->term_im + d->term_off[t] : nullptr;
     double mx = 0;
@@ -665,7 +690,7 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
       const int De = P->c_D[g];
       auto& H = hdense[g];
       if (H.empty()) H.assign((size_t)De * De, 0.0);
-      lift_add(H, keys[h.c].k, h, kt, re, im, 1.0);
+      lift_add(H, keys[h.c], h, kt, re, im, 1.0);
     }
   }
   std::vector<double> hpack;
@@ -700,7 +725,8 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
       if (pidx < 0) continue;
       if (pidx >= d->n_params) return fail(LRH_E_INVALID, "term_param out of range");
       const int kt = (int)(d->term_ptr[t + 1] - d->term_ptr[t]);
-      const int Dt = 1 << kt;
+      int Dt = 1;
+      for (int64_t q = d->term_ptr[t]; q < d->term_ptr[t + 1]; ++q) Dt *= sd[d->term_sites[q]];
       const double* re = d->dterm_re + d->term_off[t];
       const double* im = d->dterm_im ? d->dterm_im + d->term_off[t] : nullptr;
       for (int i = 0; i < Dt; ++i)
@@ -713,7 +739,7 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
         const int32_t g = gid_of[h.c];
         const int D = P->c_D[g];
         std::vector<std::complex<double>> B((size_t)D * D, 0.0);
-        lift_add(B, keys[h.c].k, h, kt, re, im, 1.0);
+        lift_add(B, keys[h.c], h, kt, re, im, 1.0);
         const int64_t doff = (int64_t)dterm_pack.size();
         for (int i = 0; i < D; ++i)
           for (int j = i; j < D; ++j) dterm_pack.push_back(0.5 * (B[i * D + j].real() + B[j * D + i].real()));
@@ -780,7 +806,7 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
     size_t deg = 0;
     for (int64_t g = 0; g < nc; ++g)
       if (P->c_ptr[g + 1] - P->c_ptr[g] == 1) deg = std::max(deg, parents[g].size());
-    P->Lambda = (double)deg + 2.0;  // Delta_G + d
+    P->Lambda = (double)deg + (double)dmax;  // Delta_G + d
   } else {
     double lam = 0;
     for (size_t m = 0; m < P->m_parent.size(); ++m) {
@@ -822,6 +848,41 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
         if (h_ch[b][i] >= 0) chrs[i] = h_mrs[B.mb_child][h_ch[b][i]];
     if (chrs.empty()) chrs.push_back(-1);
     UP(B.chrs, chrs);
+    if (generic_dim(B.De) && B.maxch > 0) {
+      // per (child slot, cluster, cluster index i): i's child index a and remaining index r, and the
+      // cluster index of the child/remainder pair (a, r) = (i / NR, i % NR), NR = De / Dc
+      std::vector<int32_t> gt((size_t)B.maxch * B.n * B.De, 0);
+      for (int sl = 0; sl < B.maxch; ++sl)
+        for (int64_t c = 0; c < B.n; ++c) {
+          if (h_ch[b][(size_t)sl * B.n + c] < 0) continue;
+          const int32_t g = B.h_gid[c];
+          const int k = (int)(P->c_ptr[g + 1] - P->c_ptr[g]);
+          const int32_t kmask = h_chmask[b][(size_t)sl * B.n + c];
+          int de[8], stride[8];
+          int De = 1;
+          for (int p = k - 1; p >= 0; --p) {
+            de[p] = sd[P->c_sites[P->c_ptr[g] + p]];
+            stride[p] = De;
+            De *= de[p];
+          }
+          int Dc = 1;
+          for (int p = 0; p < k; ++p)
+            if (kmask >> (k - 1 - p) & 1) Dc *= de[p];
+          const int NR = De / Dc;
+          int32_t* out = gt.data() + ((size_t)sl * B.n + c) * B.De;
+          for (int i = 0; i < De; ++i) {
+            int a = 0, r = 0;
+            for (int p = 0; p < k; ++p) {
+              const int dg = (i / stride[p]) % de[p];
+              if (kmask >> (k - 1 - p) & 1) a = a * de[p] + dg;
+              else r = r * de[p] + dg;
+            }
+            out[i] |= a | (r << 8);
+            out[a * NR + r] |= i << 16;
+          }
+        }
+      UP(B.gtab, gt);
+    }
     UP(B.gid, B.h_gid);
     UP(B.hoff, h_hoff[b]);
     UP(B.ch, h_ch[b]);
@@ -970,6 +1031,7 @@ ClusterArgs<T> base_args(lrh_problem_s* P, const CBucket& B) {
   a.ch = B.ch;
   a.chmask = B.chmask;
   a.ch_rslot = B.chrs;
+  a.gtab = B.gtab;
   a.par = B.par;
   a.rslot = B.rslot;
   a.h = P->h;

@@ -51,6 +51,10 @@ struct ClusterArgs {
   const int64_t* hoff;  // [n] offset into h (packed comps), -1: h_e = 0
   const int32_t* ch;    // [maxch][n] child-message index in the Dc bucket, -1 unused
   const int32_t* chmask;// [maxch][n] bit mask of the child's sites inside the cluster
+  const int32_t* gtab;  // clusters holding a spin-1 site (De not a power of two): [maxch][n][De]
+                        // entry i = a(i) | r(i) << 8 | idx(i / NR, i % NR) << 16, with a(i), r(i) the
+                        // child and remaining indices of cluster index i and idx(a, r) the inverse
+                        // (NR = De / Dc); nullptr for spin-1/2 buckets
   const int32_t* par;   // [maxpar][n] parent-message index in the De bucket, -1 unused
   const int32_t* rslot; // [n] marginal slot in the De marginal buffer, -1: no parents
   const double* h;      // packed term blocks (double)

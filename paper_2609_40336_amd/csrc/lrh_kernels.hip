@@ -229,6 +229,10 @@ __global__ __launch_bounds__(256) void k_scale_offdiag(double* x, int64_t M, int
 
 int cluster_shapes(int De, int Dc, bool dbl, bool cplx, int mode, int* out) {
   int n = 0;
+  if ((De & (De - 1)) != 0) {   // a spin-1 site: the table-driven kernel only
+    if (De <= 64) out[n++] = 5;
+    return n;
+  }
   bool reg = reg_pair(De, Dc);
   if (reg && De >= 8) {
     if (De == 8) reg = !(dbl && cplx && mode != MODE_CERTIFY);

@@ -437,8 +437,9 @@ class Problem:
         v = marg.detach().double().cpu().numpy()
         out = {}
         off = 0
+        sd = np.asarray(self.desc.site_dim)
         for c, sites in enumerate(self.clusters):
-            D = 2 ** len(sites)
+            D = int(np.prod([int(sd[x]) for x in sites]))
             ntri = D * (D + 1) // 2
             n = D * D if not self.is_real else ntri
             blk = v[off:off + n]

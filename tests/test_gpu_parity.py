@@ -91,6 +91,10 @@ PROBLEMS = {
     # growing-cluster hierarchy on a 4 x 4 torus: plaquettes plus 2 x 3 and 3 x 2 rectangles
     # (64-dimensional clusters over two 16-dimensional plaquettes, which have rectangle parents)
     "tfim_grow4_level1": lambda: W.tfim_growing_clusters(4, 2.5, 1),
+    # spin-1 sites (local dimension 3): the table-driven kernels on 3-, 9- and 27-dimensional clusters
+    "spin1_chain": lambda: W.spin1_chain(7, Dz=0.4, hx=0.3),
+    "spin1_Y3_complex": lambda: W.spin1_chain(7, dm=0.25, hx=0.2, top_len=3, subintervals=True),
+    "spin1_T3_two_level": lambda: W.spin1_chain(8, hx=0.3, top_len=3, two_level=True),
 }
 
 
@@ -120,6 +124,7 @@ def test_dual_eval_fp64(name, beta):
 
 
 @pytest.mark.parametrize("name", ["c1_tfim16_complex", "randchain_Y4", "plaq_batch_ragged", "gue_Y5", "gue_Y8",
+                                  "spin1_chain", "spin1_Y3_complex",
                                   "gue_T8_two_level", "plaq_two_level"])
 def test_dual_eval_fp32(name):
     """FP32 iteration arithmetic: values within 2e-5 per site, gradients within 5e-5."""
@@ -141,7 +146,8 @@ def test_dual_eval_fp32(name):
 
 @pytest.mark.parametrize("name", ["c1_tfim16_complex", "randchain_Y6", "plaq_batch_ragged", "xxz_tri3", "gue_Y7",
                                   "gue_Y8", "randchain_Y7_real", "k5_complete", "tfim_rect2x3", "gue_T5_two_level",
-                                  "gue_T8_two_level", "plaq_two_level", "tfim_grow4_level1"])
+                                  "gue_T8_two_level", "plaq_two_level", "tfim_grow4_level1", "spin1_chain",
+                                  "spin1_Y3_complex", "spin1_T3_two_level"])
 def test_certify_fp64_and_from_fp32(name):
     lrh = lrhmod()
     say(f"[certify] {name}")
@@ -237,6 +243,9 @@ NEST = {
     "gue_T6_two_level": (lambda: W.interval_chain_gue(10, 6, 0.1, seed=3, two_level=True), [(2.0, 12), (8.0, 12)]),
     "tree_two_level": (lambda: two_level(W.classical_ising_tree(9, 4, rotate=True)), [(4.0, 40)]),
     "tfim_grow4_level1": (lambda: W.tfim_growing_clusters(4, 2.5, 1), [(2.0, 12), (16.0, 12)]),
+    "spin1_chain": (lambda: W.spin1_chain(7, Dz=0.4, hx=0.3), [(1.0, 30), (6.0, 30)]),
+    "spin1_Y3_complex": (lambda: W.spin1_chain(6, dm=0.25, hx=0.2, top_len=3, subintervals=True),
+                         [(2.0, 20), (8.0, 20)]),
 }
 
 
@@ -411,14 +420,15 @@ def test_health_flags():
 
 
 @pytest.mark.parametrize("f32", [False, True])
-@pytest.mark.parametrize("name", ["plaq", "interval_Y4"])
+@pytest.mark.parametrize("name", ["plaq", "interval_Y4", "spin1_Y3"])
 def test_graph_replayed_general_problem_equals_plain(name, f32):
     """LRH_FUSED on a problem with larger clusters replays the plain launches from a captured
     graph with per-iteration scalars in device memory: identical bits to the plain loop."""
     lrh = lrhmod()
     say(f"[graph==plain] {name} f32={f32}")
-    d = (W.tfim_plaquette_batch([3, 4, 5], [0.9, 2.1, 3.3]) if name == "plaq"
-         else W.interval_chain_gue(10, 4, 0.1, seed=3))
+    d = {"plaq": lambda: W.tfim_plaquette_batch([3, 4, 5], [0.9, 2.1, 3.3]),
+         "interval_Y4": lambda: W.interval_chain_gue(10, 4, 0.1, seed=3),
+         "spin1_Y3": lambda: W.spin1_chain(7, dm=0.25, hx=0.2, top_len=3, subintervals=True)}[name]()
     P = lrh.Problem(d, 0)
     res = []
     for fused in (False, True):

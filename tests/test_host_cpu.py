@@ -44,6 +44,9 @@ PROBLEMS = [
     lambda: W.random_chain(9, seed=1, top_len=2, two_level=True),
     lambda: _two_level(W.classical_ising_tree(9, 3)),
     lambda: _two_level(W.tfim_plaquette_batch([3, 5, 4], [0.5, 1.0, 3.0])),
+    lambda: W.spin1_chain(6),
+    lambda: W.spin1_chain(7, top_len=3, subintervals=True, dm=0.2),
+    lambda: W.spin1_chain(7, top_len=3, two_level=True),
 ]
 
 
@@ -89,11 +92,12 @@ def test_validation_errors():
     bad.term_im = np.zeros_like(bad.term_re)
     bad.term_im[1] = 0.3
     _expect(1, lambda: lrh.Problem(bad, -1))
-    # site dimension 3
-    d3 = W.tfim_chain(4, 1.0, 0.5)
-    d3.site_dim = d3.site_dim.copy()
-    d3.site_dim[0] = 3
-    _expect(2, lambda: lrh.Problem(d3, -1))
+    # site dimension 4 (spin-1/2 and spin-1 sites only); a spin-1 cluster above 64 dimensions
+    d4 = W.tfim_chain(4, 1.0, 0.5)
+    d4.site_dim = d4.site_dim.copy()
+    d4.site_dim[0] = 4
+    _expect(2, lambda: lrh.Problem(d4, -1))
+    _expect(2, lambda: lrh.Problem(W.spin1_chain(6, top_len=4, subintervals=True), -1))
     # cluster spanning two instances
     sp = W.tfim_chain(4, 1.0, 0.5)
     sp.site_instance = np.array([0, 0, 1, 1], dtype=np.int32)

@@ -881,3 +881,32 @@ def test_growing_cluster_hierarchy_tightens_the_bound_on_a_torus():
     # the plaquette family is converged: more iterations move it by far less than that gain
     q0b, m0b = R0.certify(_solve_smoothed(R0, [2.0 ** s for s in range(0, 16, 3)], 800))
     assert abs((q0b - m0b)[0] - b0) <= 0.003 * 16
+
+
+# ------------------------------------------------------------------------------------------
+# spin-1 sites (local dimension 3)
+# ------------------------------------------------------------------------------------------
+
+def test_spin1_heisenberg_level1_closed_form():
+    """Two spin-1 sites: S.S = (S_tot^2 - 4)/2 has lambda_min = -2 (the singlet), whose one-site
+    marginals are 1/3, so singlets on every bond are locally consistent: the level-1 optimum is
+    the Anderson bound -2 J (n - 1), reached at zero messages, where the gradient vanishes."""
+    n = 6
+    R = O.Relaxation(W.spin1_chain(n, J=1.0, Dz=0.0, hx=0.0))
+    assert R.Q(R.zeros())[0] == pytest.approx(-2.0 * (n - 1), abs=1e-12)
+    _, g = R.grad_beta(R.zeros(), 50.0)
+    assert max(float(np.abs(v).max()) for v in g.values()) < 1e-10
+    E0 = E.ground_energy(W.spin1_chain(n, J=1.0, Dz=0.0, hx=0.0))
+    assert -2.0 * (n - 1) <= E0   # weak duality with the exact ground energy (AKLT-like chain: E0 > -2(n-1))
+
+
+@pytest.mark.parametrize("maker", [lambda: W.spin1_chain(6, Dz=0.4, hx=0.3),
+                                   lambda: W.spin1_chain(6, dm=0.3, top_len=3, subintervals=True),
+                                   lambda: W.spin1_chain(7, hx=0.5, top_len=3, two_level=True)])
+def test_spin1_weak_duality_random_messages(maker):
+    """Q(nu) <= E0 for random messages on spin-1 chains (Sec. 4.1), E0 by Lanczos on 3^n states."""
+    d = maker()
+    R = O.Relaxation(d)
+    E0 = E.ground_energy(d)
+    for seed in range(4):
+        assert R.Q(R.draw(80 + seed, 0.7))[0] <= E0 + 1e-10
