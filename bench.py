@@ -232,7 +232,14 @@ def dominant_kernel_roofline(P, nu, beta, f32, torch, reps=3):
         peak = FP32_VALU_PEAK_TFLOPS if f32 else FP64_VALU_PEAK_TFLOPS
         kind = "Jacobi cluster kernel (vector ALU)"
     ach = F / t / 1e12
-    return dict(bound=bound, achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak, traffic=None,
+    extra = {}
+    if bound == "mfma":
+        from paper_2609_40336_amd import lrh
+        sus = lrh.lrh_measure_fp64_mfma(0)
+        extra = dict(sustained_fp64_mfma_tflops=sus, frac_of_sustained=ach / sus,
+                     executed_tflops_note="the exponential executes (5 + s) products of 2 D^3 flops per "
+                                          "cluster, s the squarings (more than the 11 D^3 counted here)")
+    return dict(bound=bound, achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak, traffic=None, **extra,
                 kernel=f"{kind}, bucket D={D} (n={n}), beta={beta:g}",
                 per_launch=dict(flops=F, seconds=t), all_buckets_us=[round(u, 3) for u in us])
 
@@ -468,6 +475,22 @@ def cpu_oracle_legs(Ls, hs, beta, budget):
     return out
 
 
+def profile_traffic_run(P, torch, beta, passes=3):
+    """Short run for hardware counters: `passes` Gibbs passes over every cluster bucket (FP32
+    messages, seeded noise of scale 0.3) at `beta`, then a 64 MiB device copy (a plain copy kernel
+    of known size, to scale FETCH_SIZE / WRITE_SIZE)."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    nu = (0.3 * torch.randn(P.nu_len, generator=g, device="cuda", dtype=torch.float64)).float()
+    for _ in range(passes):
+        P.dual_eval(nu, beta, grad=True)
+    src = torch.ones(16 * 2 ** 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_traffic": "done", "beta": beta, "passes": passes, "copy_bytes": src.numel() * 4}))
+
+
 def bench_c4_default(args, torch, cpu):
     """The default line: the 512-lattice plaquette sweep (see the module docstring)."""
     import lrh_workloads as W
@@ -484,17 +507,19 @@ def bench_c4_default(args, torch, cpu):
     P.autotune(False, cache)
     beta = GAP_BETA_FINAL
     ips = ITERS_PER_STEP
+    if args.profile_traffic:
+        return profile_traffic_run(P, torch, beta)
 
-    def timed_steps(f32, fused, steps, warmup, nu, ze):
+    def timed_steps(f32, fused, steps, warmup):
         """`steps` steps (ips iterations + one FP64 certification) of Algorithm 2 at the solve's
-        final beta, continuing from the solved state (nu, ze) -- the regime where the solve spends
-        most of its iterations -- after `warmup` untimed steps on a copy of it."""
-        w_nu, w_ze = nu.clone(), ze.clone()
+        final beta from nu = 0, after `warmup` untimed steps on another state."""
+        w_nu, w_ze = P.zeros(f32), P.zeros(f32)
         w_st = P.new_nesterov_state(beta)
         for _ in range(warmup):
             P.step_nesterov(w_nu, w_ze, w_st, ips, fused=fused)
             P.certify(w_nu)
         del w_nu, w_ze
+        nu, ze = P.zeros(f32), P.zeros(f32)
         st = P.new_nesterov_state(beta)
         q = torch.zeros((steps, P.n_inst), dtype=torch.float64, device="cuda")
         mg = torch.zeros_like(q)
@@ -506,30 +531,31 @@ def bench_c4_default(args, torch, cpu):
             lrh.lrh_certify(P.h, nu, lrh.LRH_F32 if f32 else 0, q[k], mg[k])
         e1.record()
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / 1e3
+        return e0.elapsed_time(e1) / 1e3, nu, ze
 
-    t1 = time.perf_counter()
-    ref, ref_last = plaquette_reference(hs, torch)
-    print(f"[bench] per-field references in {time.perf_counter() - t1:.1f} s (last stage moved "
-          f"{ref_last:.1e} per site)", file=sys.stderr, flush=True)
-    tte, nu, ze = solve_to_gap(P, True, True, ref, n_sites, torch)
-    print(f"[bench] fused fp32 to {GAP_TARGET:g}: {tte}", file=sys.stderr, flush=True)
     iters = args.steps * ips
-    sec = timed_steps(True, True, args.steps, args.warmup, nu, ze)
+    sec, nu, ze = timed_steps(True, True, args.steps, args.warmup)
     print(f"[bench] fused fp32: {sec:.3f} s for {iters} iterations at beta = {beta:g}", file=sys.stderr, flush=True)
     roof = dominant_kernel_roofline(P, nu, beta, True, torch)
     roof64 = dominant_kernel_roofline(P, nu, 64.0, True, torch)
     msg_roof = message_kernel_roofline(P, nu, ze, beta, torch)
     del nu, ze
-    tte_plain = None
-    if not args.no_plain_gap:
-        tte_plain, nu, ze = solve_to_gap(P, False, False, ref, n_sites, torch)
-        print(f"[bench] plain fp64 to {GAP_TARGET:g}: {tte_plain}", file=sys.stderr, flush=True)
-    else:
-        nu, ze = P.zeros(False), P.zeros(False)
-    sec_plain = timed_steps(False, False, args.steps, min(args.warmup, 1), nu, ze)
+    sec_plain, _, _ = timed_steps(False, False, args.steps, min(args.warmup, 1))
     print(f"[bench] plain fp64: {sec_plain:.3f} s for {iters} iterations", file=sys.stderr, flush=True)
-    del nu, ze
+    tte = tte_plain = None
+    ref_last = None
+    if not args.no_gap:
+        t1 = time.perf_counter()
+        ref, ref_last = plaquette_reference(hs, torch)
+        print(f"[bench] per-field references in {time.perf_counter() - t1:.1f} s (last stage moved "
+              f"{ref_last:.1e} per site)", file=sys.stderr, flush=True)
+        tte, nu, ze = solve_to_gap(P, True, True, ref, n_sites, torch)
+        del nu, ze
+        print(f"[bench] fused fp32 to {GAP_TARGET:g}: {tte}", file=sys.stderr, flush=True)
+        if not args.no_plain_gap:
+            tte_plain, nu, ze = solve_to_gap(P, False, False, ref, n_sites, torch)
+            del nu, ze
+            print(f"[bench] plain fp64 to {GAP_TARGET:g}: {tte_plain}", file=sys.stderr, flush=True)
     nchk, nnf = P.check()
     out = {
         "metric": "cluster updates/s and time-to-1e-4 gap/site: fused vs plain FP64, 1 MI355X",
@@ -541,7 +567,7 @@ def bench_c4_default(args, torch, cpu):
                    "instances": P.n_inst, "clusters": P.n_clusters, "messages": P.n_msgs,
                    "iters_per_step": ips, "beta_of_timed_steps": beta, "parallelism": "single_gpu"},
         "us_per_iteration": sec / iters * 1e6,
-        "time_to_1e-4_gap_per_site_s": tte["seconds"],
+        "time_to_1e-4_gap_per_site_s": tte["seconds"] if tte else None,
         "time_to_gap": {
             "fused_fp32": tte, "plain_fp64": tte_plain,
             "target_gap_per_site": GAP_TARGET,
@@ -617,6 +643,8 @@ def bench_rate(workload, args, torch):
     shapes = P.autotune(True, cache)
     P.autotune(False, cache)
     print(f"[bench] shapes {shapes}", file=sys.stderr, flush=True)
+    if args.profile_traffic:
+        return profile_traffic_run(P, torch, 64.0, passes=2)
     sched = [(2.0 ** s, ips) for s in range(11)]
 
     def timed_schedule(f32, fused):
@@ -974,6 +1002,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-plain-gap", action="store_true",
                     help="default workload: skip the plain FP64 solve to the gap target")
+    ap.add_argument("--no-gap", action="store_true",
+                    help="default workload: timed steps and rooflines only, no solves to the gap target "
+                         "(the command of the kernel-trace profiles)")
     ap.add_argument("--workload", default="c4",
                     help="c4 (default: the 512-lattice plaquette sweep, rate and time to 1e-4), c2 (the "
                          "32x32 Heisenberg solve), c1 (TFIM chain, Algorithm 1), c3k<k> "
@@ -990,8 +1021,9 @@ def main():
     ap.add_argument("--iters-per-stage", type=int, default=0,
                     help="c3k<k>, c3t<k>, c4: iterations per beta stage (default 50; 10 for k = 8)")
     ap.add_argument("--profile-traffic", action="store_true",
-                    help="short run for hardware counters: 4 fused graph chunks, then a 64 MiB "
-                         "device copy (a plain copy kernel of known size, for calibration)")
+                    help="short run for hardware counters, then a 64 MiB device copy (a plain copy kernel "
+                         "of known size, for calibration): c2 4 fused graph chunks; c4, c3k<k>, c3t<k>: Gibbs "
+                         "passes over every bucket (c4 at beta 12288, the others at 64)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the path is single-GPU; --gpus {args.gpus} "

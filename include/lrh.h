@@ -350,6 +350,14 @@ lrh_status lrh_set_jacobi(lrh_problem p, int32_t max_sweeps, double rel_tol);
  * used.  Errors: LRH_E_INVALID (null problem, max_slabs < 0). */
 lrh_status lrh_set_slab_limit(lrh_problem p, int64_t max_slabs);
 
+/* Measurement aid for roofline reports: the FP64 matrix-core rate this device sustains (TFLOP/s),
+ * from eight independent chains of v_mfma_f64_16x16x4_f64 per lane at eight waves per SIMD on
+ * every compute unit, timed with events on `stream` (synchronous; allocates and frees its own
+ * small output buffer).  The published dense FP64 peak is the nominal figure; this is what the
+ * instruction delivers at the device's operating clocks.
+ * Errors: LRH_E_INVALID (null tflops), LRH_E_DEVICE. */
+lrh_status lrh_measure_fp64_mfma(int hip_device, double* tflops, hipStream_t stream);
+
 void lrh_destroy(lrh_problem p);
 const char* lrh_last_error(void);
 /* Static text naming the HIP headers the library was compiled against and its device

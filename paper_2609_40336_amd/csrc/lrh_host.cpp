@@ -2089,6 +2089,37 @@ lrh_status lrh_set_slab_limit(lrh_problem p, int64_t max_slabs) {
   return LRH_OK;
 }
 
+lrh_status lrh_measure_fp64_mfma(int hip_device, double* tflops, hipStream_t stream) {
+  if (!tflops) return fail(LRH_E_INVALID, "null argument");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev)
+    return fail(LRH_E_DEVICE, "invalid HIP device");
+  DeviceGuard guard(hip_device);
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, hip_device));
+  const int blocks = 8 * prop.multiProcessorCount;   // 8 waves per SIMD
+  const int iters = 4000;
+  double* out = nullptr;
+  HIP_TRY(hipMalloc(&out, (size_t)blocks * 256 * sizeof(double)));
+  hipEvent_t e0, e1;
+  hipError_t err = hipEventCreate(&e0);
+  if (err == hipSuccess) err = hipEventCreate(&e1);
+  if (err == hipSuccess) err = launch_mfma_f64_rate(out, blocks, iters, stream);   // warm-up
+  if (err == hipSuccess) err = hipEventRecord(e0, stream);
+  if (err == hipSuccess) err = launch_mfma_f64_rate(out, blocks, iters, stream);
+  if (err == hipSuccess) err = hipEventRecord(e1, stream);
+  if (err == hipSuccess) err = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(out);
+  if (err != hipSuccess) return fail(LRH_E_DEVICE, std::string("fp64 rate probe: ") + hipGetErrorString(err));
+  const double flops = (double)blocks * 4.0 /* waves */ * iters * 8.0 /* chains */ * 2048.0;
+  *tflops = flops / (ms * 1e-3) / 1e12;
+  return LRH_OK;
+}
+
 void lrh_destroy(lrh_problem p) { delete p; }
 
 }  // extern "C"

@@ -163,6 +163,9 @@ template <typename T>
 hipError_t launch_fill_noise(T* x, int64_t n, double scale, uint32_t seed, hipStream_t s);
 template <typename T>
 hipError_t launch_extrap(T* dst, const T* nu, const T* ze, double th, int64_t n, hipStream_t s);
+// sustained FP64 matrix-core rate probe: blocks x 256 threads, 8 MFMA chains of `iters` steps per
+// lane; out: blocks * 256 doubles
+hipError_t launch_mfma_f64_rate(double* out, int blocks, int iters, hipStream_t s);
 // scale the off-diagonal components of every message of a bucket by f
 hipError_t launch_scale_offdiag(double* x, int64_t M, int D, bool cplx, double f, hipStream_t s);
 

@@ -227,6 +227,28 @@ __global__ __launch_bounds__(256) void k_scale_offdiag(double* x, int64_t M, int
 }
 
 
+// Sustained FP64 matrix-core rate: every lane runs 8 independent chains of
+// v_mfma_f64_16x16x4_f64 (2048 flops each per wave); out receives one value per thread.
+__global__ __launch_bounds__(256) void k_mfma_f64_rate(double* out, int iters, double seed) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  d4 c[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) c[i] = d4{0.0, 0.0, 0.0, 0.0};
+  const double a = seed + threadIdx.x, b = 0.5 * seed;
+  for (int it = 0; it < iters; ++it)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) c[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c[i], 0, 0, 0);
+  double r = 0.0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r += c[i][0] + c[i][3];
+  out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = r;
+}
+
+hipError_t launch_mfma_f64_rate(double* out, int blocks, int iters, hipStream_t s) {
+  hipLaunchKernelGGL(k_mfma_f64_rate, dim3((unsigned)blocks), dim3(256), 0, s, out, iters, 1e-3);
+  return hipGetLastError();
+}
+
 int cluster_shapes(int De, int Dc, bool dbl, bool cplx, int mode, int* out) {
   int n = 0;
   if ((De & (De - 1)) != 0) {   // a spin-1 site: the table-driven kernel only

@@ -71,7 +71,7 @@ EXPORTS = ["lrh_build_clusters", "lrh_query", "lrh_export_clusters", "lrh_export
            "lrh_dual_eval", "lrh_step_subgrad", "lrh_step_nesterov", "lrh_certify", "lrh_check",
            "lrh_set_jacobi", "lrh_destroy", "lrh_last_error", "lrh_set_params", "lrh_dual_vjp",
            "lrh_unrolled_bound_grad", "lrh_autotune", "lrh_get_shapes", "lrh_set_shape", "lrh_time_buckets", "lrh_time_messages",
-           "lrh_set_slab_limit", "lrh_build_info", "lrh_certify_noalloc"]
+           "lrh_set_slab_limit", "lrh_build_info", "lrh_certify_noalloc", "lrh_measure_fp64_mfma"]
 
 
 def load(path: str = LIB_PATH):
@@ -115,6 +115,7 @@ def load(path: str = LIB_PATH):
         "lrh_destroy": (None, [vp]),
         "lrh_last_error": (C.c_char_p, []),
         "lrh_build_info": (C.c_char_p, []),
+        "lrh_measure_fp64_mfma": (i32, [C.c_int, C.POINTER(dbl), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -315,6 +316,13 @@ def lrh_get_shapes(h):
                                  W.ctypes.data, us.ctypes.data, C.byref(cnt)))
     return [dict(De=int(De[i]), Dc=int(Dc[i]), n=int(nn[i]), block=int(blk[i]), W=int(W[i]), us=float(us[i]))
             for i in range(n)]
+
+
+def lrh_measure_fp64_mfma(device: int = 0, stream=None) -> float:
+    """Sustained FP64 matrix-core TFLOP/s of the device (see include/lrh.h)."""
+    v = C.c_double(0.0)
+    _check(load().lrh_measure_fp64_mfma(int(device), C.byref(v), _stream(stream)))
+    return v.value
 
 
 def lrh_destroy(h):

@@ -317,3 +317,13 @@ def test_smoothed_dual_backward_uses_its_forward_couplings():
     q3, _ = lrh.smoothed_dual(nu2, None, P, beta)
     q3.sum().backward()
     assert nu2.grad is not None
+
+
+def test_sustained_fp64_mfma_measurement():
+    """The measurement aid behind the roofline reports returns a rate between a tenth of and the
+    published dense FP64 peak (78.6 TFLOP/s)."""
+    lrh = lrhmod()
+    say("[measure] sustained fp64 mfma")
+    v = lrh.lrh_measure_fp64_mfma(0)
+    say(f"  {v:.1f} TFLOP/s")
+    assert 7.86 < v <= 78.6 * 1.02
