@@ -5,12 +5,16 @@ Default workload: the batched sweep of 512 periodic L x L transverse-field Ising
 sites: 3.33 M clusters, 6.66 M messages, real symmetric), entropy-smoothed Algorithm 2 with FP32
 iterations replayed from captured HIP graphs in autotuned launch shapes, FP64 certification
 (lambda_min of every cluster + rounding margin).  A "step" is 50 accelerated iterations
-followed by one certification (every hot-path step a1-a8 over the whole batch); `value` is the
-cluster-update rate over the timed steps.  The same steps in the plain FP64 form (one launch
-per phase, no graph) are reported beside it, then the time to a certified gap of 1e-4 per site
-in every instance for both forms, against per-instance references (see plaquette_reference),
-and the FP64 CPU oracle on one host core and on all of them over a bounded sample.  Inputs are
-synthetic, built on the host and resident in HBM before any timing starts.
+followed by one certification (extrapolation, assembly, Gibbs states, partial traces, message
+updates and the dual value over the whole batch, then the certified bound); `value` is the
+cluster-update rate over the timed steps.  The timed steps run at the final beta of the gap
+schedule, continuing from the schedule's lower-beta stages (an untimed pre-phase), i.e. in
+the regime that takes most of a solve.  The same steps in the plain FP64 form (one launch per
+phase, no graph) are reported beside it, then the time to a certified gap of 1e-4 per site in
+every instance for both forms, from zero messages, against per-instance references (see
+plaquette_reference), and the FP64 CPU oracle on one host core and on all of them over a
+bounded sample.  Inputs are synthetic, built on the host and resident in HBM before any timing
+starts.
 
 Other workloads (--workload): c2 (32 x 32 Heisenberg), c1, c3k<k>, c3t<k>, c4t, c5, ex2, ex3.
 """
@@ -32,10 +36,18 @@ TOTAL_ITERS = 5000
 BETA0, BETA_MAX = 1.0, 1024.0
 Q_REF = -6144.0            # closed form: -3 J per bond, 2048 bonds (singlet on every bond)
 HBM_PEAK_GBS = 8000.0
-# HBM-side bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by
-# a 64 MiB copy (profiles/k_cluster_pair_heisenberg32x32_traffic.md), keyed by the hash of the kernel
-# sources they were taken with; reported as null once the sources change.
-TRAFFIC_BYTES = {"827efd5cb85fcb4b": 1050237}
+# HBM-side bytes per launch of the dominant kernel, per workload: rocprofv3 FETCH_SIZE + WRITE_SIZE
+# of the kernel, each scaled by what the counter reads for a 64 MiB device copy in the same run,
+# stored with the hash of the library sources (kernel_sources_hash) the counters were taken with;
+# reported as null once the sources change.
+TRAFFIC_BYTES = {}
+
+
+def traffic_bytes(workload):
+    rec = TRAFFIC_BYTES.get(workload)
+    return rec[1] if rec and rec[0] == kernel_sources_hash() else None
+
+
 FP32_VALU_PEAK_TFLOPS = 157.3
 
 
@@ -142,10 +154,13 @@ def algorithmic_work(P):
 
 
 def kernel_sources_hash():
+    """First 16 hex digits of the sha256 over every kernel and host source of the library."""
+    import glob
     import hashlib
     h = hashlib.sha256()
-    for f in ("lrh_kernels.hip", "lrh_host.cpp", "lrh_internal.h"):
-        with open(os.path.join(ROOT, "paper_2609_40336_amd", "csrc", f), "rb") as fh:
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2609_40336_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -210,14 +225,15 @@ def message_kernel_roofline(P, nu, ze, beta, torch, reps=3):
                 per_iteration=dict(bytes=nbytes, seconds=sec), buckets_us=[round(u, 3) for u in us])
 
 
-def dominant_kernel_roofline(P, nu, beta, f32, torch, reps=3):
-    """Roofline of the slowest cluster-kernel launch of one pass at messages nu: the bucket's
-    algorithmic flops (11 D^3 real / 44 D^3 complex per cluster: symmetric QR with vectors plus
-    the reconstruction) over its launch duration timed live with HIP events on the launch
-    stream.  The
+def dominant_kernel_roofline(P, nus, beta, f32, torch, reps=3):
+    """Roofline of the slowest cluster-kernel launch of one pass: the bucket's algorithmic flops
+    (11 D^3 real / 44 D^3 complex per cluster: symmetric QR with vectors plus the
+    reconstruction) over its launch duration, timed live with HIP events on the launch stream
+    at each message state in `nus` (the start and end of the timed region) and averaged.  The
     scaling-and-squaring kernel (shape 0) runs in FP64 on the matrix cores, the others on the
     vector ALUs in the iteration precision."""
-    us = P.time_buckets(nu, beta, reps)
+    per_state = [P.time_buckets(nu, beta, reps) for nu in nus]
+    us = [float(np.mean(col)) for col in zip(*per_state)]
     shapes = P.shapes()
     b = int(np.argmax(us))
     sh = shapes[b]
@@ -241,7 +257,9 @@ def dominant_kernel_roofline(P, nu, beta, f32, torch, reps=3):
                                           "cluster, s the squarings (more than the 11 D^3 counted here)")
     return dict(bound=bound, achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak, traffic=None, **extra,
                 kernel=f"{kind}, bucket D={D} (n={n}), beta={beta:g}",
-                per_launch=dict(flops=F, seconds=t), all_buckets_us=[round(u, 3) for u in us])
+                per_launch=dict(flops=F, seconds=t,
+                                seconds_per_state=[round(x[b] * 1e-6, 7) for x in per_state]),
+                all_buckets_us=[round(u, 3) for u in us])
 
 
 def oracle_rate(desc, budget_s, beta=1.0):
@@ -401,6 +419,8 @@ def solve_to_gap(P, f32, fused, ref, n_sites, torch, max_iters=GAP_MAX_ITERS):
         gap = float(np.max(gaps))
         if k % 2500 == 0:
             trace.append((k, gap))
+            print(f"[bench]   {'fp32 fused' if fused else 'fp64 plain'}: {k} iterations, max gap "
+                  f"{gap:.3g} per site", file=sys.stderr, flush=True)
         if gap <= GAP_TARGET:
             reached = k
             break
@@ -510,37 +530,59 @@ def bench_c4_default(args, torch, cpu):
     if args.profile_traffic:
         return profile_traffic_run(P, torch, beta)
 
+    # Pre-phase (untimed): the gap schedule's stages below the final beta (beta = 1, 2, ..., 8192,
+    # GAP_STAGE_ITERS iterations each, FP32 fused), so that the timed steps run in the regime that
+    # takes most of a solve: beta = beta_final near the optimum, where the scaling-and-squaring
+    # kernel's squaring count no longer changes.
+    t1 = time.perf_counter()
+    pre_nu, pre_ze = P.zeros(True), P.zeros(True)
+    pre_iters = 0
+    for b, K in gap_stages()[:-1]:
+        P.step_nesterov(pre_nu, pre_ze, P.new_nesterov_state(b), K, fused=True)
+        pre_iters += K
+    torch.cuda.synchronize()
+    print(f"[bench] pre-phase: {pre_iters} iterations at beta = 1 .. {gap_stages()[-2][0]:g} in "
+          f"{time.perf_counter() - t1:.1f} s", file=sys.stderr, flush=True)
+
     def timed_steps(f32, fused, steps, warmup):
-        """`steps` steps (ips iterations + one FP64 certification) of Algorithm 2 at the solve's
-        final beta from nu = 0, after `warmup` untimed steps on another state."""
-        w_nu, w_ze = P.zeros(f32), P.zeros(f32)
-        w_st = P.new_nesterov_state(beta)
-        for _ in range(warmup):
-            P.step_nesterov(w_nu, w_ze, w_st, ips, fused=fused)
-            P.certify(w_nu)
-        del w_nu, w_ze
+        """`warmup` untimed steps, then `steps` timed steps (ips iterations + one FP64
+        certification each) of Algorithm 2 at the final beta, continuing from the pre-phase's
+        messages (widened to FP64 for the FP64 form) with a fresh accelerated state, as the
+        solve's final stage does.  A short spin kernel marks each end of the timed region in a
+        kernel trace.  Returns the seconds and the messages at the start and end of the timed
+        region."""
         nu, ze = P.zeros(f32), P.zeros(f32)
+        nu.copy_(pre_nu)
+        ze.copy_(pre_ze)
         st = P.new_nesterov_state(beta)
+        for _ in range(warmup):
+            P.step_nesterov(nu, ze, st, ips, fused=fused)
+            P.certify(nu)
+        nu_start = nu.clone()
         q = torch.zeros((steps, P.n_inst), dtype=torch.float64, device="cuda")
         mg = torch.zeros_like(q)
         e0, e1 = _events(torch)
         torch.cuda.synchronize()
+        torch.cuda._sleep(1000)
         e0.record()
         for k in range(steps):
             P.step_nesterov(nu, ze, st, ips, fused=fused)
             lrh.lrh_certify(P.h, nu, lrh.LRH_F32 if f32 else 0, q[k], mg[k])
         e1.record()
+        torch.cuda._sleep(1000)
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / 1e3, nu, ze
+        return e0.elapsed_time(e1) / 1e3, nu_start, nu, ze
 
     iters = args.steps * ips
-    sec, nu, ze = timed_steps(True, True, args.steps, args.warmup)
+    sec, nu_a, nu, ze = timed_steps(True, True, args.steps, args.warmup)
     print(f"[bench] fused fp32: {sec:.3f} s for {iters} iterations at beta = {beta:g}", file=sys.stderr, flush=True)
-    roof = dominant_kernel_roofline(P, nu, beta, True, torch)
-    roof64 = dominant_kernel_roofline(P, nu, 64.0, True, torch)
+    roof = dominant_kernel_roofline(P, [nu_a, nu], beta, True, torch)
+    roof["traffic"] = traffic_bytes("c4")
+    roof64 = dominant_kernel_roofline(P, [nu], 64.0, True, torch)
     msg_roof = message_kernel_roofline(P, nu, ze, beta, torch)
-    del nu, ze
-    sec_plain, _, _ = timed_steps(False, False, args.steps, min(args.warmup, 1))
+    del nu, ze, nu_a
+    sec_plain, _, _, _ = timed_steps(False, False, args.steps, min(args.warmup, 1))
+    del pre_nu, pre_ze
     print(f"[bench] plain fp64: {sec_plain:.3f} s for {iters} iterations", file=sys.stderr, flush=True)
     tte = tte_plain = None
     ref_last = None
@@ -565,7 +607,10 @@ def bench_c4_default(args, torch, cpu):
         "dtype": "f32 iterations, f64 certify", "data": "synthetic",
         "config": {"workload": "tfim_plaquette_sweep_512_L8to64_h0.5to4_seed4_plaquettes_nesterov",
                    "instances": P.n_inst, "clusters": P.n_clusters, "messages": P.n_msgs,
-                   "iters_per_step": ips, "beta_of_timed_steps": beta, "parallelism": "single_gpu"},
+                   "iters_per_step": ips, "beta_of_timed_steps": beta,
+                   "timed_steps_start": f"after the gap schedule's {pre_iters} iterations below beta = {beta:g} "
+                                        f"and {args.warmup} warm-up steps at it",
+                   "parallelism": "single_gpu"},
         "us_per_iteration": sec / iters * 1e6,
         "time_to_1e-4_gap_per_site_s": tte["seconds"] if tte else None,
         "time_to_gap": {
@@ -673,7 +718,7 @@ def bench_rate(workload, args, torch):
     print(f"[bench] fused fp32: {sec:.3f} s for {iters} iterations", file=sys.stderr, flush=True)
     nchk, nnf = P.check()
     n_sites = np.bincount(desc.site_instance, minlength=desc.n_instances)
-    roof = dominant_kernel_roofline(P, S.nu, 64.0, True, torch)
+    roof = dominant_kernel_roofline(P, [S.nu], 64.0, True, torch)
     msg_roof = message_kernel_roofline(P, S.nu, S.ze, 64.0, torch)
     del S
     _, sec_plain, stage_plain, bounds_plain, t_at_plain = timed_schedule(False, False)
@@ -804,7 +849,7 @@ def bench_c5(args, torch):
     e1.record()
     torch.cuda.synchronize()
     t_grad = e0.elapsed_time(e1) / 1e3 / reps
-    roof = dominant_kernel_roofline(P, nu, beta, False, torch)
+    roof = dominant_kernel_roofline(P, [nu], beta, False, torch)
     nchk, nnf = P.check()
     extra = {
         "ms_per_step": t_fwd * 1e3, "dtype": "f64", "beta": beta, "T": T,
@@ -1088,7 +1133,7 @@ def main():
     else:
         roof = dict(bound="alu", achieved=F / t_it / 1e12, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = TRAFFIC_BYTES.get(kernel_sources_hash())
+    roof["traffic"] = traffic_bytes("c2")
     roof["kernel"] = "k_cluster_pair<float,false,MODE_GIBBS> (one fused iteration)"
     roof["per_launch"] = dict(bytes=B, flops=F, seconds=t_it)
     updates = P.n_clusters * fused["iters"]

@@ -206,11 +206,22 @@ lrh_status lrh_step_nesterov(lrh_problem p, void* nu, void* zeta, lrh_nesterov_s
                              int32_t n_iter, uint32_t flags, hipStream_t stream);
 
 /* Certified lower bound (weak duality, Sec. 4.1): FP64 lambda_min of every cluster at
- * nu, summed per instance in a fixed order.  q_dev[i] = Q_C(nu), margin_dev[i] =
- * sum_e [8 D_e eps_64 ||theta_e||_F + r_e] (backward-error margin of the FP64 eigen-solve;
- * r_e = Frobenius norm of the off-diagonal part left by the Jacobi sweeps at D_e <= 8, so the
- * bound holds even when a solve stops at its sweep cap, 0 at D_e >= 16 where the value is the
- * lower end of a Sturm bracket); the certified bound is q - margin <= f*_C <= E0.
+ * nu, summed per instance in a fixed order.  q_dev[i] = Q_C(nu), margin_dev[i] = sum_e m_e,
+ * the rounding margin of each cluster's FP64 solve; the certified bound is
+ * q - margin <= f*_C <= E0.  By dimension:
+ *   D_e <= 8 (Jacobi): m_e = 8 D_e eps_64 ||theta_e||_F + r_e, r_e the Frobenius norm of the
+ *     off-diagonal part left by the sweeps (the bound holds even when a solve stops at its
+ *     sweep cap);
+ *   D_e = 16, 32 (Householder tridiagonalisation, Sturm bisection): m_e = 8 D_e eps_64
+ *     ||theta_e||_F, the value being the lower end of the Sturm bracket;
+ *   D_e = 64, 128: as D_e = 16, 32 (one workgroup per cluster, the matrix in a device slab);
+ *   D_e = 256 (lambda_min only, Sec. 4.2: Lanczos for the Ritz value rho, then one
+ *     Cholesky factorisation of theta_e - sigma I, sigma = rho - eta, that proves
+ *     lambda_min >= sigma - g || |R| ||_1 || |R| ||_inf - 2 u max_i |theta_ii - sigma| - a_e,
+ *     g the Cholesky backward-error constant, a_e an assembly-rounding term): the value is rho
+ *     and m_e = rho minus that bound.  Where the factorisation breaks down the cluster is
+ *     certified by the tridiagonalisation instead (counted, see lrh_certify_fallbacks).
+ * lrh_set_certify_method selects the tridiagonalisation, or the certificate, at every D_e >= 64.
  * Certification always uses the FP64 default Jacobi tolerance (lrh_set_jacobi's tolerance
  * does not apply; its sweep cap does).  nu may be float (LRH_F32); it is widened to double
  * before theta_e is formed.  lmin_dev: device double[n_clusters] (library cluster order) or NULL.
@@ -274,6 +285,19 @@ lrh_status lrh_unrolled_bound_grad(lrh_problem p, const double* nu0_dev, double 
  * non-zero (NONFINITE first), LRH_OK otherwise.  Either pointer may be NULL. */
 lrh_status lrh_check(lrh_problem p, hipStream_t stream, int64_t* noconv, int64_t* nonfinite);
 
+/* Synchronise `stream`, then *count = clusters of D_e >= 64 whose Cholesky certificate broke
+ * down since the last call (certified by the tridiagonalisation instead), and reset it.
+ * Errors: LRH_E_INVALID (null problem or count, host-only problem). */
+lrh_status lrh_certify_fallbacks(lrh_problem p, hipStream_t stream, int64_t* count);
+
+/* Certification of D_e >= 64 clusters: method 0 (default) the Lanczos + Cholesky certificate at
+ * D_e = 256 and Householder tridiagonalisation + Sturm bisection at D_e = 64, 128; 1 the
+ * tridiagonalisation at every D_e >= 64; 3 the certificate at every D_e >= 64; 2 (for tests of
+ * the fallback) the certificate at every D_e >= 64, tried at a shift above lambda_min, so it breaks
+ * down and every such cluster is certified by the tridiagonalisation.
+ * Errors: LRH_E_INVALID (null problem, other method). */
+lrh_status lrh_set_certify_method(lrh_problem p, int32_t method);
+
 /* Launch shapes (the W of the calls below), per cluster bucket and precision:
  *   W = 1      register kernel, one lane per cluster (D_e <= 8), Jacobi
  *   W = 8..64  LDS kernel, W lanes per cluster, 64/W clusters per wave (8 <= D_e <= 64), Jacobi
@@ -287,9 +311,11 @@ lrh_status lrh_check(lrh_problem p, hipStream_t stream, int64_t* noconv, int64_t
  *   W = 5      clusters holding a spin-1 site (D_e not a power of two): the LDS Jacobi kernel
  *              driven by index tables (lift and partial-trace maps per cluster and child) on the
  *              next power of two, with decoupled padding; every mode, the only shape there
- * Certification at D_e >= 16 (spin-1/2) always uses Householder tridiagonalisation and Sturm
- * counts (reported as W = 2 internally: at D_e = 16 and 32 one lane group per cluster holding the
- * rows in registers, then bisection with one lane per cluster; one workgroup per cluster above);
+ * Certification at D_e >= 16 (spin-1/2) uses its own kernels (W = 2 internally): at D_e = 16
+ * and 32 Householder tridiagonalisation with one lane group per cluster holding the rows in
+ * registers, then Sturm bisection with one lane per cluster; at D_e >= 64 one workgroup per
+ * cluster runs the tridiagonalisation (64, 128) or Lanczos and the Cholesky certificate (256; see
+ * lrh_certify);
  * the ground projector and the adjoint use the Jacobi shapes.  The adjoint (lrh_dual_vjp,
  * lrh_unrolled_bound_grad) covers spin-1/2 clusters only.
  *

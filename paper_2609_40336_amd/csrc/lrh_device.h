@@ -1455,45 +1455,55 @@ __device__ void mfma_rebuild(const T* ur, const T* ui, const T* sq, T* orr, T* o
 // theta_e of cluster c assembled element by element into a row-major D x D slab (ar, ai) of
 // element type S; with VEC the slab (ur, ui) is set to the identity.  Returns this thread's
 // share of ||theta||_F^2.
+// Element (i, j) of theta_e for cluster c: h_e, minus the lifted child messages, plus the parent
+// messages (extrapolated with weight th when the zeta pointers are set).
+template <typename T, bool CPLX>
+__device__ __forceinline__ void theta_elem(const ClusterArgs<T>& A, int64_t c, int D, int NB, int64_t ho, int i, int j,
+                                           T th, T& vr, T& vi) {
+  const int Dc = A.Dc;
+  vr = T(0);
+  vi = T(0);
+  if (ho >= 0) herm_elem<T>([&](int k) { return (T)A.h[ho + k]; }, i, j, D, CPLX, vr, vi);
+  for (int s = 0; s < A.maxch; ++s) {
+    const int m = A.ch[(int64_t)s * A.n + c];
+    if (m < 0) continue;
+    const int mask = A.chmask[(int64_t)s * A.n + c];
+    if (((i ^ j) & ~mask & (D - 1)) != 0) continue;
+    const int a = pext_rt(i, mask, NB), b = pext_rt(j, mask, NB);
+    T er, ei;
+    if (A.ze_c)
+      herm_elem<T>([&](int k) { const int64_t o = (int64_t)k * A.Mc + m;
+                                return extrap<T>(A.nu_c[o], A.ze_c[o], th); }, a, b, Dc, CPLX, er, ei);
+    else
+      herm_elem<T>([&](int k) { return A.nu_c[(int64_t)k * A.Mc + m]; }, a, b, Dc, CPLX, er, ei);
+    vr -= er;
+    vi -= ei;
+  }
+  for (int s = 0; s < A.maxpar; ++s) {
+    const int m = A.par[(int64_t)s * A.n + c];
+    if (m < 0) continue;
+    T er, ei;
+    if (A.ze_p)
+      herm_elem<T>([&](int k) { const int64_t o = (int64_t)k * A.Mp + m;
+                                return extrap<T>(A.nu_p[o], A.ze_p[o], th); }, i, j, D, CPLX, er, ei);
+    else
+      herm_elem<T>([&](int k) { return A.nu_p[(int64_t)k * A.Mp + m]; }, i, j, D, CPLX, er, ei);
+    vr += er;
+    vi += ei;
+  }
+}
+
 template <typename T, typename S, bool CPLX, bool VEC>
 __device__ T big_assemble(const ClusterArgs<T>& A, int64_t c, int D, S* ar, S* ai, S* ur, S* ui, T th, int tid,
                           int nth) {
   const int NB = log2i(D);
   const int64_t DD = (int64_t)D * D;
   const int64_t ho = A.hoff[c];
-  const int Dc = A.Dc;
   T my_n2 = T(0);
   for (int64_t idx = tid; idx < DD; idx += nth) {
     const int i = (int)(idx / D), j = (int)(idx % D);
-    T vr = T(0), vi = T(0);
-    if (ho >= 0) herm_elem<T>([&](int k) { return (T)A.h[ho + k]; }, i, j, D, CPLX, vr, vi);
-    for (int s = 0; s < A.maxch; ++s) {
-      const int m = A.ch[(int64_t)s * A.n + c];
-      if (m < 0) continue;
-      const int mask = A.chmask[(int64_t)s * A.n + c];
-      if (((i ^ j) & ~mask & (D - 1)) != 0) continue;
-      const int a = pext_rt(i, mask, NB), b = pext_rt(j, mask, NB);
-      T er, ei;
-      if (A.ze_c)
-        herm_elem<T>([&](int k) { const int64_t o = (int64_t)k * A.Mc + m;
-                                  return extrap<T>(A.nu_c[o], A.ze_c[o], th); }, a, b, Dc, CPLX, er, ei);
-      else
-        herm_elem<T>([&](int k) { return A.nu_c[(int64_t)k * A.Mc + m]; }, a, b, Dc, CPLX, er, ei);
-      vr -= er;
-      vi -= ei;
-    }
-    for (int s = 0; s < A.maxpar; ++s) {
-      const int m = A.par[(int64_t)s * A.n + c];
-      if (m < 0) continue;
-      T er, ei;
-      if (A.ze_p)
-        herm_elem<T>([&](int k) { const int64_t o = (int64_t)k * A.Mp + m;
-                                  return extrap<T>(A.nu_p[o], A.ze_p[o], th); }, i, j, D, CPLX, er, ei);
-      else
-        herm_elem<T>([&](int k) { return A.nu_p[(int64_t)k * A.Mp + m]; }, i, j, D, CPLX, er, ei);
-      vr += er;
-      vi += ei;
-    }
+    T vr, vi;
+    theta_elem<T, CPLX>(A, c, D, NB, ho, i, j, th, vr, vi);
     ar[idx] = (S)vr;
     if constexpr (CPLX) ai[idx] = (S)vi;
     if constexpr (VEC) {
@@ -2407,19 +2417,13 @@ __global__ __launch_bounds__(256) void k_cluster_expm_wg(ClusterArgs<T> A, doubl
 // (number of eigenvalues below x from the signs of the LDL^T pivots), 256 points per round;
 // the lower end of the final bracket, below which no eigenvalue lies, is returned.
 template <bool CPLX, int DE>
-__global__ __launch_bounds__(256) void k_cluster_tridiag(ClusterArgs<double> A, double* scratch, int64_t slab) {
-  constexpr int64_t DD = (int64_t)DE * DE;
+__device__ void tridiag_lambda_min(const ClusterArgs<double>& A, int64_t c, double* ar, double* ai, double nrm2) {
   __shared__ double vr[DE], vi[DE], pr[DE], pi[DE];
   __shared__ double qvr[DE], qvi[DE], qwr[DE], qwi[DE];
   __shared__ double dg[DE], e2[DE];
-  __shared__ double red[8];
+  __shared__ double red[16];
   const int tid = threadIdx.x, nth = blockDim.x;
-  double* ar = scratch + (int64_t)blockIdx.x * slab;
-  double* ai = CPLX ? ar + DD : nullptr;
-  for (int64_t c = blockIdx.x; c < A.n; c += gridDim.x) {
-    const double my_n2 = big_assemble<double, double, CPLX, false>(A, c, DE, ar, ai, (double*)nullptr,
-                                                                    (double*)nullptr, 0.0, tid, nth);
-    const double nrm2 = block_sum(my_n2, red);
+  {
     // The rank-2 update of each reflection is applied during the next reflection's sweep over
     // the trailing matrix (pending vectors qv, qw): every trailing element is read and written
     // once per reflection instead of read twice and written once.  Row k and the final 2 x 2
@@ -2571,6 +2575,356 @@ __global__ __launch_bounds__(256) void k_cluster_tridiag(ClusterArgs<double> A, 
       if (!isfinite(lo) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
     }
     __syncthreads();
+  }
+}
+
+template <bool CPLX, int DE>
+__global__ __launch_bounds__(256) void k_cluster_tridiag(ClusterArgs<double> A, double* scratch, int64_t slab) {
+  constexpr int64_t DD = (int64_t)DE * DE;
+  __shared__ double red[8];
+  const int tid = threadIdx.x, nth = blockDim.x;
+  double* ar = scratch + (int64_t)blockIdx.x * slab;
+  double* ai = CPLX ? ar + DD : nullptr;
+  for (int64_t c = blockIdx.x; c < A.n; c += gridDim.x) {
+    const double my_n2 = big_assemble<double, double, CPLX, false>(A, c, DE, ar, ai, (double*)nullptr,
+                                                                    (double*)nullptr, 0.0, tid, nth);
+    tridiag_lambda_min<CPLX, DE>(A, c, ar, ai, block_sum(my_n2, red));
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// lambda_min-only certification, De = 64, 128, 256 (one workgroup of 256 threads per cluster)
+// ------------------------------------------------------------------------------------------
+//
+// Q_C needs lambda_min of every theta_e and nothing else (Sec. 4.2).  Lanczos from a seeded
+// start vector builds the tridiagonal T_k of theta_e on the Krylov space; its smallest
+// eigenvalue rho is, by interlacing, at least lambda_min and converges to it, typically long
+// before k = De.  rho is certified from below by one Cholesky factorisation of
+// S = theta_e - sigma I at sigma = rho - eta.  If the factorisation runs to completion in
+// floating point, the computed factor R satisfies R^H R = S + dS with |dS| <= g |R^H| |R|
+// (backward error of Cholesky: g = gamma_{De+1} for real and sqrt(2) gamma_{2De+4} for complex
+// arithmetic), so R^H R is positive semidefinite and
+//     lambda_min(theta_e) >= sigma - g || |R| ||_2^2 - u max_i |theta_ii - sigma|
+//                         >= sigma - g || |R| ||_1 || |R| ||_inf - u max_i |theta_ii - sigma|,
+// the last term for the rounding of the shift.  The bound returned is that right-hand side less
+// a term for the rounding of the assembly of theta_e; it is handed over as lambda = rho and
+// margin = rho - bound.  If a pivot is not positive (rho not yet converged, or the start vector
+// blind to the lowest eigenvector), the cluster is certified by the tridiagonalisation path
+// instead (counted in the fallback counter).
+//
+// Memory: theta_e (full, row-major) in the workgroup's slab; Lanczos vectors, T_k and one
+// column-major panel of NB columns of the factor in LDS.  A matrix-vector product reads the
+// slab once (column t of the Hermitian theta_e gives row t of theta_e q, coalesced across t);
+// the right-looking blocked factorisation reads and writes the trailing lower triangle once per
+// panel.
+
+// Smallest eigenvalue of the symmetric tridiagonal (al[0..k-1], off-diagonal be[0..k-2]) by
+// multisection on Sturm counts with every thread of the workgroup, from the bracket
+// [Gershgorin lower end, min_i al_i]; the midpoint of the final bracket.
+__device__ double ritz_min(const double* al, const double* be, int k, double* red) {
+  const int tid = threadIdx.x, nth = blockDim.x;
+  double lo = INFINITY, hi = INFINITY, emax = 0.0;
+  for (int i = 0; i < k; ++i) {   // every thread, same order: identical values
+    const double bl = i > 0 ? be[i - 1] : 0.0, br = i + 1 < k ? be[i] : 0.0;
+    lo = fmin(lo, al[i] - fabs(bl) - fabs(br));
+    hi = fmin(hi, al[i]);
+    emax = fmax(emax, br * br);
+  }
+  const double pivmin = DBL_MIN * fmax(1.0, emax);
+  for (int round = 0; round < 12; ++round) {
+    if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi))) break;
+    const double x = lo + (hi - lo) * (double)(tid + 1) / (double)(nth + 1);
+    int cnt = 0;
+    double q = al[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+    for (int i = 1; i < k; ++i) {
+      q = (al[i] - x) - be[i - 1] * be[i - 1] / q;
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0;
+    }
+    const int t = (int)block_min(cnt > 0 ? (double)tid : (double)nth, red);
+    const double nlo = t == 0 ? lo : lo + (hi - lo) * (double)t / (double)(nth + 1);
+    const double nhi = t == nth ? hi : lo + (hi - lo) * (double)(t + 1) / (double)(nth + 1);
+    if (!(nhi - nlo < hi - lo)) break;
+    lo = nlo;
+    hi = nhi;
+  }
+  return 0.5 * (lo + hi);
+}
+
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {   // a 32-bit integer finaliser
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+template <bool CPLX, int DE>
+__global__ __launch_bounds__(1024) void k_certify_lanczos(ClusterArgs<double> A, double* scratch, int64_t slab) {
+  constexpr int64_t DD = (int64_t)DE * DE;
+  constexpr int NT = 1024;
+  constexpr int NW = NT / 64;
+  constexpr int H = DE / 2;                  // shift-diagonals 0 .. H of the half storage
+  constexpr int G = NT / DE;                 // threads per row in the matrix-vector product
+  constexpr int KMAX = DE < 192 ? DE : 192;  // Lanczos steps at most
+  constexpr int NB = 16;                     // Cholesky panel width (one wave per panel column)
+  __shared__ double qr[DE], qi[CPLX ? DE : 1];
+  __shared__ double yr[G][DE], yi[CPLX ? G : 1][CPLX ? DE : 1];
+  __shared__ double al[KMAX], be[KMAX];
+  __shared__ double Pr[NB][DE], Pi[CPLX ? NB : 1][CPLX ? DE : 1];
+  __shared__ double rsum[DE];
+  __shared__ double csum[NB];
+  __shared__ double red[NW];
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int t = tid % DE, g = tid / DE;
+  const double u = 0.5 * DBL_EPSILON;
+  const int NBITS = log2i(DE);
+  double* ar = scratch + (int64_t)blockIdx.x * slab;
+  double* ai = CPLX ? ar + DD : nullptr;
+  // half storage for the Lanczos products: B[s][t] = theta[(t + s) mod De][t], s = 0 .. De/2
+  double* br = ar;
+  double* bi = CPLX ? ar + (int64_t)(H + 1) * DE : nullptr;
+  for (int64_t c = blockIdx.x; c < A.n; c += gridDim.x) {
+    const int32_t gid = A.gid[c];
+    const int64_t ho = A.hoff[c];
+    double my = 0.0;
+    for (int idx = tid; idx < (H + 1) * DE; idx += NT) {
+      const int sh = idx / DE, tt = idx % DE;
+      double vr_, vi_;
+      theta_elem<double, CPLX>(A, c, DE, NBITS, ho, (tt + sh) & (DE - 1), tt, 0.0, vr_, vi_);
+      br[idx] = vr_;
+      if constexpr (CPLX) bi[idx] = vi_;
+      // every off-diagonal pair once, except on the last shift-diagonal (twice there)
+      const double w = (sh == 0 || sh == H) ? 1.0 : 2.0;
+      my = fma(w * vr_, vr_, my);
+      if constexpr (CPLX) my = fma(w * vi_, vi_, my);
+    }
+    const double nf = sqrt(block_sum(my, red));
+    // ---- Lanczos ----
+    my = 0.0;
+    if (tid < DE) {
+      const uint32_t h0 = mix32((uint32_t)gid * 0x9e3779b9u ^ mix32(2u * (uint32_t)tid + 1u));
+      qr[tid] = (double)h0 * 0x1p-32 - 0.5;
+      my = qr[tid] * qr[tid];
+      if constexpr (CPLX) {
+        qi[tid] = (double)mix32(h0 + 0x632be5abu) * 0x1p-32 - 0.5;
+        my = fma(qi[tid], qi[tid], my);
+      }
+    }
+    const double q0 = 1.0 / sqrt(block_sum(my, red));
+    if (tid < DE) {
+      qr[tid] *= q0;
+      if constexpr (CPLX) qi[tid] *= q0;
+    }
+    double ppr = 0.0, ppi = 0.0, bprev = 0.0;   // q_{k-1} (thread tid < De) and beta_{k-1}
+    double rho = INFINITY, rho_old = INFINITY, dlast = INFINITY;
+    __syncthreads();
+    for (int k = 0; k < KMAX; ++k) {
+      {
+        // (theta q)_t = sum_s conj(B[s][t]) q_{t+s} + sum_{0<s<H} B[s][t-s] q_{t-s}; both reads of
+        // shift-diagonal s are coalesced across t (the second is the first rotated by s).
+        // Thread (g, t) takes the shift-diagonals s = g mod G.
+        double sr = 0.0, si = 0.0;
+#pragma unroll 2
+        for (int sh = g; sh <= H; sh += G) {
+          const double* rr = br + (int64_t)sh * DE;
+          const int up = (t + sh) & (DE - 1), dn = (t - sh) & (DE - 1);
+          const bool two = sh > 0 && sh < H;
+          const double b_r = rr[t];
+          const double c_r = two ? rr[dn] : 0.0;
+          double b_i = 0.0, c_i = 0.0;
+          if constexpr (CPLX) {
+            const double* ri = bi + (int64_t)sh * DE;
+            b_i = ri[t];
+            c_i = two ? ri[dn] : 0.0;
+          }
+          const double xr = qr[up], yr_ = qr[dn];
+          sr = fma(b_r, xr, sr);
+          sr = fma(c_r, yr_, sr);
+          if constexpr (CPLX) {
+            const double xi = qi[up], yi_ = qi[dn];
+            sr = fma(b_i, xi, sr);
+            sr = fma(-c_i, yi_, sr);
+            si = fma(b_r, xi, fma(-b_i, xr, si));
+            si = fma(c_r, yi_, fma(c_i, yr_, si));
+          }
+        }
+        yr[g][t] = sr;
+        if constexpr (CPLX) yi[g][t] = si;
+      }
+      __syncthreads();
+      double wr = 0.0, wi = 0.0, ma = 0.0;
+      if (tid < DE) {
+#pragma unroll
+        for (int h = 0; h < G; ++h) {
+          wr += yr[h][tid];
+          if constexpr (CPLX) wi += yi[h][tid];
+        }
+        wr = fma(-bprev, ppr, wr);
+        ma = qr[tid] * wr;
+        if constexpr (CPLX) {
+          wi = fma(-bprev, ppi, wi);
+          ma = fma(qi[tid], wi, ma);
+        }
+      }
+      const double alpha = block_sum(ma, red);
+      double mb = 0.0;
+      if (tid < DE) {
+        wr = fma(-alpha, qr[tid], wr);
+        mb = wr * wr;
+        if constexpr (CPLX) {
+          wi = fma(-alpha, qi[tid], wi);
+          mb = fma(wi, wi, mb);
+        }
+      }
+      const double beta = sqrt(block_sum(mb, red));
+      const bool invariant = !(beta > 64.0 * u * nf);   // Krylov space invariant (or no progress)
+      if (tid == 0) {
+        al[k] = alpha;
+        be[k] = beta;
+      }
+      if (tid < DE) {
+        ppr = qr[tid];
+        if constexpr (CPLX) ppi = qi[tid];
+        if (!invariant) {
+          const double ib = 1.0 / beta;
+          qr[tid] = wr * ib;
+          if constexpr (CPLX) qi[tid] = wi * ib;
+        }
+      }
+      bprev = beta;
+      __syncthreads();
+      const int kk = k + 1;
+      if (invariant || kk == KMAX || (kk >= 16 && (kk & 7) == 0)) {
+        rho = ritz_min(al, be, kk, red);
+        dlast = invariant ? 0.0 : fabs(rho_old - rho);
+        rho_old = rho;
+        if (dlast <= 64.0 * u * nf) break;
+      }
+    }
+    // the full matrix for the factorisation, over the half storage
+    big_assemble<double, double, CPLX, false>(A, c, DE, ar, ai, (double*)nullptr, (double*)nullptr, 0.0, tid, NT);
+    __syncthreads();
+    // ---- Cholesky of theta - sigma I, sigma = rho - eta ----
+    const double eta = 2.0 * dlast + 16.0 * DE * u * nf;
+    const double sigma = A.cert_method == 2 ? rho + 1.0 + nf : rho - eta;
+    bool ok = isfinite(sigma) && dlast <= 1e-10 * nf;   // unconverged Ritz value: fall back
+    double dmax = 0.0, cmax = 0.0;
+    for (int i = tid; i < DE; i += NT) rsum[i] = 0.0;
+    for (int p = 0; p < DE && ok; p += NB) {
+      const int m = DE - p;   // rows p .. De-1 of the panel
+      for (int idx = tid; idx < m * NB; idx += NT) {
+        const int r = idx / NB, q = idx % NB;
+        const int64_t o = (int64_t)(p + r) * DE + p + q;
+        double vr_ = ar[o], vi_ = CPLX ? ai[o] : 0.0;
+        if (r == q) {
+          vr_ -= sigma;
+          vi_ = 0.0;
+          dmax = fmax(dmax, fabs(vr_));
+        }
+        Pr[q][r] = vr_;
+        if constexpr (CPLX) Pi[q][r] = vi_;
+      }
+      __syncthreads();
+      for (int q = 0; q < NB; ++q) {
+        const double d = Pr[q][q];
+        if (!(d > 0.0) || !isfinite(d)) {   // every thread reads the same value: uniform
+          ok = false;
+          break;
+        }
+        const double l = sqrt(d), il = 1.0 / l;
+        __syncthreads();
+        for (int r = q + tid; r < m; r += NT) {
+          Pr[q][r] = r == q ? l : Pr[q][r] * il;
+          if constexpr (CPLX) Pi[q][r] = r == q ? 0.0 : Pi[q][r] * il;
+        }
+        __syncthreads();
+        // S[r][q2] -= L[r][q] conj(L[q2][q]) for the panel's later columns q2 <= r (wave per column)
+        for (int q2 = q + 1 + wave; q2 < NB; q2 += NW) {
+          const double kr = Pr[q][q2], ki = CPLX ? Pi[q][q2] : 0.0;
+          for (int r = q2 + lane; r < m; r += 64) {
+            const double lr = Pr[q][r];
+            if constexpr (CPLX) {
+              const double li = Pi[q][r];
+              Pr[q2][r] -= fma(lr, kr, li * ki);
+              Pi[q2][r] -= fma(li, kr, -lr * ki);
+            } else {
+              Pr[q2][r] -= lr * kr;
+            }
+          }
+        }
+        __syncthreads();
+      }
+      if (!ok) break;
+      // sums of |L| along the panel's rows (this thread's rows) and columns (wave per column)
+      for (int r = tid; r < m; r += NT) {
+        double rs = 0.0;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          if (r < q) continue;
+          rs += CPLX ? sqrt(fma(Pr[q][r], Pr[q][r], Pi[q][r] * Pi[q][r])) : fabs(Pr[q][r]);
+        }
+        rsum[p + r] += rs;
+      }
+      for (int q = wave; q < NB; q += NW) {
+        double cs = 0.0;
+        for (int r = q + lane; r < m; r += 64)
+          cs += CPLX ? sqrt(fma(Pr[q][r], Pr[q][r], Pi[q][r] * Pi[q][r])) : fabs(Pr[q][r]);
+        cs = wave_sum(cs);
+        if (lane == 0) csum[q] = cs;
+      }
+      // trailing update S[i][j] -= sum_q L[i][q] conj(L[j][q]), i >= j >= p + NB: wave per row
+      const int mt = m - NB;
+      for (int r = wave; r < mt; r += NW) {
+        const int i = NB + r;
+        for (int cc = lane; cc <= r; cc += 64) {
+          const int j = NB + cc;
+          double sr = 0.0, si = 0.0;
+#pragma unroll 4
+          for (int q = 0; q < NB; ++q) {
+            const double ar_ = Pr[q][i], br_ = Pr[q][j];
+            sr = fma(ar_, br_, sr);
+            if constexpr (CPLX) {
+              const double ai_ = Pi[q][i], bi_ = Pi[q][j];
+              sr = fma(ai_, bi_, sr);
+              si = fma(ai_, br_, fma(-ar_, bi_, si));
+            }
+          }
+          const int64_t o = (int64_t)(p + i) * DE + p + j;
+          ar[o] -= sr;
+          if constexpr (CPLX) ai[o] -= si;
+        }
+      }
+      __syncthreads();
+      if (tid == 0)
+        for (int q = 0; q < NB; ++q) cmax = fmax(cmax, csum[q]);
+    }
+    ok = ok && A.cert_method != 2;
+    if (ok) {
+      double rmax = 0.0;
+      for (int i = tid; i < DE; i += NT) rmax = fmax(rmax, rsum[i]);
+      rmax = block_max(rmax, red);
+      dmax = block_max(dmax, red);
+      if (tid == 0) {
+        constexpr double nn = CPLX ? 2.0 * DE + 4.0 : DE + 1.0;
+        const double gam = (CPLX ? 1.4142135623730951 : 1.0) * nn * u / (1.0 - nn * u);
+        const double c_chol = gam * cmax * rmax * (1.0 + 4.0 * DE * u);
+        const double c_shift = 2.0 * u * dmax;
+        const double c_asm = 2.0 * (A.maxch + A.maxpar + 1) * u * nf;
+        A.scal[gid] = rho;
+        A.scal2[gid] = (rho - sigma) + c_chol + c_shift + c_asm;
+        if (!isfinite(rho) && A.nonfinite) atomicAdd(A.nonfinite, 1ull);
+      }
+      __syncthreads();
+    } else {
+      if (tid == 0 && A.cert_fallback) atomicAdd(A.cert_fallback, 1ull);
+      const double n2 = block_sum(big_assemble<double, double, CPLX, false>(A, c, DE, ar, ai, (double*)nullptr,
+                                                                            (double*)nullptr, 0.0, tid, NT), red);
+      tridiag_lambda_min<CPLX, DE>(A, c, ar, ai, n2);
+    }
   }
 }
 
@@ -3192,6 +3546,19 @@ static hipError_t launch_cluster_m(const ClusterArgs<T>& a, int block, int W, hi
       }
       if (a.expm_scratch == nullptr || a.expm_blocks <= 0) return hipErrorInvalidValue;
       const unsigned grid = (unsigned)std::min<int64_t>(a.n, a.expm_blocks);
+      // Lanczos + Cholesky certificate at D_e = 256 by default (methods 2 and 3: every D_e >= 64);
+      // at 64 and 128 the tridiagonalisation is as fast and its margin tighter
+      if (a.cert_method >= 2 || (a.cert_method == 0 && a.De >= 256)) {
+        if (a.De == 64)
+          hipLaunchKernelGGL((k_certify_lanczos<CPLX, 64>), dim3(grid), dim3(1024), 0, s, a, a.expm_scratch, a.expm_slab);
+        else if (a.De == 128)
+          hipLaunchKernelGGL((k_certify_lanczos<CPLX, 128>), dim3(grid), dim3(1024), 0, s, a, a.expm_scratch, a.expm_slab);
+        else if (a.De == 256)
+          hipLaunchKernelGGL((k_certify_lanczos<CPLX, 256>), dim3(grid), dim3(1024), 0, s, a, a.expm_scratch, a.expm_slab);
+        else
+          return hipErrorInvalidValue;
+        return hipGetLastError();
+      }
       if (a.De == 64)
         hipLaunchKernelGGL((k_cluster_tridiag<CPLX, 64>), dim3(grid), dim3(256), 0, s, a, a.expm_scratch, a.expm_slab);
       else if (a.De == 128)

@@ -193,7 +193,8 @@ struct lrh_problem_s {
   double* scal = nullptr;
   double* scal2 = nullptr;
   int64_t* marg_off = nullptr;
-  unsigned long long* health = nullptr;  // [0] noconv, [1] nonfinite
+  unsigned long long* health = nullptr;  // [0] noconv, [1] nonfinite, [2] certificate fallbacks
+  int cert_method = 0;                   // lrh_set_certify_method
   int32_t* improved = nullptr;
   double* nu64_tmp = nullptr;            // widened copy of a float nu for certify
   double* cert_ws = nullptr;             // tridiagonals of the 16- and 32-dimensional buckets (certify)
@@ -925,9 +926,9 @@ lrh_status build(const lrh_problem_desc* d, lrh_problem_s* P) {
   if (st != LRH_OK) return st;
   st = P->dalloc(&P->scal2, nc);
   if (st != LRH_OK) return st;
-  st = P->dalloc(&P->health, 2);
+  st = P->dalloc(&P->health, 3);
   if (st != LRH_OK) return st;
-  HIP_TRY(hipMemset(P->health, 0, 2 * sizeof(unsigned long long)));
+  HIP_TRY(hipMemset(P->health, 0, 3 * sizeof(unsigned long long)));
   st = P->dalloc(&P->improved, std::max<int64_t>(n_inst, 1));
   if (st != LRH_OK) return st;
   st = P->dalloc(&P->fp, kFusedTableMax);
@@ -1042,6 +1043,8 @@ ClusterArgs<T> base_args(lrh_problem_s* P, const CBucket& B) {
   a.tol = P->tol_override > 0 ? P->tol_override : default_tol<T>();
   a.noconv = P->health;
   a.nonfinite = P->health + 1;
+  a.cert_fallback = P->health + 2;
+  a.cert_method = P->cert_method;
   if (B.mb_child >= 0) a.Mc = P->mb[B.mb_child].M;
   if (B.mb_self >= 0) {
     a.Mp = P->mb[B.mb_self].M;
@@ -2003,6 +2006,25 @@ lrh_status lrh_check(lrh_problem p, hipStream_t stream, int64_t* noconv, int64_t
   if (nonfinite) *nonfinite = (int64_t)h[1];
   if (h[1]) return fail(LRH_E_NONFINITE, "non-finite eigenvalue in " + std::to_string(h[1]) + " cluster solves");
   if (h[0]) return fail(LRH_E_NOCONV, "Jacobi sweep cap reached in " + std::to_string(h[0]) + " cluster solves");
+  return LRH_OK;
+}
+
+lrh_status lrh_certify_fallbacks(lrh_problem p, hipStream_t stream, int64_t* count) {
+  if (!p || !count) return fail(LRH_E_INVALID, "null argument");
+  if (p->host_only) return fail(LRH_E_INVALID, "problem was built without a device");
+  DeviceGuard guard(p->device);
+  HIP_TRY(hipStreamSynchronize(stream));
+  unsigned long long h = 0;
+  HIP_TRY(hipMemcpy(&h, p->health + 2, sizeof(h), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemset(p->health + 2, 0, sizeof(h)));
+  *count = (int64_t)h;
+  return LRH_OK;
+}
+
+lrh_status lrh_set_certify_method(lrh_problem p, int32_t method) {
+  if (!p) return fail(LRH_E_INVALID, "null problem");
+  if (method < 0 || method > 3) return fail(LRH_E_INVALID, "method must be 0, 1, 2 or 3");
+  p->cert_method = method;
   return LRH_OK;
 }
 

@@ -100,6 +100,12 @@ struct ClusterArgs {
   // ---- certification at De = 16, 32: tridiagonals of the bucket (2 De n doubles); nullptr: the
   // one-wave kernel with multisection instead ----
   double* cert_ws;
+  // ---- certification at De >= 64: 0 Lanczos + Cholesky certificate at De = 256 (tridiagonalisation
+  // where the certificate fails, and at De = 64, 128), 1 tridiagonalisation only, 2 test hook: the
+  // certificate is tried at a shift above lambda_min at every De >= 64, so every such cluster takes
+  // the tridiagonalisation, 3 the certificate at every De >= 64 ----
+  int cert_method;
+  unsigned long long* cert_fallback;   // clusters certified by the tridiagonalisation instead
 };
 
 template <typename T>

@@ -71,7 +71,8 @@ EXPORTS = ["lrh_build_clusters", "lrh_query", "lrh_export_clusters", "lrh_export
            "lrh_dual_eval", "lrh_step_subgrad", "lrh_step_nesterov", "lrh_certify", "lrh_check",
            "lrh_set_jacobi", "lrh_destroy", "lrh_last_error", "lrh_set_params", "lrh_dual_vjp",
            "lrh_unrolled_bound_grad", "lrh_autotune", "lrh_get_shapes", "lrh_set_shape", "lrh_time_buckets", "lrh_time_messages",
-           "lrh_set_slab_limit", "lrh_build_info", "lrh_certify_noalloc", "lrh_measure_fp64_mfma"]
+           "lrh_set_slab_limit", "lrh_build_info", "lrh_certify_noalloc", "lrh_measure_fp64_mfma",
+           "lrh_certify_fallbacks", "lrh_set_certify_method"]
 
 
 def load(path: str = LIB_PATH):
@@ -104,6 +105,8 @@ def load(path: str = LIB_PATH):
         "lrh_check": (i32, [vp, vp, C.POINTER(i64), C.POINTER(i64)]),
         "lrh_set_jacobi": (i32, [vp, i32, dbl]),
         "lrh_set_slab_limit": (i32, [vp, i64]),
+        "lrh_certify_fallbacks": (i32, [vp, vp, C.POINTER(i64)]),
+        "lrh_set_certify_method": (i32, [vp, i32]),
         "lrh_set_params": (i32, [vp, vp, vp]),
         "lrh_autotune": (i32, [vp, u32, C.c_char_p, vp]),
         "lrh_set_shape": (i32, [vp, i32, i32, i32, u32]),
@@ -259,6 +262,16 @@ def lrh_set_jacobi(h, max_sweeps: int, rel_tol: float = 0.0):
 
 def lrh_set_slab_limit(h, max_slabs: int):
     _check(load().lrh_set_slab_limit(h, int(max_slabs)))
+
+
+def lrh_certify_fallbacks(h, stream=None) -> int:
+    n = C.c_int64(0)
+    _check(load().lrh_certify_fallbacks(h, _stream(stream), C.byref(n)))
+    return int(n.value)
+
+
+def lrh_set_certify_method(h, method: int):
+    _check(load().lrh_set_certify_method(h, int(method)))
 
 
 def lrh_set_params(h, params, stream=None):
@@ -529,6 +542,15 @@ class Problem:
 
     def set_slab_limit(self, max_slabs: int):
         lrh_set_slab_limit(self.h, max_slabs)
+
+    def certify_fallbacks(self, stream=None) -> int:
+        """Clusters (D_e >= 64) certified by the tridiagonalisation since the last call."""
+        return lrh_certify_fallbacks(self.h, stream)
+
+    def set_certify_method(self, method: int):
+        """0: certificate at D_e = 256, tridiagonalisation at 64, 128 (default); 1: tridiagonalisation;
+        3: certificate at every D_e >= 64; 2: fallback test hook (see lrh_set_certify_method)."""
+        lrh_set_certify_method(self.h, method)
 
     def autotune(self, f32: bool = False, cache_path: Optional[str] = None, stream=None):
         lrh_autotune(self.h, LRH_F32 if f32 else 0, cache_path, stream)
