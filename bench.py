@@ -880,7 +880,8 @@ EX3_EPS = [0.02, 0.0139, 0.00965, 0.0067, 0.00465, 0.00323, 0.00224, 0.002]
 def bench_ex3(args, torch):
     """Iterations to epsilon (the paper's comparison of the subgradient and smooth methods):
     level-1 relaxation of 16-site open chains (Heisenberg J = 1 with an on-site X field 0.5,
-    anisotropic Heisenberg (2, -3, 0.5), critical TFIM J = h = 1, a seeded random chain).
+    anisotropic Heisenberg (2, -3, 0.5) with the same field, critical TFIM J = h = 1, a seeded
+    random chain).
 
     * Algorithm 1 with the constant step alpha = eps / (2 Delta_G) (Sec. 4.1.1): since the ground
       projector is scale-invariant, it is Algorithm 1 with step 1 on H / alpha.
@@ -895,7 +896,7 @@ def bench_ex3(args, torch):
     n = 16
     models = {
         "heisenberg_field0.5": W.heisenberg_chain(n, field_x=0.5),
-        "xyz_2_-3_0.5": W.anisotropic_heisenberg_chain(n),
+        "xyz_2_-3_0.5_field0.5": W.anisotropic_heisenberg_chain(n, field_x=0.5),
         "tfim_critical": W.tfim_chain(n, 1.0, 1.0, complex_storage=False),
         "random": W.random_chain(n, seed=7),
     }

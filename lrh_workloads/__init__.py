@@ -262,13 +262,17 @@ def heisenberg_chain(n: int, J: float = 1.0, field_x: float = 0.0) -> ProblemDes
                             name=f"heisenberg_chain_n{n}", field_x=field_x)
 
 
-def anisotropic_heisenberg_chain(n: int, Jx: float = 2.0, Jy: float = -3.0, Jz: float = 0.5):
-    b = _Builder(f"xyz_chain_n{n}", n)
+def anisotropic_heisenberg_chain(n: int, Jx: float = 2.0, Jy: float = -3.0, Jz: float = 0.5,
+                                 field_x: float = 0.0):
+    b = _Builder(f"xyz_chain_n{n}" + (f"_hx{field_x:g}" if field_x else ""), n)
     hh = Jx * kron(X, X) + Jy * kron(Y, Y) + Jz * kron(Z, Z)
     for i in range(n - 1):
         b.add_term((i, i + 1), hh)
         b.add_top((i, i + 1))
-    return b.build(real=True, meta=dict(model="xyz", J=(Jx, Jy, Jz)))
+    if field_x:
+        for i in range(n):
+            b.add_term((i,), field_x * X)
+    return b.build(real=True, meta=dict(model="xyz", J=(Jx, Jy, Jz), field_x=field_x))
 
 
 def random_chain(n: int, seed: int, scale: float = 1.0, top_len: int = 2,

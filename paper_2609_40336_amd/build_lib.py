@@ -21,6 +21,11 @@ HIPCC_FLAGS = [
 ]
 
 
+# the scaling-and-squaring kernels keep their matrix-core results in ordinary VGPRs (the unified
+# register file of gfx950): no copies out of the accumulation registers between products
+FILE_FLAGS = {f: ["-mllvm", "-amdgpu-mfma-vgpr-form=1"] for f in ("lrh_k_f32_gibbs.hip", "lrh_k_f64_gibbs.hip")}
+
+
 def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip"))) + sorted(glob.glob(os.path.join(CSRC, "*.cpp")))
 
@@ -32,7 +37,7 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
     with tempfile.TemporaryDirectory(prefix="lrh_build_") as tmpd:
         def compile_one(src):
             obj = os.path.join(tmpd, os.path.basename(src) + ".o")
-            cmd = [hipcc, *HIPCC_FLAGS, *inc, "-c", "-o", obj, src]
+            cmd = [hipcc, *HIPCC_FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), *inc, "-c", "-o", obj, src]
             if verbose:
                 print(" ".join(cmd), flush=True)
             r = subprocess.run(cmd, capture_output=True, text=True)
