@@ -40,7 +40,12 @@ HBM_PEAK_GBS = 8000.0
 # of the kernel, each scaled by what the counter reads for a 64 MiB device copy in the same run,
 # stored with the hash of the library sources (kernel_sources_hash) the counters were taken with;
 # reported as null once the sources change.
-TRAFFIC_BYTES = {}
+TRAFFIC_BYTES = {
+    # k_cluster_expm<float,false,16>, beta = 12288 (profiles/k_cluster_expm_c4_plaquette_sweep_counters.md)
+    "c4": ("3e94efec74c8e519", 336974809),
+    # k_cluster_expm_wg<float,true,256>, beta = 64 (profiles/k_cluster_expm_wg_c3_interval_k8_counters.md)
+    "c3k8": ("3e94efec74c8e519", 664906881308),
+}
 
 
 def traffic_bytes(workload):
@@ -497,13 +502,15 @@ def cpu_oracle_legs(Ls, hs, beta, budget):
 
 def profile_traffic_run(P, torch, beta, passes=3):
     """Short run for hardware counters: `passes` Gibbs passes over every cluster bucket (FP32
-    messages, seeded noise of scale 0.3) at `beta`, then a 64 MiB device copy (a plain copy kernel
-    of known size, to scale FETCH_SIZE / WRITE_SIZE)."""
+    messages, seeded noise of scale 0.3) at `beta` and one FP64 certification of the same
+    messages, then a 64 MiB device copy (a plain copy kernel of known size, to scale FETCH_SIZE /
+    WRITE_SIZE)."""
     g = torch.Generator(device="cuda")
     g.manual_seed(1)
     nu = (0.3 * torch.randn(P.nu_len, generator=g, device="cuda", dtype=torch.float64)).float()
     for _ in range(passes):
         P.dual_eval(nu, beta, grad=True)
+    P.certify(nu)
     src = torch.ones(16 * 2 ** 20, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
@@ -719,6 +726,7 @@ def bench_rate(workload, args, torch):
     nchk, nnf = P.check()
     n_sites = np.bincount(desc.site_instance, minlength=desc.n_instances)
     roof = dominant_kernel_roofline(P, [S.nu], 64.0, True, torch)
+    roof["traffic"] = traffic_bytes(workload)
     msg_roof = message_kernel_roofline(P, S.nu, S.ze, 64.0, torch)
     del S
     _, sec_plain, stage_plain, bounds_plain, t_at_plain = timed_schedule(False, False)
