@@ -45,6 +45,8 @@ TRAFFIC_BYTES = {
     "c4": ("3e94efec74c8e519", 336974809),
     # k_cluster_expm_wg<float,true,256>, beta = 64 (profiles/k_cluster_expm_wg_c3_interval_k8_counters.md)
     "c3k8": ("3e94efec74c8e519", 664906881308),
+    # k_cluster_pair<float,false,GIBBS> (profiles/k_cluster_pair_heisenberg32x32_traffic.md)
+    "c2": ("3e94efec74c8e519", 1057613),
 }
 
 
