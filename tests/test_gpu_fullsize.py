@@ -210,23 +210,34 @@ def test_fp32_fused_stages_certified_vs_fp64_oracle(name):
 # the certified margin
 # ------------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("D,cplx", [(8, False), (8, True), (16, False), (16, True), (64, True)])
+@pytest.mark.parametrize("D,cplx", [(8, False), (8, True), (16, False), (16, True), (64, True), (128, True),
+                                    (256, False), (256, True)])
 def test_certify_on_exact_spectra(D, cplx):
     """Terms whose spectrum is known exactly (integers up to 1e6): q - margin <= lambda_min
-    exactly, on the Jacobi (D = 8), one-wave tridiagonal (D = 16) and workgroup tridiagonal
-    (D = 64) certification kernels."""
+    exactly, on the Jacobi (D = 8), register-row tridiagonal (D = 16), workgroup tridiagonal
+    (D = 64, 128) and Lanczos + Cholesky (D = 256; at 64 and 128 too with method 3) kernels.
+    Half the draws separate the lowest eigenvalue from the rest by 2e5, where the certificate
+    must hold without falling back; on the others either path may serve."""
     lrh = lrhmod()
     say(f"[certify exact spectrum] D={D} cplx={cplx}")
     rng = np.random.default_rng(300 + D + cplx)
-    for _ in range(12):
+    for t in range(12 if D <= 64 else 6):
         lam = rng.integers(-10 ** 6, 10 ** 6, D)
+        gapped = t % 2 == 0
+        if gapped:
+            lam[int(np.argmin(lam))] = int(lam.min()) - 200000
         d = W.exact_spectrum_problem(lam, cplx)
         P = lrh.Problem(d, 0)
-        q, mg, _ = P.certify(P.zeros())
-        torch.cuda.synchronize()
-        exact = float(lam.min())
-        assert q.item() - mg.item() <= exact
-        assert q.item() - mg.item() >= exact - 1e-6 * 1e6
+        for method in ((0, 3) if D >= 64 else (0,)):
+            P.set_certify_method(method)
+            q, mg, _ = P.certify(P.zeros())
+            torch.cuda.synchronize()
+            exact = float(lam.min())
+            assert q.item() - mg.item() <= exact
+            assert q.item() - mg.item() >= exact - 1e-6 * 1.2e6
+            fb = P.certify_fallbacks()
+            if gapped and (D >= 256 or method == 3):
+                assert fb == 0
 
 
 @pytest.mark.parametrize("name", ["xxz_tri3", "randchain_Y3_complex"])
