@@ -249,7 +249,10 @@ def dominant_kernel_roofline(P, nus, beta, f32, torch, reps=3):
     t = us[b] * 1e-6
     W = sh["W"] if f32 else sh.get("W", 0)
     if W in (0, 4) and D >= 16 and beta > 0:
-        bound, peak, kind = "mfma", FP64_MFMA_PEAK_TFLOPS, "scaling-and-squaring Gibbs kernel (FP64 MFMA)"
+        bound, peak = "mfma", FP64_MFMA_PEAK_TFLOPS
+        kind = ("scaling-and-squaring Gibbs kernel (matrix cores: FP64 polynomial and first four squarings, "
+                "FP32 for the rest; priced against the FP64 peak)" if (f32 and W == 0) else
+                "scaling-and-squaring Gibbs kernel (FP64 MFMA)")
     else:
         bound = "alu"
         peak = FP32_VALU_PEAK_TFLOPS if f32 else FP64_VALU_PEAK_TFLOPS

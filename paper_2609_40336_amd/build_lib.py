@@ -21,9 +21,11 @@ HIPCC_FLAGS = [
 ]
 
 
-# the scaling-and-squaring kernels keep their matrix-core results in ordinary VGPRs (the unified
-# register file of gfx950): no copies out of the accumulation registers between products
-FILE_FLAGS = {f: ["-mllvm", "-amdgpu-mfma-vgpr-form=1"] for f in ("lrh_k_f32_gibbs.hip", "lrh_k_f64_gibbs.hip")}
+# the matrix-core kernels (scaling and squaring; the sustained-rate probe in lrh_kernels.hip) keep
+# their results in ordinary VGPRs (the unified register file of gfx950): no copies through the
+# accumulation registers between instructions
+FILE_FLAGS = {f: ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]
+              for f in ("lrh_k_f32_gibbs.hip", "lrh_k_f64_gibbs.hip", "lrh_kernels.hip")}
 
 
 def sources():

@@ -1735,6 +1735,7 @@ __global__ __launch_bounds__(1024) void k_cluster_big(ClusterArgs<T> A, T* scrat
 // k-step kk, element (16 I + l%16, 16 K + 4 kk + l/16), is the conjugate of register kk of
 // block (K, I): both operands come straight from the registers, with no data movement.
 constexpr int kExpmLut = 8;   // children handled through the LDS index tables (more: generic path)
+constexpr int kF64Squarings = 4;   // float-message path: squarings kept in FP64 before the FP32 ones
 
 // pext and pdep over the site bits of a one-wave cluster (at most 5 sites), for every site mask,
 // built at compile time: pext[mask][i] packs the bits of i at the mask positions;
@@ -1805,6 +1806,62 @@ __device__ __forceinline__ void xmm(const XMat<NB, CPLX>& X, const XMat<NB, CPLX
 
 // lane-local diagonal test for register r of a diagonal block
 __device__ __forceinline__ bool xdiag(int r, int l) { return 4 * r + (l >> 4) == (l & 15); }
+
+// FP32 matrices for the last squarings of the float-message path, in the v_mfma_f32_16x16x4_f32
+// result layout: lane l, register r of block (I, J) is element (16 I + 4 (l/16) + r, 16 J + l%16).
+// Lane group g = l/16 supplies the k index 4 g + kk at k-step kk, so for Hermitian X the A operand
+// of block (I, K) is the conjugate of register kk of block (K, I), as in the FP64 layout.
+template <int NB, bool CPLX>
+struct XMat32 {
+  float re[NB][NB][4];
+  float im[CPLX ? NB : 1][CPLX ? NB : 1][4];
+};
+typedef float mfma_f32x4 __attribute__((ext_vector_type(4)));
+
+template <int NB, bool CPLX>
+__device__ __forceinline__ void xmm32(const XMat32<NB, CPLX>& X, const XMat32<NB, CPLX>& Y, XMat32<NB, CPLX>& C) {
+#pragma unroll
+  for (int J = 0; J < NB; ++J) {
+    mfma_f32x4 cr[NB], ci[NB];
+#pragma unroll
+    for (int I = 0; I < NB; ++I) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        cr[I][r] = C.re[I][J][r];
+        if constexpr (CPLX) ci[I][r] = C.im[I][J][r];
+      }
+#pragma unroll
+      for (int K = 0; K < NB; ++K)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          cr[I] = __builtin_amdgcn_mfma_f32_16x16x4f32(X.re[K][I][kk], Y.re[K][J][kk], cr[I], 0, 0, 0);
+          if constexpr (CPLX) {
+            cr[I] = __builtin_amdgcn_mfma_f32_16x16x4f32(X.im[K][I][kk], Y.im[K][J][kk], cr[I], 0, 0, 0);
+            ci[I] = __builtin_amdgcn_mfma_f32_16x16x4f32(X.re[K][I][kk], Y.im[K][J][kk], ci[I], 0, 0, 0);
+            ci[I] = __builtin_amdgcn_mfma_f32_16x16x4f32(-X.im[K][I][kk], Y.re[K][J][kk], ci[I], 0, 0, 0);
+          }
+        }
+    }
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        C.re[I][J][r] = cr[I][r];
+        if constexpr (CPLX) C.im[I][J][r] = ci[I][r];
+      }
+  }
+}
+
+template <int NB, bool CPLX>
+__device__ __forceinline__ float xtrace32(const XMat32<NB, CPLX>& M, int l) {
+  float t = 0.f;
+#pragma unroll
+  for (int I = 0; I < NB; ++I)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (4 * (l >> 4) + r == (l & 15)) t += M.re[I][I][r];
+  return (float)wave_sum_dpp((double)t);
+}
 
 template <int NB, bool CPLX>
 __device__ __forceinline__ void xzero(XMat<NB, CPLX>& M) {
@@ -2069,6 +2126,15 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
   //     log Z = 2^s log Tr E0 + E log 2 + log Tr Y_s,   rho = Y_s / Tr Y_s.
   // X and M alternate as product buffers (the loop is unrolled by two).
   double E = 0.0;
+  // Float messages: the squarings after the first kF64Squarings (that is, after the fourth
+  // rescaling point) run on the FP32 matrix cores.  A relative rounding error e in Y_j acts on rho
+  // like an error of about 2^(s-j) e in X = beta (theta - mu), and 2^s is about 2 ||X||, so for
+  // j >= 4 the float squarings perturb X by at most about ||X|| u_32 / 8 times the product's error
+  // growth, the order of what the float rounding of the messages themselves puts on X
+  // (beta ||nu|| u_32).  The polynomial and the first squarings, where the error would be
+  // amplified most, stay in FP64.
+  int n64 = s;
+  if constexpr (std::is_same<T, float>::value) n64 = s < kF64Squarings ? s : kF64Squarings;
   auto post = [&](XMat<NB, CPLX>& Y, int j) {
     E *= 2.0;
     if ((j & 3) == 3 || j == s - 1) {
@@ -2086,17 +2152,110 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
           }
     }
   };
-  for (int j = 0; j < s; j += 2) {
+  for (int j = 0; j < n64; j += 2) {
     xzero(X);
     xmm(M, M, X);
     post(X, j);
-    if (j + 1 < s) {
+    if (j + 1 < n64) {
       xzero(M);
       xmm(X, X, M);
       post(M, j + 1);
     } else {
       M = X;
     }
+  }
+  if (n64 < s) {
+    // to the FP32 layout through LDS, squarings n64 .. s-1, and back
+    XMat32<NB, CPLX> Ya, Yb;
+    __syncthreads();
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+      for (int J = 0; J < NB; ++J)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int o = (16 * I + 4 * r + (l >> 4)) * LD + 16 * J + (l & 15);
+          sar[o] = (T)M.re[I][J][r];
+          if constexpr (CPLX) sai[o] = (T)M.im[I][J][r];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+      for (int J = 0; J < NB; ++J)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int o = (16 * I + 4 * (l >> 4) + r) * LD + 16 * J + (l & 15);
+          Ya.re[I][J][r] = (float)sar[o];
+          if constexpr (CPLX) Ya.im[I][J][r] = (float)sai[o];
+        }
+    auto post32 = [&](XMat32<NB, CPLX>& Y, int j) {
+      E *= 2.0;
+      if ((j & 3) == 3 || j == s - 1) {
+        const int e = __builtin_amdgcn_readfirstlane(ilogbf(xtrace32(Y, l)));
+        E += (double)e;
+        const float sc2 = ldexpf(1.f, -e);
+#pragma unroll
+        for (int I = 0; I < NB; ++I)
+#pragma unroll
+          for (int J = 0; J < NB; ++J)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              Y.re[I][J][r] *= sc2;
+              if constexpr (CPLX) Y.im[I][J][r] *= sc2;
+            }
+      }
+    };
+    for (int j = n64; j < s; j += 2) {
+#pragma unroll
+      for (int I = 0; I < NB; ++I)
+#pragma unroll
+        for (int J = 0; J < NB; ++J)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            Yb.re[I][J][r] = 0.f;
+            if constexpr (CPLX) Yb.im[I][J][r] = 0.f;
+          }
+      xmm32(Ya, Ya, Yb);
+      post32(Yb, j);
+      if (j + 1 < s) {
+#pragma unroll
+        for (int I = 0; I < NB; ++I)
+#pragma unroll
+          for (int J = 0; J < NB; ++J)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              Ya.re[I][J][r] = 0.f;
+              if constexpr (CPLX) Ya.im[I][J][r] = 0.f;
+            }
+        xmm32(Yb, Yb, Ya);
+        post32(Ya, j + 1);
+      } else {
+        Ya = Yb;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+      for (int J = 0; J < NB; ++J)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int o = (16 * I + 4 * (l >> 4) + r) * LD + 16 * J + (l & 15);
+          sar[o] = (T)Ya.re[I][J][r];
+          if constexpr (CPLX) sai[o] = (T)Ya.im[I][J][r];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+      for (int J = 0; J < NB; ++J)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int o = (16 * I + 4 * r + (l >> 4)) * LD + 16 * J + (l & 15);
+          M.re[I][J][r] = (double)sar[o];
+          if constexpr (CPLX) M.im[I][J][r] = (double)sai[o];
+        }
   }
   {
     const double tf = xtrace(M, l);
