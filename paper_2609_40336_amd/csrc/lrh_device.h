@@ -2464,6 +2464,87 @@ __device__ double gmm(const double* xr, const double* xi, const double* yr, cons
   return tr;
 }
 
+// C = scale (Y Y) for Hermitian Y in FP32 (the float-message path's later squarings): gmm's tiling
+// and operand reads on FP32 slabs with v_mfma_f32_16x16x4_f32, whose operands are laid out like
+// the FP64 instruction's and whose result register r of lane l holds row 4 (l/16) + r.  Returns
+// this thread's share of the trace.
+template <bool CPLX, int DE>
+__device__ double gsq32(const float* yr, const float* yi, float* cr_, float* ci_, float scale, int tid) {
+  constexpr int TB = DE >= 128 ? 2 : 1;
+  constexpr int NB = DE / 16, NT = NB / TB;
+  constexpr int NP = CPLX ? 2 : 1;
+  const int wave = tid / 64, l = tid % 64;
+  const int lr = l >> 4, lc = l & 15;
+  double tr = 0.0;
+  for (int t = wave; t < NT * (NT + 1) / 2; t += 4) {
+    int TI = 0, TJ = t;
+    while (TJ >= NT - TI) {
+      TJ -= NT - TI;
+      ++TI;
+    }
+    TJ += TI;
+    mfma_f32x4 accr[TB][TB], acci[TB][TB];
+#pragma unroll
+    for (int ii = 0; ii < TB; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < TB; ++jj) {
+        accr[ii][jj] = mfma_f32x4{0.f, 0.f, 0.f, 0.f};
+        acci[ii][jj] = mfma_f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll 1
+    for (int K = 0; K < NB; ++K) {
+      float ga[4][TB][NP], gb[4][TB][NP];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int64_t row = (int64_t)(16 * K + 4 * kk + lr) * DE;
+#pragma unroll
+        for (int q = 0; q < TB; ++q) {
+          const int ca = 16 * (TB * TI + q) + lc, cb = 16 * (TB * TJ + q) + lc;
+          ga[kk][q][0] = yr[row + ca];
+          gb[kk][q][0] = yr[row + cb];
+          if constexpr (CPLX) {
+            ga[kk][q][1] = yi[row + ca];
+            gb[kk][q][1] = yi[row + cb];
+          }
+        }
+      }
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+        for (int ii = 0; ii < TB; ++ii)
+#pragma unroll
+          for (int jj = 0; jj < TB; ++jj) {
+            accr[ii][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[kk][ii][0], gb[kk][jj][0], accr[ii][jj], 0, 0, 0);
+            if constexpr (CPLX) {
+              accr[ii][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[kk][ii][1], gb[kk][jj][1], accr[ii][jj], 0, 0, 0);
+              acci[ii][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[kk][ii][0], gb[kk][jj][1], acci[ii][jj], 0, 0, 0);
+              acci[ii][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ga[kk][ii][1], gb[kk][jj][0], acci[ii][jj], 0, 0, 0);
+            }
+          }
+    }
+#pragma unroll
+    for (int ii = 0; ii < TB; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < TB; ++jj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * (TB * TI + ii) + 4 * lr + r, j = 16 * (TB * TJ + jj) + lc;
+          const int64_t o = (int64_t)i * DE + j;
+          const float vr = scale * accr[ii][jj][r];
+          if (i == j) tr += vr;
+          cr_[o] = vr;
+          const int64_t ot = (int64_t)j * DE + i;
+          if (TI != TJ) cr_[ot] = vr;
+          if constexpr (CPLX) {
+            const float vi = scale * acci[ii][jj][r];
+            ci_[o] = (i == j) ? 0.f : vi;
+            if (TI != TJ) ci_[ot] = -vi;
+          }
+        }
+  }
+  return tr;
+}
+
 template <typename T, bool CPLX, int DE>
 __global__ __launch_bounds__(256) void k_cluster_expm_wg(ClusterArgs<T> A, double* scratch, int64_t slab) {
   constexpr int64_t DD = (int64_t)DE * DE;
@@ -2542,15 +2623,42 @@ __global__ __launch_bounds__(256) void k_cluster_expm_wg(ClusterArgs<T> A, doubl
       tp = Mi; Mi = Bi; Bi = tp;
     }
     // ---- normalise and square: Z_{j+1} = Z_j^2 / (Tr Z_j)^2 ----
+    // (float messages: the squarings after the first kF64Squarings in FP32, in the buffers of X^2
+    // and X^3, which the polynomial no longer needs; see k_cluster_expm)
     double t = block_sum(trp, red);
     double L = log(t);
-    for (int j = 0; j < s; ++j) {
+    const int n64 = std::is_same<T, float>::value ? (s < kF64Squarings ? s : kF64Squarings) : s;
+    for (int j = 0; j < n64; ++j) {
       trp = gmm<CPLX, DE>(Mr, Mi, Mr, Mi, Br, Bi, 1.0 / (t * t), zero, tid);
       __syncthreads();
       double* tp = Mr; Mr = Br; Br = tp;
       tp = Mi; Mi = Bi; Bi = tp;
       t = block_sum(trp, red);
       L = fma(2.0, L, log(t));
+    }
+    if (n64 < s) {
+      float* fa_r = reinterpret_cast<float*>(P2r);
+      float* fa_i = CPLX ? fa_r + DD : nullptr;
+      float* fb_r = fa_r + NPL * DD;
+      float* fb_i = CPLX ? fb_r + DD : nullptr;
+      for (int64_t idx = tid; idx < DD; idx += nth) {
+        fa_r[idx] = (float)Mr[idx];
+        if constexpr (CPLX) fa_i[idx] = (float)Mi[idx];
+      }
+      __syncthreads();
+      for (int j = n64; j < s; ++j) {
+        trp = gsq32<CPLX, DE>(fa_r, fa_i, fb_r, fb_i, (float)(1.0 / (t * t)), tid);
+        __syncthreads();
+        float* tp = fa_r; fa_r = fb_r; fb_r = tp;
+        tp = fa_i; fa_i = fb_i; fb_i = tp;
+        t = block_sum(trp, red);
+        L = fma(2.0, L, log(t));
+      }
+      for (int64_t idx = tid; idx < DD; idx += nth) {
+        Mr[idx] = (double)fa_r[idx];
+        if constexpr (CPLX) Mi[idx] = (double)fa_i[idx];
+      }
+      __syncthreads();
     }
     const double F = mu - L / beta;
     const int32_t gid = A.gid[c];
