@@ -167,3 +167,17 @@ def test_settings_calls_and_defaults_on_host_problem():
     st = lrh.NesterovState()
     st.k, st.theta, st.beta, st.L = 0, 1.0, 2.0, 0.0
     _expect(1, lambda: lrh._check(lrh.load().lrh_step_nesterov(P.h, 8, 8, lrh.C.byref(st), 1, 0, None)))
+
+
+def test_certify_method_and_fallback_counter_validation():
+    """The certification switch accepts methods 0..3 on any problem; the fallback counter needs a
+    device problem and a count pointer."""
+    P = lrh.Problem(W.tfim_chain(4, 1.0, 0.5), -1)
+    for m in (0, 1, 2, 3, 0):
+        P.set_certify_method(m)
+    _expect(1, lambda: P.set_certify_method(-1))
+    _expect(1, lambda: P.set_certify_method(4))
+    n = lrh.C.c_int64(0)
+    _expect(1, lambda: lrh._check(lrh.load().lrh_certify_fallbacks(P.h, None, lrh.C.byref(n))))
+    _expect(1, lambda: lrh._check(lrh.load().lrh_certify_fallbacks(P.h, None, None)))
+    _expect(1, lambda: lrh._check(lrh.load().lrh_set_certify_method(None, 0)))
