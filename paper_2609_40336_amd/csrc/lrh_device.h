@@ -1852,15 +1852,25 @@ __device__ __forceinline__ void xmm32(const XMat32<NB, CPLX>& X, const XMat32<NB
   }
 }
 
+// Trace of an FP32-layout matrix: the diagonal sits in lanes whose 4-lane group (l % 16) / 4
+// equals l / 16 (lanes 0-3, 20-23, 40-43, 60-63), register l % 4; two quad-permute DPP steps
+// and four readlanes sum it.  Used only for the binary exponent of the rescaling steps.
+template <int CTRL>
+__device__ __forceinline__ float dpp_movf(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
 template <int NB, bool CPLX>
 __device__ __forceinline__ float xtrace32(const XMat32<NB, CPLX>& M, int l) {
-  float t = 0.f;
+  float v = 0.f;
 #pragma unroll
   for (int I = 0; I < NB; ++I)
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      if (4 * (l >> 4) + r == (l & 15)) t += M.re[I][I][r];
-  return (float)wave_sum_dpp((double)t);
+      if (4 * (l >> 4) + r == (l & 15)) v += M.re[I][I][r];
+  v += dpp_movf<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_movf<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  const auto rl = [&](int lane) { return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane)); };
+  return (rl(0) + rl(20)) + (rl(40) + rl(60));
 }
 
 template <int NB, bool CPLX>
@@ -1876,22 +1886,74 @@ __device__ __forceinline__ void xzero(XMat<NB, CPLX>& M) {
       }
 }
 
+// Trace of an FP64-layout matrix: the diagonal sits in lanes with l % 4 == l / 16, register
+// (l % 16) / 4 of every diagonal block, four lanes 4 apart in each row of 16.  Two row-shift
+// DPP steps leave each row's sum in its lane 12 + l / 16; four readlanes add the rows.
 template <int NB, bool CPLX>
 __device__ __forceinline__ double xtrace(const XMat<NB, CPLX>& M, int l) {
-  double t = 0.0;
+  double v = 0.0;
 #pragma unroll
   for (int I = 0; I < NB; ++I)
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      if (xdiag(r, l)) t += M.re[I][I][r];
-  return wave_sum_dpp(t);
+      if (xdiag(r, l)) v += M.re[I][I][r];
+  v += dpp_mov<0x114>(v);   // row_shr:4
+  v += dpp_mov<0x118>(v);   // row_shr:8
+  return (readlane_d(v, 12) + readlane_d(v, 29)) + (readlane_d(v, 46) + readlane_d(v, 63));
 }
+
+// log x = k log 2 + log m for a positive double x: k (returned in kk, an integer-valued double)
+// and log m, m = x 2^-k in [1/sqrt 2, sqrt 2), from log m = 2 atanh(z), z = (m - 1) / (m + 1),
+// |z| <= 0.1716, with the odd series of atanh summed to z^19 (the first omitted term is below
+// 1e-17).  m - 1 is exact, so log m is accurate to a few units in the last place.  A NaN or
+// infinite x gives a NaN.
+__device__ __forceinline__ double log_split(double x, double& kk) {
+  int k = __builtin_amdgcn_frexp_exp(x);          // x = m 2^k, m in [0.5, 1)
+  double m = __builtin_amdgcn_frexp_mant(x);
+  if (m < 0.70710678118654752440) {
+    m *= 2.0;
+    --k;
+  }
+  kk = (double)k;
+  const double z = (m - 1.0) / (m + 1.0), z2 = z * z;
+  double p = 1.0 / 19;
+  p = fma(p, z2, 1.0 / 17);
+  p = fma(p, z2, 1.0 / 15);
+  p = fma(p, z2, 1.0 / 13);
+  p = fma(p, z2, 1.0 / 11);
+  p = fma(p, z2, 1.0 / 9);
+  p = fma(p, z2, 1.0 / 7);
+  p = fma(p, z2, 1.0 / 5);
+  p = fma(p, z2, 1.0 / 3);
+  p = fma(p, z2, 1.0);
+  return 2.0 * z * p;
+}
+
+// Diagonal updates v + a of a diagonal block: for the real 16 x 16 case (registers to spare at
+// full occupancy) as fma(a, dg[r], v) with a per-lane 0.0 / 1.0 indicator, one instruction; in
+// the other cases as a lane select, which keeps the indicator out of the registers.
+template <int NB, bool CPLX>
+struct XDiag {
+  static constexpr bool kFma = NB == 1 && !CPLX;
+  double dg[kFma ? 4 : 1];
+  int l;
+  __device__ __forceinline__ explicit XDiag(int lane) : l(lane) {
+    if constexpr (kFma) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dg[r] = xdiag(r, lane) ? 1.0 : 0.0;
+    }
+  }
+  __device__ __forceinline__ double add(int r, double a, double v) const {
+    if constexpr (kFma) return fma(a, dg[r], v);   // exactly v off the diagonal
+    else return xdiag(r, l) ? v + a : v;
+  }
+};
 
 // D = a I + b A + c A2 (+ d A3)
 template <int NB, bool CPLX, bool WITH3>
 __device__ __forceinline__ void xpoly(XMat<NB, CPLX>& D, double a, double b, double c, double d,
                                       const XMat<NB, CPLX>& A1, const XMat<NB, CPLX>& A2,
-                                      const XMat<NB, CPLX>& A3, int l) {
+                                      const XMat<NB, CPLX>& A3, const XDiag<NB, CPLX>& dg) {
 #pragma unroll
   for (int I = 0; I < NB; ++I)
 #pragma unroll
@@ -1900,7 +1962,7 @@ __device__ __forceinline__ void xpoly(XMat<NB, CPLX>& D, double a, double b, dou
       for (int r = 0; r < 4; ++r) {
         double v = fma(c, A2.re[I][J][r], b * A1.re[I][J][r]);
         if constexpr (WITH3) v = fma(d, A3.re[I][J][r], v);
-        if (I == J && xdiag(r, l)) v += a;
+        if (I == J) v = dg.add(r, a, v);
         D.re[I][J][r] = v;
         if constexpr (CPLX) {
           double w = fma(c, A2.im[I][J][r], b * A1.im[I][J][r]);
@@ -1950,18 +2012,39 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
     // (h_e, then the children in slot order, then the parents: the order of the generic path)
     const int64_t ho = A.hoff[c];
     T acr[NB][NB][4], aci[NB][NB][4];
+    // h_e from its packed upper triangle (real plane, then the strict upper imaginary plane);
+    // the cluster-uniform test sits outside the loop so that a lane's loads issue together.  The
+    // packed index of (lo, hi), lo <= hi, is lo (2D + 1 - lo) / 2 + hi - lo, and the strict one
+    // lo (2D - 1 - lo) / 2 + hi - lo - 1; both products are even.
+    if (ho >= 0) {
+      const double* hp = A.h + ho;
 #pragma unroll
-    for (int I = 0; I < NB; ++I)
+      for (int I = 0; I < NB; ++I)
 #pragma unroll
-      for (int J = 0; J < NB; ++J)
+        for (int J = 0; J < NB; ++J)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = 16 * I + 4 * r + (l >> 4), j = 16 * J + (l & 15);
-          double vr = 0.0, vi = 0.0;
-          if (ho >= 0) herm_elem_bf<double, CPLX>([&](int k) { return A.h[ho + k]; }, i, j, DE, vr, vi);
-          acr[I][J][r] = (T)vr;
-          aci[I][J][r] = (T)vi;
-        }
+          for (int r = 0; r < 4; ++r) {
+            const int i = 16 * I + 4 * r + (l >> 4), j = 16 * J + (l & 15);
+            const unsigned lo = (unsigned)min(i, j), hi = (unsigned)max(i, j);
+            acr[I][J][r] = (T)hp[((lo * (2u * DE + 1u - lo)) >> 1) + hi - lo];
+            if constexpr (CPLX) {
+              const double v = hp[DE * (DE + 1) / 2 + (lo < hi ? ((lo * (2u * DE - 1u - lo)) >> 1) + hi - lo - 1u : 0u)];
+              aci[I][J][r] = (T)(i < j ? v : (i > j ? -v : 0.0));
+            } else {
+              aci[I][J][r] = T(0);
+            }
+          }
+    } else {
+#pragma unroll
+      for (int I = 0; I < NB; ++I)
+#pragma unroll
+        for (int J = 0; J < NB; ++J)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            acr[I][J][r] = T(0);
+            aci[I][J][r] = T(0);
+          }
+    }
     // the (extrapolated) child messages, dense D_c x D_c in LDS, one pass over all children
     for (int idx = l; idx < nch << (2 * ldc); idx += 64) {
       const int s = idx >> (2 * ldc), ab = idx & ((1 << (2 * ldc)) - 1);
@@ -2040,6 +2123,7 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
   }
   // ---- shift, scale ----
   const double mu = xtrace(X, l) / DE;
+  const XDiag<NB, CPLX> dg(l);
   double n2 = 0.0;
 #pragma unroll
   for (int I = 0; I < NB; ++I)
@@ -2048,30 +2132,49 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         double v = X.re[I][J][r];
-        if (I == J && xdiag(r, l)) v -= mu;
+        if (I == J) v = dg.add(r, -mu, v);
         X.re[I][J][r] = v;
         n2 = fma(v, v, n2);
         if constexpr (CPLX) n2 = fma(X.im[I][J][r], X.im[I][J][r], n2);
       }
-  // induced 1-norm: row (16 I + 4 r + l/16) is spread over the blocks J and the 16 lanes that
-  // share l/16 (one DPP row), whose reduction leaves every lane of the row with the same sum
+  // induced 1-norm as the largest column sum (theta is Hermitian, so it equals the largest row
+  // sum): column 16 J + l%16 of block column J is spread over the registers of the lanes
+  // l%16 + 16 g; two xor-shuffles complete it in every lane, a DPP row maximum then leaves the
+  // largest column sum in every lane
   double rmax = 0.0;
 #pragma unroll
-  for (int I = 0; I < NB; ++I)
+  for (int J = 0; J < NB; ++J) {
+    double a = 0.0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      double a = 0.0;
+    for (int I = 0; I < NB; ++I)
 #pragma unroll
-      for (int J = 0; J < NB; ++J) {
+      for (int r = 0; r < 4; ++r) {
         if constexpr (CPLX) a += sqrt(fma(X.re[I][J][r], X.re[I][J][r], X.im[I][J][r] * X.im[I][J][r]));
         else a += fabs(X.re[I][J][r]);
       }
-      rmax = fmax(rmax, row_sum16(a));
-    }
-  rmax = wave_max_rows(rmax);
-  const double nrm = beta * fmin(sqrt(wave_sum_dpp(n2)), rmax);
-  int s = 0;
-  while (s < 200 && nrm > ldexp(0.5, s)) ++s;
+    a += __shfl_xor(a, 16, 64);
+    a += __shfl_xor(a, 32, 64);
+    rmax = fmax(rmax, a);
+  }
+  rmax = fmax(rmax, dpp_mov<0xB1>(rmax));    // quad_perm [1, 0, 3, 2]
+  rmax = fmax(rmax, dpp_mov<0x4E>(rmax));    // quad_perm [2, 3, 0, 1]
+  rmax = fmax(rmax, dpp_mov<0x141>(rmax));   // row_half_mirror
+  rmax = fmax(rmax, dpp_mov<0x140>(rmax));   // row_mirror
+  // (the hardware square root: nrm only chooses s, where a relative error of a few units in
+  // the last place is immaterial)
+  const double nrm = beta * fmin(__builtin_amdgcn_sqrt(wave_sum_dpp(n2)), rmax);
+  // s = the least s >= 0 with nrm <= 2^(s-1), at most 200 (0 for a NaN norm): from the binary
+  // exponent of nrm instead of a search
+  int s;
+  if (!(nrm > 0.5)) {
+    s = 0;
+  } else if (!(nrm <= 0x1p199)) {
+    s = 200;
+  } else {
+    int e;
+    const double m = frexp(nrm, &e);   // nrm = m 2^e, 0.5 <= m < 1
+    s = m == 0.5 ? e : e + 1;
+  }
   s = __builtin_amdgcn_readfirstlane(s);   // every lane holds the same value; make it scalar
   const double sc = -ldexp(beta, -s);
 #pragma unroll
@@ -2091,43 +2194,46 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
   xmm(X, X, P2);
   xzero(P3);
   xmm(X, P2, P3);
-  xpoly<NB, CPLX, true>(M, c9, c10, c11, c12, X, P2, P3, l);    // B3
+  xpoly<NB, CPLX, true>(M, c9, c10, c11, c12, X, P2, P3, dg);    // B3
   {
     XMat<NB, CPLX> B;
-    xpoly<NB, CPLX, false>(B, c6, c7, c8, 0.0, X, P2, P3, l);   // B2 + X^3 B3
+    xpoly<NB, CPLX, false>(B, c6, c7, c8, 0.0, X, P2, P3, dg);   // B2 + X^3 B3
     xmm(P3, M, B);
     M = B;
-    xpoly<NB, CPLX, false>(B, c3, c4, c5, 0.0, X, P2, P3, l);   // B1 + X^3 (...)
+    xpoly<NB, CPLX, false>(B, c3, c4, c5, 0.0, X, P2, P3, dg);   // B1 + X^3 (...)
     xmm(P3, M, B);
     M = B;
-    xpoly<NB, CPLX, false>(B, c0, c1, c2, 0.0, X, P2, P3, l);   // B0 + X^3 (...)
+    xpoly<NB, CPLX, false>(B, c0, c1, c2, 0.0, X, P2, P3, dg);   // B0 + X^3 (...)
     xmm(P3, M, B);
     M = B;
   }
   // ---- normalise and square s times ----
-  double t = xtrace(M, l);
-  double L = log(t);
+  // Every rescaling is by an exact power of two 2^-e_j, e_j the binary exponent of the trace
+  // (frexp's exponent minus one; a non-finite trace leaves the result non-finite, which is flagged):
+  // first E0 itself (e_0, so Y_0 has trace in [1, 2)), then the squares j = 3, 7, 11, ...  For a
+  // PSD Y with trace at least 1 the largest eigenvalue is at least 1/D, so four unscaled
+  // squarings keep the trace within [D^-16, 2^16], far inside the FP32 and FP64 ranges, and up to
+  // three more after the last rescaling keep it above D^-8.  The exponents are accumulated as an
+  // integer, E <- 2E + e_j (starting from E = e_0), so no logarithm or division sits in the loop:
+  //     log Z = E log 2 + log Tr Y_s,   rho = Y_s / Tr Y_s.
+  // X and M alternate as product buffers (the loop is unrolled by two).
+  double E;
   {
-    const double it = 1.0 / t;
+    const int e0 = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_frexp_exp(xtrace(M, l)) - 1);
+    E = (double)e0;
+    const double sc0 = ldexp(1.0, -e0);
 #pragma unroll
     for (int I = 0; I < NB; ++I)
 #pragma unroll
       for (int J = 0; J < NB; ++J)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          M.re[I][J][r] *= it;
-          if constexpr (CPLX) M.im[I][J][r] *= it;
+          M.re[I][J][r] *= sc0;
+          if constexpr (CPLX) M.im[I][J][r] *= sc0;
         }
   }
-  // Squarings are rescaled by exact powers of two 2^-e_j, j = 3, 7, 11, ... and the last, chosen
-  // from the trace (for a PSD Y of trace 1, Tr(Y^(2^k)) >= D^(1 - 2^k), so four unscaled
-  // squarings stay far above the FP64 range limit); e_j = 0 elsewhere.  The exponents are
-  // accumulated as an integer, E <- 2E + e_j, so no logarithm or division sits in the loop:
-  //     log Z = 2^s log Tr E0 + E log 2 + log Tr Y_s,   rho = Y_s / Tr Y_s.
-  // X and M alternate as product buffers (the loop is unrolled by two).
-  double E = 0.0;
-  // Float messages: the squarings after the first kF64Squarings (that is, after the fourth
-  // rescaling point) run on the FP32 matrix cores.  A relative rounding error e in Y_j acts on rho
+  // Float messages: the squarings after the first kF64Squarings (up to and including the
+  // rescaling at j = 3) run on the FP32 matrix cores.  A relative rounding error e in Y_j acts on rho
   // like an error of about 2^(s-j) e in X = beta (theta - mu), and 2^s is about 2 ||X||, so for
   // j >= 4 the float squarings perturb X by at most about ||X|| u_32 / 8 times the product's error
   // growth, the order of what the float rounding of the messages themselves puts on X
@@ -2137,8 +2243,8 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
   if constexpr (std::is_same<T, float>::value) n64 = s < kF64Squarings ? s : kF64Squarings;
   auto post = [&](XMat<NB, CPLX>& Y, int j) {
     E *= 2.0;
-    if ((j & 3) == 3 || j == s - 1) {
-      const int e = __builtin_amdgcn_readfirstlane(ilogb(xtrace(Y, l)));
+    if ((j & 3) == 3) {
+      const int e = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_frexp_exp(xtrace(Y, l)) - 1);
       E += (double)e;
       const double sc2 = ldexp(1.0, -e);
 #pragma unroll
@@ -2191,8 +2297,8 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
         }
     auto post32 = [&](XMat32<NB, CPLX>& Y, int j) {
       E *= 2.0;
-      if ((j & 3) == 3 || j == s - 1) {
-        const int e = __builtin_amdgcn_readfirstlane(ilogbf(xtrace32(Y, l)));
+      if ((j & 3) == 3) {
+        const int e = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_frexp_expf(xtrace32(Y, l)) - 1);
         E += (double)e;
         const float sc2 = ldexpf(1.f, -e);
 #pragma unroll
@@ -2257,9 +2363,12 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
           if constexpr (CPLX) M.im[I][J][r] = (double)sai[o];
         }
   }
+  double L;
   {
     const double tf = xtrace(M, l);
-    L = fma(ldexp(1.0, s), L, fma(E, 0.69314718055994530942, log(tf)));
+    double kf;
+    const double lm = log_split(tf, kf);
+    L = fma(E + kf, 0.69314718055994530942, lm);   // E + kf is exact
     const double it = 1.0 / tf;
 #pragma unroll
     for (int I = 0; I < NB; ++I)
