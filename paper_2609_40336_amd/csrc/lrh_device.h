@@ -1902,6 +1902,23 @@ __device__ __forceinline__ double xtrace(const XMat<NB, CPLX>& M, int l) {
   return (readlane_d(v, 12) + readlane_d(v, 29)) + (readlane_d(v, 46) + readlane_d(v, 63));
 }
 
+// FP32 estimate of the trace of an FP64-layout matrix, for the binary exponent of a rescaling
+// (the value only picks an exact power of two): the diagonal lanes as in xtrace, the sum in FP32.
+template <int NB, bool CPLX>
+__device__ __forceinline__ float xtrace_est(const XMat<NB, CPLX>& M, int l) {
+  double t = 0.0;
+#pragma unroll
+  for (int I = 0; I < NB; ++I)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (xdiag(r, l)) t += M.re[I][I][r];
+  float v = (float)t;
+  v += dpp_movf<0x114>(v);   // row_shr:4
+  v += dpp_movf<0x118>(v);   // row_shr:8
+  const auto rl = [&](int lane) { return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane)); };
+  return (rl(12) + rl(29)) + (rl(46) + rl(63));
+}
+
 // log x = k log 2 + log m for a positive double x: k (returned in kk, an integer-valued double)
 // and log m, m = x 2^-k in [1/sqrt 2, sqrt 2), from log m = 2 atanh(z), z = (m - 1) / (m + 1),
 // |z| <= 0.1716, with the odd series of atanh summed to z^19 (the first omitted term is below
@@ -2219,7 +2236,7 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
   // X and M alternate as product buffers (the loop is unrolled by two).
   double E;
   {
-    const int e0 = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_frexp_exp(xtrace(M, l)) - 1);
+    const int e0 = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_frexp_expf(xtrace_est(M, l)) - 1);
     E = (double)e0;
     const double sc0 = ldexp(1.0, -e0);
 #pragma unroll
@@ -2244,7 +2261,7 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
   auto post = [&](XMat<NB, CPLX>& Y, int j) {
     E *= 2.0;
     if ((j & 3) == 3) {
-      const int e = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_frexp_exp(xtrace(Y, l)) - 1);
+      const int e = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_frexp_expf(xtrace_est(Y, l)) - 1);
       E += (double)e;
       const double sc2 = ldexp(1.0, -e);
 #pragma unroll

@@ -465,6 +465,34 @@ def test_health_flags():
 
 
 @pytest.mark.parametrize("f32", [False, True])
+@pytest.mark.parametrize("name,beta", [("plaq_batch_ragged", 6.0), ("plaq_batch_ragged", 5000.0),
+                                       ("gue_Y5", 6.0), ("gue_Y5", 5000.0)])
+def test_gibbs_nonfinite_message_is_flagged(name, beta, f32):
+    """A NaN in one message of a top cluster (16 x 16 plaquette, 32 x 32 interval; the
+    scaling-and-squaring kernels, FP32 tail included at beta = 5000) makes the value of that
+    instance NaN and raises the non-finite flag; every other instance keeps its value bit for bit."""
+    lrh = lrhmod()
+    say(f"[nonfinite gibbs] {name} beta={beta} f32={f32}")
+    d = PROBLEMS[name]()
+    P = lrh.Problem(d, 0)
+    R = O.Relaxation(d)
+    pairs = R.to_pairs(R.draw(13, 0.5))
+    q0 = P.dual_eval(P.from_dense(pairs, f32=f32), beta)[0].cpu().numpy()
+    assert P.check() == (0, 0) and np.all(np.isfinite(q0))
+    top = max(len(e) for e, _ in pairs)
+    key = next(k for k in pairs if len(k[0]) == top)
+    pairs[key] = pairs[key].copy()
+    pairs[key][0, 0] = float("nan")
+    q = P.dual_eval(P.from_dense(pairs, f32=f32), beta)[0].cpu().numpy()
+    with pytest.raises(lrh.LrhError) as e:
+        P.check()
+    assert e.value.code == 6
+    bad = np.isnan(q)
+    assert bad.sum() == 1
+    assert np.array_equal(q[~bad], q0[~bad])
+
+
+@pytest.mark.parametrize("f32", [False, True])
 @pytest.mark.parametrize("name", ["plaq", "interval_Y4", "spin1_Y3"])
 def test_graph_replayed_general_problem_equals_plain(name, f32):
     """LRH_FUSED on a problem with larger clusters replays the plain launches from a captured
