@@ -197,7 +197,13 @@ __device__ __forceinline__ void pack(Put put, const HMat<T, CPLX, D>& M) {
 template <int DE, int DC, int M, typename F>
 __device__ __forceinline__ void mask_case(int mask, F& f) {
   if constexpr (__builtin_popcount(M) == log2i(DC)) {
-    if (mask == M) f(std::integral_constant<int, M>{});
+    if (mask == M) {
+      f(std::integral_constant<int, M>{});
+      // An empty statement that differs per case: without it the compiler merges the cases into
+      // one path that indexes the register matrices with a runtime offset, which moves them to
+      // scratch memory (12-24 bytes per lane in every register kernel with children).
+      __asm__ volatile("; mask case %0" :: "n"(M));
+    }
   }
 }
 template <int DE, int DC, typename F, int... I>
@@ -639,6 +645,8 @@ __device__ void cluster_reg_body(const ClusterArgs<T>& A, int64_t c) {
     // ---- a5: partial traces onto the children ----
     if constexpr (DC > 0) {
       if (A.Tout) {
+        // (unrolled, so that the hoisted slot arrays are indexed by constants and stay in registers)
+#pragma unroll
         for (int s = 0; s < (HOIST_CH ? MAXCH : A.maxch); ++s) {
           int m, mask;
           if constexpr (HOIST_CH) {
