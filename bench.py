@@ -42,11 +42,11 @@ HBM_PEAK_GBS = 8000.0
 # reported as null once the sources change.
 TRAFFIC_BYTES = {
     # k_cluster_expm<float,false,16>, beta = 12288 (profiles/k_cluster_expm_c4_plaquette_sweep_counters.md)
-    "c4": ("42570c0e67b58886", 336388099),
+    "c4": ("b592ce4eb2fe8f1e", 336832399),
     # k_cluster_expm_wg<float,true,256>, beta = 64 (profiles/k_cluster_expm_wg_c3_interval_k8_counters.md)
-    "c3k8": ("42570c0e67b58886", 517188139007),
+    "c3k8": ("b592ce4eb2fe8f1e", 517217408009),
     # k_cluster_pair<float,false,GIBBS> (profiles/k_cluster_pair_heisenberg32x32_traffic.md)
-    "c2": ("42570c0e67b58886", 1046499),
+    "c2": ("b592ce4eb2fe8f1e", 1038181),
 }
 
 
