@@ -42,11 +42,11 @@ HBM_PEAK_GBS = 8000.0
 # reported as null once the sources change.
 TRAFFIC_BYTES = {
     # k_cluster_expm<float,false,16>, beta = 12288 (profiles/k_cluster_expm_c4_plaquette_sweep_counters.md)
-    "c4": ("b592ce4eb2fe8f1e", 336832399),
+    "c4": ("ac1f30d11fe8f688", 336599361),
     # k_cluster_expm_wg<float,true,256>, beta = 64 (profiles/k_cluster_expm_wg_c3_interval_k8_counters.md)
-    "c3k8": ("b592ce4eb2fe8f1e", 517217408009),
+    "c3k8": ("ac1f30d11fe8f688", 474577706657),
     # k_cluster_pair<float,false,GIBBS> (profiles/k_cluster_pair_heisenberg32x32_traffic.md)
-    "c2": ("b592ce4eb2fe8f1e", 1038181),
+    "c2": ("ac1f30d11fe8f688", 1038186),
 }
 
 
@@ -263,8 +263,9 @@ def dominant_kernel_roofline(P, nus, beta, f32, torch, reps=3):
         from paper_2609_40336_amd import lrh
         sus = lrh.lrh_measure_fp64_mfma(0)
         extra = dict(sustained_fp64_mfma_tflops=sus, frac_of_sustained=ach / sus,
-                     executed_tflops_note="the exponential executes (5 + s) products of 2 D^3 flops per "
-                                          "cluster, s the squarings (more than the 11 D^3 counted here)")
+                     executed_tflops_note="the exponential executes (4 + s) products of 2 D^3 flops per "
+                                          "cluster with float messages, (5 + s) with double ones, s the "
+                                          "squarings (more than the 11 D^3 counted here)")
     return dict(bound=bound, achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak, traffic=None, **extra,
                 kernel=f"{kind}, bucket D={D} (n={n}), beta={beta:g}",
                 per_launch=dict(flops=F, seconds=t,
