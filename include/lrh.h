@@ -66,7 +66,12 @@ typedef enum {
 
 /* flags for the compute calls */
 #define LRH_F32    0x1u   /* state buffers (nu, zeta, grad, marginals) are float, and the
-                             iterations compute in FP32; certification stays FP64          */
+                             iterations compute in FP32; certification stays FP64.  Gibbs
+                             states of clusters with D_e >= 16 come from scaling and
+                             squaring: a degree-8 Taylor polynomial and the first four
+                             squarings in FP64, the later squarings in FP32 (FP64 messages:
+                             degree 12, every squaring in FP64); the result is within the
+                             float rounding of the messages                                 */
 #define LRH_FUSED  0x2u   /* graph-replayed iterations: for 2-local problems one launch per
                              iteration (the message update of the previous step folded into
                              the cluster kernel); otherwise the plain launches of each
