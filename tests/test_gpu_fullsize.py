@@ -173,11 +173,12 @@ def test_gibbs_at_solve_beta_matches_oracle(name, beta):
 @pytest.mark.parametrize("name", list(BIG_BETA))
 @pytest.mark.parametrize("beta", [1024.0, 12288.0])
 def test_fp32_gibbs_at_solve_beta(name, beta):
-    """Float messages at the solve's beta (the squarings after the fourth on the FP32 matrix
-    cores, theta assembled in FP32): F_beta per site within 2e-5 of the FP64 oracle evaluated at
-    the same (float-rounded) messages -- F_beta is 1-Lipschitz in theta, so the float assembly
-    and squarings move it by about their backward error -- and every marginal a density matrix
-    (unit trace, no eigenvalue below -1e-5)."""
+    """Float messages at the solve's beta (degree-8 polynomial, the squarings after the fourth on
+    the FP32 matrix cores, theta assembled in FP32): F_beta per site within 2e-6 of the FP64
+    oracle evaluated at the same (float-rounded) messages -- F_beta is 1-Lipschitz in theta, so
+    the float assembly and squarings move it by about their backward error, a few u_32 = 6e-8
+    times ||theta|| (up to ~30) per cluster; observed at most 2e-7 -- and every marginal a
+    density matrix (unit trace, no eigenvalue below -1e-5)."""
     lrh = lrhmod()
     say(f"[fp32 gibbs big beta] {name} beta={beta}")
     d = BIG_BETA[name]()
@@ -191,7 +192,7 @@ def test_fp32_gibbs_at_solve_beta(name, beta):
     n = sites_per_instance(d)
     err_q = float(np.max(np.abs(q.cpu().numpy() - q_o) / n))
     say(f"  per-site value err {err_q:.2e}")
-    assert err_q <= 2e-5
+    assert err_q <= 2e-6
     for c, rho in P.marg_dense(m).items():
         assert abs(np.trace(rho).real - 1.0) <= 1e-5
         assert np.linalg.eigvalsh(rho).min() >= -1e-5
