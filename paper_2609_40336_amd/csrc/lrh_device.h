@@ -2149,23 +2149,16 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
   // ---- shift, scale ----
   const double mu = xtrace(X, l) / DE;
   const XDiag<NB, CPLX> dg(l);
-  double n2 = 0.0;
 #pragma unroll
   for (int I = 0; I < NB; ++I)
 #pragma unroll
-    for (int J = 0; J < NB; ++J)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        double v = X.re[I][J][r];
-        if (I == J) v = dg.add(r, -mu, v);
-        X.re[I][J][r] = v;
-        n2 = fma(v, v, n2);
-        if constexpr (CPLX) n2 = fma(X.im[I][J][r], X.im[I][J][r], n2);
-      }
-  // induced 1-norm as the largest column sum (theta is Hermitian, so it equals the largest row
-  // sum): column 16 J + l%16 of block column J is spread over the registers of the lanes
-  // l%16 + 16 g; two xor-shuffles complete it in every lane, a DPP row maximum then leaves the
-  // largest column sum in every lane
+    for (int r = 0; r < 4; ++r) X.re[I][I][r] = dg.add(r, -mu, X.re[I][I][r]);
+  // The scale uses the induced 1-norm, an upper bound of the spectral radius: the largest column
+  // sum (theta is Hermitian, so it equals the largest row sum).  Column 16 J + l%16 of block
+  // column J is spread over the registers of the lanes l%16 + 16 g; two xor-shuffles complete it
+  // in every lane, a DPP row maximum then leaves the largest column sum in every lane.  (On these
+  // clusters it is at most the Frobenius norm, the other bound at hand, so that one is not
+  // formed; moduli of complex entries use the hardware square root, as nrm only chooses s.)
   double rmax = 0.0;
 #pragma unroll
   for (int J = 0; J < NB; ++J) {
@@ -2174,7 +2167,7 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
     for (int I = 0; I < NB; ++I)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        if constexpr (CPLX) a += sqrt(fma(X.re[I][J][r], X.re[I][J][r], X.im[I][J][r] * X.im[I][J][r]));
+        if constexpr (CPLX) a += __builtin_amdgcn_sqrt(fma(X.re[I][J][r], X.re[I][J][r], X.im[I][J][r] * X.im[I][J][r]));
         else a += fabs(X.re[I][J][r]);
       }
     a += __shfl_xor(a, 16, 64);
@@ -2185,9 +2178,7 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
   rmax = fmax(rmax, dpp_mov<0x4E>(rmax));    // quad_perm [2, 3, 0, 1]
   rmax = fmax(rmax, dpp_mov<0x141>(rmax));   // row_half_mirror
   rmax = fmax(rmax, dpp_mov<0x140>(rmax));   // row_mirror
-  // (the hardware square root: nrm only chooses s, where a relative error of a few units in
-  // the last place is immaterial)
-  const double nrm = beta * fmin(__builtin_amdgcn_sqrt(wave_sum_dpp(n2)), rmax);
+  const double nrm = beta * rmax;
   // s = the least s >= 0 with nrm <= 2^(s-1), at most 200 (0 for a NaN norm): from the binary
   // exponent of nrm instead of a search
   int s;
@@ -2249,7 +2240,10 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
   // integer, E <- 2E + e_j (starting from E = e_0), so no logarithm or division sits in the loop:
   //     log Z = E log 2 + log Tr Y_s,   rho = Y_s / Tr Y_s.
   // X and M alternate as product buffers (the loop is unrolled by two).
+  // E holds the accumulated exponent as of squaring jr (jr = -1: before the first); the value
+  // after squaring j is E 2^(j - jr), so only the rescaling points touch it (ldexp is exact here).
   double E;
+  int jr = -1;
   {
     const int e0 = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_frexp_expf(xtrace_est(M, l)) - 1);
     E = (double)e0;
@@ -2274,10 +2268,10 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
   int n64 = s;
   if constexpr (std::is_same<T, float>::value) n64 = s < kF64Squarings ? s : kF64Squarings;
   auto post = [&](XMat<NB, CPLX>& Y, int j) {
-    E *= 2.0;
     if ((j & 3) == 3) {
       const int e = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_frexp_expf(xtrace_est(Y, l)) - 1);
-      E += (double)e;
+      E = ldexp(E, j - jr) + (double)e;
+      jr = j;
       const double sc2 = ldexp(1.0, -e);
 #pragma unroll
       for (int I = 0; I < NB; ++I)
@@ -2328,10 +2322,10 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
           if constexpr (CPLX) Ya.im[I][J][r] = (float)sai[o];
         }
     auto post32 = [&](XMat32<NB, CPLX>& Y, int j) {
-      E *= 2.0;
       if ((j & 3) == 3) {
         const int e = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_frexp_expf(xtrace32(Y, l)) - 1);
-        E += (double)e;
+        E = ldexp(E, j - jr) + (double)e;
+        jr = j;
         const float sc2 = ldexpf(1.f, -e);
 #pragma unroll
         for (int I = 0; I < NB; ++I)
@@ -2397,11 +2391,15 @@ __global__ __launch_bounds__(64) void k_cluster_expm(ClusterArgs<T> A) {
   }
   double L;
   {
+    E = ldexp(E, s - 1 - jr);   // the exponent after the last squaring
     const double tf = xtrace(M, l);
     double kf;
     const double lm = log_split(tf, kf);
     L = fma(E + kf, 0.69314718055994530942, lm);   // E + kf is exact
-    const double it = 1.0 / tf;
+    // 1 / tf from the hardware reciprocal and two Newton steps (tf is a positive normal number)
+    double it = __builtin_amdgcn_rcp(tf);
+    it = fma(fma(-tf, it, 1.0), it, it);
+    it = fma(fma(-tf, it, 1.0), it, it);
 #pragma unroll
     for (int I = 0; I < NB; ++I)
 #pragma unroll
