@@ -1722,20 +1722,24 @@ __global__ __launch_bounds__(1024) void k_cluster_big(ClusterArgs<T> A, T* scrat
 //
 // The smoothed dual needs rho_e = exp(-beta theta_e) / Z and F_beta = -(1/beta) log Z only
 // (Sec. 4.1.2); the eigenvectors are not needed for that.  With mu = Tr(theta)/D and
-// X = beta (theta - mu), the scaling s is the least s >= 0 with ||X|| / 2^s <= 1/2, where
-// ||X|| = min(||X||_F, ||X||_1) (both norms are submultiplicative, so the Taylor remainder
-// bound holds in either; the induced 1-norm, the largest absolute row sum, is the tight one
+// X = beta (theta - mu), the scaling s is the least s >= 0 with ||X|| / 2^s <= 1/2, where ||X||
+// is an upper bound of the spectral norm: the induced 1-norm (largest absolute row sum) in the
+// one-wave kernel, min(||X||_F, ||X||_1) in the workgroup kernel (both norms are
+// submultiplicative, so the Taylor remainder bound holds in either; the 1-norm is the tight one
 // for lifted local terms 1 (x) h, whose Frobenius norm carries a factor sqrt(D / D_h)), and
-//     E0 = T12(-X / 2^s)                (degree-12 Taylor polynomial, Paterson-Stockmeyer, p = 3)
-//     Y0 = E0 / Tr E0,  Y_j = Y_{j-1}^2 / tau_j    (j = 1..s)
-//     rho = Y_s / Tr Y_s,  log Z = 2^s log Tr E0 + sum_j 2^(s-j) log tau_j + log Tr Y_s
-// for any positive rescalings tau_j of the squarings (here exact powers of two).
+//     E0 = T_m(-X / 2^s)                (Taylor polynomial, Paterson-Stockmeyer, p = 3; m = 12,
+//                                        or 8 for float messages)
+//     Y0 = E0 / tau_0,  Y_j = Y_{j-1}^2 / tau_j    (j = 1..s)
+//     rho = Y_s / Tr Y_s,  log Z = 2^s log tau_0 + sum_j 2^(s-j) log tau_j + log Tr Y_s
+// for any positive rescalings tau_j (the one-wave kernel uses exact powers of two; the
+// workgroup kernel tau_0 = Tr E0, tau_j = (Tr Y_{j-1})^2).
 // The truncation error of T12 at norm 1/2 is below 2e-14 relative (in the norm that set s),
-// i.e. a backward error of about 7e-14 ||X|| in X, which exact squaring preserves.  Rounding in the squarings adds a
-// relative error of order D u (spectral spread / gap) to rho: the part along the dominant
-// eigenvector is removed by the final trace normalisation, the rest is damped once the
-// spectrum separates.  All of it runs in FP64 on v_mfma_f64_16x16x4_f64 whatever the message
-// precision.
+// i.e. a backward error of about 7e-14 ||X|| in X, which exact squaring preserves (T8: 5.4e-9,
+// under the float rounding of the messages).  Rounding in the squarings adds a relative error of
+// order D u (spectral spread / gap) to rho: the part along the dominant eigenvector is removed
+// by the final trace normalisation, the rest is damped once the spectrum separates.  The
+// polynomial and the first four squarings run in FP64 on the matrix cores; with double messages
+// so do the rest, with float messages the later squarings run in FP32.
 //
 // One wavefront per cluster.  A matrix is NB x NB blocks of 16 x 16 held in the MFMA result
 // layout: lane l, register r of block (I, J) is element (16 I + 4 r + l/16, 16 J + l%16).
