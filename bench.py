@@ -42,11 +42,11 @@ HBM_PEAK_GBS = 8000.0
 # reported as null once the sources change.
 TRAFFIC_BYTES = {
     # k_cluster_expm<float,false,16>, beta = 12288 (profiles/k_cluster_expm_c4_plaquette_sweep_counters.md)
-    "c4": ("27775a908486b614", 336909924),
+    "c4": ("08381585aefdc54d", 336836217),
     # k_cluster_expm_wg<float,true,256>, beta = 64 (profiles/k_cluster_expm_wg_c3_interval_k8_counters.md)
-    "c3k8": ("27775a908486b614", 474840890402),
+    "c3k8": ("08381585aefdc54d", 474942516323),
     # k_cluster_pair<float,false,GIBBS> (profiles/k_cluster_pair_heisenberg32x32_traffic.md)
-    "c2": ("27775a908486b614", 1038137),
+    "c2": ("08381585aefdc54d", 1038195),
 }
 
 
